@@ -1,0 +1,182 @@
+/*
+ * liblm.h -- C ABI of the MI355X (gfx950) library for geodesic landmark shooting with the
+ * N-particle Euler-Poincare system (Camassa, Kuang & Lee, "A class of fast geodesic
+ * shooting algorithms for template matching and its applications via the N-particle system
+ * of the Euler-Poincare equations", arXiv 1510.03816).
+ *
+ * Problem statement (section "Algorithm for Landmark Shooting", equation "exact-matching"):
+ * given labelled template landmarks X and target landmarks Y in R^dim, find initial momenta
+ * p0 such that the flow of the N-particle system started at (X, p0) carries X onto Y at
+ * t = 1.  Everything here runs on the GPU; no entry point falls back to host arithmetic.
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are DEVICE pointers unless a comment says "host".  Point sets are stored
+ *     component-major ("SoA"): element (c, i) -- coordinate c of landmark i -- lives at
+ *     x[c*n + i], c < dim, i < n.  Every array is contiguous and owned by the caller.
+ *   - Element type of q/p/dq/dp/u buffers: double when params->dtype == LM_F64, float when
+ *     LM_F32.  Feedback matching and the adjoint always take double buffers.
+ *   - Kernels run on the caller's HIP stream (`stream`, a hipStream_t passed as void*;
+ *     NULL = the default stream).  Entry points documented "asynchronous" return after
+ *     enqueueing; those documented "synchronous" return after the stream has drained.
+ *   - Temporary device memory is taken from the stream-ordered allocator of the stream's
+ *     device and released on the same stream; nothing is cached between calls.
+ *   - Arguments are checked before anything is enqueued: an invalid argument returns
+ *     LM_EINVAL and enqueues nothing.  A HIP runtime failure returns LM_EHIP.
+ *     lm_last_error() then describes the failure (thread-local text).
+ *   - All entry points are thread-safe; calls that share output buffers must be ordered by
+ *     the caller.
+ */
+#ifndef LIBLM_H
+#define LIBLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lm_status {
+    LM_OK = 0,
+    LM_EINVAL = -1,        /* invalid argument (nothing was enqueued) */
+    LM_ENOMEM = -2,        /* device memory exhausted */
+    LM_EHIP = -3,          /* HIP runtime error (text in lm_last_error) */
+    LM_ENOTCONV = -4,      /* iteration limit reached before the tolerance */
+    LM_EDIVERGED = -5,     /* non-finite residual: the iteration blew up */
+    LM_ESINGULAR = -6,     /* kernel matrix not numerically positive definite */
+    LM_EUNSUPPORTED = -7   /* combination of options not provided */
+} lm_status;
+
+typedef enum lm_kernel {
+    /* Conical kernel ("conon") G(r) = exp(-r/sigma): the Green's function of the
+     * N-particle system for the metric H^{3/2} in the plane, normalised so that G(0) = 1
+     * (equation of G_{1/2} and the normalisation stated with the exact-matching
+     * experiments; sigma is the paper's alpha). */
+    LM_KERNEL_CONON = 0,
+    /* Gaussian kernel G(r) = exp(-r^2/sigma^2) (the smooth kernel of the metric H^infinity
+     * in the metric-comparison section; sigma^2 is the paper's alpha^2). */
+    LM_KERNEL_GAUSS = 1
+} lm_kernel;
+
+typedef enum lm_dtype { LM_F64 = 0, LM_F32 = 1 } lm_dtype;
+
+/* Model parameters shared by every entry point. */
+typedef struct lm_params {
+    int32_t dim;      /* spatial dimension: 2 or 3 */
+    int32_t kernel;   /* lm_kernel */
+    int32_t dtype;    /* lm_dtype of q/p buffers (lm_rhs, lm_shoot, lm_hamiltonian, lm_velocity) */
+    int32_t flags;    /* reserved, must be 0 */
+    double sigma;     /* kernel width, > 0 and finite */
+    double tau;       /* >= 0: weight of the inexact advection term tau*p_i (equation
+                         "N-particle-inexact", where the paper writes sigma^2); 0 = exact */
+    double cutoff;    /* 0 = every pair (exact).  > 0: pairs of particle tiles whose bounding
+                         boxes lie farther apart than `cutoff` are skipped (an approximation;
+                         the dropped terms are bounded by G(cutoff) and |G'(cutoff)|) */
+} lm_params;
+
+/* Settings of Algorithm 1 (feedback-control iteration) with the constant gain M = h I. */
+typedef struct lm_match_opts {
+    double h;             /* search length h > 0 (M = h I) */
+    double tol;           /* tolerance > 0 of the stopping test */
+    int32_t max_iter;     /* >= 0: most momentum updates made */
+    int32_t steps;        /* >= 1: RK4 steps of each shoot on t in [0, 1] */
+    int32_t stop_rule;    /* 0: stop when max_{c,i} |Y - q(1)| < tol (exact matching);
+                             1: stop when max |u^k - u^(k-1)| = h max|Y - q(1)|_(k-1) < tol
+                                (the rule stated for inexact matching) */
+    int32_t cg_max_iter;  /* conjugate-gradient iterations per solve; 0 = 20*n + 100 */
+    double cg_rtol;       /* relative residual of each K-solve; 0 = 1e-13 */
+    double *resid_hist;   /* HOST, nullable: receives the residual of each shoot */
+    int32_t hist_len;     /* capacity of resid_hist */
+    int32_t reserved;
+} lm_match_opts;
+
+/* What a feedback match reports (HOST struct). */
+typedef struct lm_match_info {
+    int32_t iters;        /* momentum updates made before the final shoot */
+    int32_t cg_iters;     /* conjugate-gradient iterations summed over every solve */
+    double resid_inf;     /* max_{c,i} |Y - q(1)| of the final shoot */
+    double H;             /* Hamiltonian 1/2 sum_ij (p_i.p_j) G(|X_i-X_j|) at (X, p0);
+                             the values the paper prints are 2H */
+} lm_match_info;
+
+/* Right-hand side of the N-particle system (equation "N-particle"; with tau > 0 the inexact
+ * system, equation "N-particle-inexact"):
+ *     dq_i = sum_{j=1..n} G(|q_i - q_j|) p_j + tau p_i
+ *     dp_i = -sum_{j != i} (p_i . p_j) G'(|q_i - q_j|) (q_i - q_j)/|q_i - q_j|
+ * Distinct particles at the same point exert no force on each other.
+ * q, p: inputs (dim, n); dq, dp: outputs (dim, n), must not overlap q or p.
+ * Asynchronous. */
+lm_status lm_rhs(const lm_params *params, int64_t n, const void *q, const void *p,
+                 void *dq, void *dp, void *stream);
+
+/* Shooting map: integrates the N-particle system from (q0, p0) at t = 0 to t = t1 with
+ * `steps` steps of the classical fourth-order Runge-Kutta method (the explicit integrator
+ * the paper names for evolving the system in Algorithm 1, step 1).  Writes (q(t1), p(t1))
+ * to q1, p1; q1/p1 may be the same buffers as q0/p0 (in-place shoot).  t1 may be any
+ * finite value (t1 = 1 in Algorithm 1).  Asynchronous. */
+lm_status lm_shoot(const lm_params *params, int64_t n, const void *q0, const void *p0,
+                   double t1, int32_t steps, void *q1, void *p1, void *stream);
+
+/* Discrete Hamiltonian H = 1/2 sum_i sum_j (p_i . p_j) G(|q_i - q_j|) (equation "H").
+ * *H_out is a HOST double.  Synchronous. */
+lm_status lm_hamiltonian(const lm_params *params, int64_t n, const void *q, const void *p,
+                         double *H_out, void *stream);
+
+/* Solves (K(X) + tau I) x = b for every component c, with K_ij = G(|X_i - X_j|): the
+ * conversion of a velocity field u at the landmarks into momenta p (Algorithm 1, step 4,
+ * read as p = K(X)^{-1} u).  Matrix-free conjugate gradients, every product computed on
+ * the fly on the GPU.  X, b, x: double (dim, n); x may alias b.  Stops when
+ * ||b_c - K x_c||_2 <= rtol ||b_c||_2 for every c.  *iters_out (HOST, nullable) receives
+ * the iteration count.  Synchronous.  LM_ESINGULAR if a curvature p.Kp <= 0 appears,
+ * LM_ENOTCONV if max_iter is reached (x then holds the last iterate). */
+lm_status lm_ksolve(const lm_params *params, int64_t n, const double *X, const double *b,
+                    double *x, double rtol, int32_t max_iter, int32_t *iters_out,
+                    void *stream);
+
+/* Algorithm 1 (feedback-control iteration) with M = h I:
+ *     p <- p0;  for k = 0, 1, ...:  q(1) = shoot(X, p);  e = Y - q(1);
+ *         stop by opts->stop_rule;  u <- u + h e, i.e. p <- p + h (K(X) + tau I)^{-1} e
+ * X, Y: double (dim, n).  p0: double (dim, n), in: initial momenta (zeros in the paper),
+ * out: the final momenta.  q1 (nullable): double (dim, n), receives q(1) of the last
+ * shoot.  info: HOST.  params->dtype = LM_F32 shoots in single precision while the
+ * momenta, the residual and the K-solves stay in double.  Synchronous.
+ * Returns LM_OK, LM_ENOTCONV, LM_EDIVERGED (non-finite residual, as the paper's NaN for
+ * h > 1) or LM_ESINGULAR; in every case p0 and info describe the last iterate. */
+lm_status lm_feedback_match(const lm_params *params, const lm_match_opts *opts, int64_t n,
+                            const double *X, const double *Y, double *p0, double *q1,
+                            lm_match_info *info, void *stream);
+
+/* What one feedback iteration reports (HOST struct). */
+typedef struct lm_step_info {
+    double resid_inf;     /* max_{c,i} |Y - q(1)| of this iteration's shoot */
+    double shoot_ms;      /* GPU time of the shoot (HIP events on the stream) */
+    double solve_ms;      /* GPU time of the K-solve and momentum update (0 if none) */
+    int32_t converged;    /* 1 when resid_inf < tol (p then unchanged) */
+    int32_t cg_iters;     /* CG iterations of the solve */
+} lm_step_info;
+
+/* One iteration of Algorithm 1 (the loop body of lm_feedback_match with the exact stopping
+ * rule): shoots (X, p) to t = 1, computes r = max_{c,i} |Y - q(1)| and, unless r < tol,
+ * updates p in place by p <- p + h (K(X) + tau I)^{-1} (Y - q(1)).  Lets a caller drive,
+ * interleave, checkpoint or resume the iteration itself: its whole state is p.
+ * opts->max_iter, stop_rule and the history fields are ignored.  q1 (nullable) receives
+ * q(1).  info: HOST.  Synchronous.  LM_EDIVERGED for a non-finite residual. */
+lm_status lm_feedback_step(const lm_params *params, const lm_match_opts *opts, int64_t n,
+                           const double *X, const double *Y, double *p, double *q1,
+                           lm_step_info *info, void *stream);
+
+/* Velocity field at arbitrary points (equation "u"): u(x_a) = sum_j G(|x_a - q_j|) p_j.
+ * q, p: (dim, n); x, u: (dim, m).  Asynchronous. */
+lm_status lm_velocity(const lm_params *params, int64_t n, const void *q, const void *p,
+                      int64_t m, const void *x, void *u, void *stream);
+
+/* Text describing the last non-OK status returned on the calling thread ("" if none). */
+const char *lm_last_error(void);
+
+/* Library version string. */
+const char *lm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBLM_H */

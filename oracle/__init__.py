@@ -45,12 +45,16 @@ def lib():
             build()
         L = ctypes.CDLL(LIB)
         d, i, l, P = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p
+        L.orc_num_threads.restype = i
+        L.orc_num_threads.argtypes = []
         L.orc_green.restype = d
         L.orc_green.argtypes = [i, d, d]
         L.orc_green_prime.restype = d
         L.orc_green_prime.argtypes = [i, d, d]
         L.orc_rhs.restype = None
         L.orc_rhs.argtypes = [i, l, i, d, d, P, P, P, P]
+        L.orc_rhs_rows.restype = None
+        L.orc_rhs_rows.argtypes = [i, l, i, d, d, P, P, P, l, P, P]
         L.orc_hamiltonian.restype = d
         L.orc_hamiltonian.argtypes = [i, l, i, d, P, P]
         L.orc_shoot.restype = None
@@ -79,6 +83,11 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return lib().orc_num_threads()
+
+
 def green(kernel: int, sigma: float, r: float) -> float:
     return lib().orc_green(kernel, sigma, r)
 
@@ -93,6 +102,17 @@ def rhs(q, p, kernel: int, sigma: float, tau: float = 0.0):
     dim, n = q.shape
     dq, dp = np.empty_like(q), np.empty_like(p)
     lib().orc_rhs(dim, n, kernel, sigma, tau, _ptr(q), _ptr(p), _ptr(dq), _ptr(dp))
+    return dq, dp
+
+
+def rhs_rows(q, p, idx, kernel: int, sigma: float, tau: float = 0.0):
+    """Rows idx of the right-hand side: returns (dq, dp) of shape (dim, len(idx))."""
+    q, p = _c(q), _c(p)
+    dim, n = q.shape
+    ix = np.ascontiguousarray(idx, dtype=np.int64)
+    dq = np.empty((dim, len(ix)))
+    dp = np.empty((dim, len(ix)))
+    lib().orc_rhs_rows(dim, n, kernel, sigma, tau, _ptr(q), _ptr(p), _ptr(ix), len(ix), _ptr(dq), _ptr(dp))
     return dq, dp
 
 

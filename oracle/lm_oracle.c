@@ -33,12 +33,25 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
 #define ORC_ENOTPD (-2)
 #define ORC_ENOTCONV (-4)
 #define ORC_EDIVERGED (-5)
+
+/* Threads the OpenMP loops use (reported with timings of the oracle). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---- Green's functions: G(r) and its radial derivative G'(r) -------------------------- */
 
@@ -102,6 +115,34 @@ void orc_rhs(int dim, long n, int kernel, double sigma, double tau,
         for (int c = 0; c < dim; ++c) {
             dq[c * n + i] = v[c] + tau * p[c * n + i];
             dp[c * n + i] = f[c];
+        }
+    }
+}
+
+/* The same right-hand side for a subset of targets: rows idx[0..nidx) of (dq, dp), written
+ * to dq_rows/dp_rows as (dim, nidx).  Lets large problems be checked on sampled outputs. */
+void orc_rhs_rows(int dim, long n, int kernel, double sigma, double tau,
+                  const double *q, const double *p, const long *idx, long nidx,
+                  double *dq_rows, double *dp_rows)
+{
+#pragma omp parallel for schedule(static) if (nidx >= 16)
+    for (long a = 0; a < nidx; ++a) {
+        long i = idx[a];
+        double v[3] = {0.0, 0.0, 0.0}, f[3] = {0.0, 0.0, 0.0};
+        for (long j = 0; j < n; ++j) {
+            double r = dist(dim, n, q, i, j);
+            double g = green(kernel, sigma, r);
+            for (int c = 0; c < dim; ++c) v[c] += g * p[c * n + j];
+            if (j == i || r == 0.0) continue;
+            double pp = 0.0;
+            for (int c = 0; c < dim; ++c) pp += p[c * n + i] * p[c * n + j];
+            double gp = green_prime_g(kernel, sigma, r, g);
+            for (int c = 0; c < dim; ++c)
+                f[c] -= pp * gp * (q[c * n + i] - q[c * n + j]) / r;
+        }
+        for (int c = 0; c < dim; ++c) {
+            dq_rows[c * nidx + a] = v[c] + tau * p[c * n + i];
+            dp_rows[c * nidx + a] = f[c];
         }
     }
 }

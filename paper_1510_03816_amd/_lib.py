@@ -1,0 +1,214 @@
+"""ctypes binding of liblm.so (include/liblm.h).  Argument marshalling only.
+
+Functions carry the C names and take torch tensors on the GPU (shape (dim, n), contiguous,
+float64 or float32) plus an optional stream; every computation runs in the HIP library.
+A non-OK status raises LmError with the library's message.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblm.so")
+
+LM_OK, LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_ENOTCONV, LM_EDIVERGED, LM_ESINGULAR, LM_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+STATUS_NAMES = {0: "LM_OK", -1: "LM_EINVAL", -2: "LM_ENOMEM", -3: "LM_EHIP", -4: "LM_ENOTCONV",
+                -5: "LM_EDIVERGED", -6: "LM_ESINGULAR", -7: "LM_EUNSUPPORTED"}
+CONON, GAUSS = 0, 1
+F64, F32 = 0, 1
+
+# every symbol include/liblm.h declares
+EXPORTS = ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
+           "lm_feedback_step", "lm_velocity", "lm_last_error", "lm_version"]
+
+
+class LmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), message))
+        self.status = status
+
+
+class lm_params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("kernel", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("sigma", ctypes.c_double), ("tau", ctypes.c_double),
+                ("cutoff", ctypes.c_double)]
+
+
+class lm_match_opts(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("stop_rule", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32),
+                ("cg_rtol", ctypes.c_double), ("resid_hist", ctypes.POINTER(ctypes.c_double)),
+                ("hist_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lm_match_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("resid_inf", ctypes.c_double),
+                ("H", ctypes.c_double)]
+
+
+class lm_step_info(ctypes.Structure):
+    _fields_ = [("resid_inf", ctypes.c_double), ("shoot_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("converged", ctypes.c_int32), ("cg_iters", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree liblm.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblm.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_1510_03816_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        PP = ctypes.POINTER(lm_params)
+        L.lm_rhs.argtypes = [PP, i64, P, P, P, P, P]
+        L.lm_shoot.argtypes = [PP, i64, P, P, d, i32, P, P, P]
+        L.lm_hamiltonian.argtypes = [PP, i64, P, P, ctypes.POINTER(d), P]
+        L.lm_ksolve.argtypes = [PP, i64, P, P, P, d, i32, ctypes.POINTER(i32), P]
+        L.lm_feedback_match.argtypes = [PP, ctypes.POINTER(lm_match_opts), i64, P, P, P, P,
+                                        ctypes.POINTER(lm_match_info), P]
+        L.lm_feedback_step.argtypes = [PP, ctypes.POINTER(lm_match_opts), i64, P, P, P, P,
+                                       ctypes.POINTER(lm_step_info), P]
+        L.lm_velocity.argtypes = [PP, i64, P, P, i64, P, P, P]
+        for name in ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
+                     "lm_feedback_step", "lm_velocity"]:
+            getattr(L, name).restype = ctypes.c_int
+        L.lm_last_error.restype = ctypes.c_char_p
+        L.lm_last_error.argtypes = []
+        L.lm_version.restype = ctypes.c_char_p
+        L.lm_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return load().lm_last_error().decode()
+
+
+def _check(status: int, allow=()):
+    if status != LM_OK and status not in allow:
+        raise LmError(status, last_error())
+    return status
+
+
+def make_params(dim: int, kernel: int, sigma: float, dtype: int = F64, tau: float = 0.0,
+                cutoff: float = 0.0) -> lm_params:
+    return lm_params(dim, kernel, dtype, 0, float(sigma), float(tau), float(cutoff))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _check_tensor(t, dim, n, dtype, name):
+    import torch
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a GPU tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if tuple(t.shape) != (dim, n):
+        raise ValueError("%s must have shape (%d, %d), got %s" % (name, dim, n, tuple(t.shape)))
+    want = torch.float64 if dtype == F64 else torch.float32
+    if t.dtype != want:
+        raise ValueError("%s must be %s" % (name, want))
+
+
+def lm_rhs(params: lm_params, q, p, dq, dp, stream=None):
+    dim, n = q.shape
+    for t, nm in [(q, "q"), (p, "p"), (dq, "dq"), (dp, "dp")]:
+        _check_tensor(t, params.dim, n, params.dtype, nm)
+    return _check(load().lm_rhs(ctypes.byref(params), n, _ptr(q), _ptr(p), _ptr(dq), _ptr(dp), _stream(stream)))
+
+
+def lm_shoot(params: lm_params, q0, p0, t1: float, steps: int, q1, p1, stream=None):
+    dim, n = q0.shape
+    for t, nm in [(q0, "q0"), (p0, "p0"), (q1, "q1"), (p1, "p1")]:
+        _check_tensor(t, params.dim, n, params.dtype, nm)
+    return _check(load().lm_shoot(ctypes.byref(params), n, _ptr(q0), _ptr(p0), float(t1), int(steps),
+                                  _ptr(q1), _ptr(p1), _stream(stream)))
+
+
+def lm_hamiltonian(params: lm_params, q, p, stream=None) -> float:
+    dim, n = q.shape
+    for t, nm in [(q, "q"), (p, "p")]:
+        _check_tensor(t, params.dim, n, params.dtype, nm)
+    H = ctypes.c_double(0.0)
+    _check(load().lm_hamiltonian(ctypes.byref(params), n, _ptr(q), _ptr(p), ctypes.byref(H), _stream(stream)))
+    return H.value
+
+
+def lm_ksolve(params: lm_params, X, b, x, rtol: float = 1e-13, max_iter: int = 0, stream=None) -> int:
+    dim, n = X.shape
+    for t, nm in [(X, "X"), (b, "b"), (x, "x")]:
+        _check_tensor(t, params.dim, n, F64, nm)
+    it = ctypes.c_int32(0)
+    mi = int(max_iter) if max_iter > 0 else 20 * n + 100
+    _check(load().lm_ksolve(ctypes.byref(params), n, _ptr(X), _ptr(b), _ptr(x), float(rtol), mi,
+                            ctypes.byref(it), _stream(stream)))
+    return it.value
+
+
+def lm_feedback_match(params: lm_params, X, Y, p0, h: float, tol: float, steps: int, max_iter: int = 500,
+                      q1=None, stop_rule: int = 0, cg_rtol: float = 0.0, cg_max_iter: int = 0,
+                      hist_len: int = 1024, stream=None, raise_on=(LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_EUNSUPPORTED)):
+    """Runs Algorithm 1 in place on p0.  Returns (status, info, residual history).
+
+    Statuses describing the iteration itself (not converged, diverged, singular K) are
+    returned, not raised; argument and runtime errors raise LmError.
+    """
+    dim, n = X.shape
+    for t, nm in [(X, "X"), (Y, "Y"), (p0, "p0")] + ([(q1, "q1")] if q1 is not None else []):
+        _check_tensor(t, params.dim, n, F64, nm)
+    hist = (ctypes.c_double * max(1, hist_len))()
+    o = lm_match_opts(float(h), float(tol), int(max_iter), int(steps), int(stop_rule), int(cg_max_iter),
+                      float(cg_rtol), ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(hist_len), 0)
+    info = lm_match_info()
+    st = load().lm_feedback_match(ctypes.byref(params), ctypes.byref(o), n, _ptr(X), _ptr(Y), _ptr(p0),
+                                  _ptr(q1), ctypes.byref(info), _stream(stream))
+    if st in raise_on:
+        raise LmError(st, last_error())
+    k = min(info.iters + 1, hist_len)
+    return st, info, [hist[i] for i in range(k)]
+
+
+def lm_feedback_step(params: lm_params, X, Y, p, h: float, tol: float, steps: int, q1=None,
+                     cg_rtol: float = 0.0, cg_max_iter: int = 0, stream=None) -> lm_step_info:
+    """One iteration of Algorithm 1 on p (in place); returns the lm_step_info."""
+    dim, n = X.shape
+    for t, nm in [(X, "X"), (Y, "Y"), (p, "p")] + ([(q1, "q1")] if q1 is not None else []):
+        _check_tensor(t, params.dim, n, F64, nm)
+    o = lm_match_opts(float(h), float(tol), 0, int(steps), 0, int(cg_max_iter), float(cg_rtol), None, 0, 0)
+    info = lm_step_info()
+    _check(load().lm_feedback_step(ctypes.byref(params), ctypes.byref(o), n, _ptr(X), _ptr(Y), _ptr(p), _ptr(q1),
+                                   ctypes.byref(info), _stream(stream)))
+    return info
+
+
+def lm_velocity(params: lm_params, q, p, x, u, stream=None):
+    dim, n = q.shape
+    m = x.shape[1]
+    for t, nm in [(q, "q"), (p, "p")]:
+        _check_tensor(t, params.dim, n, params.dtype, nm)
+    for t, nm in [(x, "x"), (u, "u")]:
+        _check_tensor(t, params.dim, m, params.dtype, nm)
+    return _check(load().lm_velocity(ctypes.byref(params), n, _ptr(q), _ptr(p), m, _ptr(x), _ptr(u),
+                                     _stream(stream)))
+
+
+def lm_version() -> str:
+    return load().lm_version().decode()

@@ -1,0 +1,628 @@
+// lm_api.hip -- host side of the C ABI declared in include/liblm.h.
+//
+// Argument checks, stream-ordered workspace, and the loops that sequence the kernels of
+// lm_kernels.hip: the Runge-Kutta stage loop of a shoot, the conjugate-gradient K-solve and
+// Algorithm 1's feedback loop.  No arithmetic of the method runs on the host: the host only
+// decides what to launch next and reads back the scalars that decide it (the residual of
+// each shoot, the CG residual norms).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lm_status fail(lm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+lm_status fail_hip(hipError_t e, const char* what)
+{
+    if (e == hipErrorOutOfMemory) return fail(LM_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(LM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define LM_HIP(expr)                                                  \
+    do {                                                              \
+        hipError_t e_ = (expr);                                       \
+        if (e_ != hipSuccess) return fail_hip(e_, #expr);             \
+    } while (0)
+
+#define LM_TRY(expr)                                                  \
+    do {                                                              \
+        lm_status s_ = (expr);                                        \
+        if (s_ != LM_OK) return s_;                                   \
+    } while (0)
+
+// Stream-ordered device allocations released (on the same stream) when the owner dies.
+class Workspace {
+public:
+    explicit Workspace(hipStream_t st) : st_(st) {}
+    ~Workspace()
+    {
+        for (void* p : ptrs_) (void)hipFreeAsync(p, st_);
+    }
+    Workspace(const Workspace&) = delete;
+    Workspace& operator=(const Workspace&) = delete;
+
+    template <class T>
+    lm_status get(T** out, int64_t count)
+    {
+        void* p = nullptr;
+        size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+        hipError_t e = hipMallocAsync(&p, bytes, st_);
+        if (e != hipSuccess) return fail_hip(e, "hipMallocAsync");
+        ptrs_.push_back(p);
+        *out = (T*)p;
+        return LM_OK;
+    }
+
+private:
+    hipStream_t st_;
+    std::vector<void*> ptrs_;
+};
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+// Four HIP events for phase timings, destroyed with the owner.
+struct EventTimer {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    lm_status init()
+    {
+        for (auto& e : ev) {
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return fail_hip(err, "hipEventCreate");
+        }
+        return LM_OK;
+    }
+    double ms(int a, int b) const
+    {
+        float t = 0.0f;
+        return hipEventElapsedTime(&t, ev[a], ev[b]) == hipSuccess ? (double)t : -1.0;
+    }
+    ~EventTimer()
+    {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+lm_status check_params(const lm_params* prm)
+{
+    if (!prm) return fail(LM_EINVAL, "params is NULL");
+    if (prm->dim != 2 && prm->dim != 3) return fail(LM_EINVAL, "dim must be 2 or 3 (got %d)", prm->dim);
+    if (prm->kernel != LM_KERNEL_CONON && prm->kernel != LM_KERNEL_GAUSS)
+        return fail(LM_EINVAL, "unknown kernel %d", prm->kernel);
+    if (prm->dtype != LM_F64 && prm->dtype != LM_F32) return fail(LM_EINVAL, "unknown dtype %d", prm->dtype);
+    if (prm->flags != 0) return fail(LM_EINVAL, "flags must be 0");
+    if (!(prm->sigma > 0.0) || !is_finite(prm->sigma)) return fail(LM_EINVAL, "sigma must be positive and finite");
+    if (!(prm->tau >= 0.0) || !is_finite(prm->tau)) return fail(LM_EINVAL, "tau must be >= 0 and finite");
+    if (!(prm->cutoff >= 0.0) || !is_finite(prm->cutoff)) return fail(LM_EINVAL, "cutoff must be >= 0 and finite");
+    if (prm->cutoff > 0.0) return fail(LM_EUNSUPPORTED, "cutoff > 0 (tile skipping) is not provided by this build");
+    return LM_OK;
+}
+
+constexpr int64_t kMaxN = (int64_t)1 << 34;
+
+lm_status check_n(int64_t n, const char* name = "n")
+{
+    if (n < 1 || n > kMaxN) return fail(LM_EINVAL, "%s must be in [1, 2^34] (got %lld)", name, (long long)n);
+    return LM_OK;
+}
+
+// Exponent scale and force constant of the pair bodies.
+void kernel_scales(const lm_params* prm, bool f32, double* kq, double* wscale)
+{
+    const double s = prm->sigma;
+    const double log2e = 1.4426950408889634;
+    if (prm->kernel == LM_KERNEL_CONON) {
+        *kq = -1.0 / s;
+        *wscale = 1.0 / s;
+    } else {
+        *kq = -1.0 / (s * s);
+        *wscale = 2.0 / (s * s);
+    }
+    if (f32) *kq *= log2e;
+}
+
+// One evaluation of the pair sums with targets (qt, pt) [nt] and sources (qs, ps) [ns].
+template <class T>
+lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, int64_t ns, const T* qt,
+                    const T* pt, int64_t nt, const lm::EpiArgs<T>& epi, double* part, hipStream_t st)
+{
+    lm::PairPlan pl = lm::plan_pair(nt, ns);
+    lm::PairArgs<T> a{};
+    a.qs = qs;
+    a.ps = ps;
+    a.qt = qt;
+    a.pt = pt;
+    a.nt = nt;
+    a.ns = ns;
+    a.jchunk = pl.jchunk;
+    kernel_scales(prm, sizeof(T) == 4, &a.kq, &a.wscale);
+    a.part = part;
+    a.epi = epi;
+    LM_HIP(lm::launch_pair<T>(prm->dim, prm->kernel, force, a, pl, st));
+    return LM_OK;
+}
+
+int64_t part_elems(const lm_params* prm, int64_t nt, int64_t ns)
+{
+    lm::PairPlan pl = lm::plan_pair(nt, ns);
+    return pl.nsplit > 1 ? (int64_t)pl.nsplit * 2 * prm->dim * nt : 1;
+}
+
+// RK4 shoot of (q, p) in place over [0, t1] with `steps` steps.  ws must provide 6 state
+// buffers of dim*n T and the split workspace.
+template <class T>
+lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, int32_t steps, T* aq, T* ap,
+                        T* bq, T* bp, T* cq, T* cp, double* part, hipStream_t st)
+{
+    const double dt = t1 / steps;
+    lm::EpiArgs<T> e{};
+    e.dt = dt;
+    e.tau = prm->tau;
+    e.base_q = q;
+    e.base_p = p;
+    e.acc_q = cq;
+    e.acc_p = cp;
+    for (int32_t s = 0; s < steps; ++s) {
+        // stage 1: input y, output A ; stage 2: A -> B ; stage 3: B -> A ; stage 4: A -> y
+        const T* in_q[4] = {q, aq, bq, aq};
+        const T* in_p[4] = {p, ap, bp, ap};
+        T* out_q[4] = {aq, bq, aq, q};
+        T* out_p[4] = {ap, bp, ap, p};
+        for (int k = 0; k < 4; ++k) {
+            e.kind = lm::EPI_RK1 + k;
+            e.in_p = in_p[k];
+            e.out_q = out_q[k];
+            e.out_p = out_p[k];
+            LM_TRY(pair_eval<T>(prm, true, in_q[k], in_p[k], n, in_q[k], in_p[k], n, e, part, st));
+        }
+    }
+    return LM_OK;
+}
+
+template <class T>
+lm_status shoot_t(const lm_params* prm, int64_t n, const T* q0, const T* p0, double t1, int32_t steps, T* q1,
+                  T* p1, hipStream_t st)
+{
+    const int64_t m = (int64_t)prm->dim * n;
+    Workspace ws(st);
+    T *aq, *ap, *bq, *bp, *cq, *cp;
+    double* part;
+    LM_TRY(ws.get(&aq, m));
+    LM_TRY(ws.get(&ap, m));
+    LM_TRY(ws.get(&bq, m));
+    LM_TRY(ws.get(&bp, m));
+    LM_TRY(ws.get(&cq, m));
+    LM_TRY(ws.get(&cp, m));
+    LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+    if (q1 != q0) LM_HIP(hipMemcpyAsync(q1, q0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (p1 != p0) LM_HIP(hipMemcpyAsync(p1, p0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return shoot_inplace<T>(prm, n, q1, p1, t1, steps, aq, ap, bq, bp, cq, cp, part, st);
+}
+
+// Hamiltonian in double: H = 1/2 sum_c p_c . (K p)_c.  q, p double.
+lm_status hamiltonian_f64(const lm_params* prm, int64_t n, const double* q, const double* p, double* H,
+                          hipStream_t st)
+{
+    const int dim = prm->dim;
+    Workspace ws(st);
+    double *v, *part, *red, *dots;
+    LM_TRY(ws.get(&v, dim * n));
+    LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+    LM_TRY(ws.get(&red, (int64_t)lm::reduce_blocks(n) * dim));
+    LM_TRY(ws.get(&dots, dim));
+    lm::EpiArgs<double> e{};
+    e.kind = lm::EPI_STORE;
+    e.tau = 0.0;
+    e.out_q = v;
+    LM_TRY(pair_eval<double>(prm, false, q, p, n, q, p, n, e, part, st));
+    LM_HIP(lm::launch_dots(p, v, n, dim, red, dots, st));
+    double hd[3] = {0, 0, 0};
+    LM_HIP(hipMemcpyAsync(hd, dots, dim * sizeof(double), hipMemcpyDeviceToHost, st));
+    LM_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (int c = 0; c < dim; ++c) s += hd[c];
+    *H = 0.5 * s;
+    return LM_OK;
+}
+
+// CG for (K(X) + tau I) x_c = b_c, all components in lockstep.  Buffers in `cg` are dim*n
+// doubles each (r, p, Ap) plus scalars; `part` is the pair-split workspace.
+struct CgBuffers {
+    double *r, *p, *ap, *red, *rr, *rr_new, *pap, *bb;
+};
+
+lm_status cg_alloc(Workspace& ws, const lm_params* prm, int64_t n, CgBuffers* b)
+{
+    const int64_t m = (int64_t)prm->dim * n;
+    LM_TRY(ws.get(&b->r, m));
+    LM_TRY(ws.get(&b->p, m));
+    LM_TRY(ws.get(&b->ap, m));
+    LM_TRY(ws.get(&b->red, (int64_t)lm::reduce_blocks(n) * prm->dim));
+    LM_TRY(ws.get(&b->rr, 3));
+    LM_TRY(ws.get(&b->rr_new, 3));
+    LM_TRY(ws.get(&b->pap, 3));
+    LM_TRY(ws.get(&b->bb, 3));
+    return LM_OK;
+}
+
+lm_status ksolve_impl(const lm_params* prm, int64_t n, const double* X, const double* b, double* x, double rtol,
+                      int32_t max_iter, int32_t* iters_out, CgBuffers& cg, double* part, hipStream_t st)
+{
+    const int dim = prm->dim;
+    const int64_t m = (int64_t)dim * n;
+    // r = b ; x = 0 ; p = r ; rr = bb = r.r
+    LM_HIP(hipMemcpyAsync(cg.r, b, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(lm::launch_zero(x, m, st));
+    LM_HIP(hipMemcpyAsync(cg.p, cg.r, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(lm::launch_dots(cg.r, cg.r, n, dim, cg.red, cg.rr, st));
+    LM_HIP(hipMemcpyAsync(cg.bb, cg.rr, dim * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double bb[3] = {0, 0, 0}, h[6];
+    LM_HIP(hipMemcpyAsync(bb, cg.bb, dim * sizeof(double), hipMemcpyDeviceToHost, st));
+    LM_HIP(hipStreamSynchronize(st));
+    for (int c = 0; c < dim; ++c)
+        if (!is_finite(bb[c])) return fail(LM_EDIVERGED, "non-finite right-hand side in the K-solve");
+
+    lm::EpiArgs<double> e{};
+    e.kind = lm::EPI_STORE;
+    e.tau = prm->tau;
+    e.out_q = cg.ap;
+    int32_t it = 0;
+    bool done = true;
+    for (int c = 0; c < dim; ++c) done = done && (bb[c] == 0.0);
+    while (!done) {
+        if (it >= max_iter) {
+            if (iters_out) *iters_out = it;
+            return fail(LM_ENOTCONV, "K-solve: %d CG iterations without reaching rtol %.3g", it, rtol);
+        }
+        // Ap = (K + tau I) p
+        e.in_p = cg.p;
+        LM_TRY(pair_eval<double>(prm, false, X, cg.p, n, X, cg.p, n, e, part, st));
+        LM_HIP(lm::launch_dots(cg.p, cg.ap, n, dim, cg.red, cg.pap, st));
+        LM_HIP(lm::launch_cg_update_xr(x, cg.r, cg.p, cg.ap, cg.rr, cg.pap, n, dim, st));
+        LM_HIP(lm::launch_dots(cg.r, cg.r, n, dim, cg.red, cg.rr_new, st));
+        LM_HIP(lm::launch_cg_update_p(cg.p, cg.r, cg.rr_new, cg.rr, n, dim, st));
+        LM_HIP(hipMemcpyAsync(h, cg.rr_new, dim * sizeof(double), hipMemcpyDeviceToHost, st));
+        LM_HIP(hipMemcpyAsync(h + 3, cg.pap, dim * sizeof(double), hipMemcpyDeviceToHost, st));
+        std::swap(cg.rr, cg.rr_new);
+        LM_HIP(hipStreamSynchronize(st));
+        ++it;
+        done = true;
+        for (int c = 0; c < dim; ++c) {
+            const double rrc = h[c], papc = h[3 + c];
+            if (!is_finite(rrc) || !is_finite(papc)) {
+                if (iters_out) *iters_out = it;
+                return fail(LM_ESINGULAR, "K-solve: non-finite CG scalars (K not positive definite?)");
+            }
+            if (bb[c] > 0.0 && !(papc > 0.0) && rrc > rtol * rtol * bb[c]) {
+                if (iters_out) *iters_out = it;
+                return fail(LM_ESINGULAR, "K-solve: non-positive curvature p.Kp = %g", papc);
+            }
+            if (!(rrc <= rtol * rtol * bb[c])) done = false;
+        }
+    }
+    if (iters_out) *iters_out = it;
+    return LM_OK;
+}
+
+lm_status check_match_args(const lm_match_opts* o, const double* X, const double* Y, const double* p0)
+{
+    if (!o) return fail(LM_EINVAL, "opts is NULL");
+    if (!X || !Y || !p0) return fail(LM_EINVAL, "NULL buffer");
+    if (!(o->h > 0.0) || !is_finite(o->h)) return fail(LM_EINVAL, "h must be positive");
+    if (!(o->tol > 0.0) || !is_finite(o->tol)) return fail(LM_EINVAL, "tol must be positive");
+    if (o->max_iter < 0) return fail(LM_EINVAL, "max_iter must be >= 0");
+    if (o->steps < 1) return fail(LM_EINVAL, "steps must be >= 1");
+    if (o->stop_rule != 0 && o->stop_rule != 1) return fail(LM_EINVAL, "stop_rule must be 0 or 1");
+    if (o->cg_max_iter < 0 || !(o->cg_rtol >= 0.0)) return fail(LM_EINVAL, "bad CG settings");
+    if (o->hist_len < 0 || (o->hist_len > 0 && !o->resid_hist)) return fail(LM_EINVAL, "bad history buffer");
+    return LM_OK;
+}
+
+// Device buffers of one feedback match.
+struct FeedbackWork {
+    double *qd = nullptr, *pd = nullptr, *e = nullptr, *delta = nullptr, *part = nullptr, *red = nullptr,
+           *rdev = nullptr;
+    double *aq = nullptr, *ap = nullptr, *bq = nullptr, *bp = nullptr, *cq = nullptr, *cp = nullptr;
+    float *qf = nullptr, *pf = nullptr, *aqf = nullptr, *apf = nullptr, *bqf = nullptr, *bpf = nullptr,
+          *cqf = nullptr, *cpf = nullptr;
+    CgBuffers cg;
+
+    lm_status alloc(Workspace& ws, const lm_params* prm, int64_t n)
+    {
+        const int64_t m = (int64_t)prm->dim * n;
+        LM_TRY(ws.get(&qd, m));
+        LM_TRY(ws.get(&pd, m));
+        LM_TRY(ws.get(&e, m));
+        LM_TRY(ws.get(&delta, m));
+        LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+        LM_TRY(ws.get(&red, lm::reduce_blocks(m)));
+        LM_TRY(ws.get(&rdev, 1));
+        if (prm->dtype == LM_F32) {
+            LM_TRY(ws.get(&qf, m));
+            LM_TRY(ws.get(&pf, m));
+            LM_TRY(ws.get(&aqf, m));
+            LM_TRY(ws.get(&apf, m));
+            LM_TRY(ws.get(&bqf, m));
+            LM_TRY(ws.get(&bpf, m));
+            LM_TRY(ws.get(&cqf, m));
+            LM_TRY(ws.get(&cpf, m));
+        } else {
+            LM_TRY(ws.get(&aq, m));
+            LM_TRY(ws.get(&ap, m));
+            LM_TRY(ws.get(&bq, m));
+            LM_TRY(ws.get(&bp, m));
+            LM_TRY(ws.get(&cq, m));
+            LM_TRY(ws.get(&cp, m));
+        }
+        return cg_alloc(ws, prm, n, &cg);
+    }
+};
+
+// Algorithm 1, steps 1-2: q(1) of the shoot from (X, p) into w.qd, and r = max |Y - q(1)|
+// (read back to the host: it decides the next launch).
+lm_status feedback_shoot_residual(const lm_params* prm, const lm_match_opts* o, int64_t n, const double* X,
+                                  const double* Y, const double* p, FeedbackWork& w, double* r, hipStream_t st,
+                                  hipEvent_t after_shoot = nullptr)
+{
+    const int64_t m = (int64_t)prm->dim * n;
+    if (prm->dtype == LM_F32) {
+        // single-precision shoot; the momenta, the residual and the solve stay in double
+        LM_HIP((lm::launch_convert<float, double>(w.qf, X, m, st)));
+        LM_HIP((lm::launch_convert<float, double>(w.pf, p, m, st)));
+        LM_TRY(shoot_inplace<float>(prm, n, w.qf, w.pf, 1.0, o->steps, w.aqf, w.apf, w.bqf, w.bpf, w.cqf, w.cpf,
+                                    w.part, st));
+        LM_HIP((lm::launch_convert<double, float>(w.qd, w.qf, m, st)));
+    } else {
+        LM_HIP(hipMemcpyAsync(w.qd, X, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        LM_HIP(hipMemcpyAsync(w.pd, p, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        LM_TRY(shoot_inplace<double>(prm, n, w.qd, w.pd, 1.0, o->steps, w.aq, w.ap, w.bq, w.bp, w.cq, w.cp, w.part,
+                                     st));
+    }
+    if (after_shoot) LM_HIP(hipEventRecord(after_shoot, st));
+    LM_HIP((lm::launch_maxabsdiff<double, double>(Y, w.qd, m, w.red, w.rdev, st)));
+    LM_HIP(hipMemcpyAsync(r, w.rdev, sizeof(double), hipMemcpyDeviceToHost, st));
+    LM_HIP(hipStreamSynchronize(st));
+    return LM_OK;
+}
+
+// Algorithm 1, steps 3-4 with M = h I: u <- u + h e, i.e. p <- p + h (K(X) + tau I)^{-1} e,
+// e = Y - q(1) taken from w.qd.
+lm_status feedback_update(const lm_params* prm, const lm_match_opts* o, int64_t n, const double* X, const double* Y,
+                          double* p, FeedbackWork& w, int32_t* cg_iters, hipStream_t st)
+{
+    const int64_t m = (int64_t)prm->dim * n;
+    const double cg_rtol = o->cg_rtol > 0.0 ? o->cg_rtol : 1e-13;
+    const int64_t cgmax64 = o->cg_max_iter > 0 ? o->cg_max_iter : 20 * n + 100;
+    const int32_t cg_max = (int32_t)(cgmax64 > (1 << 30) ? (1 << 30) : cgmax64);
+    LM_HIP(lm::launch_sub(w.e, Y, w.qd, m, st));
+    LM_TRY(ksolve_impl(prm, n, X, w.e, w.delta, cg_rtol, cg_max, cg_iters, w.cg, w.part, st));
+    LM_HIP(lm::launch_axpy(p, p, o->h, w.delta, m, st));
+    return LM_OK;
+}
+
+}  // namespace
+
+// =========================================================================================
+// C ABI
+// =========================================================================================
+
+extern "C" {
+
+const char* lm_last_error(void) { return g_err.c_str(); }
+
+const char* lm_version(void) { return "liblm 0.1 (gfx950)"; }
+
+lm_status lm_rhs(const lm_params* prm, int64_t n, const void* q, const void* p, void* dq, void* dp, void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    if (!q || !p || !dq || !dp) return fail(LM_EINVAL, "NULL buffer");
+    if (dq == q || dq == p || dp == q || dp == p) return fail(LM_EINVAL, "dq/dp must not alias q/p");
+    hipStream_t st = (hipStream_t)stream;
+    Workspace ws(st);
+    double* part;
+    LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+    if (prm->dtype == LM_F64) {
+        lm::EpiArgs<double> e{};
+        e.kind = lm::EPI_STORE;
+        e.tau = prm->tau;
+        e.in_p = (const double*)p;
+        e.out_q = (double*)dq;
+        e.out_p = (double*)dp;
+        return pair_eval<double>(prm, true, (const double*)q, (const double*)p, n, (const double*)q,
+                                 (const double*)p, n, e, part, st);
+    }
+    lm::EpiArgs<float> e{};
+    e.kind = lm::EPI_STORE;
+    e.tau = prm->tau;
+    e.in_p = (const float*)p;
+    e.out_q = (float*)dq;
+    e.out_p = (float*)dp;
+    return pair_eval<float>(prm, true, (const float*)q, (const float*)p, n, (const float*)q, (const float*)p, n, e,
+                            part, st);
+}
+
+lm_status lm_shoot(const lm_params* prm, int64_t n, const void* q0, const void* p0, double t1, int32_t steps,
+                   void* q1, void* p1, void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    if (!q0 || !p0 || !q1 || !p1) return fail(LM_EINVAL, "NULL buffer");
+    if (steps < 1) return fail(LM_EINVAL, "steps must be >= 1 (got %d)", steps);
+    if (!is_finite(t1)) return fail(LM_EINVAL, "t1 must be finite");
+    if (q1 == p1) return fail(LM_EINVAL, "q1 and p1 must be distinct buffers");
+    hipStream_t st = (hipStream_t)stream;
+    if (prm->dtype == LM_F64)
+        return shoot_t<double>(prm, n, (const double*)q0, (const double*)p0, t1, steps, (double*)q1, (double*)p1,
+                               st);
+    return shoot_t<float>(prm, n, (const float*)q0, (const float*)p0, t1, steps, (float*)q1, (float*)p1, st);
+}
+
+lm_status lm_hamiltonian(const lm_params* prm, int64_t n, const void* q, const void* p, double* H_out,
+                         void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    if (!q || !p || !H_out) return fail(LM_EINVAL, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (prm->dtype == LM_F64) return hamiltonian_f64(prm, n, (const double*)q, (const double*)p, H_out, st);
+    const int64_t m = (int64_t)prm->dim * n;
+    Workspace ws(st);
+    double *qd, *pd;
+    LM_TRY(ws.get(&qd, m));
+    LM_TRY(ws.get(&pd, m));
+    LM_HIP((lm::launch_convert<double, float>(qd, (const float*)q, m, st)));
+    LM_HIP((lm::launch_convert<double, float>(pd, (const float*)p, m, st)));
+    return hamiltonian_f64(prm, n, qd, pd, H_out, st);
+}
+
+lm_status lm_ksolve(const lm_params* prm, int64_t n, const double* X, const double* b, double* x, double rtol,
+                    int32_t max_iter, int32_t* iters_out, void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    if (!X || !b || !x) return fail(LM_EINVAL, "NULL buffer");
+    if (!(rtol > 0.0) || !is_finite(rtol)) return fail(LM_EINVAL, "rtol must be positive");
+    if (max_iter < 1) return fail(LM_EINVAL, "max_iter must be >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    Workspace ws(st);
+    CgBuffers cg;
+    double* part;
+    LM_TRY(cg_alloc(ws, prm, n, &cg));
+    LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+    return ksolve_impl(prm, n, X, b, x, rtol, max_iter, iters_out, cg, part, st);
+}
+
+lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_t n, const double* X,
+                            const double* Y, double* p0, double* q1_out, lm_match_info* info, void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    if (!info) return fail(LM_EINVAL, "info is NULL");
+    LM_TRY(check_match_args(o, X, Y, p0));
+    hipStream_t st = (hipStream_t)stream;
+    std::memset(info, 0, sizeof *info);
+    Workspace ws(st);
+    FeedbackWork w;
+    LM_TRY(w.alloc(ws, prm, n));
+
+    lm_status result = LM_OK;
+    double r = 0.0, prev_step = INFINITY;
+    int32_t k = 0;
+    for (k = 0;; ++k) {
+        // Algorithm 1, steps 1-2: shoot (X, p) to t = 1, residual r = max |Y - q(1)|
+        LM_TRY(feedback_shoot_residual(prm, o, n, X, Y, p0, w, &r, st));
+        if (k < o->hist_len) o->resid_hist[k] = r;
+        if (!is_finite(r)) {
+            result = fail(LM_EDIVERGED, "feedback iteration %d: non-finite residual", k);
+            break;
+        }
+        if (o->stop_rule == 0 ? (r < o->tol) : (k >= 1 && prev_step < o->tol)) break;
+        if (k >= o->max_iter) {
+            result = fail(LM_ENOTCONV, "feedback: %d updates without reaching tol %.3g (residual %.3g)", k, o->tol, r);
+            break;
+        }
+        // steps 3-4: u <- u + h e, i.e. p <- p + h (K + tau I)^{-1} e
+        int32_t cgit = 0;
+        lm_status s = feedback_update(prm, o, n, X, Y, p0, w, &cgit, st);
+        info->cg_iters += cgit;
+        if (s != LM_OK) {
+            result = s;
+            break;
+        }
+        prev_step = o->h * r;
+    }
+    info->iters = k;
+    info->resid_inf = r;
+    if (q1_out) LM_HIP(hipMemcpyAsync(q1_out, w.qd, (int64_t)prm->dim * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double H = NAN;
+    lm_status hs = hamiltonian_f64(prm, n, X, p0, &H, st);
+    info->H = H;
+    if (result == LM_OK && hs != LM_OK) return hs;
+    return result;
+}
+
+lm_status lm_feedback_step(const lm_params* prm, const lm_match_opts* o, int64_t n, const double* X,
+                           const double* Y, double* p, double* q1_out, lm_step_info* info, void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    LM_TRY(check_match_args(o, X, Y, p));
+    if (!info) return fail(LM_EINVAL, "info is NULL");
+    std::memset(info, 0, sizeof *info);
+    hipStream_t st = (hipStream_t)stream;
+    Workspace ws(st);
+    FeedbackWork w;
+    LM_TRY(w.alloc(ws, prm, n));
+    EventTimer timer;
+    LM_TRY(timer.init());
+    LM_HIP(hipEventRecord(timer.ev[0], st));
+    double r = 0.0;
+    LM_TRY(feedback_shoot_residual(prm, o, n, X, Y, p, w, &r, st, timer.ev[1]));
+    info->shoot_ms = timer.ms(0, 1);
+    info->resid_inf = r;
+    if (q1_out) LM_HIP(hipMemcpyAsync(q1_out, w.qd, (int64_t)prm->dim * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (!is_finite(r)) return fail(LM_EDIVERGED, "non-finite residual");
+    if (r < o->tol) {
+        info->converged = 1;
+        LM_HIP(hipStreamSynchronize(st));
+        return LM_OK;
+    }
+    LM_HIP(hipEventRecord(timer.ev[2], st));
+    int32_t cgit = 0;
+    lm_status s = feedback_update(prm, o, n, X, Y, p, w, &cgit, st);
+    info->cg_iters = cgit;
+    LM_TRY(s);
+    LM_HIP(hipEventRecord(timer.ev[3], st));
+    LM_HIP(hipEventSynchronize(timer.ev[3]));
+    info->solve_ms = timer.ms(2, 3);
+    return LM_OK;
+}
+
+lm_status lm_velocity(const lm_params* prm, int64_t n, const void* q, const void* p, int64_t m, const void* x,
+                      void* u, void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    LM_TRY(check_n(m, "m"));
+    if (!q || !p || !x || !u) return fail(LM_EINVAL, "NULL buffer");
+    hipStream_t st = (hipStream_t)stream;
+    Workspace ws(st);
+    double* part;
+    LM_TRY(ws.get(&part, part_elems(prm, m, n)));
+    if (prm->dtype == LM_F64) {
+        lm::EpiArgs<double> e{};
+        e.kind = lm::EPI_STORE;
+        e.tau = 0.0;
+        e.out_q = (double*)u;
+        return pair_eval<double>(prm, false, (const double*)q, (const double*)p, n, (const double*)x, nullptr, m, e,
+                                 part, st);
+    }
+    lm::EpiArgs<float> e{};
+    e.kind = lm::EPI_STORE;
+    e.tau = 0.0;
+    e.out_q = (float*)u;
+    return pair_eval<float>(prm, false, (const float*)q, (const float*)p, n, (const float*)x, nullptr, m, e, part,
+                            st);
+}
+
+}  // extern "C"

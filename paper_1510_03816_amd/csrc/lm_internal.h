@@ -1,0 +1,78 @@
+// lm_internal.h -- declarations shared by the kernels (lm_kernels.hip) and the host API
+// (lm_api.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/liblm.h"
+
+namespace lm {
+
+enum EpiKind : int {
+    EPI_STORE = 0,   // out_q = v + tau p_i, out_p = f            (right-hand side, K x)
+    EPI_RK1 = 1,     // RK4 stage 1: acc = k1,    out = base + dt/2 k1
+    EPI_RK2 = 2,     // RK4 stage 2: acc += 2k2,  out = base + dt/2 k2
+    EPI_RK3 = 3,     // RK4 stage 3: acc += 2k3,  out = base + dt k3
+    EPI_RK4 = 4      // RK4 stage 4: out = base + dt/6 (acc + k4)
+};
+
+template <class T>
+struct EpiArgs {
+    int kind;
+    double dt;
+    double tau;
+    const T* in_p;     // target momenta (tau term), (dim, nt)
+    const T* base_q;   // state at the start of the step
+    const T* base_p;
+    T* acc_q;          // RK4 running sum k1 + 2k2 + 2k3
+    T* acc_p;
+    T* out_q;          // stage output
+    T* out_p;
+};
+
+template <class T>
+struct PairArgs {
+    const T* qs;       // sources (dim, ns)
+    const T* ps;
+    const T* qt;       // targets (dim, nt)
+    const T* pt;
+    int64_t nt, ns;
+    int64_t jchunk;    // sources per wave chunk
+    double kq;         // exponent scale: conon -1/sigma, Gaussian -1/sigma^2 (x log2 e in f32)
+    double wscale;     // force-weight constant: conon 1/sigma, Gaussian 2/sigma^2
+    double* part;      // split partial sums (nsplit, 2 dim, nt), used when nsplit > 1
+    EpiArgs<T> epi;
+};
+
+struct PairPlan {
+    int64_t itiles;
+    int nsplit;
+    int64_t jchunk;
+};
+
+PairPlan plan_pair(int64_t nt, int64_t ns);
+
+template <class T>
+hipError_t launch_pair(int dim, int kernel, bool force, const PairArgs<T>& a, const PairPlan& pl,
+                       hipStream_t st);
+
+int reduce_blocks(int64_t m);
+
+template <class TA, class TB>
+hipError_t launch_maxabsdiff(const TA* x, const TB* y, int64_t m, double* partial, double* out, hipStream_t st);
+
+hipError_t launch_dots(const double* x, const double* y, int64_t n, int ncomp, double* partial, double* out,
+                       hipStream_t st);
+hipError_t launch_cg_update_xr(double* x, double* r, const double* p, const double* ap, const double* rr,
+                               const double* pap, int64_t n, int ncomp, hipStream_t st);
+hipError_t launch_cg_update_p(double* p, const double* r, const double* rr_new, const double* rr, int64_t n,
+                              int ncomp, hipStream_t st);
+hipError_t launch_axpy(double* y, const double* x, double alpha, const double* z, int64_t m, hipStream_t st);
+hipError_t launch_zero(double* y, int64_t m, hipStream_t st);
+hipError_t launch_sub(double* y, const double* x, const double* z, int64_t m, hipStream_t st);
+
+template <class TO, class TI>
+hipError_t launch_convert(TO* y, const TI* x, int64_t m, hipStream_t st);
+
+}  // namespace lm

@@ -1,0 +1,628 @@
+// lm_kernels.hip -- gfx950 kernels of the N-particle Euler-Poincare landmark shooter.
+//
+// The hot path is the pair sum of the N-particle system (equation "N-particle"):
+//     v_i = sum_j G(|q_i - q_j|) p_j                       (velocity, j = i included)
+//     f_i = sum_{j != i} (p_i . p_j) w(|q_i - q_j|) (q_i - q_j),  w = -G'(r)/r  (force)
+// evaluated once per Runge-Kutta stage.  It is bound by vector ALU issue (a pair costs
+// about 45 VALU instructions in double precision and touches no memory), not by HBM, and
+// it is not a dense contraction, so it runs on the vector units rather than on MFMA.
+//
+// Work decomposition.  A workgroup owns a tile of 64 targets i, one per lane, and
+// W = 4 wavefronts; the sources j of the tile are split into W * S contiguous chunks,
+// one per (wave, grid-y) pair.  Inside a chunk every lane of a wave reads the same source,
+// so the source coordinates are wave-uniform: they are fetched with scalar loads into SGPRs
+// and used directly as VALU operands, with no LDS traffic and no per-lane address math.
+// The W partial sums of a workgroup are combined in LDS in wave order; when the grid is
+// split along y (S > 1, used when the targets alone cannot fill 256 CUs), each split
+// writes its partial sums to a workspace and lm_finish_kernel adds them in split order.
+// Every sum therefore has a fixed order: results are bitwise reproducible run to run.
+//
+// Epilogues.  The thread that owns target i after the reduction also performs the
+// classical RK4 bookkeeping for that particle (stage input for the next stage, the
+// k1 + 2k2 + 2k3 running sum, the step update), so a Runge-Kutta stage is one launch
+// (two when S > 1) and the state never takes a separate pass through memory.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lm_internal.h"
+#include "lm_math.h"
+
+namespace lm {
+
+constexpr int kTile = 64;    // targets per workgroup (one per lane)
+constexpr int kWaves = 4;    // wavefronts per workgroup
+
+// ---------------------------------------------------------------------------------------
+// Pair bodies.  `kq` holds the kernel-argument scale: for the conon -1/sigma, for the
+// Gaussian -1/sigma^2 (double); in single precision the factor log2(e) is folded in so the
+// exponential is the hardware 2^x.  The force weight's constant (1/sigma for the conon,
+// 2/sigma^2 for the Gaussian) is folded into the target momentum `psi` by the caller.
+// ---------------------------------------------------------------------------------------
+
+template <int DIM, int KER, bool FORCE>
+__device__ __forceinline__ void pair_f64(const double (&qi)[DIM], const double (&psi)[DIM],
+                                         const double (&qj)[DIM], const double (&pj)[DIM],
+                                         double kq, double (&v)[DIM], double (&f)[DIM])
+{
+    double d[DIM];
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        d[c] = qi[c] - qj[c];
+        s = __builtin_fma(d[c], d[c], s);
+    }
+    double g, w;
+    if constexpr (KER == LM_KERNEL_CONON) {
+        // s is clamped away from 0: for the self pair (d = 0) this gives r ~ 1e-150,
+        // g = 1 and a finite w that multiplies d = 0, so the pair adds p_j to v and nothing
+        // to f, as the system prescribes.
+        const double sc = __builtin_fmax(s, 1e-300);
+        const double rho = rsqrt_pos(sc);
+        const double r = sc * rho;
+        g = exp_nonpos(r * kq);
+        w = g * rho;
+    } else {
+        g = exp_nonpos(s * kq);
+        w = g;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) v[c] = __builtin_fma(g, pj[c], v[c]);
+    if constexpr (FORCE) {
+        double pp = psi[0] * pj[0];
+#pragma unroll
+        for (int c = 1; c < DIM; ++c) pp = __builtin_fma(psi[c], pj[c], pp);
+        const double cw = pp * w;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) f[c] = __builtin_fma(cw, d[c], f[c]);
+    }
+}
+
+template <int DIM, int KER, bool FORCE>
+__device__ __forceinline__ void pair_f32(const float (&qi)[DIM], const float (&psi)[DIM],
+                                         const float (&qj)[DIM], const float (&pj)[DIM],
+                                         float kq, float (&v)[DIM], float (&f)[DIM])
+{
+    float d[DIM];
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        d[c] = qi[c] - qj[c];
+        s = __builtin_fmaf(d[c], d[c], s);
+    }
+    float g, w;
+    if constexpr (KER == LM_KERNEL_CONON) {
+        const float sc = __builtin_fmaxf(s, 1e-30f);
+        const float rho = rsqrt_f32(sc);
+        g = exp2_f32(sc * rho * kq);
+        w = g * rho;
+    } else {
+        g = exp2_f32(s * kq);
+        w = g;
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) v[c] = __builtin_fmaf(g, pj[c], v[c]);
+    if constexpr (FORCE) {
+        float pp = psi[0] * pj[0];
+#pragma unroll
+        for (int c = 1; c < DIM; ++c) pp = __builtin_fmaf(psi[c], pj[c], pp);
+        const float cw = pp * w;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) f[c] = __builtin_fmaf(cw, d[c], f[c]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Epilogue: what the owner of target i does with its full sums (v, f).
+// ---------------------------------------------------------------------------------------
+
+template <class T, int DIM, bool FORCE>
+__device__ __forceinline__ void epilogue(const EpiArgs<T>& e, int64_t n, int64_t i,
+                                         const double (&v)[DIM], const double (&f)[DIM])
+{
+    // k = (v + tau p_i, f): the time derivative of particle i at the stage input
+    double kq[DIM], kp[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        kq[c] = v[c];
+        if (e.tau != 0.0) kq[c] += e.tau * (double)e.in_p[c * n + i];
+        kp[c] = FORCE ? f[c] : 0.0;
+    }
+    switch (e.kind) {
+    case EPI_STORE:
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            e.out_q[c * n + i] = (T)kq[c];
+            if (FORCE) e.out_p[c * n + i] = (T)kp[c];
+        }
+        break;
+    case EPI_RK1:
+    case EPI_RK2:
+    case EPI_RK3: {
+        // stage s: acc (+)= (1 or 2) k_s ; next stage input = y + a_s dt k_s
+        const double a = (e.kind == EPI_RK3) ? e.dt : 0.5 * e.dt;
+        const double wgt = (e.kind == EPI_RK1) ? 1.0 : 2.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t k = c * n + i;
+            double aq = wgt * kq[c], ap = wgt * kp[c];
+            if (e.kind != EPI_RK1) {
+                aq += (double)e.acc_q[k];
+                ap += (double)e.acc_p[k];
+            }
+            e.acc_q[k] = (T)aq;
+            e.acc_p[k] = (T)ap;
+            e.out_q[k] = (T)((double)e.base_q[k] + a * kq[c]);
+            e.out_p[k] = (T)((double)e.base_p[k] + a * kp[c]);
+        }
+        break;
+    }
+    case EPI_RK4: {
+        // y <- y + dt/6 (k1 + 2k2 + 2k3 + k4); out may alias base (own element only)
+        const double h6 = e.dt / 6.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const int64_t k = c * n + i;
+            const double sq = (double)e.acc_q[k] + kq[c];
+            const double sp = (double)e.acc_p[k] + kp[c];
+            e.out_q[k] = (T)((double)e.base_q[k] + h6 * sq);
+            e.out_p[k] = (T)((double)e.base_p[k] + h6 * sp);
+        }
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// The pair-sum kernel.
+//   grid  = (ceil(nt / 64), S),  block = 64 * kWaves
+//   wave w of block (bx, by) sums sources j in [(by*kWaves + w) * jchunk, ... + jchunk)
+//   for the targets i = bx*64 + lane.
+// Sources: (qs, ps) with ns points; targets: (qt, pt) with nt points (the same arrays for
+// the N-particle right-hand side).
+// ---------------------------------------------------------------------------------------
+
+template <class T, int DIM, int KER, bool FORCE>
+__global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
+{
+    const int lane = threadIdx.x & (kTile - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i = (int64_t)blockIdx.x * kTile + lane;
+    const bool live = i < a.nt;
+    const int64_t ic = live ? i : (a.nt - 1);       // idle lanes read a valid target
+
+    // target data, kept in VGPRs; the force constant is folded into psi
+    T qi[DIM], psi[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        qi[c] = a.qt[c * a.nt + ic];
+        psi[c] = FORCE ? (T)(a.wscale * (double)a.pt[c * a.nt + ic]) : (T)0;
+    }
+
+    const int64_t chunk_id = (int64_t)blockIdx.y * kWaves + wave;
+    const int64_t j0 = chunk_id * a.jchunk;
+    const int64_t j1 = (j0 + a.jchunk < a.ns) ? (j0 + a.jchunk) : a.ns;
+
+    double v[DIM], f[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { v[c] = 0.0; f[c] = 0.0; }
+
+    const T* __restrict__ qs = a.qs;
+    const T* __restrict__ ps = a.ps;
+    const int64_t ns = a.ns;
+
+    if constexpr (sizeof(T) == 8) {
+        const double kq = a.kq;
+        int64_t j = j0;
+        for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                double qj[DIM], pj[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    qj[c] = qs[c * ns + j + u];
+                    pj[c] = ps[c * ns + j + u];
+                }
+                pair_f64<DIM, KER, FORCE>(qi, psi, qj, pj, kq, v, f);
+            }
+        }
+        for (; j < j1; ++j) {
+            double qj[DIM], pj[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                qj[c] = qs[c * ns + j];
+                pj[c] = ps[c * ns + j];
+            }
+            pair_f64<DIM, KER, FORCE>(qi, psi, qj, pj, kq, v, f);
+        }
+    } else {
+        // single precision: pairs summed in float over runs of 64 sources, the runs summed
+        // in double, which keeps the rounding error of long sums at the level of one run
+        const float kq = (float)a.kq;
+        for (int64_t jr = j0; jr < j1; jr += 64) {
+            const int64_t je = (jr + 64 < j1) ? (jr + 64) : j1;
+            float vs[DIM], fs[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) { vs[c] = 0.0f; fs[c] = 0.0f; }
+            int64_t j = jr;
+            for (; j + 4 <= je; j += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    float qj[DIM], pj[DIM];
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        qj[c] = qs[c * ns + j + u];
+                        pj[c] = ps[c * ns + j + u];
+                    }
+                    pair_f32<DIM, KER, FORCE>(qi, psi, qj, pj, kq, vs, fs);
+                }
+            }
+            for (; j < je; ++j) {
+                float qj[DIM], pj[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    qj[c] = qs[c * ns + j];
+                    pj[c] = ps[c * ns + j];
+                }
+                pair_f32<DIM, KER, FORCE>(qi, psi, qj, pj, kq, vs, fs);
+            }
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) { v[c] += (double)vs[c]; f[c] += (double)fs[c]; }
+        }
+    }
+
+    // combine the wave partials in wave order
+    __shared__ double red[kWaves][2 * DIM][kTile];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        red[wave][c][lane] = v[c];
+        red[wave][DIM + c][lane] = f[c];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        double sv = red[0][c][lane], sf = red[0][DIM + c][lane];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            sv += red[w][c][lane];
+            sf += red[w][DIM + c][lane];
+        }
+        v[c] = sv;
+        f[c] = sf;
+    }
+    if (!live) return;
+    if (gridDim.y > 1) {
+        double* part = a.part + (int64_t)blockIdx.y * (2 * DIM) * a.nt;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            part[c * a.nt + i] = v[c];
+            part[(DIM + c) * a.nt + i] = f[c];
+        }
+        return;
+    }
+    epilogue<T, DIM, FORCE>(a.epi, a.nt, i, v, f);
+}
+
+// Adds the S split partials of each target in split order, then runs the epilogue.
+template <class T, int DIM, bool FORCE>
+__global__ __launch_bounds__(256) void lm_finish_kernel(const double* __restrict__ part, int nsplit,
+                                                        int64_t nt, EpiArgs<T> e)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    double v[DIM], f[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        v[c] = part[c * nt + i];
+        f[c] = part[(DIM + c) * nt + i];
+    }
+    for (int s = 1; s < nsplit; ++s) {
+        const double* ps = part + (int64_t)s * (2 * DIM) * nt;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            v[c] += ps[c * nt + i];
+            f[c] += ps[(DIM + c) * nt + i];
+        }
+    }
+    epilogue<T, DIM, FORCE>(e, nt, i, v, f);
+}
+
+// ---------------------------------------------------------------------------------------
+// Reductions (double precision, fixed order: per-block tree in LDS, then one block adds
+// the block results in block order).
+// ---------------------------------------------------------------------------------------
+
+constexpr int kRedThreads = 256;
+
+// out[b] = max over this block's elements of |a[k] - b[k]| (float or double inputs, the
+// difference taken in double); NaN wins over every number.
+template <class TA, class TB>
+__global__ __launch_bounds__(kRedThreads) void lm_maxabsdiff_kernel(const TA* __restrict__ x,
+                                                                    const TB* __restrict__ y,
+                                                                    int64_t m, double* __restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    double r = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * kRedThreads) {
+        const double d = __builtin_fabs((double)x[k] - (double)y[k]);
+        r = (d > r || d != d) ? d : r;
+    }
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double b = sh[threadIdx.x + o], a = sh[threadIdx.x];
+            sh[threadIdx.x] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kRedThreads) void lm_max_final_kernel(const double* __restrict__ in, int nb,
+                                                                   double* __restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    double r = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kRedThreads) {
+        const double d = in[k];
+        r = (d > r || d != d) ? d : r;
+    }
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double b = sh[threadIdx.x + o], a = sh[threadIdx.x];
+            sh[threadIdx.x] = (b > a || b != b) ? b : a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// Per-component dot products: out[(c) * nb + b] = partial of sum_i x[c n + i] y[c n + i]
+// over block b's range.  grid = (nb, ncomp).
+__global__ __launch_bounds__(kRedThreads) void lm_dot_partial_kernel(const double* __restrict__ x,
+                                                                     const double* __restrict__ y,
+                                                                     int64_t n, double* __restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    const int c = blockIdx.y;
+    const double* xc = x + (int64_t)c * n;
+    const double* yc = y + (int64_t)c * n;
+    double r = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * kRedThreads)
+        r = __builtin_fma(xc[k], yc[k], r);
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)c * gridDim.x + blockIdx.x] = sh[0];
+}
+
+// Sums nb partials per component in block order: out[c] = sum_b in[c nb + b].  One block
+// per component.
+__global__ __launch_bounds__(kRedThreads) void lm_sum_final_kernel(const double* __restrict__ in, int nb,
+                                                                   double* __restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    const int c = blockIdx.x;
+    double r = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kRedThreads) r += in[(int64_t)c * nb + k];
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = sh[0];
+}
+
+// ---------------------------------------------------------------------------------------
+// Conjugate-gradient vector updates for (K + tau I) x_c = b_c, one system per component.
+// The scalars live on the device: rr[c] = r_c.r_c, pap[c] = p_c.A p_c, rr_new[c].
+// ---------------------------------------------------------------------------------------
+
+// x += alpha p ; r -= alpha Ap, alpha = rr / pap (per component)
+__global__ __launch_bounds__(256) void lm_cg_update_xr_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                              const double* __restrict__ p,
+                                                              const double* __restrict__ ap,
+                                                              const double* __restrict__ rr,
+                                                              const double* __restrict__ pap, int64_t n)
+{
+    const int c = blockIdx.y;
+    // a component that has converged exactly (p = 0, so p.Ap = 0) stays where it is
+    const double alpha = pap[c] > 0.0 ? rr[c] / pap[c] : 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = (int64_t)c * n + k;
+        x[o] = __builtin_fma(alpha, p[o], x[o]);
+        r[o] = __builtin_fma(-alpha, ap[o], r[o]);
+    }
+}
+
+// p = r + beta p, beta = rr_new / rr (per component)
+__global__ __launch_bounds__(256) void lm_cg_update_p_kernel(double* __restrict__ p, const double* __restrict__ r,
+                                                             const double* __restrict__ rr_new,
+                                                             const double* __restrict__ rr, int64_t n)
+{
+    const int c = blockIdx.y;
+    const double beta = rr[c] > 0.0 ? rr_new[c] / rr[c] : 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = (int64_t)c * n + k;
+        p[o] = __builtin_fma(beta, p[o], r[o]);
+    }
+}
+
+// y = x + alpha * z (elementwise, m elements)
+__global__ __launch_bounds__(256) void lm_axpy_kernel(double* __restrict__ y, const double* __restrict__ x,
+                                                      double alpha, const double* __restrict__ z, int64_t m)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * blockDim.x)
+        y[k] = __builtin_fma(alpha, z[k], x[k]);
+}
+
+// y[k] = 0
+__global__ __launch_bounds__(256) void lm_zero_kernel(double* __restrict__ y, int64_t m)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * blockDim.x)
+        y[k] = 0.0;
+}
+
+// y[k] = x[k] - z[k]
+__global__ __launch_bounds__(256) void lm_sub_kernel(double* __restrict__ y, const double* __restrict__ x,
+                                                     const double* __restrict__ z, int64_t m)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * blockDim.x)
+        y[k] = x[k] - z[k];
+}
+
+// type conversion copy
+template <class TO, class TI>
+__global__ __launch_bounds__(256) void lm_convert_kernel(TO* __restrict__ y, const TI* __restrict__ x, int64_t m)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * blockDim.x)
+        y[k] = (TO)x[k];
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers (host side).
+// ---------------------------------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t m, int threads, unsigned cap = 8192)
+{
+    int64_t b = (m + threads - 1) / threads;
+    if (b < 1) b = 1;
+    return (unsigned)(b < (int64_t)cap ? b : cap);
+}
+
+PairPlan plan_pair(int64_t nt, int64_t ns)
+{
+    PairPlan pl;
+    pl.itiles = (nt + kTile - 1) / kTile;
+    // aim for >= 1024 workgroups (4096 wavefronts: four per SIMD on 256 CUs) while keeping
+    // every wave's source chunk at >= 32 sources
+    int64_t s = (1024 + pl.itiles - 1) / pl.itiles;
+    int64_t smax = ns / (kWaves * 32);
+    if (smax < 1) smax = 1;
+    if (s > smax) s = smax;
+    if (s > 64) s = 64;
+    if (s < 1) s = 1;
+    pl.nsplit = (int)s;
+    int64_t chunks = (int64_t)pl.nsplit * kWaves;
+    pl.jchunk = (ns + chunks - 1) / chunks;
+    return pl;
+}
+
+template <class T, int DIM, int KER, bool FORCE>
+static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStream_t st)
+{
+    dim3 grid((unsigned)pl.itiles, (unsigned)pl.nsplit);
+    hipLaunchKernelGGL((lm_pair_kernel<T, DIM, KER, FORCE>), grid, dim3(kTile * kWaves), 0, st, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || pl.nsplit == 1) return err;
+    hipLaunchKernelGGL((lm_finish_kernel<T, DIM, FORCE>), dim3(blocks_for(a.nt, 256, 1u << 30)), dim3(256), 0, st,
+                       (const double*)a.part, pl.nsplit, a.nt, a.epi);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_pair(int dim, int kernel, bool force, const PairArgs<T>& a, const PairPlan& pl,
+                       hipStream_t st)
+{
+    if (dim == 2) {
+        if (kernel == LM_KERNEL_CONON)
+            return force ? launch_pair_t<T, 2, LM_KERNEL_CONON, true>(a, pl, st)
+                         : launch_pair_t<T, 2, LM_KERNEL_CONON, false>(a, pl, st);
+        return force ? launch_pair_t<T, 2, LM_KERNEL_GAUSS, true>(a, pl, st)
+                     : launch_pair_t<T, 2, LM_KERNEL_GAUSS, false>(a, pl, st);
+    }
+    if (kernel == LM_KERNEL_CONON)
+        return force ? launch_pair_t<T, 3, LM_KERNEL_CONON, true>(a, pl, st)
+                     : launch_pair_t<T, 3, LM_KERNEL_CONON, false>(a, pl, st);
+    return force ? launch_pair_t<T, 3, LM_KERNEL_GAUSS, true>(a, pl, st)
+                 : launch_pair_t<T, 3, LM_KERNEL_GAUSS, false>(a, pl, st);
+}
+
+template hipError_t launch_pair<double>(int, int, bool, const PairArgs<double>&, const PairPlan&, hipStream_t);
+template hipError_t launch_pair<float>(int, int, bool, const PairArgs<float>&, const PairPlan&, hipStream_t);
+
+int reduce_blocks(int64_t m) { return (int)blocks_for(m, kRedThreads, 1024); }
+
+template <class TA, class TB>
+hipError_t launch_maxabsdiff(const TA* x, const TB* y, int64_t m, double* partial, double* out, hipStream_t st)
+{
+    const int nb = reduce_blocks(m);
+    hipLaunchKernelGGL((lm_maxabsdiff_kernel<TA, TB>), dim3(nb), dim3(kRedThreads), 0, st, x, y, m, partial);
+    hipLaunchKernelGGL(lm_max_final_kernel, dim3(1), dim3(kRedThreads), 0, st, (const double*)partial, nb, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_maxabsdiff<double, double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
+template hipError_t launch_maxabsdiff<double, float>(const double*, const float*, int64_t, double*, double*, hipStream_t);
+
+hipError_t launch_dots(const double* x, const double* y, int64_t n, int ncomp, double* partial, double* out,
+                       hipStream_t st)
+{
+    const int nb = reduce_blocks(n);
+    hipLaunchKernelGGL(lm_dot_partial_kernel, dim3(nb, ncomp), dim3(kRedThreads), 0, st, x, y, n, partial);
+    hipLaunchKernelGGL(lm_sum_final_kernel, dim3(ncomp), dim3(kRedThreads), 0, st, (const double*)partial, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_xr(double* x, double* r, const double* p, const double* ap, const double* rr,
+                               const double* pap, int64_t n, int ncomp, hipStream_t st)
+{
+    hipLaunchKernelGGL(lm_cg_update_xr_kernel, dim3(blocks_for(n, 256, 2048), ncomp), dim3(256), 0, st,
+                       x, r, p, ap, rr, pap, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update_p(double* p, const double* r, const double* rr_new, const double* rr, int64_t n,
+                              int ncomp, hipStream_t st)
+{
+    hipLaunchKernelGGL(lm_cg_update_p_kernel, dim3(blocks_for(n, 256, 2048), ncomp), dim3(256), 0, st,
+                       p, r, rr_new, rr, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double* y, const double* x, double alpha, const double* z, int64_t m, hipStream_t st)
+{
+    hipLaunchKernelGGL(lm_axpy_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, y, x, alpha, z, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* y, int64_t m, hipStream_t st)
+{
+    hipLaunchKernelGGL(lm_zero_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, y, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub(double* y, const double* x, const double* z, int64_t m, hipStream_t st)
+{
+    hipLaunchKernelGGL(lm_sub_kernel, dim3(blocks_for(m, 256)), dim3(256), 0, st, y, x, z, m);
+    return hipGetLastError();
+}
+
+template <class TO, class TI>
+hipError_t launch_convert(TO* y, const TI* x, int64_t m, hipStream_t st)
+{
+    hipLaunchKernelGGL((lm_convert_kernel<TO, TI>), dim3(blocks_for(m, 256)), dim3(256), 0, st, y, x, m);
+    return hipGetLastError();
+}
+
+template hipError_t launch_convert<float, double>(float*, const double*, int64_t, hipStream_t);
+template hipError_t launch_convert<double, float>(double*, const float*, int64_t, hipStream_t);
+
+}  // namespace lm

@@ -1,0 +1,292 @@
+"""Parity of the HIP library with the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances (normwise per output array, max|gpu - oracle| / max|oracle|): 1e-10 for the
+double-precision path and 1e-4 for the single-precision form, the bars the performance
+target states.  Single-precision runs feed the oracle the same float-rounded inputs.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+import paper_1510_03816_amd as lm
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = {lm.F64: 1e-10, lm.F32: 1e-4}
+TDT = {lm.F64: torch.float64, lm.F32: torch.float32}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+
+
+def dev(a, dtype=lm.F64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=TDT[dtype], device=DEV)
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rounded(a, dtype):
+    return a.astype(np.float32).astype(np.float64) if dtype == lm.F32 else a
+
+
+def rel_err(got, want):
+    scale = np.max(np.abs(want))
+    d = np.max(np.abs(got - want))
+    return d / scale if scale > 0 else d
+
+
+def gpu_rhs(q, p, kernel, sigma, tau, dtype):
+    prm = lm.make_params(q.shape[0], kernel, sigma, dtype=dtype, tau=tau)
+    qd, pd = dev(q, dtype), dev(p, dtype)
+    dq, dp = torch.empty_like(qd), torch.empty_like(pd)
+    lm.lm_rhs(prm, qd, pd, dq, dp)
+    torch.cuda.synchronize()
+    return host(dq), host(dp)
+
+
+# ------------------------------------------------------------------ right-hand side
+
+
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 65, 1000, 4096])
+def test_rhs_matches_oracle(n, dim, kernel, dtype):
+    q, p = inputs.random_state(n, dim, seed=[100, n, dim], box=1.0, pscale=0.3)
+    q, p = rounded(q, dtype), rounded(p, dtype)
+    sigma, tau = (0.3 if dim == 3 else 0.25), 0.1
+    dq_o, dp_o = oracle.rhs(q, p, kernel, sigma, tau)
+    dq, dp = gpu_rhs(q, p, kernel, sigma, tau, dtype)
+    print("n=%d dim=%d kernel=%d dtype=%d: %.2e %.2e" % (n, dim, kernel, dtype, rel_err(dq, dq_o), rel_err(dp, dp_o)))
+    assert rel_err(dq, dq_o) <= TOL[dtype]
+    assert rel_err(dp, dp_o) <= TOL[dtype]
+    if n == 1:
+        assert np.all(dp == 0.0)
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_rhs_coincident_particles(kernel):
+    q, p = inputs.random_state(40, 2, seed=101)
+    q[:, 10:20] = q[:, 0:10]          # ten pairs of coincident distinct particles
+    dq_o, dp_o = oracle.rhs(q, p, kernel, 0.4)
+    dq, dp = gpu_rhs(q, p, kernel, 0.4, 0.0, lm.F64)
+    assert np.all(np.isfinite(dp))
+    assert rel_err(dq, dq_o) <= 1e-10 and rel_err(dp, dp_o) <= 1e-10
+
+
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_rhs_full_size_sampled(kernel, dtype):
+    """N = 65536 on the unit sphere (the 3-D workload) in the benchmark's launch shape;
+    256 sampled rows are checked against the oracle, which computes rows one by one."""
+    pr = inputs.config_sphere3d(65536, kernel=kernel)
+    q, p = rounded(pr.X, dtype), rounded(pr.p_bench(), dtype)
+    dq, dp = gpu_rhs(q, p, kernel, pr.sigma, 0.0, dtype)
+    idx = np.sort(np.random.default_rng(102).choice(pr.n, 256, replace=False))
+    idx = np.concatenate([[0, 63, 64, pr.n - 1], idx])
+    rq, rp = oracle.rhs_rows(q, p, idx, kernel, pr.sigma)
+    eq = np.max(np.abs(dq[:, idx] - rq)) / np.max(np.abs(rq))
+    ep = np.max(np.abs(dp[:, idx] - rp)) / np.max(np.abs(rp))
+    print("full-size sampled kernel=%d dtype=%d: %.2e %.2e" % (kernel, dtype, eq, ep))
+    assert eq <= TOL[dtype] and ep <= TOL[dtype]
+    # the forces of the whole system sum to zero (antisymmetry), at any size
+    if dtype == lm.F64:
+        assert np.max(np.abs(dp.sum(axis=1))) <= 1e-9 * np.max(np.abs(dp))
+
+
+# ------------------------------------------------------------------ shooting
+
+
+SHOOT_CASES = [
+    ("circle_ellipse_64", lambda: inputs.config_circle_ellipse(64), 100),
+    ("curve2d_700", lambda: inputs.config_curve2d(700), 40),
+    ("sphere3d_600_conon", lambda: inputs.config_sphere3d(600, sigma=0.2), 20),
+    ("sphere3d_600_gauss", lambda: inputs.config_sphere3d(600, kernel=1, sigma=0.2), 20),
+]
+
+
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+@pytest.mark.parametrize("name,make,steps", SHOOT_CASES, ids=[c[0] for c in SHOOT_CASES])
+def test_shoot_matches_oracle(name, make, steps, dtype):
+    pr = make()
+    q0, p0 = rounded(pr.X, dtype), rounded(pr.p_bench(), dtype)
+    oq, op = oracle.shoot(q0, p0, pr.kernel, pr.sigma, steps)
+    prm = lm.make_params(pr.dim, pr.kernel, pr.sigma, dtype=dtype)
+    q, p = dev(q0, dtype), dev(p0, dtype)
+    q1, p1 = torch.empty_like(q), torch.empty_like(p)
+    lm.lm_shoot(prm, q, p, 1.0, steps, q1, p1)
+    torch.cuda.synchronize()
+    eq, ep = rel_err(host(q1), oq), rel_err(host(p1), op)
+    print("%s dtype=%d: %.2e %.2e" % (name, dtype, eq, ep))
+    assert eq <= TOL[dtype] and ep <= TOL[dtype]
+
+
+def test_shoot_in_place_and_time_span():
+    pr = inputs.config_curve2d(300)
+    p0 = pr.p_bench()
+    oq, op = oracle.shoot(pr.X, p0, 0, pr.sigma, 30, T=0.7, tau=0.2)
+    prm = lm.make_params(2, lm.CONON, pr.sigma, tau=0.2)
+    q, p = dev(pr.X), dev(p0)
+    lm.lm_shoot(prm, q, p, 0.7, 30, q, p)           # outputs alias the inputs
+    torch.cuda.synchronize()
+    assert rel_err(host(q), oq) <= 1e-10 and rel_err(host(p), op) <= 1e-10
+
+
+def test_single_particle_straight_line():
+    prm = lm.make_params(3, lm.CONON, 0.1, tau=0.5)
+    q = dev(np.array([[0.3], [-1.2], [2.0]]))
+    p = dev(np.array([[0.7], [0.1], [-0.4]]))
+    q1, p1 = torch.empty_like(q), torch.empty_like(p)
+    lm.lm_shoot(prm, q, p, 1.0, 7, q1, p1)
+    torch.cuda.synchronize()
+    assert np.allclose(host(q1), host(q) + 1.5 * host(p), rtol=0, atol=1e-14)
+    assert np.array_equal(host(p1), host(p))
+
+
+def test_shoot_is_deterministic():
+    pr = inputs.config_curve2d(2000)
+    prm = lm.make_params(2, lm.CONON, pr.sigma)
+    q, p = dev(pr.X), dev(pr.p_bench())
+    outs = []
+    for _ in range(2):
+        q1, p1 = torch.empty_like(q), torch.empty_like(p)
+        lm.lm_shoot(prm, q, p, 1.0, 10, q1, p1)
+        torch.cuda.synchronize()
+        outs.append((host(q1), host(p1)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_full_size_shoot_conserves_momentum_and_energy(kernel):
+    """At N = 65536 the oracle cannot shoot in seconds; properties that hold at any size
+    are checked instead: total momentum is exact, H drifts at RK4 order."""
+    pr = inputs.config_sphere3d(65536, kernel=kernel)
+    prm = lm.make_params(3, kernel, pr.sigma)
+    q, p = dev(pr.X), dev(pr.p_bench())
+    H0 = lm.lm_hamiltonian(prm, q, p)
+    q1, p1 = torch.empty_like(q), torch.empty_like(p)
+    lm.lm_shoot(prm, q, p, 1.0, 4, q1, p1)
+    H1 = lm.lm_hamiltonian(prm, q1, p1)
+    P0, P1 = host(p).sum(axis=1), host(p1).sum(axis=1)
+    print("kernel %d: H %.10e -> %.10e, sum p drift %.2e" % (kernel, H0, H1, np.max(np.abs(P1 - P0))))
+    assert np.max(np.abs(P1 - P0)) <= 1e-11 * np.max(np.abs(host(p))) * pr.n
+    assert abs(H1 - H0) <= 1e-6 * abs(H0)
+
+
+# ------------------------------------------------------------------ Hamiltonian, velocity, K-solve
+
+
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+@pytest.mark.parametrize("dim,kernel", [(2, 0), (2, 1), (3, 0), (3, 1)])
+def test_hamiltonian_matches_oracle(dim, kernel, dtype):
+    q, p = inputs.random_state(777, dim, seed=[103, dim], pscale=0.2)
+    q, p = rounded(q, dtype), rounded(p, dtype)
+    prm = lm.make_params(dim, kernel, 0.3, dtype=dtype)
+    H = lm.lm_hamiltonian(prm, dev(q, dtype), dev(p, dtype))
+    assert H == pytest.approx(oracle.hamiltonian(q, p, kernel, 0.3), rel=1e-10)
+
+
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+@pytest.mark.parametrize("dim,kernel", [(2, 0), (3, 1)])
+def test_velocity_field_matches_oracle(dim, kernel, dtype):
+    q, p = inputs.random_state(500, dim, seed=[104, dim])
+    x, _ = inputs.random_state(333, dim, seed=[105, dim], box=1.5)
+    q, p, x = rounded(q, dtype), rounded(p, dtype), rounded(x, dtype)
+    prm = lm.make_params(dim, kernel, 0.3, dtype=dtype)
+    u = torch.empty((dim, 333), dtype=TDT[dtype], device=DEV)
+    lm.lm_velocity(prm, dev(q, dtype), dev(p, dtype), dev(x, dtype), u)
+    torch.cuda.synchronize()
+    assert rel_err(host(u), oracle.velocity(q, p, x, kernel, 0.3)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("name,make", [
+    ("circle_ellipse_64", lambda: inputs.config_circle_ellipse(64)),
+    ("curve2d_1000", lambda: inputs.config_curve2d(1000)),
+    ("example1_64", lambda: inputs.Problem("ex1", inputs.example1(64)[0], None, 0, 1.0, 50)),
+])
+def test_ksolve_matches_cholesky(name, make):
+    pr = make()
+    X = pr.X
+    b = np.random.default_rng(106).standard_normal(X.shape)
+    st, L = oracle.cholesky(oracle.kmatrix(X, pr.kernel, pr.sigma))
+    assert st == 0
+    want = np.stack([oracle.cholesky_solve(L, b[c]) for c in range(X.shape[0])])
+    prm = lm.make_params(X.shape[0], pr.kernel, pr.sigma)
+    x = torch.empty((X.shape[0], X.shape[1]), dtype=torch.float64, device=DEV)
+    it = lm.lm_ksolve(prm, dev(X), dev(b), x, rtol=1e-13)
+    print("%s: %d CG iterations, rel err %.2e" % (name, it, rel_err(host(x), want)))
+    assert rel_err(host(x), want) <= 1e-8
+
+
+# ------------------------------------------------------------------ feedback matching
+
+
+def gpu_match(X, Y, kernel, sigma, h, tol, steps, dtype=lm.F64, max_iter=500, tau=0.0, stop_rule=0):
+    prm = lm.make_params(X.shape[0], kernel, sigma, dtype=dtype, tau=tau)
+    p0 = torch.zeros(X.shape, dtype=torch.float64, device=DEV)
+    st, info, hist = lm.lm_feedback_match(prm, dev(X), dev(Y), p0, h=h, tol=tol, steps=steps,
+                                          max_iter=max_iter, stop_rule=stop_rule)
+    return st, info, hist, host(p0)
+
+
+def test_feedback_circle_to_ellipse_matches_oracle():
+    pr = inputs.config_circle_ellipse(64)
+    st, info, hist, p0 = gpu_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, pr.steps)
+    ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, pr.steps)
+    print("gpu %d its (%d CG) resid %.3e H %.8f | oracle %d its resid %.3e H %.8f" % (
+        info.iters, info.cg_iters, info.resid_inf, info.H, ref.iters, ref.resid, ref.H))
+    assert st == 0 and ref.status == 0
+    assert info.iters == ref.iters
+    assert rel_err(p0, ref.p0) <= 1e-8
+    assert info.H == pytest.approx(ref.H, rel=1e-9)
+    assert np.allclose(hist, ref.hist, rtol=1e-6, atol=1e-12)
+
+
+def test_feedback_example1_reproduces_paper_count():
+    X, Y = inputs.example1(64)
+    st, info, _, p0 = gpu_match(X, Y, 0, 1.0, 0.3, 1e-3, 50)
+    assert st == 0 and info.iters == 197
+    assert float("%.1e" % info.resid_inf) == 9.5e-4
+    assert 2 * info.H == pytest.approx(46.5022, rel=1e-4)
+
+
+def test_feedback_table2_divergence_is_reported():
+    X, Y = inputs.example2(64)
+    st, info, hist, _ = gpu_match(X, Y, 0, 1.0, 1.1, 1e-3, 50)
+    assert st == lm.LM_EDIVERGED
+    st, info, hist, _ = gpu_match(X, Y, 0, 1.0, 0.8, 1e-3, 50)
+    assert st == 0 and info.iters == 18
+
+
+def test_feedback_single_precision_shoot():
+    pr = inputs.config_circle_ellipse(64)
+    st, info, _, p0 = gpu_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-5, pr.steps, dtype=lm.F32)
+    ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-5, pr.steps)
+    assert st == 0 and abs(info.iters - ref.iters) <= 1
+    assert rel_err(p0, ref.p0) <= 1e-4
+
+
+def test_feedback_max_iter_reports_not_converged():
+    pr = inputs.config_circle_ellipse(64)
+    st, info, _, _ = gpu_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, pr.steps, max_iter=3)
+    assert st == lm.LM_ENOTCONV and info.iters == 3
+
+
+def test_bad_arguments_raise():
+    prm = lm.make_params(2, lm.CONON, 0.5)
+    q = torch.zeros((2, 10), dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError):
+        lm.lm_rhs(prm, q, q[:, :5].contiguous(), torch.empty_like(q), torch.empty_like(q))
+    with pytest.raises(lm.LmError):
+        lm.lm_shoot(prm, q, q.clone(), 1.0, 0, torch.empty_like(q), torch.empty_like(q))
