@@ -290,3 +290,20 @@ def test_bad_arguments_raise():
         lm.lm_rhs(prm, q, q[:, :5].contiguous(), torch.empty_like(q), torch.empty_like(q))
     with pytest.raises(lm.LmError):
         lm.lm_shoot(prm, q, q.clone(), 1.0, 0, torch.empty_like(q), torch.empty_like(q))
+
+
+def test_feedback_step_matches_oracle_iterates():
+    """Three calls of the one-iteration entry point equal three updates of Algorithm 1."""
+    pr = inputs.config_circle_ellipse(64)
+    prm = lm.make_params(2, lm.CONON, pr.sigma)
+    X, Y = dev(pr.X), dev(pr.Y)
+    p = torch.zeros_like(X)
+    resids = []
+    for _ in range(3):
+        info = lm.lm_feedback_step(prm, X, Y, p, h=0.8, tol=1e-6, steps=pr.steps)
+        assert info.converged == 0 and info.cg_iters > 0 and info.shoot_ms > 0
+        resids.append(info.resid_inf)
+    ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, pr.steps, max_iter=3)
+    assert ref.status == oracle.ENOTCONV and ref.iters == 3
+    assert np.allclose(resids, ref.hist[:3], rtol=1e-8, atol=0)
+    assert rel_err(host(p), ref.p0) <= 1e-9
