@@ -68,9 +68,17 @@ typedef struct lm_params {
     double sigma;     /* kernel width, > 0 and finite */
     double tau;       /* >= 0: weight of the inexact advection term tau*p_i (equation
                          "N-particle-inexact", where the paper writes sigma^2); 0 = exact */
-    double cutoff;    /* 0 = every pair (exact).  > 0: pairs of particle tiles whose bounding
-                         boxes lie farther apart than `cutoff` are skipped (an approximation;
-                         the dropped terms are bounded by G(cutoff) and |G'(cutoff)|) */
+    double cutoff;    /* 0 = every pair (exact).  > 0: tile skipping, an approximation that is
+                         not in the paper.  Points are grouped in tiles of 64; a source tile
+                         whose bounding box lies farther than `cutoff` from a target tile's box
+                         is skipped, so only pairs farther apart than `cutoff` are dropped.
+                         What a target loses is bounded by G(cutoff) sum_j |p_j| in velocity
+                         and |G'(cutoff)| |p_i| sum_j |p_j| in force (for the Gaussian when
+                         cutoff >= sigma/sqrt(2)).  lm_shoot and the feedback entry points
+                         order the points by Morton code internally (outputs keep the
+                         caller's order); lm_rhs and lm_velocity tile the caller's order, so
+                         give them spatially ordered points.  lm_hamiltonian and lm_ksolve
+                         ignore it and always sum every pair.  Needs n < 2^31. */
 } lm_params;
 
 /* Settings of Algorithm 1 (feedback-control iteration) with the constant gain M = h I. */
@@ -82,7 +90,7 @@ typedef struct lm_match_opts {
     int32_t stop_rule;    /* 0: stop when max_{c,i} |Y - q(1)| < tol (exact matching);
                              1: stop when max |u^k - u^(k-1)| = h max|Y - q(1)|_(k-1) < tol
                                 (the rule stated for inexact matching) */
-    int32_t cg_max_iter;  /* conjugate-gradient iterations per solve; 0 = 20*n + 100 */
+    int32_t cg_max_iter;  /* conjugate-gradient iterations per solve; 0 = min(20n+100, 10000) */
     double cg_rtol;       /* relative residual of each K-solve; 0 = 1e-13 */
     double *resid_hist;   /* HOST, nullable: receives the residual of each shoot */
     int32_t hist_len;     /* capacity of resid_hist */

@@ -187,16 +187,23 @@ def lm_feedback_match(params: lm_params, X, Y, p0, h: float, tol: float, steps: 
 
 
 def lm_feedback_step(params: lm_params, X, Y, p, h: float, tol: float, steps: int, q1=None,
-                     cg_rtol: float = 0.0, cg_max_iter: int = 0, stream=None) -> lm_step_info:
-    """One iteration of Algorithm 1 on p (in place); returns the lm_step_info."""
+                     cg_rtol: float = 0.0, cg_max_iter: int = 0, stream=None,
+                     raise_on=(LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_EUNSUPPORTED)):
+    """One iteration of Algorithm 1 on p (in place).  Returns (status, lm_step_info).
+
+    Statuses describing the iteration (diverged, K-solve not converged or singular) are
+    returned, not raised; argument and runtime errors raise LmError.
+    """
     dim, n = X.shape
     for t, nm in [(X, "X"), (Y, "Y"), (p, "p")] + ([(q1, "q1")] if q1 is not None else []):
         _check_tensor(t, params.dim, n, F64, nm)
     o = lm_match_opts(float(h), float(tol), 0, int(steps), 0, int(cg_max_iter), float(cg_rtol), None, 0, 0)
     info = lm_step_info()
-    _check(load().lm_feedback_step(ctypes.byref(params), ctypes.byref(o), n, _ptr(X), _ptr(Y), _ptr(p), _ptr(q1),
-                                   ctypes.byref(info), _stream(stream)))
-    return info
+    st = load().lm_feedback_step(ctypes.byref(params), ctypes.byref(o), n, _ptr(X), _ptr(Y), _ptr(p), _ptr(q1),
+                                 ctypes.byref(info), _stream(stream))
+    if st in raise_on:
+        raise LmError(st, last_error())
+    return st, info
 
 
 def lm_velocity(params: lm_params, q, p, x, u, stream=None):

@@ -113,7 +113,6 @@ lm_status check_params(const lm_params* prm)
     if (!(prm->sigma > 0.0) || !is_finite(prm->sigma)) return fail(LM_EINVAL, "sigma must be positive and finite");
     if (!(prm->tau >= 0.0) || !is_finite(prm->tau)) return fail(LM_EINVAL, "tau must be >= 0 and finite");
     if (!(prm->cutoff >= 0.0) || !is_finite(prm->cutoff)) return fail(LM_EINVAL, "cutoff must be >= 0 and finite");
-    if (prm->cutoff > 0.0) return fail(LM_EUNSUPPORTED, "cutoff > 0 (tile skipping) is not provided by this build");
     return LM_OK;
 }
 
@@ -140,12 +139,21 @@ void kernel_scales(const lm_params* prm, bool f32, double* kq, double* wscale)
     if (f32) *kq *= log2e;
 }
 
+// Cutoff mode: tile boxes of the sources and of the targets (the same buffer when the
+// targets are the sources) and the squared radius.  box_s == nullptr means every pair.
+struct Cut {
+    const double* box_s = nullptr;
+    const double* box_t = nullptr;
+    double rc2 = 0.0;
+};
+
 // One evaluation of the pair sums with targets (qt, pt) [nt] and sources (qs, ps) [ns].
 template <class T>
 lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, int64_t ns, const T* qt,
-                    const T* pt, int64_t nt, const lm::EpiArgs<T>& epi, double* part, hipStream_t st)
+                    const T* pt, int64_t nt, const lm::EpiArgs<T>& epi, double* part, hipStream_t st,
+                    const Cut& cut = Cut())
 {
-    lm::PairPlan pl = lm::plan_pair(nt, ns);
+    lm::PairPlan pl = lm::plan_pair(nt, ns, cut.box_s != nullptr);
     lm::PairArgs<T> a{};
     a.qs = qs;
     a.ps = ps;
@@ -156,6 +164,9 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
     a.jchunk = pl.jchunk;
     kernel_scales(prm, sizeof(T) == 4, &a.kq, &a.wscale);
     a.part = part;
+    a.box_s = cut.box_s;
+    a.box_t = cut.box_t;
+    a.rc2 = cut.rc2;
     a.epi = epi;
     LM_HIP(lm::launch_pair<T>(prm->dim, prm->kernel, force, a, pl, st));
     return LM_OK;
@@ -163,15 +174,16 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
 
 int64_t part_elems(const lm_params* prm, int64_t nt, int64_t ns)
 {
-    lm::PairPlan pl = lm::plan_pair(nt, ns);
+    lm::PairPlan pl = lm::plan_pair(nt, ns, false);
     return pl.nsplit > 1 ? (int64_t)pl.nsplit * 2 * prm->dim * nt : 1;
 }
 
-// RK4 shoot of (q, p) in place over [0, t1] with `steps` steps.  ws must provide 6 state
-// buffers of dim*n T and the split workspace.
+// RK4 shoot of (q, p) in place over [0, t1] with `steps` steps.  a*, b*: stage buffers, c*:
+// the RK4 running sum (dim*n T each); part: the split workspace.  box (non-null in cutoff
+// mode, tiles_of(n)*8 doubles) receives the tile boxes of every stage input.
 template <class T>
 lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, int32_t steps, T* aq, T* ap,
-                        T* bq, T* bp, T* cq, T* cp, double* part, hipStream_t st)
+                        T* bq, T* bp, T* cq, T* cp, double* part, hipStream_t st, double* box = nullptr)
 {
     const double dt = t1 / steps;
     lm::EpiArgs<T> e{};
@@ -181,6 +193,11 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
     e.base_p = p;
     e.acc_q = cq;
     e.acc_p = cp;
+    Cut cut;
+    if (box) {
+        cut.box_s = cut.box_t = box;
+        cut.rc2 = prm->cutoff * prm->cutoff;
+    }
     for (int32_t s = 0; s < steps; ++s) {
         // stage 1: input y, output A ; stage 2: A -> B ; stage 3: B -> A ; stage 4: A -> y
         const T* in_q[4] = {q, aq, bq, aq};
@@ -192,11 +209,39 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
             e.in_p = in_p[k];
             e.out_q = out_q[k];
             e.out_p = out_p[k];
-            LM_TRY(pair_eval<T>(prm, true, in_q[k], in_p[k], n, in_q[k], in_p[k], n, e, part, st));
+            if (box) LM_HIP(lm::launch_tile_boxes<T>(prm->dim, in_q[k], n, box, st));
+            LM_TRY(pair_eval<T>(prm, true, in_q[k], in_p[k], n, in_q[k], in_p[k], n, e, part, st, cut));
         }
     }
     return LM_OK;
 }
+
+// Spatial order of a point set for the cutoff mode: perm (n indices) sorts the points by
+// the Morton code of their position.
+struct Ordering {
+    int64_t* perm = nullptr;
+    double* box = nullptr;    // tile boxes, reused by the shoot for its stage boxes
+    lm_status alloc(Workspace& ws, int64_t n);
+    template <class T>
+    lm_status compute(int dim, const T* q, int64_t n, Workspace& ws, hipStream_t st)
+    {
+        double* gbox;
+        uint64_t* keys;
+        LM_TRY(ws.get(&gbox, 8));
+        LM_TRY(ws.get(&keys, lm::sort_pad(n)));
+        LM_HIP(lm::launch_morton_order<T>(dim, q, n, box, gbox, keys, perm, st));
+        return LM_OK;
+    }
+};
+
+lm_status Ordering::alloc(Workspace& ws, int64_t n)
+{
+    LM_TRY(ws.get(&perm, n));
+    LM_TRY(ws.get(&box, lm::tiles_of(n) * 8));
+    return LM_OK;
+}
+
+constexpr int64_t kMaxCutN = ((int64_t)1 << 31) - 1;
 
 template <class T>
 lm_status shoot_t(const lm_params* prm, int64_t n, const T* q0, const T* p0, double t1, int32_t steps, T* q1,
@@ -213,6 +258,22 @@ lm_status shoot_t(const lm_params* prm, int64_t n, const T* q0, const T* p0, dou
     LM_TRY(ws.get(&cq, m));
     LM_TRY(ws.get(&cp, m));
     LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+    if (prm->cutoff > 0.0) {
+        // shoot in Morton order so that tiles are compact, then scatter back
+        if (n > kMaxCutN) return fail(LM_EINVAL, "cutoff mode needs n < 2^31");
+        Ordering ord;
+        LM_TRY(ord.alloc(ws, n));
+        LM_TRY(ord.compute<T>(prm->dim, q0, n, ws, st));
+        T *sq, *sp;
+        LM_TRY(ws.get(&sq, m));
+        LM_TRY(ws.get(&sp, m));
+        LM_HIP((lm::launch_permute<T, T>(sq, q0, ord.perm, n, prm->dim, false, st)));
+        LM_HIP((lm::launch_permute<T, T>(sp, p0, ord.perm, n, prm->dim, false, st)));
+        LM_TRY(shoot_inplace<T>(prm, n, sq, sp, t1, steps, aq, ap, bq, bp, cq, cp, part, st, ord.box));
+        LM_HIP((lm::launch_permute<T, T>(q1, sq, ord.perm, n, prm->dim, true, st)));
+        LM_HIP((lm::launch_permute<T, T>(p1, sp, ord.perm, n, prm->dim, true, st)));
+        return LM_OK;
+    }
     if (q1 != q0) LM_HIP(hipMemcpyAsync(q1, q0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
     if (p1 != p0) LM_HIP(hipMemcpyAsync(p1, p0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
     return shoot_inplace<T>(prm, n, q1, p1, t1, steps, aq, ap, bq, bp, cq, cp, part, st);
@@ -323,6 +384,56 @@ lm_status ksolve_impl(const lm_params* prm, int64_t n, const double* X, const do
     return LM_OK;
 }
 
+// Right-hand side in the caller's order; in cutoff mode the tiles are 64 consecutive points
+// of that order.
+template <class T>
+lm_status rhs_t(const lm_params* prm, int64_t n, const T* q, const T* p, T* dq, T* dp, hipStream_t st)
+{
+    Workspace ws(st);
+    double* part;
+    LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+    Cut cut;
+    if (prm->cutoff > 0.0) {
+        double* box;
+        LM_TRY(ws.get(&box, lm::tiles_of(n) * 8));
+        LM_HIP(lm::launch_tile_boxes<T>(prm->dim, q, n, box, st));
+        cut.box_s = cut.box_t = box;
+        cut.rc2 = prm->cutoff * prm->cutoff;
+    }
+    lm::EpiArgs<T> e{};
+    e.kind = lm::EPI_STORE;
+    e.tau = prm->tau;
+    e.in_p = p;
+    e.out_q = dq;
+    e.out_p = dp;
+    return pair_eval<T>(prm, true, q, p, n, q, p, n, e, part, st, cut);
+}
+
+template <class T>
+lm_status velocity_t(const lm_params* prm, int64_t n, const T* q, const T* p, int64_t m, const T* x, T* u,
+                     hipStream_t st)
+{
+    Workspace ws(st);
+    double* part;
+    LM_TRY(ws.get(&part, part_elems(prm, m, n)));
+    Cut cut;
+    if (prm->cutoff > 0.0) {
+        double *bs, *bt;
+        LM_TRY(ws.get(&bs, lm::tiles_of(n) * 8));
+        LM_TRY(ws.get(&bt, lm::tiles_of(m) * 8));
+        LM_HIP(lm::launch_tile_boxes<T>(prm->dim, q, n, bs, st));
+        LM_HIP(lm::launch_tile_boxes<T>(prm->dim, x, m, bt, st));
+        cut.box_s = bs;
+        cut.box_t = bt;
+        cut.rc2 = prm->cutoff * prm->cutoff;
+    }
+    lm::EpiArgs<T> e{};
+    e.kind = lm::EPI_STORE;
+    e.tau = 0.0;
+    e.out_q = u;
+    return pair_eval<T>(prm, false, q, p, n, x, (const T*)nullptr, m, e, part, st, cut);
+}
+
 lm_status check_match_args(const lm_match_opts* o, const double* X, const double* Y, const double* p0)
 {
     if (!o) return fail(LM_EINVAL, "opts is NULL");
@@ -344,11 +455,21 @@ struct FeedbackWork {
     double *aq = nullptr, *ap = nullptr, *bq = nullptr, *bp = nullptr, *cq = nullptr, *cp = nullptr;
     float *qf = nullptr, *pf = nullptr, *aqf = nullptr, *apf = nullptr, *bqf = nullptr, *bpf = nullptr,
           *cqf = nullptr, *cpf = nullptr;
+    double* q1 = nullptr;     // q(1) in the caller's order (== qd unless the shoot is reordered)
+    bool ordered = false;     // cutoff mode: shoots run in the Morton order of X
+    Ordering ord;
     CgBuffers cg;
 
-    lm_status alloc(Workspace& ws, const lm_params* prm, int64_t n)
+    lm_status alloc(Workspace& ws, const lm_params* prm, int64_t n, const double* X, hipStream_t st)
     {
         const int64_t m = (int64_t)prm->dim * n;
+        ordered = prm->cutoff > 0.0;
+        if (ordered) {
+            if (n > kMaxCutN) return fail(LM_EINVAL, "cutoff mode needs n < 2^31");
+            LM_TRY(ord.alloc(ws, n));
+            LM_TRY(ord.compute<double>(prm->dim, X, n, ws, st));
+            LM_TRY(ws.get(&q1, m));
+        }
         LM_TRY(ws.get(&qd, m));
         LM_TRY(ws.get(&pd, m));
         LM_TRY(ws.get(&e, m));
@@ -373,32 +494,50 @@ struct FeedbackWork {
             LM_TRY(ws.get(&cq, m));
             LM_TRY(ws.get(&cp, m));
         }
+        if (!ordered) q1 = qd;
         return cg_alloc(ws, prm, n, &cg);
     }
 };
 
-// Algorithm 1, steps 1-2: q(1) of the shoot from (X, p) into w.qd, and r = max |Y - q(1)|
+// Algorithm 1, steps 1-2: q(1) of the shoot from (X, p) into w.q1, and r = max |Y - q(1)|
 // (read back to the host: it decides the next launch).
 lm_status feedback_shoot_residual(const lm_params* prm, const lm_match_opts* o, int64_t n, const double* X,
                                   const double* Y, const double* p, FeedbackWork& w, double* r, hipStream_t st,
                                   hipEvent_t after_shoot = nullptr)
 {
-    const int64_t m = (int64_t)prm->dim * n;
+    const int dim = prm->dim;
+    const int64_t m = (int64_t)dim * n;
+    const int64_t* perm = w.ord.perm;
+    double* box = w.ordered ? w.ord.box : nullptr;
     if (prm->dtype == LM_F32) {
         // single-precision shoot; the momenta, the residual and the solve stay in double
-        LM_HIP((lm::launch_convert<float, double>(w.qf, X, m, st)));
-        LM_HIP((lm::launch_convert<float, double>(w.pf, p, m, st)));
+        if (w.ordered) {
+            LM_HIP((lm::launch_permute<float, double>(w.qf, X, perm, n, dim, false, st)));
+            LM_HIP((lm::launch_permute<float, double>(w.pf, p, perm, n, dim, false, st)));
+        } else {
+            LM_HIP((lm::launch_convert<float, double>(w.qf, X, m, st)));
+            LM_HIP((lm::launch_convert<float, double>(w.pf, p, m, st)));
+        }
         LM_TRY(shoot_inplace<float>(prm, n, w.qf, w.pf, 1.0, o->steps, w.aqf, w.apf, w.bqf, w.bpf, w.cqf, w.cpf,
-                                    w.part, st));
-        LM_HIP((lm::launch_convert<double, float>(w.qd, w.qf, m, st)));
+                                    w.part, st, box));
+        if (w.ordered)
+            LM_HIP((lm::launch_permute<double, float>(w.q1, w.qf, perm, n, dim, true, st)));
+        else
+            LM_HIP((lm::launch_convert<double, float>(w.qd, w.qf, m, st)));
     } else {
-        LM_HIP(hipMemcpyAsync(w.qd, X, m * sizeof(double), hipMemcpyDeviceToDevice, st));
-        LM_HIP(hipMemcpyAsync(w.pd, p, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        if (w.ordered) {
+            LM_HIP((lm::launch_permute<double, double>(w.qd, X, perm, n, dim, false, st)));
+            LM_HIP((lm::launch_permute<double, double>(w.pd, p, perm, n, dim, false, st)));
+        } else {
+            LM_HIP(hipMemcpyAsync(w.qd, X, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+            LM_HIP(hipMemcpyAsync(w.pd, p, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
         LM_TRY(shoot_inplace<double>(prm, n, w.qd, w.pd, 1.0, o->steps, w.aq, w.ap, w.bq, w.bp, w.cq, w.cp, w.part,
-                                     st));
+                                     st, box));
+        if (w.ordered) LM_HIP((lm::launch_permute<double, double>(w.q1, w.qd, perm, n, dim, true, st)));
     }
     if (after_shoot) LM_HIP(hipEventRecord(after_shoot, st));
-    LM_HIP((lm::launch_maxabsdiff<double, double>(Y, w.qd, m, w.red, w.rdev, st)));
+    LM_HIP((lm::launch_maxabsdiff<double, double>(Y, w.q1, m, w.red, w.rdev, st)));
     LM_HIP(hipMemcpyAsync(r, w.rdev, sizeof(double), hipMemcpyDeviceToHost, st));
     LM_HIP(hipStreamSynchronize(st));
     return LM_OK;
@@ -411,9 +550,9 @@ lm_status feedback_update(const lm_params* prm, const lm_match_opts* o, int64_t 
 {
     const int64_t m = (int64_t)prm->dim * n;
     const double cg_rtol = o->cg_rtol > 0.0 ? o->cg_rtol : 1e-13;
-    const int64_t cgmax64 = o->cg_max_iter > 0 ? o->cg_max_iter : 20 * n + 100;
-    const int32_t cg_max = (int32_t)(cgmax64 > (1 << 30) ? (1 << 30) : cgmax64);
-    LM_HIP(lm::launch_sub(w.e, Y, w.qd, m, st));
+    const int64_t cgdef = 20 * n + 100 < 10000 ? 20 * n + 100 : 10000;
+    const int32_t cg_max = o->cg_max_iter > 0 ? o->cg_max_iter : (int32_t)cgdef;
+    LM_HIP(lm::launch_sub(w.e, Y, w.q1, m, st));
     LM_TRY(ksolve_impl(prm, n, X, w.e, w.delta, cg_rtol, cg_max, cg_iters, w.cg, w.part, st));
     LM_HIP(lm::launch_axpy(p, p, o->h, w.delta, m, st));
     return LM_OK;
@@ -438,27 +577,9 @@ lm_status lm_rhs(const lm_params* prm, int64_t n, const void* q, const void* p, 
     if (!q || !p || !dq || !dp) return fail(LM_EINVAL, "NULL buffer");
     if (dq == q || dq == p || dp == q || dp == p) return fail(LM_EINVAL, "dq/dp must not alias q/p");
     hipStream_t st = (hipStream_t)stream;
-    Workspace ws(st);
-    double* part;
-    LM_TRY(ws.get(&part, part_elems(prm, n, n)));
-    if (prm->dtype == LM_F64) {
-        lm::EpiArgs<double> e{};
-        e.kind = lm::EPI_STORE;
-        e.tau = prm->tau;
-        e.in_p = (const double*)p;
-        e.out_q = (double*)dq;
-        e.out_p = (double*)dp;
-        return pair_eval<double>(prm, true, (const double*)q, (const double*)p, n, (const double*)q,
-                                 (const double*)p, n, e, part, st);
-    }
-    lm::EpiArgs<float> e{};
-    e.kind = lm::EPI_STORE;
-    e.tau = prm->tau;
-    e.in_p = (const float*)p;
-    e.out_q = (float*)dq;
-    e.out_p = (float*)dp;
-    return pair_eval<float>(prm, true, (const float*)q, (const float*)p, n, (const float*)q, (const float*)p, n, e,
-                            part, st);
+    if (prm->dtype == LM_F64)
+        return rhs_t<double>(prm, n, (const double*)q, (const double*)p, (double*)dq, (double*)dp, st);
+    return rhs_t<float>(prm, n, (const float*)q, (const float*)p, (float*)dq, (float*)dp, st);
 }
 
 lm_status lm_shoot(const lm_params* prm, int64_t n, const void* q0, const void* p0, double t1, int32_t steps,
@@ -523,7 +644,7 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
     std::memset(info, 0, sizeof *info);
     Workspace ws(st);
     FeedbackWork w;
-    LM_TRY(w.alloc(ws, prm, n));
+    LM_TRY(w.alloc(ws, prm, n, X, st));
 
     lm_status result = LM_OK;
     double r = 0.0, prev_step = INFINITY;
@@ -553,7 +674,7 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
     }
     info->iters = k;
     info->resid_inf = r;
-    if (q1_out) LM_HIP(hipMemcpyAsync(q1_out, w.qd, (int64_t)prm->dim * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (q1_out) LM_HIP(hipMemcpyAsync(q1_out, w.q1, (int64_t)prm->dim * n * sizeof(double), hipMemcpyDeviceToDevice, st));
     double H = NAN;
     lm_status hs = hamiltonian_f64(prm, n, X, p0, &H, st);
     info->H = H;
@@ -572,7 +693,7 @@ lm_status lm_feedback_step(const lm_params* prm, const lm_match_opts* o, int64_t
     hipStream_t st = (hipStream_t)stream;
     Workspace ws(st);
     FeedbackWork w;
-    LM_TRY(w.alloc(ws, prm, n));
+    LM_TRY(w.alloc(ws, prm, n, X, st));
     EventTimer timer;
     LM_TRY(timer.init());
     LM_HIP(hipEventRecord(timer.ev[0], st));
@@ -580,7 +701,7 @@ lm_status lm_feedback_step(const lm_params* prm, const lm_match_opts* o, int64_t
     LM_TRY(feedback_shoot_residual(prm, o, n, X, Y, p, w, &r, st, timer.ev[1]));
     info->shoot_ms = timer.ms(0, 1);
     info->resid_inf = r;
-    if (q1_out) LM_HIP(hipMemcpyAsync(q1_out, w.qd, (int64_t)prm->dim * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (q1_out) LM_HIP(hipMemcpyAsync(q1_out, w.q1, (int64_t)prm->dim * n * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (!is_finite(r)) return fail(LM_EDIVERGED, "non-finite residual");
     if (r < o->tol) {
         info->converged = 1;
@@ -606,23 +727,9 @@ lm_status lm_velocity(const lm_params* prm, int64_t n, const void* q, const void
     LM_TRY(check_n(m, "m"));
     if (!q || !p || !x || !u) return fail(LM_EINVAL, "NULL buffer");
     hipStream_t st = (hipStream_t)stream;
-    Workspace ws(st);
-    double* part;
-    LM_TRY(ws.get(&part, part_elems(prm, m, n)));
-    if (prm->dtype == LM_F64) {
-        lm::EpiArgs<double> e{};
-        e.kind = lm::EPI_STORE;
-        e.tau = 0.0;
-        e.out_q = (double*)u;
-        return pair_eval<double>(prm, false, (const double*)q, (const double*)p, n, (const double*)x, nullptr, m, e,
-                                 part, st);
-    }
-    lm::EpiArgs<float> e{};
-    e.kind = lm::EPI_STORE;
-    e.tau = 0.0;
-    e.out_q = (float*)u;
-    return pair_eval<float>(prm, false, (const float*)q, (const float*)p, n, (const float*)x, nullptr, m, e, part,
-                            st);
+    if (prm->dtype == LM_F64)
+        return velocity_t<double>(prm, n, (const double*)q, (const double*)p, m, (const double*)x, (double*)u, st);
+    return velocity_t<float>(prm, n, (const float*)q, (const float*)p, m, (const float*)x, (float*)u, st);
 }
 
 }  // extern "C"

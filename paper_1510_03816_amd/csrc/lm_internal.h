@@ -42,6 +42,9 @@ struct PairArgs {
     double kq;         // exponent scale: conon -1/sigma, Gaussian -1/sigma^2 (x log2 e in f32)
     double wscale;     // force-weight constant: conon 1/sigma, Gaussian 2/sigma^2
     double* part;      // split partial sums (nsplit, 2 dim, nt), used when nsplit > 1
+    const double* box_s;   // cutoff mode: source tile boxes (8 doubles per 64-point tile), else null
+    const double* box_t;   // cutoff mode: target tile boxes
+    double rc2;            // cutoff radius squared
     EpiArgs<T> epi;
 };
 
@@ -51,7 +54,7 @@ struct PairPlan {
     int64_t jchunk;
 };
 
-PairPlan plan_pair(int64_t nt, int64_t ns);
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut);
 
 template <class T>
 hipError_t launch_pair(int dim, int kernel, bool force, const PairArgs<T>& a, const PairPlan& pl,
@@ -74,5 +77,22 @@ hipError_t launch_sub(double* y, const double* x, const double* z, int64_t m, hi
 
 template <class TO, class TI>
 hipError_t launch_convert(TO* y, const TI* x, int64_t m, hipStream_t st);
+
+int64_t tiles_of(int64_t n);     // 64-point tiles covering n points
+int64_t sort_pad(int64_t n);     // power of two >= max(n, 2)
+
+// Bounding boxes of the 64-point tiles of q (8 doubles per tile: lo[4], hi[4]).
+template <class T>
+hipError_t launch_tile_boxes(int dim, const T* q, int64_t n, double* box, hipStream_t st);
+
+// perm = the order of the points sorted by the Morton code of their position in the global
+// bounding box.  box: tiles_of(n)*8 doubles; gbox: 8 doubles; keys: sort_pad(n) words.
+template <class T>
+hipError_t launch_morton_order(int dim, const T* q, int64_t n, double* box, double* gbox, uint64_t* keys,
+                               int64_t* perm, hipStream_t st);
+
+// out[c][i] = in[c][perm[i]] (gather) or out[c][perm[i]] = in[c][i] (scatter)
+template <class TO, class TI>
+hipError_t launch_permute(TO* out, const TI* in, const int64_t* perm, int64_t n, int dim, bool scatter, hipStream_t st);
 
 }  // namespace lm

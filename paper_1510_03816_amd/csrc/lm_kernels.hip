@@ -183,7 +183,93 @@ __device__ __forceinline__ void epilogue(const EpiArgs<T>& e, int64_t n, int64_t
 // the N-particle right-hand side).
 // ---------------------------------------------------------------------------------------
 
-template <class T, int DIM, int KER, bool FORCE>
+// Sums sources [j0, j1) into (v, f) for one target per lane.  Sources are wave-uniform:
+// the loads become scalar loads and the values SGPR operands.
+template <int DIM, int KER, bool FORCE>
+__device__ __forceinline__ void sum_sources(const double* __restrict__ qs, const double* __restrict__ ps,
+                                            int64_t ns, int64_t j0, int64_t j1, const double (&qi)[DIM],
+                                            const double (&psi)[DIM], double kq, double (&v)[DIM],
+                                            double (&f)[DIM])
+{
+    int64_t j = j0;
+    for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double qj[DIM], pj[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                qj[c] = qs[c * ns + j + u];
+                pj[c] = ps[c * ns + j + u];
+            }
+            pair_f64<DIM, KER, FORCE>(qi, psi, qj, pj, kq, v, f);
+        }
+    }
+    for (; j < j1; ++j) {
+        double qj[DIM], pj[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            qj[c] = qs[c * ns + j];
+            pj[c] = ps[c * ns + j];
+        }
+        pair_f64<DIM, KER, FORCE>(qi, psi, qj, pj, kq, v, f);
+    }
+}
+
+// Single precision: pairs summed in float over runs of 64 sources, the runs added in double,
+// which keeps the rounding error of long sums at the level of one run.
+template <int DIM, int KER, bool FORCE>
+__device__ __forceinline__ void sum_sources(const float* __restrict__ qs, const float* __restrict__ ps,
+                                            int64_t ns, int64_t j0, int64_t j1, const float (&qi)[DIM],
+                                            const float (&psi)[DIM], double kqd, double (&v)[DIM],
+                                            double (&f)[DIM])
+{
+    const float kq = (float)kqd;
+    for (int64_t jr = j0; jr < j1; jr += 64) {
+        const int64_t je = (jr + 64 < j1) ? (jr + 64) : j1;
+        float vs[DIM], fs[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) { vs[c] = 0.0f; fs[c] = 0.0f; }
+        int64_t j = jr;
+        for (; j + 4 <= je; j += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                float qj[DIM], pj[DIM];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    qj[c] = qs[c * ns + j + u];
+                    pj[c] = ps[c * ns + j + u];
+                }
+                pair_f32<DIM, KER, FORCE>(qi, psi, qj, pj, kq, vs, fs);
+            }
+        }
+        for (; j < je; ++j) {
+            float qj[DIM], pj[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                qj[c] = qs[c * ns + j];
+                pj[c] = ps[c * ns + j];
+            }
+            pair_f32<DIM, KER, FORCE>(qi, psi, qj, pj, kq, vs, fs);
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) { v[c] += (double)vs[c]; f[c] += (double)fs[c]; }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// The pair-sum kernel.
+//   grid  = (ceil(nt / 64), S),  block = 64 * kWaves
+//   wave w of block (bx, by) sums sources j in [(by*kWaves + w) * jchunk, ... + jchunk)
+//   for the targets i = bx*64 + lane.
+// Sources: (qs, ps) with ns points; targets: (qt, pt) with nt points (the same arrays for
+// the N-particle right-hand side).
+// CUT: sources are visited tile by tile (64 consecutive sources); a source tile whose
+// bounding box lies farther than the cutoff from the target tile's box is skipped as a
+// whole -- every pair it holds is farther apart than the cutoff.  The test is wave-uniform,
+// so skipping is a scalar branch.
+// ---------------------------------------------------------------------------------------
+
+template <class T, int DIM, int KER, bool FORCE, bool CUT>
 __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
 {
     const int lane = threadIdx.x & (kTile - 1);
@@ -208,67 +294,30 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
 #pragma unroll
     for (int c = 0; c < DIM; ++c) { v[c] = 0.0; f[c] = 0.0; }
 
-    const T* __restrict__ qs = a.qs;
-    const T* __restrict__ ps = a.ps;
-    const int64_t ns = a.ns;
-
-    if constexpr (sizeof(T) == 8) {
-        const double kq = a.kq;
-        int64_t j = j0;
-        for (; j + 4 <= j1; j += 4) {
+    if constexpr (!CUT) {
+        sum_sources<DIM, KER, FORCE>(a.qs, a.ps, a.ns, j0, j1, qi, psi, a.kq, v, f);
+    } else {
+        const double* __restrict__ tb = a.box_t + (int64_t)blockIdx.x * 8;
+        double tlo[DIM], thi[DIM];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                double qj[DIM], pj[DIM];
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    qj[c] = qs[c * ns + j + u];
-                    pj[c] = ps[c * ns + j + u];
-                }
-                pair_f64<DIM, KER, FORCE>(qi, psi, qj, pj, kq, v, f);
-            }
-        }
-        for (; j < j1; ++j) {
-            double qj[DIM], pj[DIM];
+        for (int c = 0; c < DIM; ++c) { tlo[c] = tb[c]; thi[c] = tb[4 + c]; }
+        // source tiles are dealt round-robin to the (grid-y, wave) chunks: in a spatial
+        // order the tiles near a target tile are consecutive, and dealing them out spreads
+        // that work over every wave instead of leaving it to the one whose chunk holds them
+        const int64_t ntiles_s = (a.ns + kTile - 1) / kTile;
+        const int64_t nchunks = (int64_t)gridDim.y * kWaves;
+        for (int64_t t = chunk_id; t < ntiles_s; t += nchunks) {
+            const double* __restrict__ sb = a.box_s + t * 8;
+            double g2 = 0.0;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                qj[c] = qs[c * ns + j];
-                pj[c] = ps[c * ns + j];
+                const double gap = __builtin_fmax(__builtin_fmax(sb[c] - thi[c], tlo[c] - sb[4 + c]), 0.0);
+                g2 = __builtin_fma(gap, gap, g2);
             }
-            pair_f64<DIM, KER, FORCE>(qi, psi, qj, pj, kq, v, f);
-        }
-    } else {
-        // single precision: pairs summed in float over runs of 64 sources, the runs summed
-        // in double, which keeps the rounding error of long sums at the level of one run
-        const float kq = (float)a.kq;
-        for (int64_t jr = j0; jr < j1; jr += 64) {
-            const int64_t je = (jr + 64 < j1) ? (jr + 64) : j1;
-            float vs[DIM], fs[DIM];
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) { vs[c] = 0.0f; fs[c] = 0.0f; }
-            int64_t j = jr;
-            for (; j + 4 <= je; j += 4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    float qj[DIM], pj[DIM];
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        qj[c] = qs[c * ns + j + u];
-                        pj[c] = ps[c * ns + j + u];
-                    }
-                    pair_f32<DIM, KER, FORCE>(qi, psi, qj, pj, kq, vs, fs);
-                }
-            }
-            for (; j < je; ++j) {
-                float qj[DIM], pj[DIM];
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    qj[c] = qs[c * ns + j];
-                    pj[c] = ps[c * ns + j];
-                }
-                pair_f32<DIM, KER, FORCE>(qi, psi, qj, pj, kq, vs, fs);
-            }
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) { v[c] += (double)vs[c]; f[c] += (double)fs[c]; }
+            if (g2 > a.rc2) continue;
+            const int64_t js = t * kTile;
+            const int64_t je = (js + kTile < a.ns) ? (js + kTile) : a.ns;
+            sum_sources<DIM, KER, FORCE>(a.qs, a.ps, a.ns, js, je, qi, psi, a.kq, v, f);
         }
     }
 
@@ -497,6 +546,189 @@ __global__ __launch_bounds__(256) void lm_convert_kernel(TO* __restrict__ y, con
 }
 
 // ---------------------------------------------------------------------------------------
+// Tile bounding boxes and spatial ordering (used by the cutoff mode).
+// ---------------------------------------------------------------------------------------
+
+// box[t*8 + c] = min over tile t (64 consecutive points) of coordinate c, box[t*8 + 4 + c] =
+// max.  One wavefront per tile; min/max combined across the wave by butterfly shuffles.
+template <class T, int DIM>
+__global__ __launch_bounds__(256) void lm_tile_box_kernel(const T* __restrict__ q, int64_t n, int64_t ntiles,
+                                                          double* __restrict__ box)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= ntiles) return;                     // whole wavefronts leave together
+    const int64_t i = t * 64 + lane;
+    const int64_t ic = i < n ? i : t * 64;       // tile t holds at least one point
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        double lo = (double)q[c * n + ic], hi = lo;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = __builtin_fmin(lo, __shfl_xor(lo, o, 64));
+            hi = __builtin_fmax(hi, __shfl_xor(hi, o, 64));
+        }
+        if (lane == 0) {
+            box[t * 8 + c] = lo;
+            box[t * 8 + 4 + c] = hi;
+        }
+    }
+}
+
+// Reduces tile boxes to the bounding box of all points: out[c] = min, out[4 + c] = max.
+template <int DIM>
+__global__ __launch_bounds__(256) void lm_box_union_kernel(const double* __restrict__ box, int64_t ntiles,
+                                                           double* __restrict__ out)
+{
+    __shared__ double sh[2 * DIM][256];
+    double lo[DIM], hi[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { lo[c] = box[c]; hi[c] = box[4 + c]; }
+    for (int64_t t = threadIdx.x; t < ntiles; t += 256) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            lo[c] = __builtin_fmin(lo[c], box[t * 8 + c]);
+            hi[c] = __builtin_fmax(hi[c], box[t * 8 + 4 + c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { sh[c][threadIdx.x] = lo[c]; sh[DIM + c][threadIdx.x] = hi[c]; }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                sh[c][threadIdx.x] = __builtin_fmin(sh[c][threadIdx.x], sh[c][threadIdx.x + o]);
+                sh[DIM + c][threadIdx.x] = __builtin_fmax(sh[DIM + c][threadIdx.x], sh[DIM + c][threadIdx.x + o]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) { out[c] = sh[c][0]; out[4 + c] = sh[DIM + c][0]; }
+    }
+}
+
+__device__ __forceinline__ uint32_t spread_bits(uint32_t x, int dim)
+{
+    // insert (dim - 1) zero bits between consecutive bits of x
+    uint32_t r = 0;
+    const int bits = dim == 2 ? 16 : 10;
+    for (int b = 0; b < bits; ++b) r |= ((x >> b) & 1u) << (dim * b);
+    return r;
+}
+
+// keys[i] = (Morton code of point i in the global box) << 32 | i; padding keys are ~0.
+template <class T, int DIM>
+__global__ __launch_bounds__(256) void lm_morton_kernel(const T* __restrict__ q, int64_t n, int64_t npad,
+                                                        const double* __restrict__ gbox, uint64_t* __restrict__ keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    if (i >= n) {
+        keys[i] = ~(uint64_t)0;
+        return;
+    }
+    const uint32_t cells = DIM == 2 ? 65536u : 1024u;
+    uint32_t code = 0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double lo = gbox[c], ext = gbox[4 + c] - gbox[c];
+        double u = ext > 0.0 ? ((double)q[c * n + i] - lo) / ext : 0.0;
+        u = __builtin_fmin(__builtin_fmax(u, 0.0), 1.0);
+        uint32_t cell = (uint32_t)(u * (double)cells);
+        if (cell >= cells) cell = cells - 1;
+        code |= spread_bits(cell, DIM) << c;
+    }
+    keys[i] = ((uint64_t)code << 32) | (uint64_t)i;
+}
+
+// Bitonic sort of npad (a power of two) 64-bit keys, ascending.
+// lm_bitonic_tile_kernel sorts/merges within tiles of kSortTile keys held in LDS;
+// lm_bitonic_step_kernel does one compare-exchange step with partner distance j >= kSortTile.
+constexpr int kSortTile = 1024;
+
+__device__ __forceinline__ void cmp_swap(uint64_t& a, uint64_t& b, bool up)
+{
+    if ((a > b) == up) {
+        const uint64_t t = a;
+        a = b;
+        b = t;
+    }
+}
+
+// k_lo == 0: full sort of each tile (k = 2 .. tile); else the merge steps j = tile/2 .. 1
+// of bitonic stage k = k_lo (> tile).
+__global__ __launch_bounds__(kSortTile / 2) void lm_bitonic_tile_kernel(uint64_t* __restrict__ keys, int64_t npad,
+                                                                         int64_t k_lo)
+{
+    __shared__ uint64_t sh[kSortTile];
+    const int tile = (int)(npad < kSortTile ? npad : kSortTile);
+    const int64_t base = (int64_t)blockIdx.x * tile;
+    for (int e = threadIdx.x; e < tile; e += blockDim.x) sh[e] = keys[base + e];
+    __syncthreads();
+    const int half = tile / 2;
+    if (k_lo == 0) {
+        for (int k = 2; k <= tile; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int pidx = threadIdx.x; pidx < half; pidx += blockDim.x) {
+                    const int li = 2 * j * (pidx / j) + (pidx % j);
+                    const bool up = (((base + li) & k) == 0);
+                    cmp_swap(sh[li], sh[li + j], up);
+                }
+                __syncthreads();
+            }
+        }
+    } else {
+        for (int j = tile >> 1; j > 0; j >>= 1) {
+            for (int pidx = threadIdx.x; pidx < half; pidx += blockDim.x) {
+                const int li = 2 * j * (pidx / j) + (pidx % j);
+                const bool up = (((base + li) & k_lo) == 0);
+                cmp_swap(sh[li], sh[li + j], up);
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < tile; e += blockDim.x) keys[base + e] = sh[e];
+}
+
+__global__ __launch_bounds__(256) void lm_bitonic_step_kernel(uint64_t* __restrict__ keys, int64_t npad, int64_t k,
+                                                              int64_t j)
+{
+    const int64_t pidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pidx >= npad / 2) return;
+    const int64_t i = 2 * j * (pidx / j) + (pidx % j);
+    uint64_t a = keys[i], b = keys[i + j];
+    cmp_swap(a, b, (i & k) == 0);
+    keys[i] = a;
+    keys[i + j] = b;
+}
+
+__global__ __launch_bounds__(256) void lm_perm_kernel(const uint64_t* __restrict__ keys, int64_t n,
+                                                      int64_t* __restrict__ perm)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[i] = (int64_t)(keys[i] & 0xffffffffull);
+}
+
+// out[c][i] = in[c][perm[i]]  (gather)  or  out[c][perm[i]] = in[c][i]  (scatter)
+template <class TO, class TI, bool SCATTER>
+__global__ __launch_bounds__(256) void lm_permute_kernel(TO* __restrict__ out, const TI* __restrict__ in,
+                                                         const int64_t* __restrict__ perm, int64_t n, int dim)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t pi = perm[i];
+    for (int c = 0; c < dim; ++c) {
+        if (SCATTER)
+            out[c * n + pi] = (TO)in[c * n + i];
+        else
+            out[c * n + i] = (TO)in[c * n + pi];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Launchers (host side).
 // ---------------------------------------------------------------------------------------
 
@@ -507,7 +739,7 @@ static inline unsigned blocks_for(int64_t m, int threads, unsigned cap = 8192)
     return (unsigned)(b < (int64_t)cap ? b : cap);
 }
 
-PairPlan plan_pair(int64_t nt, int64_t ns)
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut)
 {
     PairPlan pl;
     pl.itiles = (nt + kTile - 1) / kTile;
@@ -522,14 +754,15 @@ PairPlan plan_pair(int64_t nt, int64_t ns)
     pl.nsplit = (int)s;
     int64_t chunks = (int64_t)pl.nsplit * kWaves;
     pl.jchunk = (ns + chunks - 1) / chunks;
+    if (cut) pl.jchunk = (pl.jchunk + kTile - 1) / kTile * kTile;   // chunks start on tile boundaries
     return pl;
 }
 
-template <class T, int DIM, int KER, bool FORCE>
+template <class T, int DIM, int KER, bool FORCE, bool CUT>
 static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStream_t st)
 {
     dim3 grid((unsigned)pl.itiles, (unsigned)pl.nsplit);
-    hipLaunchKernelGGL((lm_pair_kernel<T, DIM, KER, FORCE>), grid, dim3(kTile * kWaves), 0, st, a);
+    hipLaunchKernelGGL((lm_pair_kernel<T, DIM, KER, FORCE, CUT>), grid, dim3(kTile * kWaves), 0, st, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || pl.nsplit == 1) return err;
     hipLaunchKernelGGL((lm_finish_kernel<T, DIM, FORCE>), dim3(blocks_for(a.nt, 256, 1u << 30)), dim3(256), 0, st,
@@ -537,22 +770,25 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
     return hipGetLastError();
 }
 
+template <class T, int DIM, int KER>
+static hipError_t launch_pair_k(bool force, bool cut, const PairArgs<T>& a, const PairPlan& pl, hipStream_t st)
+{
+    if (force) return cut ? launch_pair_t<T, DIM, KER, true, true>(a, pl, st)
+                          : launch_pair_t<T, DIM, KER, true, false>(a, pl, st);
+    return cut ? launch_pair_t<T, DIM, KER, false, true>(a, pl, st)
+               : launch_pair_t<T, DIM, KER, false, false>(a, pl, st);
+}
+
 template <class T>
 hipError_t launch_pair(int dim, int kernel, bool force, const PairArgs<T>& a, const PairPlan& pl,
                        hipStream_t st)
 {
-    if (dim == 2) {
-        if (kernel == LM_KERNEL_CONON)
-            return force ? launch_pair_t<T, 2, LM_KERNEL_CONON, true>(a, pl, st)
-                         : launch_pair_t<T, 2, LM_KERNEL_CONON, false>(a, pl, st);
-        return force ? launch_pair_t<T, 2, LM_KERNEL_GAUSS, true>(a, pl, st)
-                     : launch_pair_t<T, 2, LM_KERNEL_GAUSS, false>(a, pl, st);
-    }
-    if (kernel == LM_KERNEL_CONON)
-        return force ? launch_pair_t<T, 3, LM_KERNEL_CONON, true>(a, pl, st)
-                     : launch_pair_t<T, 3, LM_KERNEL_CONON, false>(a, pl, st);
-    return force ? launch_pair_t<T, 3, LM_KERNEL_GAUSS, true>(a, pl, st)
-                 : launch_pair_t<T, 3, LM_KERNEL_GAUSS, false>(a, pl, st);
+    const bool cut = a.box_s != nullptr;
+    if (dim == 2)
+        return kernel == LM_KERNEL_CONON ? launch_pair_k<T, 2, LM_KERNEL_CONON>(force, cut, a, pl, st)
+                                         : launch_pair_k<T, 2, LM_KERNEL_GAUSS>(force, cut, a, pl, st);
+    return kernel == LM_KERNEL_CONON ? launch_pair_k<T, 3, LM_KERNEL_CONON>(force, cut, a, pl, st)
+                                     : launch_pair_k<T, 3, LM_KERNEL_GAUSS>(force, cut, a, pl, st);
 }
 
 template hipError_t launch_pair<double>(int, int, bool, const PairArgs<double>&, const PairPlan&, hipStream_t);
@@ -623,6 +859,83 @@ hipError_t launch_convert(TO* y, const TI* x, int64_t m, hipStream_t st)
 }
 
 template hipError_t launch_convert<float, double>(float*, const double*, int64_t, hipStream_t);
+
+int64_t tiles_of(int64_t n) { return (n + kTile - 1) / kTile; }
+
+template <class T>
+hipError_t launch_tile_boxes(int dim, const T* q, int64_t n, double* box, hipStream_t st)
+{
+    const int64_t nt = tiles_of(n);
+    const unsigned g = (unsigned)((nt + 3) / 4);
+    if (dim == 2)
+        hipLaunchKernelGGL((lm_tile_box_kernel<T, 2>), dim3(g), dim3(256), 0, st, q, n, nt, box);
+    else
+        hipLaunchKernelGGL((lm_tile_box_kernel<T, 3>), dim3(g), dim3(256), 0, st, q, n, nt, box);
+    return hipGetLastError();
+}
+
+template hipError_t launch_tile_boxes<double>(int, const double*, int64_t, double*, hipStream_t);
+template hipError_t launch_tile_boxes<float>(int, const float*, int64_t, double*, hipStream_t);
+
+int64_t sort_pad(int64_t n)
+{
+    int64_t p = 2;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+template <class T>
+hipError_t launch_morton_order(int dim, const T* q, int64_t n, double* box, double* gbox, uint64_t* keys,
+                               int64_t* perm, hipStream_t st)
+{
+    hipError_t e = launch_tile_boxes<T>(dim, q, n, box, st);
+    if (e != hipSuccess) return e;
+    const int64_t nt = tiles_of(n);
+    if (dim == 2)
+        hipLaunchKernelGGL((lm_box_union_kernel<2>), dim3(1), dim3(256), 0, st, (const double*)box, nt, gbox);
+    else
+        hipLaunchKernelGGL((lm_box_union_kernel<3>), dim3(1), dim3(256), 0, st, (const double*)box, nt, gbox);
+    const int64_t npad = sort_pad(n);
+    const unsigned gk = (unsigned)((npad + 255) / 256);
+    if (dim == 2)
+        hipLaunchKernelGGL((lm_morton_kernel<T, 2>), dim3(gk), dim3(256), 0, st, q, n, npad, (const double*)gbox, keys);
+    else
+        hipLaunchKernelGGL((lm_morton_kernel<T, 3>), dim3(gk), dim3(256), 0, st, q, n, npad, (const double*)gbox, keys);
+    const int64_t tile = npad < kSortTile ? npad : kSortTile;
+    hipLaunchKernelGGL(lm_bitonic_tile_kernel, dim3((unsigned)(npad / tile)), dim3(kSortTile / 2), 0, st, keys, npad,
+                       (int64_t)0);
+    for (int64_t k = 2 * tile; k <= npad; k <<= 1) {
+        for (int64_t j = k >> 1; j >= tile; j >>= 1)
+            hipLaunchKernelGGL(lm_bitonic_step_kernel, dim3((unsigned)((npad / 2 + 255) / 256)), dim3(256), 0, st, keys,
+                               npad, k, j);
+        hipLaunchKernelGGL(lm_bitonic_tile_kernel, dim3((unsigned)(npad / tile)), dim3(kSortTile / 2), 0, st, keys,
+                           npad, k);
+    }
+    hipLaunchKernelGGL(lm_perm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const uint64_t*)keys, n,
+                       perm);
+    return hipGetLastError();
+}
+
+template hipError_t launch_morton_order<double>(int, const double*, int64_t, double*, double*, uint64_t*, int64_t*,
+                                                hipStream_t);
+template hipError_t launch_morton_order<float>(int, const float*, int64_t, double*, double*, uint64_t*, int64_t*,
+                                               hipStream_t);
+
+template <class TO, class TI>
+hipError_t launch_permute(TO* out, const TI* in, const int64_t* perm, int64_t n, int dim, bool scatter, hipStream_t st)
+{
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (scatter)
+        hipLaunchKernelGGL((lm_permute_kernel<TO, TI, true>), dim3(g), dim3(256), 0, st, out, in, perm, n, dim);
+    else
+        hipLaunchKernelGGL((lm_permute_kernel<TO, TI, false>), dim3(g), dim3(256), 0, st, out, in, perm, n, dim);
+    return hipGetLastError();
+}
+
+template hipError_t launch_permute<double, double>(double*, const double*, const int64_t*, int64_t, int, bool, hipStream_t);
+template hipError_t launch_permute<float, float>(float*, const float*, const int64_t*, int64_t, int, bool, hipStream_t);
+template hipError_t launch_permute<float, double>(float*, const double*, const int64_t*, int64_t, int, bool, hipStream_t);
+template hipError_t launch_permute<double, float>(double*, const float*, const int64_t*, int64_t, int, bool, hipStream_t);
 template hipError_t launch_convert<double, float>(double*, const float*, int64_t, hipStream_t);
 
 }  // namespace lm

@@ -300,10 +300,116 @@ def test_feedback_step_matches_oracle_iterates():
     p = torch.zeros_like(X)
     resids = []
     for _ in range(3):
-        info = lm.lm_feedback_step(prm, X, Y, p, h=0.8, tol=1e-6, steps=pr.steps)
-        assert info.converged == 0 and info.cg_iters > 0 and info.shoot_ms > 0
+        st, info = lm.lm_feedback_step(prm, X, Y, p, h=0.8, tol=1e-6, steps=pr.steps)
+        assert st == 0 and info.converged == 0 and info.cg_iters > 0 and info.shoot_ms > 0
         resids.append(info.resid_inf)
     ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, pr.steps, max_iter=3)
     assert ref.status == oracle.ENOTCONV and ref.iters == 3
     assert np.allclose(resids, ref.hist[:3], rtol=1e-8, atol=0)
     assert rel_err(host(p), ref.p0) <= 1e-9
+
+
+# ------------------------------------------------------------------ cutoff mode (tile skipping)
+
+
+def _morton_sorted(X):
+    """Reorder a point set spatially (Morton order) so that 64-point tiles are compact."""
+    lo, hi = X.min(axis=1, keepdims=True), X.max(axis=1, keepdims=True)
+    g = np.clip(((X - lo) / (hi - lo) * 1023).astype(np.int64), 0, 1023)
+    key = np.zeros(X.shape[1], dtype=np.int64)
+    for b in range(10):
+        for c in range(X.shape[0]):
+            key |= ((g[c] >> b) & 1) << (X.shape[0] * b + c)
+    return np.argsort(key, kind="stable")
+
+
+def _cutoff_bound(kernel, sigma, rc, p):
+    """Certified bounds on what skipping pairs farther apart than rc can drop, per target:
+    velocity <= G(rc) sum_j |p_j|, force <= |G'(rc)| |p_i| sum_j |p_j| (G and |G'| decrease
+    beyond rc; for the Gaussian that needs rc >= sigma/sqrt 2)."""
+    G = math.exp(-rc / sigma) if kernel == 0 else math.exp(-(rc / sigma) ** 2)
+    dG = G / sigma if kernel == 0 else 2 * rc / sigma ** 2 * G
+    pn = np.sqrt(np.sum(p * p, axis=0))
+    return G * pn.sum(), dG * pn * pn.sum()
+
+
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_rhs_cutoff_at_negligible_radius_meets_exact_parity(kernel, dtype):
+    """Skipping tiles beyond a radius where the kernel is below 1e-16 keeps the exact bar."""
+    pr = inputs.config_sphere3d(20000, kernel=kernel, sigma=0.05)
+    perm = _morton_sorted(pr.X)
+    q, p = rounded(pr.X[:, perm], dtype), rounded(pr.p_bench()[:, perm], dtype)
+    rc = pr.sigma * (36.9 if kernel == 0 else math.sqrt(36.9))
+    dq_o, dp_o = oracle.rhs(q, p, kernel, pr.sigma)
+    prm = lm.make_params(3, kernel, pr.sigma, dtype=dtype, cutoff=rc)
+    qd, pd = dev(q, dtype), dev(p, dtype)
+    dq, dp = torch.empty_like(qd), torch.empty_like(pd)
+    lm.lm_rhs(prm, qd, pd, dq, dp)
+    torch.cuda.synchronize()
+    eq, ep = rel_err(host(dq), dq_o), rel_err(host(dp), dp_o)
+    print("cutoff rc=%.3f kernel=%d dtype=%d: %.2e %.2e" % (rc, kernel, dtype, eq, ep))
+    assert eq <= TOL[dtype] and ep <= TOL[dtype]
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_rhs_cutoff_error_within_certified_bound(kernel):
+    pr = inputs.config_sphere3d(8000, kernel=kernel, sigma=0.05)
+    perm = _morton_sorted(pr.X)
+    q, p = pr.X[:, perm], pr.p_bench()[:, perm]
+    rc = 3.0 * pr.sigma
+    dq_o, dp_o = oracle.rhs(q, p, kernel, pr.sigma)
+    prm = lm.make_params(3, kernel, pr.sigma, cutoff=rc)
+    qd, pd = dev(q), dev(p)
+    dq, dp = torch.empty_like(qd), torch.empty_like(pd)
+    lm.lm_rhs(prm, qd, pd, dq, dp)
+    torch.cuda.synchronize()
+    bv, bf = _cutoff_bound(kernel, pr.sigma, rc, p)
+    errv = np.sqrt(np.sum((host(dq) - dq_o) ** 2, axis=0))
+    errf = np.sqrt(np.sum((host(dp) - dp_o) ** 2, axis=0))
+    slack = 1e-12 * max(np.max(np.abs(dq_o)), np.max(np.abs(dp_o)))
+    print("kernel %d: max err v %.2e (bound %.2e), f %.2e (bound max %.2e)" % (
+        kernel, errv.max(), bv, errf.max(), bf.max()))
+    assert np.all(errv <= bv + slack)
+    assert np.all(errf <= bf + slack)
+    assert errv.max() > 0.0        # something was skipped at this radius
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_shoot_cutoff_reorders_internally_and_matches(kernel):
+    """lm_shoot sorts the points itself in cutoff mode: unsorted input, outputs in the input
+    order, exact parity at a negligible radius."""
+    pr = inputs.config_sphere3d(3000, kernel=kernel, sigma=0.1)
+    q0, p0 = pr.X, pr.p_bench()
+    oq, op = oracle.shoot(q0, p0, kernel, pr.sigma, 8)
+    rc = pr.sigma * (36.9 if kernel == 0 else math.sqrt(36.9))
+    prm = lm.make_params(3, kernel, pr.sigma, cutoff=rc)
+    q, p = dev(q0), dev(p0)
+    q1, p1 = torch.empty_like(q), torch.empty_like(p)
+    lm.lm_shoot(prm, q, p, 1.0, 8, q1, p1)
+    torch.cuda.synchronize()
+    assert rel_err(host(q1), oq) <= 1e-10 and rel_err(host(p1), op) <= 1e-10
+
+
+def test_velocity_cutoff_matches():
+    q, p = inputs.random_state(3000, 2, seed=107, box=2.0)
+    x, _ = inputs.random_state(1000, 2, seed=108, box=2.0)
+    pq, px = _morton_sorted(q), _morton_sorted(x)
+    q, p, x = q[:, pq], p[:, pq], x[:, px]
+    rc = 0.05 * 36.9
+    prm = lm.make_params(2, lm.CONON, 0.05, cutoff=rc)
+    u = torch.empty((2, 1000), dtype=torch.float64, device=DEV)
+    lm.lm_velocity(prm, dev(q), dev(p), dev(x), u)
+    torch.cuda.synchronize()
+    assert rel_err(host(u), oracle.velocity(q, p, x, 0, 0.05)) <= 1e-10
+
+
+def test_feedback_cutoff_matches_exact_iteration():
+    pr = inputs.config_curve2d(1500)
+    rc = pr.sigma * 36.9
+    prm = lm.make_params(2, lm.CONON, pr.sigma, cutoff=rc)
+    p0 = torch.zeros((2, pr.n), dtype=torch.float64, device=DEV)
+    st, info, hist = lm.lm_feedback_match(prm, dev(pr.X), dev(pr.Y), p0, h=0.8, tol=1e-6, steps=20, max_iter=60)
+    ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, 20, max_iter=60)
+    assert st == 0 and ref.status == 0 and info.iters == ref.iters
+    assert rel_err(host(p0), ref.p0) <= 1e-8
