@@ -59,6 +59,14 @@ typedef enum lm_kernel {
 
 typedef enum lm_dtype { LM_F64 = 0, LM_F32 = 1 } lm_dtype;
 
+/* How the K(X) solves of Algorithm 1 are done. */
+typedef enum lm_solver {
+    LM_SOLVE_AUTO = 0,    /* dense when its n x n factor fits in half the free device memory */
+    LM_SOLVE_CG = 1,      /* matrix-free conjugate gradients: O(n) memory, K products on the fly */
+    LM_SOLVE_DENSE = 2    /* Cholesky factor of K(X) + tau I built once (8 n^2 bytes), then two
+                             triangular sweeps per solve */
+} lm_solver;
+
 /* Model parameters shared by every entry point. */
 typedef struct lm_params {
     int32_t dim;      /* spatial dimension: 2 or 3 */
@@ -94,7 +102,7 @@ typedef struct lm_match_opts {
     double cg_rtol;       /* relative residual of each K-solve; 0 = 1e-13 */
     double *resid_hist;   /* HOST, nullable: receives the residual of each shoot */
     int32_t hist_len;     /* capacity of resid_hist */
-    int32_t reserved;
+    int32_t solver;       /* K-solve: LM_SOLVE_AUTO, LM_SOLVE_CG or LM_SOLVE_DENSE */
 } lm_match_opts;
 
 /* What a feedback match reports (HOST struct). */
@@ -131,13 +139,16 @@ lm_status lm_hamiltonian(const lm_params *params, int64_t n, const void *q, cons
 
 /* Solves (K(X) + tau I) x = b for every component c, with K_ij = G(|X_i - X_j|): the
  * conversion of a velocity field u at the landmarks into momenta p (Algorithm 1, step 4,
- * read as p = K(X)^{-1} u).  Matrix-free conjugate gradients, every product computed on
- * the fly on the GPU.  X, b, x: double (dim, n); x may alias b.  Stops when
- * ||b_c - K x_c||_2 <= rtol ||b_c||_2 for every c.  *iters_out (HOST, nullable) receives
- * the iteration count.  Synchronous.  LM_ESINGULAR if a curvature p.Kp <= 0 appears,
- * LM_ENOTCONV if max_iter is reached (x then holds the last iterate). */
+ * read as p = K(X)^{-1} u).  solver: LM_SOLVE_CG (matrix-free conjugate gradients, stops when
+ * ||b_c - K x_c||_2 <= rtol ||b_c||_2 for every c or after max_iter iterations), LM_SOLVE_DENSE
+ * (Cholesky factor, rtol and max_iter unused) or LM_SOLVE_AUTO.  X, b, x: double (dim, n);
+ * x may alias b.  *iters_out (HOST, nullable) receives the CG iteration count (0 for dense).
+ * cutoff is ignored: every pair enters K.  Synchronous.  LM_ESINGULAR if K is not
+ * numerically positive definite (a CG curvature p.Kp <= 0 or a non-positive Cholesky
+ * pivot); LM_ENOTCONV if CG reaches max_iter (x then holds the last iterate); LM_ENOMEM if
+ * a forced dense factor does not fit. */
 lm_status lm_ksolve(const lm_params *params, int64_t n, const double *X, const double *b,
-                    double *x, double rtol, int32_t max_iter, int32_t *iters_out,
+                    double *x, double rtol, int32_t max_iter, int32_t solver, int32_t *iters_out,
                     void *stream);
 
 /* Algorithm 1 (feedback-control iteration) with M = h I:
@@ -146,7 +157,8 @@ lm_status lm_ksolve(const lm_params *params, int64_t n, const double *X, const d
  * X, Y: double (dim, n).  p0: double (dim, n), in: initial momenta (zeros in the paper),
  * out: the final momenta.  q1 (nullable): double (dim, n), receives q(1) of the last
  * shoot.  info: HOST.  params->dtype = LM_F32 shoots in single precision while the
- * momenta, the residual and the K-solves stay in double.  Synchronous.
+ * momenta, the residual and the K-solves stay in double.  opts->solver picks the K-solve;
+ * a dense factor is built once per call (K(X) is fixed during a match).  Synchronous.
  * Returns LM_OK, LM_ENOTCONV, LM_EDIVERGED (non-finite residual, as the paper's NaN for
  * h > 1) or LM_ESINGULAR; in every case p0 and info describe the last iterate. */
 lm_status lm_feedback_match(const lm_params *params, const lm_match_opts *opts, int64_t n,

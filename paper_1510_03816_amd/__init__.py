@@ -6,7 +6,7 @@ there is no CPU path.
 """
 
 from ._lib import (  # noqa: F401
-    CONON, GAUSS, F64, F32, EXPORTS, LmError, STATUS_NAMES,
+    CONON, GAUSS, F64, F32, SOLVE_AUTO, SOLVE_CG, SOLVE_DENSE, EXPORTS, LmError, STATUS_NAMES,
     LM_OK, LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_ENOTCONV, LM_EDIVERGED, LM_ESINGULAR, LM_EUNSUPPORTED,
     lm_params, lm_match_opts, lm_match_info, lm_step_info, make_params, last_error, load,
     lm_rhs, lm_shoot, lm_hamiltonian, lm_ksolve, lm_feedback_match, lm_feedback_step, lm_velocity,

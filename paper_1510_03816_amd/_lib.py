@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "LM_OK", -1: "LM_EINVAL", -2: "LM_ENOMEM", -3: "LM_EHIP", -4:
                 -5: "LM_EDIVERGED", -6: "LM_ESINGULAR", -7: "LM_EUNSUPPORTED"}
 CONON, GAUSS = 0, 1
 F64, F32 = 0, 1
+SOLVE_AUTO, SOLVE_CG, SOLVE_DENSE = 0, 1, 2
 
 # every symbol include/liblm.h declares
 EXPORTS = ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
@@ -41,7 +42,7 @@ class lm_match_opts(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("steps", ctypes.c_int32), ("stop_rule", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32),
                 ("cg_rtol", ctypes.c_double), ("resid_hist", ctypes.POINTER(ctypes.c_double)),
-                ("hist_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("hist_len", ctypes.c_int32), ("solver", ctypes.c_int32)]
 
 
 class lm_match_info(ctypes.Structure):
@@ -70,7 +71,7 @@ def load():
         L.lm_rhs.argtypes = [PP, i64, P, P, P, P, P]
         L.lm_shoot.argtypes = [PP, i64, P, P, d, i32, P, P, P]
         L.lm_hamiltonian.argtypes = [PP, i64, P, P, ctypes.POINTER(d), P]
-        L.lm_ksolve.argtypes = [PP, i64, P, P, P, d, i32, ctypes.POINTER(i32), P]
+        L.lm_ksolve.argtypes = [PP, i64, P, P, P, d, i32, i32, ctypes.POINTER(i32), P]
         L.lm_feedback_match.argtypes = [PP, ctypes.POINTER(lm_match_opts), i64, P, P, P, P,
                                         ctypes.POINTER(lm_match_info), P]
         L.lm_feedback_step.argtypes = [PP, ctypes.POINTER(lm_match_opts), i64, P, P, P, P,
@@ -152,20 +153,23 @@ def lm_hamiltonian(params: lm_params, q, p, stream=None) -> float:
     return H.value
 
 
-def lm_ksolve(params: lm_params, X, b, x, rtol: float = 1e-13, max_iter: int = 0, stream=None) -> int:
+def lm_ksolve(params: lm_params, X, b, x, rtol: float = 1e-13, max_iter: int = 0, solver: int = SOLVE_AUTO,
+              stream=None) -> int:
+    """Solves (K(X) + tau I) x = b per component; returns the CG iteration count (0 if dense)."""
     dim, n = X.shape
     for t, nm in [(X, "X"), (b, "b"), (x, "x")]:
         _check_tensor(t, params.dim, n, F64, nm)
     it = ctypes.c_int32(0)
-    mi = int(max_iter) if max_iter > 0 else 20 * n + 100
-    _check(load().lm_ksolve(ctypes.byref(params), n, _ptr(X), _ptr(b), _ptr(x), float(rtol), mi,
+    mi = int(max_iter) if max_iter > 0 else min(20 * n + 100, 10000)
+    _check(load().lm_ksolve(ctypes.byref(params), n, _ptr(X), _ptr(b), _ptr(x), float(rtol), mi, int(solver),
                             ctypes.byref(it), _stream(stream)))
     return it.value
 
 
 def lm_feedback_match(params: lm_params, X, Y, p0, h: float, tol: float, steps: int, max_iter: int = 500,
                       q1=None, stop_rule: int = 0, cg_rtol: float = 0.0, cg_max_iter: int = 0,
-                      hist_len: int = 1024, stream=None, raise_on=(LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_EUNSUPPORTED)):
+                      hist_len: int = 1024, solver: int = SOLVE_AUTO, stream=None,
+                      raise_on=(LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_EUNSUPPORTED)):
     """Runs Algorithm 1 in place on p0.  Returns (status, info, residual history).
 
     Statuses describing the iteration itself (not converged, diverged, singular K) are
@@ -176,7 +180,7 @@ def lm_feedback_match(params: lm_params, X, Y, p0, h: float, tol: float, steps: 
         _check_tensor(t, params.dim, n, F64, nm)
     hist = (ctypes.c_double * max(1, hist_len))()
     o = lm_match_opts(float(h), float(tol), int(max_iter), int(steps), int(stop_rule), int(cg_max_iter),
-                      float(cg_rtol), ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(hist_len), 0)
+                      float(cg_rtol), ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(hist_len), int(solver))
     info = lm_match_info()
     st = load().lm_feedback_match(ctypes.byref(params), ctypes.byref(o), n, _ptr(X), _ptr(Y), _ptr(p0),
                                   _ptr(q1), ctypes.byref(info), _stream(stream))
@@ -187,7 +191,7 @@ def lm_feedback_match(params: lm_params, X, Y, p0, h: float, tol: float, steps: 
 
 
 def lm_feedback_step(params: lm_params, X, Y, p, h: float, tol: float, steps: int, q1=None,
-                     cg_rtol: float = 0.0, cg_max_iter: int = 0, stream=None,
+                     cg_rtol: float = 0.0, cg_max_iter: int = 0, solver: int = SOLVE_CG, stream=None,
                      raise_on=(LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_EUNSUPPORTED)):
     """One iteration of Algorithm 1 on p (in place).  Returns (status, lm_step_info).
 
@@ -197,7 +201,7 @@ def lm_feedback_step(params: lm_params, X, Y, p, h: float, tol: float, steps: in
     dim, n = X.shape
     for t, nm in [(X, "X"), (Y, "Y"), (p, "p")] + ([(q1, "q1")] if q1 is not None else []):
         _check_tensor(t, params.dim, n, F64, nm)
-    o = lm_match_opts(float(h), float(tol), 0, int(steps), 0, int(cg_max_iter), float(cg_rtol), None, 0, 0)
+    o = lm_match_opts(float(h), float(tol), 0, int(steps), 0, int(cg_max_iter), float(cg_rtol), None, 0, int(solver))
     info = lm_step_info()
     st = load().lm_feedback_step(ctypes.byref(params), ctypes.byref(o), n, _ptr(X), _ptr(Y), _ptr(p), _ptr(q1),
                                  ctypes.byref(info), _stream(stream))

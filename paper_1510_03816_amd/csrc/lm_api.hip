@@ -384,6 +384,65 @@ lm_status ksolve_impl(const lm_params* prm, int64_t n, const double* X, const do
     return LM_OK;
 }
 
+// Dense Cholesky factor of K(X) + tau I (see lm_dense.hip).
+struct DenseFactor {
+    double* L = nullptr;
+    double* Linv = nullptr;
+    int* info = nullptr;
+    int64_t n = 0;
+};
+
+// Whether the dense factor of an n-point problem fits in half the free device memory.
+bool dense_fits(int64_t n)
+{
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return false;
+    const double need = 8.0 * (double)n * (double)n + 8.0 * (double)lm::dense_linv_elems(n);
+    return need <= 0.5 * (double)freeb;
+}
+
+lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspace& ws, DenseFactor* f,
+                       hipStream_t st)
+{
+    f->n = n;
+    LM_TRY(ws.get(&f->L, n * n));
+    LM_TRY(ws.get(&f->Linv, lm::dense_linv_elems(n)));
+    LM_TRY(ws.get(&f->info, 1));
+    double kq, wscale;
+    kernel_scales(prm, false, &kq, &wscale);
+    LM_HIP(lm::launch_dense_factor(prm->dim, prm->kernel, kq, prm->tau, X, n, f->L, f->Linv, f->info, st));
+    int info = 0;
+    LM_HIP(hipMemcpyAsync(&info, f->info, sizeof(int), hipMemcpyDeviceToHost, st));
+    LM_HIP(hipStreamSynchronize(st));
+    if (info != 0)
+        return fail(LM_ESINGULAR, "K(X) is not numerically positive definite (Cholesky pivot %d)", info);
+    return LM_OK;
+}
+
+// x = (K + tau I)^{-1} b with the dense factor (x may alias b).
+lm_status dense_solve(const DenseFactor& f, int dim, const double* b, double* x, hipStream_t st)
+{
+    if (x != b) LM_HIP(hipMemcpyAsync(x, b, (size_t)dim * f.n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(lm::launch_dense_solve(f.L, f.Linv, f.n, dim, x, st));
+    return LM_OK;
+}
+
+// Resolves LM_SOLVE_AUTO.
+lm_status pick_solver(int32_t solver, int64_t n, bool* dense)
+{
+    if (solver == LM_SOLVE_CG) {
+        *dense = false;
+    } else if (solver == LM_SOLVE_DENSE) {
+        if (!dense_fits(n)) return fail(LM_ENOMEM, "dense K factor of n = %lld does not fit", (long long)n);
+        *dense = true;
+    } else if (solver == LM_SOLVE_AUTO) {
+        *dense = dense_fits(n);
+    } else {
+        return fail(LM_EINVAL, "unknown solver %d", solver);
+    }
+    return LM_OK;
+}
+
 // Right-hand side in the caller's order; in cutoff mode the tiles are 64 consecutive points
 // of that order.
 template <class T>
@@ -445,6 +504,7 @@ lm_status check_match_args(const lm_match_opts* o, const double* X, const double
     if (o->stop_rule != 0 && o->stop_rule != 1) return fail(LM_EINVAL, "stop_rule must be 0 or 1");
     if (o->cg_max_iter < 0 || !(o->cg_rtol >= 0.0)) return fail(LM_EINVAL, "bad CG settings");
     if (o->hist_len < 0 || (o->hist_len > 0 && !o->resid_hist)) return fail(LM_EINVAL, "bad history buffer");
+    if (o->solver < LM_SOLVE_AUTO || o->solver > LM_SOLVE_DENSE) return fail(LM_EINVAL, "unknown solver %d", o->solver);
     return LM_OK;
 }
 
@@ -456,6 +516,8 @@ struct FeedbackWork {
     float *qf = nullptr, *pf = nullptr, *aqf = nullptr, *apf = nullptr, *bqf = nullptr, *bpf = nullptr,
           *cqf = nullptr, *cpf = nullptr;
     double* q1 = nullptr;     // q(1) in the caller's order (== qd unless the shoot is reordered)
+    bool dense = false;       // K-solves with the dense factor (else CG)
+    DenseFactor fac;
     bool ordered = false;     // cutoff mode: shoots run in the Morton order of X
     Ordering ord;
     CgBuffers cg;
@@ -496,6 +558,15 @@ struct FeedbackWork {
         }
         if (!ordered) q1 = qd;
         return cg_alloc(ws, prm, n, &cg);
+    }
+
+    // Factor K(X) once when the dense solver is chosen.
+    lm_status prepare_solver(Workspace& ws, const lm_params* prm, const lm_match_opts* o, int64_t n,
+                             const double* X, hipStream_t st)
+    {
+        LM_TRY(pick_solver(o->solver, n, &dense));
+        if (dense) LM_TRY(dense_factor(prm, n, X, ws, &fac, st));
+        return LM_OK;
     }
 };
 
@@ -553,7 +624,12 @@ lm_status feedback_update(const lm_params* prm, const lm_match_opts* o, int64_t 
     const int64_t cgdef = 20 * n + 100 < 10000 ? 20 * n + 100 : 10000;
     const int32_t cg_max = o->cg_max_iter > 0 ? o->cg_max_iter : (int32_t)cgdef;
     LM_HIP(lm::launch_sub(w.e, Y, w.q1, m, st));
-    LM_TRY(ksolve_impl(prm, n, X, w.e, w.delta, cg_rtol, cg_max, cg_iters, w.cg, w.part, st));
+    if (w.dense) {
+        *cg_iters = 0;
+        LM_TRY(dense_solve(w.fac, prm->dim, w.e, w.delta, st));
+    } else {
+        LM_TRY(ksolve_impl(prm, n, X, w.e, w.delta, cg_rtol, cg_max, cg_iters, w.cg, w.part, st));
+    }
     LM_HIP(lm::launch_axpy(p, p, o->h, w.delta, m, st));
     return LM_OK;
 }
@@ -617,15 +693,25 @@ lm_status lm_hamiltonian(const lm_params* prm, int64_t n, const void* q, const v
 }
 
 lm_status lm_ksolve(const lm_params* prm, int64_t n, const double* X, const double* b, double* x, double rtol,
-                    int32_t max_iter, int32_t* iters_out, void* stream)
+                    int32_t max_iter, int32_t solver, int32_t* iters_out, void* stream)
 {
     LM_TRY(check_params(prm));
     LM_TRY(check_n(n));
     if (!X || !b || !x) return fail(LM_EINVAL, "NULL buffer");
+    hipStream_t st = (hipStream_t)stream;
+    bool dense = false;
+    LM_TRY(pick_solver(solver, n, &dense));
+    Workspace ws(st);
+    if (iters_out) *iters_out = 0;
+    if (dense) {
+        DenseFactor f;
+        LM_TRY(dense_factor(prm, n, X, ws, &f, st));
+        LM_TRY(dense_solve(f, prm->dim, b, x, st));
+        LM_HIP(hipStreamSynchronize(st));
+        return LM_OK;
+    }
     if (!(rtol > 0.0) || !is_finite(rtol)) return fail(LM_EINVAL, "rtol must be positive");
     if (max_iter < 1) return fail(LM_EINVAL, "max_iter must be >= 1");
-    hipStream_t st = (hipStream_t)stream;
-    Workspace ws(st);
     CgBuffers cg;
     double* part;
     LM_TRY(cg_alloc(ws, prm, n, &cg));
@@ -645,6 +731,7 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
     Workspace ws(st);
     FeedbackWork w;
     LM_TRY(w.alloc(ws, prm, n, X, st));
+    LM_TRY(w.prepare_solver(ws, prm, o, n, X, st));
 
     lm_status result = LM_OK;
     double r = 0.0, prev_step = INFINITY;
@@ -694,6 +781,7 @@ lm_status lm_feedback_step(const lm_params* prm, const lm_match_opts* o, int64_t
     Workspace ws(st);
     FeedbackWork w;
     LM_TRY(w.alloc(ws, prm, n, X, st));
+    LM_TRY(w.prepare_solver(ws, prm, o, n, X, st));
     EventTimer timer;
     LM_TRY(timer.init());
     LM_HIP(hipEventRecord(timer.ev[0], st));

@@ -78,6 +78,15 @@ hipError_t launch_sub(double* y, const double* x, const double* z, int64_t m, hi
 template <class TO, class TI>
 hipError_t launch_convert(TO* y, const TI* x, int64_t m, hipStream_t st);
 
+// Dense K(X) = L L^T (lower triangle of a row-major n x n buffer) with the inverses of the
+// 128 x 128 diagonal blocks (dense_linv_elems doubles); *info != 0 flags a non-positive pivot.
+int dense_panels(int64_t n);
+int64_t dense_linv_elems(int64_t n);
+hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,
+                               double* Linv, int* info, hipStream_t st);
+// y <- (L L^T)^{-1} y for dim component vectors, in place.
+hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, int dim, double* y, hipStream_t st);
+
 int64_t tiles_of(int64_t n);     // 64-point tiles covering n points
 int64_t sort_pad(int64_t n);     // power of two >= max(n, 2)
 

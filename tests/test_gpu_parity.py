@@ -224,9 +224,13 @@ def test_ksolve_matches_cholesky(name, make):
     want = np.stack([oracle.cholesky_solve(L, b[c]) for c in range(X.shape[0])])
     prm = lm.make_params(X.shape[0], pr.kernel, pr.sigma)
     x = torch.empty((X.shape[0], X.shape[1]), dtype=torch.float64, device=DEV)
-    it = lm.lm_ksolve(prm, dev(X), dev(b), x, rtol=1e-13)
+    it = lm.lm_ksolve(prm, dev(X), dev(b), x, rtol=1e-13, solver=lm.SOLVE_CG)
     print("%s: %d CG iterations, rel err %.2e" % (name, it, rel_err(host(x), want)))
     assert rel_err(host(x), want) <= 1e-8
+    xd = torch.empty_like(x)
+    assert lm.lm_ksolve(prm, dev(X), dev(b), xd, solver=lm.SOLVE_DENSE) == 0
+    print("%s: dense rel err %.2e" % (name, rel_err(host(xd), want)))
+    assert rel_err(host(xd), want) <= 1e-9
 
 
 # ------------------------------------------------------------------ feedback matching
@@ -413,3 +417,49 @@ def test_feedback_cutoff_matches_exact_iteration():
     ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, 20, max_iter=60)
     assert st == 0 and ref.status == 0 and info.iters == ref.iters
     assert rel_err(host(p0), ref.p0) <= 1e-8
+
+
+@pytest.mark.parametrize("n,dim,kernel,sigma,tau", [
+    (1, 2, 0, 0.5, 0.0), (127, 2, 0, 0.5, 0.0), (128, 3, 1, 0.4, 0.0), (129, 2, 0, 0.2, 0.3),
+    (333, 3, 0, 0.3, 0.0), (1000, 2, 0, 0.1, 0.0), (2500, 3, 0, 0.15, 0.1),
+])
+def test_dense_ksolve_matches_cholesky(n, dim, kernel, sigma, tau):
+    """Blocked GPU Cholesky (MFMA trailing updates) against the oracle's textbook Cholesky,
+    across panel boundaries and ragged tails."""
+    X = inputs.fibonacci_sphere(n) if dim == 3 else inputs.config_curve2d(n).X
+    b = np.random.default_rng([109, n]).standard_normal(X.shape)
+    K = oracle.kmatrix(X, kernel, sigma) + tau * np.eye(n)
+    st, L = oracle.cholesky(K)
+    assert st == 0
+    want = np.stack([oracle.cholesky_solve(L, b[c]) for c in range(dim)])
+    prm = lm.make_params(dim, kernel, sigma, tau=tau)
+    x = dev(b)
+    lm.lm_ksolve(prm, dev(X), x, x, solver=lm.SOLVE_DENSE)       # in place
+    cond = np.linalg.cond(K) if n <= 1000 else 1e4
+    err = rel_err(host(x), want)
+    print("n=%d cond %.1e dense rel err %.2e" % (n, cond, err))
+    assert err <= max(1e-12, 1e-15 * cond)
+
+
+def test_dense_ksolve_reports_singular_kernel_matrix():
+    X = np.zeros((2, 300))          # every point at the origin: K is the all-ones matrix
+    X[0, :] = np.linspace(0, 1e-9, 300)
+    prm = lm.make_params(2, lm.GAUSS, 1.0)
+    x = torch.empty((2, 300), dtype=torch.float64, device=DEV)
+    with pytest.raises(lm.LmError) as e:
+        lm.lm_ksolve(prm, dev(X), dev(np.ones((2, 300))), x, solver=lm.SOLVE_DENSE)
+    assert e.value.status == lm.LM_ESINGULAR
+
+
+def test_feedback_with_cg_solver_matches_dense():
+    pr = inputs.config_circle_ellipse(64)
+    prm = lm.make_params(2, lm.CONON, pr.sigma)
+    out = {}
+    for solver in (lm.SOLVE_CG, lm.SOLVE_DENSE):
+        p0 = torch.zeros((2, 64), dtype=torch.float64, device=DEV)
+        st, info, hist = lm.lm_feedback_match(prm, dev(pr.X), dev(pr.Y), p0, h=0.8, tol=1e-6, steps=pr.steps,
+                                              solver=solver)
+        assert st == 0
+        out[solver] = (info.iters, host(p0))
+    assert out[lm.SOLVE_CG][0] == out[lm.SOLVE_DENSE][0]
+    assert rel_err(out[lm.SOLVE_CG][1], out[lm.SOLVE_DENSE][1]) <= 1e-9
