@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark: pair-interactions/s of RK4 shooting inside the feedback-control iteration.
+"""Benchmark: pair-interactions/s of RK4 shooting and time-to-match of the feedback iteration.
 
-A step is one iteration of Algorithm 1 on the workload, through the C ABI
-(lm_feedback_step): an RK4 shoot of the N-particle system (every stage one pass of the
-O(N^2) pair sums with the stage bookkeeping fused in), the max-norm residual, and the
-momentum update p <- p + h K(X)^{-1} e by matrix-free conjugate gradients.  The timed
-steps are iterations W+1 .. W+K from p = 0 (the paper's initial guess).
+A step is one whole match through the C ABI (lm_feedback_match): Algorithm 1 from p = 0 (the
+paper's initial guess) until max|q(1) - Y| < 1e-6 -- the factorisation of K(X) once, then
+per iteration an RK4 shoot of the N-particle system (every stage one pass of the O(N^2)
+pair sums, the stage bookkeeping fused in), the max-norm residual and the momentum update
+p <- p + h K(X)^{-1} e.  Every row of the hot path runs inside the timed region.
 
-value = shooting pair interactions (4 * rk4_steps * N^2 per step) / wall time of the K
-steps -- the K-solve and residual count against it.  Beside it: the dominant kernel's
-roofline (its average launch time measured live with HIP events inside the library, on
-the stream it runs on), the time to match a full problem to max|q(1) - Y| < 1e-6, and the
-FP64 oracle timed on the host cores on a bounded sample.
+value       = shooting pair interactions of the step (shoots * 4 * rk4_steps * N^2) / its
+              wall time (factorisation, solves and residuals count against it)
+ms_per_step = time to match.
+Beside them: the dominant kernel's roofline (its average launch time measured live with HIP
+events on the stream it runs on, inside the library), a second time-to-match on the 2-D
+curve workload, and the FP64 oracle timed on the host cores on a bounded sample.
 
 Default workload: 65536 Fibonacci-sphere landmarks in 3-D, conical kernel sigma = 0.05,
-100 RK4 steps on [0, 1], FP64; target = the template moved by a seeded smooth field.
+100 RK4 steps on [0, 1], FP64, h = 0.8; the target is the template moved by a seeded smooth
+field.  --mode iteration times single feedback iterations (lm_feedback_step, CG K-solve)
+instead, for workloads whose kernel matrix is singular (the Gaussian at these widths).
 """
 
 from __future__ import annotations
@@ -39,16 +42,16 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 PEAK_TFLOPS = 2.0 * PEAK_SLOTS / 1e12
 
 WORKLOADS = {
-    # name: (generator kwargs, dtype)
+    # name: (generator kwargs, dtype); eps = kernel value at the tile-skipping radius
     "sphere3d_conon_f64": (dict(kind="sphere3d", n=65536, kernel=0, sigma=0.05, steps=100), 0),
     "sphere3d_conon_f32": (dict(kind="sphere3d", n=65536, kernel=0, sigma=0.05, steps=100), 1),
     "sphere3d_gauss_f64": (dict(kind="sphere3d", n=65536, kernel=1, sigma=0.05, steps=100), 0),
-    # tile skipping at the radius where the kernel falls below eps (all-pairs-equivalent rate)
     "sphere3d_gauss_f64_cut": (dict(kind="sphere3d", n=65536, kernel=1, sigma=0.05, steps=100, eps=1e-16), 0),
     "sphere3d_conon_f64_cut": (dict(kind="sphere3d", n=65536, kernel=0, sigma=0.05, steps=100, eps=1e-16), 0),
     "sphere3d_conon_f32_cut": (dict(kind="sphere3d", n=65536, kernel=0, sigma=0.05, steps=100, eps=1e-10), 1),
     "curve2d_conon_f64": (dict(kind="curve2d", n=4096, kernel=0, sigma=0.1, steps=200), 0),
     "curve2d_conon_f32": (dict(kind="curve2d", n=4096, kernel=0, sigma=0.1, steps=200), 1),
+    "circle_ellipse_f64": (dict(kind="circle_ellipse", n=64, kernel=0, sigma=0.5, steps=100), 0),
 }
 
 
@@ -56,6 +59,8 @@ def make_problem(spec):
     import inputs
     if spec["kind"] == "sphere3d":
         return inputs.config_sphere3d(spec["n"], kernel=spec["kernel"], sigma=spec["sigma"], steps=spec["steps"])
+    if spec["kind"] == "circle_ellipse":
+        return inputs.config_circle_ellipse(spec["n"])
     return inputs.config_curve2d(spec["n"], kernel=spec["kernel"], sigma=spec["sigma"], steps=spec["steps"])
 
 
@@ -90,18 +95,28 @@ def cpu_baseline(pr, target_s: float):
                       % (rows, n, n, dt)}
 
 
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed feedback iterations")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed feedback iterations before")
+    ap.add_argument("--steps", type=int, default=1, help="timed steps (whole matches)")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed steps before")
     ap.add_argument("--workload", default="sphere3d_conon_f64", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="match", choices=["match", "iteration"])
     ap.add_argument("--h", type=float, default=0.8, help="search length of Algorithm 1")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iter", type=int, default=100)
+    ap.add_argument("--solver", type=int, default=0, help="0 auto (dense if it fits), 1 CG, 2 dense")
+    ap.add_argument("--cg-max-iter", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--cg-max-iter", type=int, default=2000, help="CG iterations per K-solve")
     ap.add_argument("--match", default="curve2d_conon_f64", choices=sorted(WORKLOADS) + ["none"],
-                    help="workload of the time-to-match measurement (full match from p = 0 to 1e-6)")
+                    help="second time-to-match measurement (untimed for value)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -109,64 +124,89 @@ def main():
               "all-gather of (q, p) per RK stage, which is not built here. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1510_03816_amd as lm
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    spec, dtype = WORKLOADS[args.workload]
-    pr = make_problem(spec)
-    n, dim = pr.n, pr.dim
-    rc = cutoff_radius(spec)
-    prm = lm.make_params(dim, pr.kernel, pr.sigma, dtype=dtype, cutoff=rc)
-    X = torch.tensor(pr.X, device=dev)
-    Y = torch.tensor(pr.Y, device=dev)
-    p = torch.zeros_like(X)
-    pairs_per_step = 4 * pr.steps * n * n
-    print("workload %s: N=%d dim=%d kernel=%s sigma=%g rk4_steps=%d dtype=%s cutoff=%g" % (
-        args.workload, n, dim, "conon" if pr.kernel == 0 else "gauss", pr.sigma, pr.steps,
-        "f64" if dtype == 0 else "f32", rc), file=sys.stderr, flush=True)
 
-    statuses = []
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * 131072, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read, %d MiB written" % (args.calibrate_copy, args.calibrate_copy))
+        del src, dst
+
+    def setup(name):
+        spec, dtype = WORKLOADS[name]
+        pr = make_problem(spec)
+        rc = cutoff_radius(spec)
+        prm = lm.make_params(pr.dim, pr.kernel, pr.sigma, dtype=dtype, cutoff=rc)
+        X = torch.tensor(pr.X, device=dev)
+        Y = torch.tensor(pr.Y, device=dev)
+        return pr, dtype, rc, prm, X, Y
+
+    def run_match(prm, pr, X, Y):
+        p = torch.zeros_like(X)
+        return lm.lm_feedback_match(prm, X, Y, p, h=args.h, tol=args.tol, steps=pr.steps,
+                                    max_iter=args.max_iter, cg_max_iter=args.cg_max_iter, solver=args.solver)
+
+    pr, dtype, rc, prm, X, Y = setup(args.workload)
+    n, dim = pr.n, pr.dim
+    pairs_per_shoot = 4 * pr.steps * n * n
+    log("workload %s: N=%d dim=%d kernel=%s sigma=%g rk4_steps=%d dtype=%s cutoff=%g mode=%s" % (
+        args.workload, n, dim, "conon" if pr.kernel == 0 else "gauss", pr.sigma, pr.steps,
+        "f64" if dtype == 0 else "f32", rc, args.mode))
+
+    p_iter = torch.zeros_like(X)
 
     def step():
-        st, info = lm.lm_feedback_step(prm, X, Y, p, h=args.h, tol=1e-6, steps=pr.steps, cg_max_iter=args.cg_max_iter)
-        if st != lm.LM_OK:
-            # e.g. the Gaussian kernel matrix is numerically singular at these widths: the
-            # shoot is timed all the same, the failed update is reported
-            statuses.append(lm.STATUS_NAMES[st])
-            print("step status %s: %s" % (lm.STATUS_NAMES[st], lm.last_error()), file=sys.stderr, flush=True)
-        return info
+        """Returns (shoots, shoot_ms, solve_ms, factor_ms, record)."""
+        if args.mode == "match":
+            st, info, hist = run_match(prm, pr, X, Y)
+            rec = {"status": lm.STATUS_NAMES[st], "iters": info.iters, "resid_inf": info.resid_inf,
+                   "cg_iters": info.cg_iters, "factor_ms": info.factor_ms, "shoot_ms": info.shoot_ms,
+                   "solve_ms": info.solve_ms, "paper_H_2H": 2 * info.H}
+            log("match: %s %d iterations, resid %.3e, factor %.0f ms, shoots %.0f ms, solves %.0f ms" % (
+                rec["status"], info.iters, info.resid_inf, info.factor_ms, info.shoot_ms, info.solve_ms))
+            return info.iters + 1, info.shoot_ms, info.solve_ms, info.factor_ms, rec
+        st, info = lm.lm_feedback_step(prm, X, Y, p_iter, h=args.h, tol=args.tol, steps=pr.steps,
+                                       cg_max_iter=args.cg_max_iter, solver=lm.SOLVE_CG)
+        rec = {"status": lm.STATUS_NAMES[st], "resid_inf": info.resid_inf, "cg_iters": info.cg_iters,
+               "shoot_ms": info.shoot_ms, "solve_ms": info.solve_ms}
+        log("iteration: %s resid %.3e shoot %.0f ms solve %.0f ms (%d CG)" % (
+            rec["status"], info.resid_inf, info.shoot_ms, info.solve_ms, info.cg_iters))
+        return 1, info.shoot_ms, info.solve_ms, 0.0, rec
 
-    for w in range(args.warmup):
-        info = step()
-        print("warmup %d: resid %.3e shoot %.1f ms solve %.1f ms (%d CG)" % (
-            w, info.resid_inf, info.shoot_ms, info.solve_ms, info.cg_iters), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    p_iter.zero_()
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    shoot_ms, solve_ms, cg_iters, resids = [], [], 0, []
-    for k in range(args.steps):
-        info = step()
-        shoot_ms.append(info.shoot_ms)
-        solve_ms.append(info.solve_ms)
-        cg_iters += info.cg_iters
-        resids.append(info.resid_inf)
-        print("step %d: resid %.3e shoot %.1f ms solve %.1f ms (%d CG)" % (
-            k, info.resid_inf, info.shoot_ms, info.solve_ms, info.cg_iters), file=sys.stderr, flush=True)
+    shoots = 0
+    shoot_ms = solve_ms = factor_ms = 0.0
+    records = []
+    for _ in range(args.steps):
+        s, a, b, c, rec = step()
+        shoots += s
+        shoot_ms += a
+        solve_ms += b
+        factor_ms += c
+        records.append(rec)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    value = pairs_per_step * args.steps / elapsed
-    # dominant kernel: the pair-sum kernel, one launch per RK stage (4 * rk4_steps per shoot)
-    launch_ms = float(np.mean(shoot_ms)) / (4 * pr.steps)
+    value = pairs_per_shoot * shoots / elapsed
+    # dominant kernel: the pair-sum kernel, one launch per RK stage
+    launch_ms = shoot_ms / (shoots * 4 * pr.steps)
     slots = SLOTS_PER_PAIR[(dim, pr.kernel)]
     achieved = n * n * slots * 2.0 / (launch_ms * 1e-3) / 1e12
     if rc > 0.0:
-        # with tile skipping the pairs actually evaluated are not counted here: the figures
-        # below are all-pairs equivalents and can exceed the peak
+        # with tile skipping the pairs evaluated are fewer than N^2: not a roofline figure
         achieved = None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": (achieved / PEAK_TFLOPS) if achieved else None, "traffic": None,
@@ -176,22 +216,23 @@ def main():
                 "pairs_per_s_in_kernel": n * n / (launch_ms * 1e-3)}
 
     ttm = None
-    if args.match != "none":
-        mspec, mdtype = WORKLOADS[args.match]
-        mp = make_problem(mspec)
-        mprm = lm.make_params(mp.dim, mp.kernel, mp.sigma, dtype=mdtype)
-        MX, MY = torch.tensor(mp.X, device=dev), torch.tensor(mp.Y, device=dev)
-        mp0 = torch.zeros_like(MX)
+    if args.mode == "match":
+        ttm = dict(records[-1], workload=args.workload, seconds=elapsed / args.steps, tol=args.tol, h=args.h)
+
+    ttm2 = None
+    if args.match != "none" and args.match != args.workload:
+        mpr, mdtype, mrc, mprm, MX, MY = setup(args.match)
+        run_match(mprm, mpr, MX, MY)                         # warm-up
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        st, minfo, hist = lm.lm_feedback_match(mprm, MX, MY, mp0, h=args.h, tol=1e-6, steps=mp.steps,
-                                               max_iter=200)
+        st, minfo, hist = run_match(mprm, mpr, MX, MY)
         torch.cuda.synchronize()
-        ttm = {"workload": args.match, "seconds": time.perf_counter() - t1, "status": lm.STATUS_NAMES[st],
-               "iters": minfo.iters, "cg_iters": minfo.cg_iters, "resid_inf": minfo.resid_inf,
-               "tol": 1e-6, "h": args.h, "paper_H_2H": 2 * minfo.H}
-        print("time to match %s: %.3f s, %d iterations, resid %.2e" % (
-            args.match, ttm["seconds"], minfo.iters, minfo.resid_inf), file=sys.stderr, flush=True)
+        ttm2 = {"workload": args.match, "seconds": time.perf_counter() - t1, "status": lm.STATUS_NAMES[st],
+                "iters": minfo.iters, "resid_inf": minfo.resid_inf, "factor_ms": minfo.factor_ms,
+                "shoot_ms": minfo.shoot_ms, "solve_ms": minfo.solve_ms, "cg_iters": minfo.cg_iters,
+                "tol": args.tol, "h": args.h, "paper_H_2H": 2 * minfo.H}
+        log("time to match %s: %.3f s, %d iterations, resid %.2e" % (
+            args.match, ttm2["seconds"], minfo.iters, minfo.resid_inf))
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(pr, args.cpu_seconds)
 
@@ -210,16 +251,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "dim": dim,
                    "kernel": "conon" if pr.kernel == 0 else "gauss", "sigma": pr.sigma,
-                   "rk4_steps": pr.steps, "h": args.h, "cutoff": rc,
-                   "step": "one feedback-control iteration: RK4 shoot + max-norm residual + CG K-solve update"},
+                   "rk4_steps": pr.steps, "h": args.h, "tol": args.tol, "cutoff": rc,
+                   "step": ("one whole feedback match from p = 0 to max|q(1) - Y| < tol"
+                            if args.mode == "match" else "one feedback iteration (CG K-solve)")},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_match": ttm,
-        "shoot_ms_mean": float(np.mean(shoot_ms)),
-        "solve_ms_mean": float(np.mean(solve_ms)),
-        "cg_iters_per_step": cg_iters / args.steps,
-        "step_statuses": statuses,
-        "residuals": resids,
+        "time_to_match_curve2d": ttm2,
+        "shoots": shoots,
+        "gpu_ms": {"shoot": shoot_ms, "solve": solve_ms, "factor": factor_ms},
+        "records": records,
     }
     print(json.dumps(out), flush=True)
 

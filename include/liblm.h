@@ -105,13 +105,17 @@ typedef struct lm_match_opts {
     int32_t solver;       /* K-solve: LM_SOLVE_AUTO, LM_SOLVE_CG or LM_SOLVE_DENSE */
 } lm_match_opts;
 
-/* What a feedback match reports (HOST struct). */
+/* What a feedback match reports (HOST struct).  GPU times come from HIP events on the
+ * stream around each phase. */
 typedef struct lm_match_info {
     int32_t iters;        /* momentum updates made before the final shoot */
     int32_t cg_iters;     /* conjugate-gradient iterations summed over every solve */
     double resid_inf;     /* max_{c,i} |Y - q(1)| of the final shoot */
     double H;             /* Hamiltonian 1/2 sum_ij (p_i.p_j) G(|X_i-X_j|) at (X, p0);
                              the values the paper prints are 2H */
+    double shoot_ms;      /* GPU time of all shoots (iters + 1 of them) */
+    double solve_ms;      /* GPU time of all K-solves and momentum updates */
+    double factor_ms;     /* GPU time of the dense factorisation (0 with CG) */
 } lm_match_info;
 
 /* Right-hand side of the N-particle system (equation "N-particle"; with tau > 0 the inexact

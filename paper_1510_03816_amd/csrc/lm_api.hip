@@ -731,14 +731,22 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
     Workspace ws(st);
     FeedbackWork w;
     LM_TRY(w.alloc(ws, prm, n, X, st));
+    EventTimer timer;
+    LM_TRY(timer.init());
+    LM_HIP(hipEventRecord(timer.ev[0], st));
     LM_TRY(w.prepare_solver(ws, prm, o, n, X, st));
+    LM_HIP(hipEventRecord(timer.ev[1], st));
+    LM_HIP(hipEventSynchronize(timer.ev[1]));
+    if (w.dense) info->factor_ms = timer.ms(0, 1);
 
     lm_status result = LM_OK;
     double r = 0.0, prev_step = INFINITY;
     int32_t k = 0;
     for (k = 0;; ++k) {
         // Algorithm 1, steps 1-2: shoot (X, p) to t = 1, residual r = max |Y - q(1)|
-        LM_TRY(feedback_shoot_residual(prm, o, n, X, Y, p0, w, &r, st));
+        LM_HIP(hipEventRecord(timer.ev[0], st));
+        LM_TRY(feedback_shoot_residual(prm, o, n, X, Y, p0, w, &r, st, timer.ev[1]));
+        info->shoot_ms += timer.ms(0, 1);
         if (k < o->hist_len) o->resid_hist[k] = r;
         if (!is_finite(r)) {
             result = fail(LM_EDIVERGED, "feedback iteration %d: non-finite residual", k);
@@ -751,12 +759,16 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
         }
         // steps 3-4: u <- u + h e, i.e. p <- p + h (K + tau I)^{-1} e
         int32_t cgit = 0;
+        LM_HIP(hipEventRecord(timer.ev[2], st));
         lm_status s = feedback_update(prm, o, n, X, Y, p0, w, &cgit, st);
         info->cg_iters += cgit;
         if (s != LM_OK) {
             result = s;
             break;
         }
+        LM_HIP(hipEventRecord(timer.ev[3], st));
+        LM_HIP(hipEventSynchronize(timer.ev[3]));
+        info->solve_ms += timer.ms(2, 3);
         prev_step = o->h * r;
     }
     info->iters = k;
