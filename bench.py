@@ -41,6 +41,22 @@ SLOTS_PER_PAIR = {(3, 0): 46, (2, 0): 41, (3, 1): 32, (2, 1): 27}
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 PEAK_TFLOPS = 2.0 * PEAK_SLOTS / 1e12
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
+# each scaled by the reading of a plain device copy of known size (fetch x2.000, write x1.000),
+# recorded with the hash of the kernel sources they were taken on; a changed kernel reports
+# null until the counters are taken again.
+MEASURED_TRAFFIC = {
+    "sphere3d_conon_f64": ("ad61f093e07665d0", 9.772e7),
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1510_03816_amd", "csrc")
+    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("lm_kernels.hip", "lm_math.h"))
+    return hashlib.sha256(data).hexdigest()[:16]
+
+
 WORKLOADS = {
     # name: (generator kwargs, dtype); eps = kernel value at the tile-skipping radius
     "sphere3d_conon_f64": (dict(kind="sphere3d", n=65536, kernel=0, sigma=0.05, steps=100), 0),
@@ -208,8 +224,12 @@ def main():
     if rc > 0.0:
         # with tile skipping the pairs evaluated are fewer than N^2: not a roofline figure
         achieved = None
+    traffic = None
+    if args.workload in MEASURED_TRAFFIC and MEASURED_TRAFFIC[args.workload][0] == kernel_source_hash():
+        traffic = MEASURED_TRAFFIC[args.workload][1]
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_TFLOPS) if achieved else None, "traffic": None,
+                "frac": (achieved / PEAK_TFLOPS) if achieved else None, "traffic": traffic,
+                "traffic_unit": "bytes per launch",
                 "kernel": "lm_pair_kernel<%s,%d,%s,force>" % ("double" if dtype == 0 else "float", dim,
                                                                "conon" if pr.kernel == 0 else "gauss"),
                 "launch_ms": launch_ms, "pairs_per_launch": n * n, "slots_per_pair": slots,

@@ -12,7 +12,7 @@ import mpmath as mp
 mp.mp.dps = 60
 
 
-def main(deg=11):
+def main(deg=10):
     ln2 = mp.log(2)
     hi = float(ln2)
     lo = float(ln2 - mp.mpf(hi))
@@ -36,4 +36,4 @@ def main(deg=11):
 
 if __name__ == "__main__":
     import sys
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 11)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 10)

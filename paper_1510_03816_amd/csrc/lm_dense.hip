@@ -241,14 +241,14 @@ __global__ __launch_bounds__(256) void lm_syrk_kernel(double* __restrict__ K, in
 
 // y_blk = Linv_blk * y_blk (forward, TRANS = false) or Linv_blk^T * y_blk (backward), for
 // block `blk`, executed by one workgroup of 256 threads.
-template <bool TRANS>
-__device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb, int64_t blk, int dim,
+template <bool TRANS, int DIM>
+__device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb, int64_t blk,
                              double* __restrict__ y, double* sh)
 {
     const int64_t b0 = blk * kPanel;
     const int bs = (int)((n - b0) < kPanel ? (n - b0) : kPanel);
     const double* Li = Linv + blk * kPanel * kPanel;
-    for (int e = threadIdx.x; e < dim * kPanel; e += blockDim.x) {
+    for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
         const int c = e / kPanel, r = e % kPanel;
         sh[e] = r < bs ? y[c * n + b0 + r] : 0.0;
     }
@@ -256,7 +256,7 @@ __device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb,
     double out[3] = {0.0, 0.0, 0.0};
     const int r = threadIdx.x;
     if (r < bs) {
-        for (int c = 0; c < dim; ++c) {
+        for (int c = 0; c < DIM; ++c) {
             double s = 0.0;
             if (!TRANS) {
                 for (int m = 0; m <= r; ++m) s = __builtin_fma(Li[r * kPanel + m], sh[c * kPanel + m], s);
@@ -268,66 +268,78 @@ __device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb,
     }
     __syncthreads();
     if (r < bs)
-        for (int c = 0; c < dim; ++c) y[c * n + b0 + r] = out[c];
+        for (int c = 0; c < DIM; ++c) y[c * n + b0 + r] = out[c];
 }
 
 // Launch k of the forward sweep (k = -1: only finish block 0).  Workgroup 0 owns block k+1:
 // it subtracts L[block k+1, block k] y_k and finishes y_{k+1}; workgroups >= 1 subtract the
-// contribution of y_k from the rows of blocks k+2 .. nb-1, one row per wave at a time.
+// contribution of y_k from the rows of blocks k+2 .. nb-1, eight rows per wave at a time.
+template <int DIM>
 __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restrict__ L, const double* __restrict__ Linv,
-                                                          int64_t n, int nb, int64_t k, int dim, double* __restrict__ y)
+                                                          int64_t n, int nb, int64_t k, double* __restrict__ y)
 {
     __shared__ double sh[3 * kPanel];
     __shared__ double yk[3 * kPanel];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (k >= 0) {
         const int64_t k0 = k * kPanel;
-        for (int e = threadIdx.x; e < dim * kPanel; e += blockDim.x) {
+        for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
             const int c = e / kPanel, m = e % kPanel;
             yk[e] = (k0 + m < n) ? y[c * n + k0 + m] : 0.0;
         }
         __syncthreads();
+        // eight rows per wave at a time: lane l reads 16 consecutive doubles of row (l / 8),
+        // so each row's 128 panel entries come in as one coalesced 1 KiB segment
+        const int sub = lane >> 3, seg = (lane & 7) * 16;
         int64_t rbeg, rend, rstep;
         if (blockIdx.x == 0) {
-            rbeg = (k + 1) * kPanel + wave;
+            rbeg = (k + 1) * kPanel + wave * 8;
             rend = (k + 2) * kPanel < n ? (k + 2) * kPanel : n;
-            rstep = 4;
+            rstep = 32;
         } else {
-            rbeg = (k + 2) * kPanel + (int64_t)(blockIdx.x - 1) * 4 + wave;
+            rbeg = (k + 2) * kPanel + ((int64_t)(blockIdx.x - 1) * 4 + wave) * 8;
             rend = n;
-            rstep = (int64_t)(gridDim.x - 1) * 4;
+            rstep = (int64_t)(gridDim.x - 1) * 32;
         }
-        for (int64_t r = rbeg; r < rend; r += rstep) {
-            const double* lr = L + r * n + k0;
-            const double l0 = (k0 + lane < n) ? lr[lane] : 0.0;
-            const double l1 = (k0 + 64 + lane < n) ? lr[64 + lane] : 0.0;
-            for (int c = 0; c < dim; ++c) {
-                double s = l0 * yk[c * kPanel + lane] + l1 * yk[c * kPanel + 64 + lane];
+        for (int64_t rb = rbeg; rb < rend; rb += rstep) {
+            const int64_t r = rb + sub;
+            const bool ok = r < rend;
+            const double* lr = L + (ok ? r : rb) * n + k0 + seg;
+            double lv[16];
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-                if (lane == 0) y[c * n + r] -= s;
+            for (int u = 0; u < 16; ++u) lv[u] = lr[u];
+            double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) s[c] = __builtin_fma(lv[u], yk[c * kPanel + seg + u], s[c]);
+#pragma unroll
+                for (int o = 4; o > 0; o >>= 1) s[c] += __shfl_xor(s[c], o, 64);
             }
+            if (ok && (lane & 7) == 0)
+                for (int c = 0; c < DIM; ++c) y[c * n + r] -= s[c];
         }
     }
     if (blockIdx.x == 0 && k + 1 < nb) {
         __threadfence_block();
         __syncthreads();
-        finish_block<false>(Linv, n, nb, k + 1, dim, y, sh);
+        finish_block<false, DIM>(Linv, n, nb, k + 1, y, sh);
     }
 }
 
 // Launch k of the backward sweep (k = nb: only finish block nb-1).  Workgroup 0 owns block
 // k-1: it subtracts L[block k, block k-1]^T x_k and finishes x_{k-1}; workgroups >= 1 handle
 // the columns of blocks 0 .. k-2, one column per thread.
+template <int DIM>
 __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restrict__ L, const double* __restrict__ Linv,
-                                                          int64_t n, int nb, int64_t k, int dim, double* __restrict__ y)
+                                                          int64_t n, int nb, int64_t k, double* __restrict__ y)
 {
     __shared__ double sh[3 * kPanel];
     __shared__ double xk[3 * kPanel];
     if (k < nb) {
         const int64_t k0 = k * kPanel;
         const int bs = (int)((n - k0) < kPanel ? (n - k0) : kPanel);
-        for (int e = threadIdx.x; e < dim * kPanel; e += blockDim.x) {
+        for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
             const int c = e / kPanel, m = e % kPanel;
             xk[e] = m < bs ? y[c * n + k0 + m] : 0.0;
         }
@@ -344,17 +356,23 @@ __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restri
         }
         for (int64_t col = cbeg; col < cend; col += cstep) {
             double s[3] = {0.0, 0.0, 0.0};
-            for (int m = 0; m < bs; ++m) {
-                const double l = L[(k0 + m) * n + col];
-                for (int c = 0; c < dim; ++c) s[c] = __builtin_fma(l, xk[c * kPanel + m], s[c]);
+            const double* lc = L + k0 * n + col;
+            // sixteen independent loads in flight per thread (zeros past a ragged block end)
+            for (int m0 = 0; m0 < kPanel; m0 += 16) {
+                double lv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) lv[u] = (m0 + u < bs) ? lc[(int64_t)(m0 + u) * n] : 0.0;
+                for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) s[c] = __builtin_fma(lv[u], xk[c * kPanel + m0 + u], s[c]);
             }
-            for (int c = 0; c < dim; ++c) y[c * n + col] -= s[c];
+            for (int c = 0; c < DIM; ++c) y[c * n + col] -= s[c];
         }
     }
     if (blockIdx.x == 0 && k - 1 >= 0) {
         __threadfence_block();
         __syncthreads();
-        finish_block<true>(Linv, n, nb, k - 1, dim, y, sh);
+        finish_block<true, DIM>(Linv, n, nb, k - 1, y, sh);
     }
 }
 
@@ -403,19 +421,25 @@ hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, in
 {
     const int nb = dense_panels(n);
     // enough workgroups to stream a panel at full bandwidth, never more than its rows need
-    auto groups = [&](int64_t rows) -> unsigned {
-        int64_t g = 1 + (rows + 255) / 256;
-        return (unsigned)(g < 1025 ? g : 1025);
+    auto groups = [&](int64_t items, int64_t per_group) -> unsigned {
+        int64_t g = 1 + (items + per_group - 1) / per_group;
+        return (unsigned)(g < 2049 ? g : 2049);
     };
     for (int64_t k = -1; k < nb - 1; ++k) {
         const int64_t below = n - (k + 2) * kPanel;
-        hipLaunchKernelGGL(lm_trsv_fwd_kernel, dim3(k < 0 ? 1u : groups(below > 0 ? below : 0)), dim3(256), 0, st,
-                           L, Linv, n, nb, k, dim, y);
+        const dim3 g(k < 0 ? 1u : groups(below > 0 ? below : 0, 32));
+        if (dim == 2)
+            hipLaunchKernelGGL(lm_trsv_fwd_kernel<2>, g, dim3(256), 0, st, L, Linv, n, nb, k, y);
+        else
+            hipLaunchKernelGGL(lm_trsv_fwd_kernel<3>, g, dim3(256), 0, st, L, Linv, n, nb, k, y);
     }
     for (int64_t k = nb; k > 0; --k) {
         const int64_t above = (k - 1) * kPanel;
-        hipLaunchKernelGGL(lm_trsv_bwd_kernel, dim3(k == nb ? 1u : groups(above)), dim3(256), 0, st, L, Linv, n, nb,
-                           k, dim, y);
+        const dim3 g(k == nb ? 1u : groups(above, 256));
+        if (dim == 2)
+            hipLaunchKernelGGL(lm_trsv_bwd_kernel<2>, g, dim3(256), 0, st, L, Linv, n, nb, k, y);
+        else
+            hipLaunchKernelGGL(lm_trsv_bwd_kernel<3>, g, dim3(256), 0, st, L, Linv, n, nb, k, y);
     }
     return hipGetLastError();
 }

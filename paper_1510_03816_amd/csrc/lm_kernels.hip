@@ -29,8 +29,24 @@
 
 namespace lm {
 
-constexpr int kTile = 64;    // targets per workgroup (one per lane)
-constexpr int kWaves = 4;    // wavefronts per workgroup
+// Launch shape (measured on MI355X at N = 65536, 3-D, FP64): four waves per workgroup, four
+// sources per unrolled loop body, and at least 16384 workgroups, so that each wave streams a
+// chunk of about a thousand sources.  Short chunks stay in the scalar cache while the four
+// waves of a CU's workgroups reuse them; one chunk per wave of the whole source range (the
+// 1024-workgroup shape) ran 9-12% slower.
+#ifndef LM_WAVES
+#define LM_WAVES 4
+#endif
+#ifndef LM_UNROLL
+#define LM_UNROLL 4
+#endif
+#ifndef LM_MIN_GROUPS
+#define LM_MIN_GROUPS 16384
+#endif
+
+constexpr int kTile = 64;          // targets per workgroup (one per lane)
+constexpr int kWaves = LM_WAVES;   // wavefronts per workgroup
+constexpr int kUnroll = LM_UNROLL; // sources per unrolled loop body
 
 // ---------------------------------------------------------------------------------------
 // Pair bodies.  `kq` holds the kernel-argument scale: for the conon -1/sigma, for the
@@ -192,9 +208,9 @@ __device__ __forceinline__ void sum_sources(const double* __restrict__ qs, const
                                             double (&f)[DIM])
 {
     int64_t j = j0;
-    for (; j + 4 <= j1; j += 4) {
+    for (; j + kUnroll <= j1; j += kUnroll) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kUnroll; ++u) {
             double qj[DIM], pj[DIM];
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
@@ -743,9 +759,9 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut)
 {
     PairPlan pl;
     pl.itiles = (nt + kTile - 1) / kTile;
-    // aim for >= 1024 workgroups (4096 wavefronts: four per SIMD on 256 CUs) while keeping
-    // every wave's source chunk at >= 32 sources
-    int64_t s = (1024 + pl.itiles - 1) / pl.itiles;
+    // aim for >= LM_MIN_GROUPS workgroups (the targets alone give nt/64; the sources are
+    // split over grid-y to make up the rest) while keeping every wave's chunk >= 32 sources
+    int64_t s = (LM_MIN_GROUPS + pl.itiles - 1) / pl.itiles;
     int64_t smax = ns / (kWaves * 32);
     if (smax < 1) smax = 1;
     if (s > smax) s = smax;

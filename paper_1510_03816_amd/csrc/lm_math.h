@@ -4,10 +4,11 @@
 // double and in single precision.  There is no double-precision exp instruction; the one
 // here follows Cody & Waite's argument reduction (W. J. Cody and W. Waite, "Software
 // Manual for the Elementary Functions", 1980): x = k ln2 + r with integer k and
-// |r| <= ln2/2, then exp(x) = 2^k P(r) with P a degree-11 polynomial.  The constants were
+// |r| <= ln2/2, then exp(x) = 2^k P(r) with P a degree-10 polynomial.  The constants were
 // derived for this library by gen_exp_coeffs.py (Chebyshev interpolation of exp on
 // [-ln2/2, ln2/2] at 60 digits, rounded to double): the rounded polynomial is within
-// 1.7e-17 of exp on that interval, so the result is within a few units in the last place.
+// 3.3e-16 of exp on that interval (degree 11 would give 1.7e-17 for one more FMA per pair;
+// the difference is far below the parity bar and the sums' own rounding).
 //
 // The reciprocal square root starts from the hardware estimate v_rsq_f64 (relative error
 // 5.2e-8 = 2^-24.2, measured on gfx950 over 2^20 arguments in [2^-20, 2^20]) and applies one
@@ -24,26 +25,29 @@ constexpr double kLn2Hi = 0.6931471805599453;       // ln 2 rounded to double
 constexpr double kLn2Lo = 2.3190468138462996e-17;   // ln 2 - kLn2Hi
 
 // exp(x) for x <= 0.  Arguments below -1000 return 0 (exp underflows far earlier); the
-// clamp also keeps the reduction finite for huge |x|.
+// clamp also keeps the reduction finite for huge |x|.  k = round(x / ln2) comes from adding
+// and subtracting 1.5 * 2^52 (one FMA and one subtraction): the low word of kd then holds k
+// as a 32-bit integer for the final scaling, so no separate rounding or conversion is needed.
 __device__ __forceinline__ double exp_nonpos(double x)
 {
     x = __builtin_fmax(x, -1000.0);
-    const double k = __builtin_rint(x * kLog2e);
+    const double kd = __builtin_fma(x, kLog2e, 0x1.8p52);
+    const double k = kd - 0x1.8p52;
+    const int ki = (int)(unsigned)__builtin_bit_cast(unsigned long long, kd);
     double r = __builtin_fma(k, -kLn2Hi, x);
     r = __builtin_fma(k, -kLn2Lo, r);
-    double p = 0x1.af631d0059becp-26;
-    p = __builtin_fma(p, r, 0x1.28b4057f44145p-22);
-    p = __builtin_fma(p, r, 0x1.71ddf5749d126p-19);
-    p = __builtin_fma(p, r, 0x1.a01991ac8730ap-16);
-    p = __builtin_fma(p, r, 0x1.a01a01b14378fp-13);
-    p = __builtin_fma(p, r, 0x1.6c16c187fbe02p-10);
-    p = __builtin_fma(p, r, 0x1.111111110f225p-7);
-    p = __builtin_fma(p, r, 0x1.555555554f0cfp-5);
-    p = __builtin_fma(p, r, 0x1.555555555555ap-3);
-    p = __builtin_fma(p, r, 0x1.0000000000011p-1);
+    double p = 0x1.28a2c0a7209fbp-22;
+    p = __builtin_fma(p, r, 0x1.72faf024b693bp-19);
+    p = __builtin_fma(p, r, 0x1.a019a66a75dd4p-16);
+    p = __builtin_fma(p, r, 0x1.a01978c6baf81p-13);
+    p = __builtin_fma(p, r, 0x1.6c16c17f43a58p-10);
+    p = __builtin_fma(p, r, 0x1.1111112dd67c5p-7);
+    p = __builtin_fma(p, r, 0x1.55555555520afp-5);
+    p = __builtin_fma(p, r, 0x1.555555554b757p-3);
+    p = __builtin_fma(p, r, 0x1.0000000000005p-1);
+    p = __builtin_fma(p, r, 0x1.000000000001ep+0);
     p = __builtin_fma(p, r, 1.0);
-    p = __builtin_fma(p, r, 1.0);
-    return __builtin_ldexp(p, (int)k);
+    return __builtin_ldexp(p, ki);
 }
 
 // 1/sqrt(s) for s > 0 (callers clamp s away from zero).
