@@ -69,6 +69,10 @@ def lib():
         L.orc_feedback_match.argtypes = [i, l, i, d, d, P, P, d, d, i, i, i, P, P,
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(d),
                                          ctypes.POINTER(d), P, i]
+        L.orc_rhs_vjp.restype = None
+        L.orc_rhs_vjp.argtypes = [i, l, i, d, d, P, P, P, P, P, P]
+        L.orc_shoot_adjoint.restype = None
+        L.orc_shoot_adjoint.argtypes = [i, l, i, d, d, d, i, P, P, P, P, P, P]
         L.orc_velocity.restype = None
         L.orc_velocity.argtypes = [i, l, l, i, d, P, P, P, P]
         _lib = L
@@ -195,3 +199,34 @@ def velocity(q, p, x, kernel: int, sigma: float) -> np.ndarray:
     u = np.empty_like(x)
     lib().orc_velocity(dim, n, m, kernel, sigma, _ptr(q), _ptr(p), _ptr(x), _ptr(u))
     return u
+
+
+def rhs_vjp(q, p, a, b, kernel: int, sigma: float, tau: float = 0.0):
+    """(aq, ap) = J^T (a, b): the cotangent of (q, p) given the cotangent (a, b) of the RHS."""
+    q, p, a, b = _c(q), _c(p), _c(a), _c(b)
+    dim, n = q.shape
+    aq, ap = np.empty_like(q), np.empty_like(p)
+    lib().orc_rhs_vjp(dim, n, kernel, sigma, tau, _ptr(q), _ptr(p), _ptr(a), _ptr(b), _ptr(aq), _ptr(ap))
+    return aq, ap
+
+
+def shoot_adjoint(q0, p0, gq1, gp1, kernel: int, sigma: float, steps: int, T: float = 1.0, tau: float = 0.0):
+    """(gq0, gp0) = J^T (gq1, gp1) for the RK4 shooting map (q0, p0) -> (q(T), p(T))."""
+    q0, p0, gq1, gp1 = _c(q0), _c(p0), _c(gq1), _c(gp1)
+    dim, n = q0.shape
+    gq0, gp0 = np.empty_like(q0), np.empty_like(p0)
+    lib().orc_shoot_adjoint(dim, n, kernel, sigma, tau, T, steps, _ptr(q0), _ptr(p0), _ptr(gq1), _ptr(gp1),
+                            _ptr(gq0), _ptr(gp0))
+    return gq0, gp0
+
+
+def energy_and_grad(X, Y, p0, kernel: int, sigma: float, lam: float, steps: int):
+    """E(p0) = 1/2 p0^T K(X) p0 + lam/2 |q(1) - Y|^2 and its gradient in p0 (the inexact
+    energy with lam = 1/sigma^2 of the paper, halved)."""
+    X, Y, p0 = _c(X), _c(Y), _c(p0)
+    Kp, _ = rhs(X, p0, kernel, sigma)
+    q1, p1 = shoot(X, p0, kernel, sigma, steps)
+    r = q1 - Y
+    E = 0.5 * float(np.sum(p0 * Kp)) + 0.5 * lam * float(np.sum(r * r))
+    _, gp0 = shoot_adjoint(X, p0, lam * r, np.zeros_like(p0), kernel, sigma, steps)
+    return E, Kp + gp0

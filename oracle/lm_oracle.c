@@ -321,6 +321,108 @@ int orc_feedback_match(int dim, long n, int kernel, double sigma, double tau,
     return st;
 }
 
+/* ---- Reverse mode (the adjoint of the shooting map; not in the paper: it differentiates the
+ * inexact-matching energy of equation "inexact-E" with respect to the initial momenta). ---
+ *
+ * Vector-Jacobian product of the right-hand side at (q, p): given the cotangent (a, b) of
+ * (dq/dt, dp/dt), returns (aq, ap) = J^T (a, b).  With w = -G'(r)/r, u = w'(r)/r,
+ * d = q_k - q_j and e = b_k - b_j, differentiating the N-particle sums gives
+ *   ap_k = tau a_k + sum_j G_kj a_j + sum_{j != k} w (e . d) p_j
+ *   aq_k = sum_{j != k} [ -w ((a_k . p_j) + (a_j . p_k)) d + (p_k . p_j) (w e + (e . d) u d) ]
+ * (coincident distinct particles contribute nothing, as in the forward sums). */
+static double wfun(int kernel, double sigma, double r, double g)
+{
+    return -green_prime_g(kernel, sigma, r, g) / r;
+}
+
+/* u = w'(r)/r: conon w = G/(sigma r), w' = -G/(sigma^2 r) - G/(sigma r^2);
+ * Gaussian w = 2G/sigma^2, w' = -4 r G/sigma^4. */
+static double ufun(int kernel, double sigma, double r, double g)
+{
+    if (kernel == 0) return (-g / (sigma * sigma * r) - g / (sigma * r * r)) / r;
+    return -4.0 * g / (sigma * sigma * sigma * sigma);
+}
+
+void orc_rhs_vjp(int dim, long n, int kernel, double sigma, double tau,
+                 const double *q, const double *p, const double *a, const double *b,
+                 double *aq, double *ap)
+{
+#pragma omp parallel for schedule(static) if (n >= 256)
+    for (long k = 0; k < n; ++k) {
+        double gq[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0};
+        for (long j = 0; j < n; ++j) {
+            double r = dist(dim, n, q, k, j);
+            double g = green(kernel, sigma, r);
+            for (int c = 0; c < dim; ++c) gp[c] += g * a[c * n + j];
+            if (j == k || r == 0.0) continue;
+            double w = wfun(kernel, sigma, r, g), u = ufun(kernel, sigma, r, g);
+            double d[3], e[3], ed = 0.0, apj = 0.0, pp = 0.0;
+            for (int c = 0; c < dim; ++c) {
+                d[c] = q[c * n + k] - q[c * n + j];
+                e[c] = b[c * n + k] - b[c * n + j];
+                ed += e[c] * d[c];
+                apj += a[c * n + k] * p[c * n + j] + a[c * n + j] * p[c * n + k];
+                pp += p[c * n + k] * p[c * n + j];
+            }
+            for (int c = 0; c < dim; ++c) {
+                gp[c] += w * ed * p[c * n + j];
+                gq[c] += -w * apj * d[c] + pp * (w * e[c] + ed * u * d[c]);
+            }
+        }
+        for (int c = 0; c < dim; ++c) {
+            aq[c * n + k] = gq[c];
+            ap[c * n + k] = gp[c] + tau * a[c * n + k];
+        }
+    }
+}
+
+/* Discrete adjoint of orc_shoot: (gq0, gp0) = J_shoot^T (gq1, gp1), every stage input kept.
+ * For one RK4 step y' = y + dt/6 (k1 + 2k2 + 2k3 + k4), k_s = f(Y_s), with cotangent abar of
+ * y': kb4 = dt/6 abar, Yb4 = J(Y4)^T kb4; kb3 = dt/3 abar + dt Yb4, Yb3 = J(Y3)^T kb3;
+ * kb2 = dt/3 abar + dt/2 Yb3, Yb2 = J(Y2)^T kb2; kb1 = dt/6 abar + dt/2 Yb2,
+ * Yb1 = J(Y1)^T kb1; the cotangent of y is abar + Yb1 + Yb2 + Yb3 + Yb4. */
+void orc_shoot_adjoint(int dim, long n, int kernel, double sigma, double tau, double T, int steps,
+                       const double *q0, const double *p0, const double *gq1, const double *gp1,
+                       double *gq0, double *gp0)
+{
+    size_t m = (size_t)dim * (size_t)n;
+    size_t per = 2 * m;                       /* one state (q, p) */
+    double *Ys = (double *)malloc(sizeof(double) * per * 4 * (size_t)steps);
+    double *y = (double *)malloc(sizeof(double) * per), *ks = (double *)malloc(sizeof(double) * per * 4);
+    double dt = T / steps;
+    const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+    memcpy(y, q0, sizeof(double) * m);
+    memcpy(y + m, p0, sizeof(double) * m);
+    for (int st = 0; st < steps; ++st) {
+        for (int s = 0; s < 4; ++s) {
+            double *Y = Ys + ((size_t)st * 4 + s) * per;
+            for (size_t k = 0; k < per; ++k) Y[k] = y[k] + (s ? cst[s] * dt * ks[(s - 1) * per + k] : 0.0);
+            orc_rhs(dim, n, kernel, sigma, tau, Y, Y + m, ks + s * per, ks + s * per + m);
+        }
+        for (size_t k = 0; k < per; ++k)
+            y[k] = y[k] + dt / 6.0 * (ks[k] + 2.0 * ks[per + k] + 2.0 * ks[2 * per + k] + ks[3 * per + k]);
+    }
+    double *lam = (double *)malloc(sizeof(double) * per), *acc = (double *)malloc(sizeof(double) * per);
+    double *kb = (double *)malloc(sizeof(double) * per), *Yb = (double *)malloc(sizeof(double) * per);
+    memcpy(lam, gq1, sizeof(double) * m);
+    memcpy(lam + m, gp1, sizeof(double) * m);
+    const double ca[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};   /* weights of abar in kb1..kb4 */
+    const double cy[4] = {0.5, 0.5, 1.0, 0.0};                           /* weight of Yb_{s+1} in kb_s */
+    for (int st = steps - 1; st >= 0; --st) {
+        memcpy(acc, lam, sizeof(double) * per);
+        for (int s = 3; s >= 0; --s) {
+            for (size_t k = 0; k < per; ++k) kb[k] = dt * ca[s] * lam[k] + (s < 3 ? dt * cy[s] * Yb[k] : 0.0);
+            const double *Y = Ys + ((size_t)st * 4 + s) * per;
+            orc_rhs_vjp(dim, n, kernel, sigma, tau, Y, Y + m, kb, kb + m, Yb, Yb + m);
+            for (size_t k = 0; k < per; ++k) acc[k] += Yb[k];
+        }
+        memcpy(lam, acc, sizeof(double) * per);
+    }
+    memcpy(gq0, lam, sizeof(double) * m);
+    memcpy(gp0, lam + m, sizeof(double) * m);
+    free(Ys); free(y); free(ks); free(lam); free(acc); free(kb); free(Yb);
+}
+
 /* ---- Velocity field at arbitrary points (equation "u"):
  *   u(x) = sum_j G(|x - q_j|) p_j,   x given as m points, component-major (dim, m). ---- */
 void orc_velocity(int dim, long n, long m, int kernel, double sigma,
