@@ -188,6 +188,36 @@ lm_status lm_feedback_step(const lm_params *params, const lm_match_opts *opts, i
                            const double *X, const double *Y, double *p, double *q1,
                            lm_step_info *info, void *stream);
 
+/* Reverse mode (not in the paper: it differentiates the inexact-matching energy of equation
+ * "inexact-E" with respect to the initial momenta).  Double precision, cutoff = 0; other
+ * settings return LM_EUNSUPPORTED.  Two distinct particles at the same point contribute only
+ * the velocity-sum term, as in the forward sums. */
+
+/* Vector-Jacobian product of the right-hand side at (q, p): (aq, ap) = J^T (a, b), where
+ * (a, b) is a cotangent of (dq/dt, dp/dt).  All buffers double (dim, n); aq/ap must not
+ * alias the inputs.  Asynchronous. */
+lm_status lm_rhs_vjp(const lm_params *params, int64_t n, const double *q, const double *p,
+                     const double *a, const double *b, double *aq, double *ap, void *stream);
+
+/* Discrete adjoint of lm_shoot: (gq0, gp0) = J^T (gq1, gp1) for the RK4 map
+ * (q0, p0) -> (q(t1), p(t1)) with `steps` steps.  The forward pass keeps the state every
+ * ckpt_every steps (0 = keep every stage input of the whole shoot) and the reverse sweep
+ * recomputes one segment at a time.  q1, p1 (nullable) receive the forward result.  gq0/gp0
+ * may alias gq1/gp1.  All buffers double (dim, n).  Asynchronous. */
+lm_status lm_shoot_adjoint(const lm_params *params, int64_t n, const double *q0, const double *p0,
+                           double t1, int32_t steps, int32_t ckpt_every, const double *gq1,
+                           const double *gp1, double *gq0, double *gp0, double *q1, double *p1,
+                           void *stream);
+
+/* Energy of inexact matching and its gradient in the initial momenta:
+ *     E(p0) = 1/2 p0^T K(X) p0 + lam/2 |q(1) - Y|^2,   grad = K(X) p0 + J^T (lam (q(1) - Y), 0)
+ * (half the paper's inexact energy with lam = 1/sigma^2, the geodesic's kinetic energy
+ * written as 2H by eq. "E=2H").  q(1) is the RK4 shoot of (X, p0) over [0, 1]; *E_out is a
+ * HOST double; grad (dim, n) must not alias p0; q1 (nullable) receives q(1).  Synchronous. */
+lm_status lm_energy_grad(const lm_params *params, int64_t n, const double *X, const double *Y,
+                         const double *p0, double lam, int32_t steps, int32_t ckpt_every,
+                         double *E_out, double *grad, double *q1, void *stream);
+
 /* Velocity field at arbitrary points (equation "u"): u(x_a) = sum_j G(|x_a - q_j|) p_j.
  * q, p: (dim, n); x, u: (dim, m).  Asynchronous. */
 lm_status lm_velocity(const lm_params *params, int64_t n, const void *q, const void *p,

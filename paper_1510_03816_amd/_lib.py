@@ -23,7 +23,8 @@ SOLVE_AUTO, SOLVE_CG, SOLVE_DENSE = 0, 1, 2
 
 # every symbol include/liblm.h declares
 EXPORTS = ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
-           "lm_feedback_step", "lm_velocity", "lm_last_error", "lm_version"]
+           "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
+           "lm_last_error", "lm_version"]
 
 
 class LmError(RuntimeError):
@@ -78,8 +79,11 @@ def load():
         L.lm_feedback_step.argtypes = [PP, ctypes.POINTER(lm_match_opts), i64, P, P, P, P,
                                        ctypes.POINTER(lm_step_info), P]
         L.lm_velocity.argtypes = [PP, i64, P, P, i64, P, P, P]
+        L.lm_rhs_vjp.argtypes = [PP, i64, P, P, P, P, P, P, P]
+        L.lm_shoot_adjoint.argtypes = [PP, i64, P, P, d, i32, i32, P, P, P, P, P, P, P]
+        L.lm_energy_grad.argtypes = [PP, i64, P, P, P, d, i32, i32, ctypes.POINTER(d), P, P, P]
         for name in ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
-                     "lm_feedback_step", "lm_velocity"]:
+                     "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad"]:
             getattr(L, name).restype = ctypes.c_int
         L.lm_last_error.restype = ctypes.c_char_p
         L.lm_last_error.argtypes = []
@@ -220,6 +224,37 @@ def lm_velocity(params: lm_params, q, p, x, u, stream=None):
         _check_tensor(t, params.dim, m, params.dtype, nm)
     return _check(load().lm_velocity(ctypes.byref(params), n, _ptr(q), _ptr(p), m, _ptr(x), _ptr(u),
                                      _stream(stream)))
+
+
+def lm_rhs_vjp(params: lm_params, q, p, a, b, aq, ap, stream=None):
+    dim, n = q.shape
+    for t, nm in [(q, "q"), (p, "p"), (a, "a"), (b, "b"), (aq, "aq"), (ap, "ap")]:
+        _check_tensor(t, params.dim, n, F64, nm)
+    return _check(load().lm_rhs_vjp(ctypes.byref(params), n, _ptr(q), _ptr(p), _ptr(a), _ptr(b), _ptr(aq), _ptr(ap),
+                                    _stream(stream)))
+
+
+def lm_shoot_adjoint(params: lm_params, q0, p0, t1: float, steps: int, ckpt_every: int, gq1, gp1, gq0, gp0,
+                     q1=None, p1=None, stream=None):
+    dim, n = q0.shape
+    for t, nm in [(q0, "q0"), (p0, "p0"), (gq1, "gq1"), (gp1, "gp1"), (gq0, "gq0"), (gp0, "gp0")] + \
+            [(t, nm) for t, nm in [(q1, "q1"), (p1, "p1")] if t is not None]:
+        _check_tensor(t, params.dim, n, F64, nm)
+    return _check(load().lm_shoot_adjoint(ctypes.byref(params), n, _ptr(q0), _ptr(p0), float(t1), int(steps),
+                                          int(ckpt_every), _ptr(gq1), _ptr(gp1), _ptr(gq0), _ptr(gp0), _ptr(q1),
+                                          _ptr(p1), _stream(stream)))
+
+
+def lm_energy_grad(params: lm_params, X, Y, p0, lam: float, steps: int, grad, ckpt_every: int = 0, q1=None,
+                   stream=None) -> float:
+    """E(p0) = 1/2 p0^T K p0 + lam/2 |q(1) - Y|^2; writes its gradient to grad, returns E."""
+    dim, n = X.shape
+    for t, nm in [(X, "X"), (Y, "Y"), (p0, "p0"), (grad, "grad")] + ([(q1, "q1")] if q1 is not None else []):
+        _check_tensor(t, params.dim, n, F64, nm)
+    E = ctypes.c_double(0.0)
+    _check(load().lm_energy_grad(ctypes.byref(params), n, _ptr(X), _ptr(Y), _ptr(p0), float(lam), int(steps),
+                                 int(ckpt_every), ctypes.byref(E), _ptr(grad), _ptr(q1), _stream(stream)))
+    return E.value
 
 
 def lm_version() -> str:

@@ -634,6 +634,182 @@ lm_status feedback_update(const lm_params* prm, const lm_match_opts* o, int64_t 
     return LM_OK;
 }
 
+// ---- Reverse mode ------------------------------------------------------------------------
+
+// One VJP launch: J(q, p)^T (a, b) handled by the epilogue e.
+lm_status vjp_eval(const lm_params* prm, int64_t n, const double* q, const double* p, const double* a,
+                   const double* b, const lm::AdjEpi& e, double* part, hipStream_t st)
+{
+    lm::PairPlan pl = lm::plan_pair(n, n, false);
+    lm::VjpArgs A{};
+    A.q = q;
+    A.p = p;
+    A.a = a;
+    A.b = b;
+    A.n = n;
+    A.jchunk = pl.jchunk;
+    const double sg = prm->sigma;
+    if (prm->kernel == LM_KERNEL_CONON) {
+        A.kq = -1.0 / sg;
+        A.c1 = 1.0 / sg;
+        A.c2 = 0.0;
+    } else {
+        A.kq = -1.0 / (sg * sg);
+        A.c1 = 2.0 / (sg * sg);
+        A.c2 = -4.0 / (sg * sg * sg * sg);
+    }
+    A.part = part;
+    A.epi = e;
+    LM_HIP(lm::launch_vjp(prm->dim, prm->kernel, A, pl, st));
+    return LM_OK;
+}
+
+// Buffers of a checkpointed adjoint: the states at segment starts, the stage inputs of one
+// segment (slot(i, s) = stage s+1 input of step i of the segment, slot(i+1, 0) its output),
+// the RK4 running sum, two cotangent and two lambda buffers.  A state is (q, p) = 2 dim n.
+struct AdjointWork {
+    int64_t m = 0;            // dim * n
+    int32_t steps = 0, ckpt = 0, nseg = 0;
+    double dt = 0.0;
+    double *ckpts = nullptr, *slots = nullptr, *acc = nullptr, *part = nullptr;
+    double *L0 = nullptr, *L1 = nullptr, *C0 = nullptr, *C1 = nullptr;
+
+    double* slot(int32_t i, int s) const { return slots + ((int64_t)i * 4 + s) * 2 * m; }
+    double* ck(int32_t seg) const { return ckpts + (int64_t)seg * 2 * m; }
+    int32_t seg_steps(int32_t seg) const { return (seg + 1) * ckpt <= steps ? ckpt : steps - seg * ckpt; }
+
+    lm_status alloc(Workspace& ws, const lm_params* prm, int64_t n, double t1, int32_t nsteps, int32_t every)
+    {
+        m = (int64_t)prm->dim * n;
+        steps = nsteps;
+        ckpt = (every <= 0 || every > nsteps) ? nsteps : every;
+        nseg = (steps + ckpt - 1) / ckpt;
+        dt = t1 / steps;
+        LM_TRY(ws.get(&ckpts, (int64_t)nseg * 2 * m));
+        LM_TRY(ws.get(&slots, ((int64_t)ckpt * 4 + 1) * 2 * m));
+        LM_TRY(ws.get(&acc, 2 * m));
+        LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+        LM_TRY(ws.get(&L0, 2 * m));
+        LM_TRY(ws.get(&L1, 2 * m));
+        LM_TRY(ws.get(&C0, 2 * m));
+        LM_TRY(ws.get(&C1, 2 * m));
+        return LM_OK;
+    }
+};
+
+// One RK4 step of the segment: stage inputs into slot(i, 1..3), the step output into
+// slot(i + 1, 0).
+lm_status rk_step_slots(const lm_params* prm, int64_t n, const AdjointWork& W, int32_t i, hipStream_t st)
+{
+    const int64_t m = W.m;
+    lm::EpiArgs<double> e{};
+    e.dt = W.dt;
+    e.tau = prm->tau;
+    double* y = W.slot(i, 0);
+    e.base_q = y;
+    e.base_p = y + m;
+    e.acc_q = W.acc;
+    e.acc_p = W.acc + m;
+    for (int k = 0; k < 4; ++k) {
+        const double* in = W.slot(i, k);
+        double* out = (k < 3) ? W.slot(i, k + 1) : W.slot(i + 1, 0);
+        e.kind = lm::EPI_RK1 + k;
+        e.in_p = in + m;
+        e.out_q = out;
+        e.out_p = out + m;
+        LM_TRY(pair_eval<double>(prm, true, in, in + m, n, in, in + m, n, e, W.part, st));
+    }
+    return LM_OK;
+}
+
+// Forward pass keeping a state every `ckpt` steps; the slots end up holding the last
+// segment, whose final output is the state at t1.  Returns that state's pointer.
+lm_status adjoint_forward(const lm_params* prm, int64_t n, const double* q0, const double* p0, AdjointWork& W,
+                          const double** final_state, hipStream_t st)
+{
+    const int64_t m = W.m;
+    LM_HIP(hipMemcpyAsync(W.ck(0), q0, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(hipMemcpyAsync(W.ck(0) + m, p0, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int32_t seg = 0; seg < W.nseg; ++seg) {
+        const int32_t ns = W.seg_steps(seg);
+        LM_HIP(hipMemcpyAsync(W.slot(0, 0), W.ck(seg), 2 * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        for (int32_t i = 0; i < ns; ++i) LM_TRY(rk_step_slots(prm, n, W, i, st));
+        if (seg + 1 < W.nseg)
+            LM_HIP(hipMemcpyAsync(W.ck(seg + 1), W.slot(ns, 0), 2 * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    *final_state = W.slot(W.seg_steps(W.nseg - 1), 0);
+    return LM_OK;
+}
+
+// Reverse sweep from the cotangent in W.L0 (of the state at t1) to that of the initial
+// state, returned through *lam.  Expects the slots to hold the last segment.
+lm_status adjoint_reverse(const lm_params* prm, int64_t n, AdjointWork& W, const double** lam, hipStream_t st)
+{
+    const int64_t m = W.m;
+    const double dt = W.dt;
+    double *Lin = W.L0, *Lout = W.L1;
+    for (int32_t seg = W.nseg - 1; seg >= 0; --seg) {
+        const int32_t ns = W.seg_steps(seg);
+        if (seg < W.nseg - 1) {   // recompute the segment's stage inputs from its checkpoint
+            LM_HIP(hipMemcpyAsync(W.slot(0, 0), W.ck(seg), 2 * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+            for (int32_t i = 0; i < ns; ++i) LM_TRY(rk_step_slots(prm, n, W, i, st));
+        }
+        for (int32_t i = ns - 1; i >= 0; --i) {
+            lm::AdjEpi e{};
+            e.tau = prm->tau;
+            e.abar_q = Lin;
+            e.abar_p = Lin + m;
+            e.lam_q = Lout;
+            e.lam_p = Lout + m;
+            // stage 4: cotangent dt/6 abar, next = dt/3 abar + dt Yb4
+            const double* Y = W.slot(i, 3);
+            e.kind = lm::ADJ_FIRST;
+            e.cscale = dt / 6.0;
+            e.ca = dt / 3.0;
+            e.cy = dt;
+            e.cot_q = Lin;
+            e.nxt_q = W.C0;
+            e.nxt_p = W.C0 + m;
+            LM_TRY(vjp_eval(prm, n, Y, Y + m, Lin, Lin + m, e, W.part, st));
+            // stage 3: next = dt/3 abar + dt/2 Yb3
+            Y = W.slot(i, 2);
+            e.kind = lm::ADJ_MID;
+            e.cscale = 1.0;
+            e.ca = dt / 3.0;
+            e.cy = 0.5 * dt;
+            e.cot_q = W.C0;
+            e.nxt_q = W.C1;
+            e.nxt_p = W.C1 + m;
+            LM_TRY(vjp_eval(prm, n, Y, Y + m, W.C0, W.C0 + m, e, W.part, st));
+            // stage 2: next = dt/6 abar + dt/2 Yb2
+            Y = W.slot(i, 1);
+            e.ca = dt / 6.0;
+            e.cy = 0.5 * dt;
+            e.cot_q = W.C1;
+            e.nxt_q = W.C0;
+            e.nxt_p = W.C0 + m;
+            LM_TRY(vjp_eval(prm, n, Y, Y + m, W.C1, W.C1 + m, e, W.part, st));
+            // stage 1
+            Y = W.slot(i, 0);
+            e.kind = lm::ADJ_LAST;
+            e.cot_q = W.C0;
+            e.nxt_q = e.nxt_p = nullptr;
+            LM_TRY(vjp_eval(prm, n, Y, Y + m, W.C0, W.C0 + m, e, W.part, st));
+            std::swap(Lin, Lout);
+        }
+    }
+    *lam = Lin;
+    return LM_OK;
+}
+
+lm_status check_adjoint_params(const lm_params* prm)
+{
+    LM_TRY(check_params(prm));
+    if (prm->dtype != LM_F64) return fail(LM_EUNSUPPORTED, "the adjoint is provided in double precision only");
+    if (prm->cutoff > 0.0) return fail(LM_EUNSUPPORTED, "the adjoint is provided for every-pair sums only (cutoff = 0)");
+    return LM_OK;
+}
+
 }  // namespace
 
 // =========================================================================================
@@ -830,6 +1006,109 @@ lm_status lm_velocity(const lm_params* prm, int64_t n, const void* q, const void
     if (prm->dtype == LM_F64)
         return velocity_t<double>(prm, n, (const double*)q, (const double*)p, m, (const double*)x, (double*)u, st);
     return velocity_t<float>(prm, n, (const float*)q, (const float*)p, m, (const float*)x, (float*)u, st);
+}
+
+
+lm_status lm_rhs_vjp(const lm_params* prm, int64_t n, const double* q, const double* p, const double* a,
+                     const double* b, double* aq, double* ap, void* stream)
+{
+    LM_TRY(check_adjoint_params(prm));
+    LM_TRY(check_n(n));
+    if (!q || !p || !a || !b || !aq || !ap) return fail(LM_EINVAL, "NULL buffer");
+    const void* ins[4] = {q, p, a, b};
+    for (const void* x : ins)
+        if (x == aq || x == ap) return fail(LM_EINVAL, "aq/ap must not alias the inputs");
+    hipStream_t st = (hipStream_t)stream;
+    Workspace ws(st);
+    double* part;
+    LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+    lm::AdjEpi e{};
+    e.kind = lm::ADJ_STORE;
+    e.cscale = 1.0;
+    e.tau = prm->tau;
+    e.cot_q = a;
+    e.lam_q = aq;
+    e.lam_p = ap;
+    return vjp_eval(prm, n, q, p, a, b, e, part, st);
+}
+
+lm_status lm_shoot_adjoint(const lm_params* prm, int64_t n, const double* q0, const double* p0, double t1,
+                           int32_t steps, int32_t ckpt_every, const double* gq1, const double* gp1, double* gq0,
+                           double* gp0, double* q1, double* p1, void* stream)
+{
+    LM_TRY(check_adjoint_params(prm));
+    LM_TRY(check_n(n));
+    if (!q0 || !p0 || !gq1 || !gp1 || !gq0 || !gp0) return fail(LM_EINVAL, "NULL buffer");
+    if (steps < 1) return fail(LM_EINVAL, "steps must be >= 1");
+    if (ckpt_every < 0) return fail(LM_EINVAL, "ckpt_every must be >= 0");
+    if (!is_finite(t1)) return fail(LM_EINVAL, "t1 must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    Workspace ws(st);
+    AdjointWork W;
+    LM_TRY(W.alloc(ws, prm, n, t1, steps, ckpt_every));
+    const int64_t m = W.m;
+    const double* yT = nullptr;
+    LM_TRY(adjoint_forward(prm, n, q0, p0, W, &yT, st));
+    if (q1) LM_HIP(hipMemcpyAsync(q1, yT, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (p1) LM_HIP(hipMemcpyAsync(p1, yT + m, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(hipMemcpyAsync(W.L0, gq1, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(hipMemcpyAsync(W.L0 + m, gp1, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    const double* lam = nullptr;
+    LM_TRY(adjoint_reverse(prm, n, W, &lam, st));
+    LM_HIP(hipMemcpyAsync(gq0, lam, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(hipMemcpyAsync(gp0, lam + m, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return LM_OK;
+}
+
+lm_status lm_energy_grad(const lm_params* prm, int64_t n, const double* X, const double* Y, const double* p0,
+                         double lam, int32_t steps, int32_t ckpt_every, double* E_out, double* grad, double* q1,
+                         void* stream)
+{
+    LM_TRY(check_adjoint_params(prm));
+    LM_TRY(check_n(n));
+    if (!X || !Y || !p0 || !E_out || !grad) return fail(LM_EINVAL, "NULL pointer");
+    if (!(lam >= 0.0) || !is_finite(lam)) return fail(LM_EINVAL, "lam must be >= 0 and finite");
+    if (steps < 1 || ckpt_every < 0) return fail(LM_EINVAL, "bad steps or ckpt_every");
+    const int p0_alias = (grad == p0);
+    if (p0_alias) return fail(LM_EINVAL, "grad must not alias p0");
+    hipStream_t st = (hipStream_t)stream;
+    const int dim = prm->dim;
+    Workspace ws(st);
+    AdjointWork W;
+    LM_TRY(W.alloc(ws, prm, n, 1.0, steps, ckpt_every));
+    const int64_t m = W.m;
+    double *v, *red, *dots;
+    LM_TRY(ws.get(&v, m));
+    LM_TRY(ws.get(&red, (int64_t)lm::reduce_blocks(n) * dim));
+    LM_TRY(ws.get(&dots, 2 * dim));
+    // regulariser 1/2 p0^T K(X) p0 and its gradient K(X) p0
+    lm::EpiArgs<double> ev{};
+    ev.kind = lm::EPI_STORE;
+    ev.tau = 0.0;
+    ev.out_q = v;
+    LM_TRY(pair_eval<double>(prm, false, X, p0, n, X, p0, n, ev, W.part, st));
+    LM_HIP(lm::launch_dots(p0, v, n, dim, red, dots, st));
+    // data term lam/2 |q(1) - Y|^2 and its cotangent lam (q(1) - Y)
+    const double* yT = nullptr;
+    LM_TRY(adjoint_forward(prm, n, X, p0, W, &yT, st));
+    if (q1) LM_HIP(hipMemcpyAsync(q1, yT, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(lm::launch_sub(W.C0, yT, Y, m, st));
+    LM_HIP(lm::launch_dots(W.C0, W.C0, n, dim, red, dots + dim, st));
+    LM_HIP(lm::launch_scale(W.L0, lam, W.C0, m, st));
+    LM_HIP(lm::launch_zero(W.L0 + m, m, st));
+    const double* lamv = nullptr;
+    LM_TRY(adjoint_reverse(prm, n, W, &lamv, st));
+    LM_HIP(lm::launch_axpy(grad, v, 1.0, lamv + m, m, st));
+    double hd[6] = {0, 0, 0, 0, 0, 0};
+    LM_HIP(hipMemcpyAsync(hd, dots, 2 * dim * sizeof(double), hipMemcpyDeviceToHost, st));
+    LM_HIP(hipStreamSynchronize(st));
+    double e1 = 0.0, e2 = 0.0;
+    for (int c = 0; c < dim; ++c) {
+        e1 += hd[c];
+        e2 += hd[dim + c];
+    }
+    *E_out = 0.5 * e1 + 0.5 * lam * e2;
+    return LM_OK;
 }
 
 }  // extern "C"

@@ -9,6 +9,25 @@
 
 namespace lm {
 
+// Launch shape (measured on MI355X at N = 65536, 3-D, FP64): four waves per workgroup, four
+// sources per unrolled loop body, and at least 16384 workgroups, so that each wave streams a
+// chunk of about a thousand sources.  Short chunks stay in the scalar cache while the four
+// waves of a CU's workgroups reuse them; one chunk per wave of the whole source range (the
+// 1024-workgroup shape) ran 9-12% slower.
+#ifndef LM_WAVES
+#define LM_WAVES 4
+#endif
+#ifndef LM_UNROLL
+#define LM_UNROLL 4
+#endif
+#ifndef LM_MIN_GROUPS
+#define LM_MIN_GROUPS 16384
+#endif
+
+constexpr int kTile = 64;          // targets per workgroup (one per lane)
+constexpr int kWaves = LM_WAVES;   // wavefronts per workgroup
+constexpr int kUnroll = LM_UNROLL; // sources per unrolled loop body
+
 enum EpiKind : int {
     EPI_STORE = 0,   // out_q = v + tau p_i, out_p = f            (right-hand side, K x)
     EPI_RK1 = 1,     // RK4 stage 1: acc = k1,    out = base + dt/2 k1
@@ -48,6 +67,41 @@ struct PairArgs {
     EpiArgs<T> epi;
 };
 
+// Reverse mode (lm_adjoint.hip).
+enum AdjKind : int {
+    ADJ_STORE = 0,   // lam = Ybar (a plain vector-Jacobian product)
+    ADJ_FIRST = 1,   // RK4 stage 4: lam = abar + Ybar, nxt = ca abar + cy Ybar
+    ADJ_MID = 2,     // stages 3 and 2: lam += Ybar, nxt = ca abar + cy Ybar
+    ADJ_LAST = 3     // stage 1: lam += Ybar
+};
+
+struct AdjEpi {
+    int kind;
+    double cscale;          // Ybar = cscale * J^T (cot_q, cot_p)
+    double ca, cy;
+    double tau;
+    const double* cot_q;    // the cotangent the VJP is taken of (its q part feeds the tau term)
+    const double* abar_q;   // cotangent of the RK4 step output
+    const double* abar_p;
+    double* lam_q;          // cotangent of the step input (running sum)
+    double* lam_p;
+    double* nxt_q;          // cotangent of the next (earlier) stage
+    double* nxt_p;
+};
+
+struct VjpArgs {
+    const double* q;        // stage input (dim, n)
+    const double* p;
+    const double* a;        // cotangent of dq/dt (dim, n)
+    const double* b;        // cotangent of dp/dt
+    int64_t n;
+    int64_t jchunk;
+    double kq;              // exponent scale (conon -1/sigma, Gaussian -1/sigma^2)
+    double c1, c2;          // conon: c1 = 1/sigma; Gaussian: c1 = 2/sigma^2, c2 = -4/sigma^4
+    double* part;
+    AdjEpi epi;
+};
+
 struct PairPlan {
     int64_t itiles;
     int nsplit;
@@ -61,6 +115,9 @@ hipError_t launch_pair(int dim, int kernel, bool force, const PairArgs<T>& a, co
                        hipStream_t st);
 
 int reduce_blocks(int64_t m);
+
+hipError_t launch_vjp(int dim, int kernel, const VjpArgs& a, const PairPlan& pl, hipStream_t st);
+hipError_t launch_scale(double* y, double alpha, const double* x, int64_t m, hipStream_t st);
 
 template <class TA, class TB>
 hipError_t launch_maxabsdiff(const TA* x, const TB* y, int64_t m, double* partial, double* out, hipStream_t st);

@@ -29,24 +29,6 @@
 
 namespace lm {
 
-// Launch shape (measured on MI355X at N = 65536, 3-D, FP64): four waves per workgroup, four
-// sources per unrolled loop body, and at least 16384 workgroups, so that each wave streams a
-// chunk of about a thousand sources.  Short chunks stay in the scalar cache while the four
-// waves of a CU's workgroups reuse them; one chunk per wave of the whole source range (the
-// 1024-workgroup shape) ran 9-12% slower.
-#ifndef LM_WAVES
-#define LM_WAVES 4
-#endif
-#ifndef LM_UNROLL
-#define LM_UNROLL 4
-#endif
-#ifndef LM_MIN_GROUPS
-#define LM_MIN_GROUPS 16384
-#endif
-
-constexpr int kTile = 64;          // targets per workgroup (one per lane)
-constexpr int kWaves = LM_WAVES;   // wavefronts per workgroup
-constexpr int kUnroll = LM_UNROLL; // sources per unrolled loop body
 
 // ---------------------------------------------------------------------------------------
 // Pair bodies.  `kq` holds the kernel-argument scale: for the conon -1/sigma, for the

@@ -463,3 +463,107 @@ def test_feedback_with_cg_solver_matches_dense():
         out[solver] = (info.iters, host(p0))
     assert out[lm.SOLVE_CG][0] == out[lm.SOLVE_DENSE][0]
     assert rel_err(out[lm.SOLVE_CG][1], out[lm.SOLVE_DENSE][1]) <= 1e-9
+
+
+# ------------------------------------------------------------------ reverse mode (adjoint)
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("n", [1, 17, 65, 1000])
+def test_rhs_vjp_matches_oracle(n, dim, kernel):
+    q, p = inputs.random_state(n, dim, seed=[110, n, dim], pscale=0.3)
+    rng = np.random.default_rng([111, n])
+    a, b = rng.standard_normal(q.shape), rng.standard_normal(q.shape)
+    prm = lm.make_params(dim, kernel, 0.3, tau=0.2)
+    aq, ap = torch.empty((dim, n), dtype=torch.float64, device=DEV), torch.empty((dim, n), dtype=torch.float64, device=DEV)
+    lm.lm_rhs_vjp(prm, dev(q), dev(p), dev(a), dev(b), aq, ap)
+    torch.cuda.synchronize()
+    oq, op = oracle.rhs_vjp(q, p, a, b, kernel, 0.3, 0.2)
+    print("vjp n=%d dim=%d kernel=%d: %.2e %.2e" % (n, dim, kernel, rel_err(host(aq), oq), rel_err(host(ap), op)))
+    assert rel_err(host(aq), oq) <= 1e-10 and rel_err(host(ap), op) <= 1e-10
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+@pytest.mark.parametrize("ckpt", [0, 1, 7, 20])
+def test_shoot_adjoint_matches_oracle(kernel, ckpt):
+    pr = inputs.config_sphere3d(300, kernel=kernel, sigma=0.3)
+    q0, p0 = pr.X, pr.p_bench()
+    rng = np.random.default_rng(112)
+    gq1, gp1 = rng.standard_normal(q0.shape), rng.standard_normal(q0.shape)
+    oq, op = oracle.shoot_adjoint(q0, p0, gq1, gp1, kernel, pr.sigma, 20, T=0.8, tau=0.1)
+    prm = lm.make_params(3, kernel, pr.sigma, tau=0.1)
+    gq0, gp0 = torch.empty((3, 300), dtype=torch.float64, device=DEV), torch.empty((3, 300), dtype=torch.float64, device=DEV)
+    q1 = torch.empty_like(gq0)
+    lm.lm_shoot_adjoint(prm, dev(q0), dev(p0), 0.8, 20, ckpt, dev(gq1), dev(gp1), gq0, gp0, q1=q1)
+    torch.cuda.synchronize()
+    fq, _ = oracle.shoot(q0, p0, kernel, pr.sigma, 20, T=0.8, tau=0.1)
+    print("adjoint kernel=%d ckpt=%d: %.2e %.2e" % (kernel, ckpt, rel_err(host(gq0), oq), rel_err(host(gp0), op)))
+    assert rel_err(host(gq0), oq) <= 1e-10 and rel_err(host(gp0), op) <= 1e-10
+    assert rel_err(host(q1), fq) <= 1e-10
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_energy_gradient_matches_oracle(kernel):
+    pr = inputs.config_sphere3d(500, kernel=kernel, sigma=0.2)
+    p0 = 0.3 * pr.p_bench()
+    E_o, g_o = oracle.energy_and_grad(pr.X, pr.Y, p0, kernel, pr.sigma, 100.0, 10)
+    prm = lm.make_params(3, kernel, pr.sigma)
+    g = torch.empty((3, 500), dtype=torch.float64, device=DEV)
+    E = lm.lm_energy_grad(prm, dev(pr.X), dev(pr.Y), dev(p0), 100.0, 10, g, ckpt_every=3)
+    assert E == pytest.approx(E_o, rel=1e-11)
+    assert rel_err(host(g), g_o) <= 1e-10
+
+
+def test_energy_gradient_at_rest_closed_form():
+    """At p0 = 0 the flow is at rest and its linearisation is q(1) = X + K(X) dp exactly, so
+    the gradient is lam K(X) (X - Y)."""
+    pr = inputs.config_adjoint3d(1024)
+    prm = lm.make_params(3, lm.GAUSS, pr.sigma)
+    g = torch.empty((3, pr.n), dtype=torch.float64, device=DEV)
+    E = lm.lm_energy_grad(prm, dev(pr.X), dev(pr.Y), dev(np.zeros_like(pr.X)), 100.0, 10, g, ckpt_every=10)
+    K = oracle.kmatrix(pr.X, 1, pr.sigma)
+    want = 100.0 * (K @ (pr.X - pr.Y).T).T
+    assert rel_err(host(g), want) <= 1e-12
+    assert E == pytest.approx(50.0 * np.sum((pr.X - pr.Y) ** 2), rel=1e-13)
+
+
+def test_energy_gradient_finite_differences_on_subset():
+    """Central differences of E on 32 seeded particle indices x 3 components (the
+    differentiation workload's check, at reduced N)."""
+    pr = inputs.config_adjoint3d(2048)
+    prm = lm.make_params(3, lm.GAUSS, pr.sigma)
+    X, Y = dev(pr.X), dev(pr.Y)
+    p = 0.3 * pr.p_bench()
+    g = torch.empty((3, pr.n), dtype=torch.float64, device=DEV)
+    lm.lm_energy_grad(prm, X, Y, dev(p), 100.0, 20, g, ckpt_every=10)
+    gh = host(g)
+    scratch = torch.empty_like(g)
+    eps = 1e-5
+    worst = 0.0
+    for i in pr.extra["fd_idx"]:
+        for c in range(3):
+            e = np.zeros_like(p)
+            e[c, i] = eps
+            Ep = lm.lm_energy_grad(prm, X, Y, dev(p + e), 100.0, 20, scratch, ckpt_every=10)
+            Em = lm.lm_energy_grad(prm, X, Y, dev(p - e), 100.0, 20, scratch, ckpt_every=10)
+            fd = (Ep - Em) / (2 * eps)
+            worst = max(worst, abs(fd - gh[c, i]) / max(abs(gh[c, i]), 1e-3 * np.abs(gh).max()))
+    print("FD worst relative difference %.2e" % worst)
+    assert worst <= 1e-6
+
+
+def test_autograd_function_uses_the_adjoint():
+    from paper_1510_03816_amd.autograd import shoot
+    pr = inputs.config_sphere3d(400, kernel=lm.GAUSS, sigma=0.3)
+    prm = lm.make_params(3, lm.GAUSS, pr.sigma)
+    q0 = dev(pr.X).requires_grad_(True)
+    p0 = dev(pr.p_bench()).requires_grad_(True)
+    q1, p1 = shoot(q0, p0, prm, 1.0, 15, 5)
+    Yt = dev(pr.Y)
+    loss = ((q1 - Yt) ** 2).sum() + (p1 ** 2).sum()
+    loss.backward()
+    gq1 = 2.0 * (host(q1.detach()) - pr.Y)
+    gp1 = 2.0 * host(p1.detach())
+    oq, op = oracle.shoot_adjoint(pr.X, pr.p_bench(), gq1, gp1, 1, pr.sigma, 15)
+    assert rel_err(host(q0.grad), oq) <= 1e-10 and rel_err(host(p0.grad), op) <= 1e-10
