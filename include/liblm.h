@@ -210,13 +210,46 @@ lm_status lm_shoot_adjoint(const lm_params *params, int64_t n, const double *q0,
                            void *stream);
 
 /* Energy of inexact matching and its gradient in the initial momenta:
- *     E(p0) = 1/2 p0^T K(X) p0 + lam/2 |q(1) - Y|^2,   grad = K(X) p0 + J^T (lam (q(1) - Y), 0)
- * (half the paper's inexact energy with lam = 1/sigma^2, the geodesic's kinetic energy
- * written as 2H by eq. "E=2H").  q(1) is the RK4 shoot of (X, p0) over [0, 1]; *E_out is a
- * HOST double; grad (dim, n) must not alias p0; q1 (nullable) receives q(1).  Synchronous. */
+ *     E(p0) = reg/2 p0^T K(X) p0 + lam/2 |q(1) - Y|^2
+ *     grad  = reg K(X) p0 + J^T (lam (q(1) - Y), 0)
+ * With reg = 1 it is half the paper's inexact energy for lam = 1/sigma^2 (the geodesic's
+ * kinetic energy written as 2H by eq. "E=2H"); reg = 0 leaves the least-squares shooting
+ * objective, whose zero is an exact match.  q(1) is the RK4 shoot of (X, p0) over [0, 1];
+ * *E_out is a HOST double; grad (dim, n) must not alias p0; q1 (nullable) receives q(1).
+ * Synchronous. */
 lm_status lm_energy_grad(const lm_params *params, int64_t n, const double *X, const double *Y,
-                         const double *p0, double lam, int32_t steps, int32_t ckpt_every,
+                         const double *p0, double lam, double reg, int32_t steps, int32_t ckpt_every,
                          double *E_out, double *grad, double *q1, void *stream);
+
+/* Settings and report of gradient-based matching (HOST structs). */
+typedef struct lm_lbfgs_opts {
+    double lam;           /* weight of the data term (>= 0) */
+    double reg;           /* weight of the kinetic-energy regulariser (>= 0) */
+    double gtol;          /* stop when max|grad| <= gtol * max|grad| at the start */
+    double match_tol;     /* also stop when max|q(1) - Y| < match_tol (0 = off) */
+    int32_t max_iter;     /* L-BFGS iterations */
+    int32_t history;      /* stored (s, y) pairs, 0 = 8, at most 64 */
+    int32_t steps;        /* RK4 steps per shoot */
+    int32_t ckpt_every;   /* adjoint checkpoint spacing (0 = every stage kept) */
+} lm_lbfgs_opts;
+
+typedef struct lm_lbfgs_info {
+    int32_t iters;        /* L-BFGS iterations made */
+    int32_t evals;        /* energy-and-gradient evaluations (each a shoot and its adjoint) */
+    double E;             /* final energy */
+    double gnorm_inf;     /* final max |grad| */
+    double resid_inf;     /* final max |q(1) - Y| */
+} lm_lbfgs_info;
+
+/* Gradient-based matching: minimises E(p0) of lm_energy_grad by limited-memory BFGS
+ * (two-loop recursion, backtracking Armijo line search) from the momenta in p0, in place.
+ * Every vector operation runs on the GPU; only scalars are read back.  It is the
+ * gradient-descent counterpart of Algorithm 1's feedback iteration.  Synchronous.
+ * LM_OK when a tolerance is met, LM_ENOTCONV after max_iter iterations or a failed line
+ * search, LM_EDIVERGED on a non-finite energy; p0 and info describe the last iterate. */
+lm_status lm_lbfgs_match(const lm_params *params, const lm_lbfgs_opts *opts, int64_t n,
+                         const double *X, const double *Y, double *p0, lm_lbfgs_info *info,
+                         void *stream);
 
 /* Velocity field at arbitrary points (equation "u"): u(x_a) = sum_j G(|x_a - q_j|) p_j.
  * q, p: (dim, n); x, u: (dim, m).  Asynchronous. */

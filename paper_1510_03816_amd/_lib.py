@@ -24,7 +24,7 @@ SOLVE_AUTO, SOLVE_CG, SOLVE_DENSE = 0, 1, 2
 # every symbol include/liblm.h declares
 EXPORTS = ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
            "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
-           "lm_last_error", "lm_version"]
+           "lm_lbfgs_match", "lm_last_error", "lm_version"]
 
 
 class LmError(RuntimeError):
@@ -57,6 +57,17 @@ class lm_step_info(ctypes.Structure):
                 ("converged", ctypes.c_int32), ("cg_iters", ctypes.c_int32)]
 
 
+class lm_lbfgs_opts(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_double), ("reg", ctypes.c_double), ("gtol", ctypes.c_double),
+                ("match_tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("history", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("ckpt_every", ctypes.c_int32)]
+
+
+class lm_lbfgs_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("evals", ctypes.c_int32), ("E", ctypes.c_double),
+                ("gnorm_inf", ctypes.c_double), ("resid_inf", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -66,7 +77,7 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("liblm.so is not built (run __graft_entry__.build() or "
-                              "python -m paper_1510_03816_amd.build)")
+                              "python paper_1510_03816_amd/build.py)")
         L = ctypes.CDLL(LIB_PATH)
         P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         PP = ctypes.POINTER(lm_params)
@@ -81,9 +92,11 @@ def load():
         L.lm_velocity.argtypes = [PP, i64, P, P, i64, P, P, P]
         L.lm_rhs_vjp.argtypes = [PP, i64, P, P, P, P, P, P, P]
         L.lm_shoot_adjoint.argtypes = [PP, i64, P, P, d, i32, i32, P, P, P, P, P, P, P]
-        L.lm_energy_grad.argtypes = [PP, i64, P, P, P, d, i32, i32, ctypes.POINTER(d), P, P, P]
+        L.lm_energy_grad.argtypes = [PP, i64, P, P, P, d, d, i32, i32, ctypes.POINTER(d), P, P, P]
+        L.lm_lbfgs_match.argtypes = [PP, ctypes.POINTER(lm_lbfgs_opts), i64, P, P, P, ctypes.POINTER(lm_lbfgs_info), P]
         for name in ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
-                     "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad"]:
+                     "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
+                     "lm_lbfgs_match"]:
             getattr(L, name).restype = ctypes.c_int
         L.lm_last_error.restype = ctypes.c_char_p
         L.lm_last_error.argtypes = []
@@ -246,15 +259,33 @@ def lm_shoot_adjoint(params: lm_params, q0, p0, t1: float, steps: int, ckpt_ever
 
 
 def lm_energy_grad(params: lm_params, X, Y, p0, lam: float, steps: int, grad, ckpt_every: int = 0, q1=None,
-                   stream=None) -> float:
-    """E(p0) = 1/2 p0^T K p0 + lam/2 |q(1) - Y|^2; writes its gradient to grad, returns E."""
+                   reg: float = 1.0, stream=None) -> float:
+    """E(p0) = reg/2 p0^T K p0 + lam/2 |q(1) - Y|^2; writes its gradient to grad, returns E."""
     dim, n = X.shape
     for t, nm in [(X, "X"), (Y, "Y"), (p0, "p0"), (grad, "grad")] + ([(q1, "q1")] if q1 is not None else []):
         _check_tensor(t, params.dim, n, F64, nm)
     E = ctypes.c_double(0.0)
-    _check(load().lm_energy_grad(ctypes.byref(params), n, _ptr(X), _ptr(Y), _ptr(p0), float(lam), int(steps),
-                                 int(ckpt_every), ctypes.byref(E), _ptr(grad), _ptr(q1), _stream(stream)))
+    _check(load().lm_energy_grad(ctypes.byref(params), n, _ptr(X), _ptr(Y), _ptr(p0), float(lam), float(reg),
+                                 int(steps), int(ckpt_every), ctypes.byref(E), _ptr(grad), _ptr(q1),
+                                 _stream(stream)))
     return E.value
+
+
+def lm_lbfgs_match(params: lm_params, X, Y, p0, lam: float, steps: int, reg: float = 1.0, gtol: float = 1e-6,
+                   match_tol: float = 0.0, max_iter: int = 200, history: int = 8, ckpt_every: int = 10,
+                   stream=None, raise_on=(LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_EUNSUPPORTED)):
+    """Gradient-based matching by L-BFGS on the GPU, in place on p0.  Returns (status, info)."""
+    dim, n = X.shape
+    for t, nm in [(X, "X"), (Y, "Y"), (p0, "p0")]:
+        _check_tensor(t, params.dim, n, F64, nm)
+    o = lm_lbfgs_opts(float(lam), float(reg), float(gtol), float(match_tol), int(max_iter), int(history),
+                      int(steps), int(ckpt_every))
+    info = lm_lbfgs_info()
+    st = load().lm_lbfgs_match(ctypes.byref(params), ctypes.byref(o), n, _ptr(X), _ptr(Y), _ptr(p0),
+                               ctypes.byref(info), _stream(stream))
+    if st in raise_on:
+        raise LmError(st, last_error())
+    return st, info
 
 
 def lm_version() -> str:

@@ -1,4 +1,8 @@
-"""Build the HIP library liblm.so in-tree for gfx950 (python -m paper_1510_03816_amd.build)."""
+"""Build the HIP library liblm.so in-tree for gfx950 (python paper_1510_03816_amd/build.py).
+
+Run it as a script (or through __graft_entry__.build()): importing the package loads the
+library, so it cannot be the way to build it.
+"""
 
 from __future__ import annotations
 

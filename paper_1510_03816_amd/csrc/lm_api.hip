@@ -802,12 +802,228 @@ lm_status adjoint_reverse(const lm_params* prm, int64_t n, AdjointWork& W, const
     return LM_OK;
 }
 
+
 lm_status check_adjoint_params(const lm_params* prm)
 {
     LM_TRY(check_params(prm));
     if (prm->dtype != LM_F64) return fail(LM_EUNSUPPORTED, "the adjoint is provided in double precision only");
     if (prm->cutoff > 0.0) return fail(LM_EUNSUPPORTED, "the adjoint is provided for every-pair sums only (cutoff = 0)");
     return LM_OK;
+}
+
+// Buffers of energy/gradient evaluations: the adjoint's, plus K p0, the residual reductions
+// and q(1).
+struct EnergyWork {
+    AdjointWork W;
+    double *v = nullptr, *red = nullptr, *dots = nullptr, *red2 = nullptr, *rmax = nullptr;
+    int64_t m = 0;
+    lm_status alloc(Workspace& ws, const lm_params* prm, int64_t n, int32_t steps, int32_t ckpt_every)
+    {
+        LM_TRY(W.alloc(ws, prm, n, 1.0, steps, ckpt_every));
+        m = W.m;
+        LM_TRY(ws.get(&v, m));
+        LM_TRY(ws.get(&red, (int64_t)lm::reduce_blocks(m) * 3));
+        LM_TRY(ws.get(&dots, 8));
+        LM_TRY(ws.get(&red2, lm::reduce_blocks(m)));
+        LM_TRY(ws.get(&rmax, 1));
+        return LM_OK;
+    }
+};
+
+// E(p0) = reg/2 p0^T K(X) p0 + lam/2 |q(1) - Y|^2 and grad = reg K(X) p0 + J^T (lam (q(1) - Y), 0);
+// *resid (nullable) receives max |q(1) - Y|.
+lm_status energy_grad_impl(const lm_params* prm, int64_t n, const double* X, const double* Y, const double* p0,
+                           double lam, double reg, EnergyWork& E, double* E_out, double* grad, double* q1,
+                           double* resid, hipStream_t st)
+{
+    const int dim = prm->dim;
+    AdjointWork& W = E.W;
+    const int64_t m = W.m;
+    lm::EpiArgs<double> ev{};
+    ev.kind = lm::EPI_STORE;
+    ev.tau = 0.0;
+    ev.out_q = E.v;
+    LM_TRY(pair_eval<double>(prm, false, X, p0, n, X, p0, n, ev, W.part, st));
+    LM_HIP(lm::launch_dots(p0, E.v, n, dim, E.red, E.dots, st));
+    const double* yT = nullptr;
+    LM_TRY(adjoint_forward(prm, n, X, p0, W, &yT, st));
+    if (q1) LM_HIP(hipMemcpyAsync(q1, yT, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LM_HIP(lm::launch_sub(W.C0, yT, Y, m, st));
+    LM_HIP(lm::launch_dots(W.C0, W.C0, n, dim, E.red, E.dots + 3, st));
+    if (resid) LM_HIP((lm::launch_maxabsdiff<double, double>(yT, Y, m, E.red2, E.rmax, st)));
+    LM_HIP(lm::launch_scale(W.L0, lam, W.C0, m, st));
+    LM_HIP(lm::launch_zero(W.L0 + m, m, st));
+    const double* lamv = nullptr;
+    LM_TRY(adjoint_reverse(prm, n, W, &lamv, st));
+    LM_HIP(lm::launch_axpy(grad, lamv + m, reg, E.v, m, st));
+    double hd[7] = {0, 0, 0, 0, 0, 0, 0};
+    LM_HIP(hipMemcpyAsync(hd, E.dots, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (resid) LM_HIP(hipMemcpyAsync(hd + 6, E.rmax, sizeof(double), hipMemcpyDeviceToHost, st));
+    LM_HIP(hipStreamSynchronize(st));
+    double e1 = 0.0, e2 = 0.0;
+    for (int c = 0; c < dim; ++c) {
+        e1 += hd[c];
+        e2 += hd[3 + c];
+    }
+    *E_out = 0.5 * reg * e1 + 0.5 * lam * e2;
+    if (resid) *resid = hd[6];
+    return LM_OK;
+}
+
+// Full dot product of two m-vectors (read back to the host).
+lm_status dot_host(const double* x, const double* y, int64_t m, EnergyWork& E, double* out, hipStream_t st)
+{
+    LM_HIP(lm::launch_dots(x, y, m, 1, E.red, E.dots + 6, st));
+    LM_HIP(hipMemcpyAsync(out, E.dots + 6, sizeof(double), hipMemcpyDeviceToHost, st));
+    LM_HIP(hipStreamSynchronize(st));
+    return LM_OK;
+}
+
+lm_status maxabs_host(const double* x, int64_t m, const double* zeros, EnergyWork& E, double* out, hipStream_t st)
+{
+    LM_HIP((lm::launch_maxabsdiff<double, double>(x, zeros, m, E.red2, E.rmax, st)));
+    LM_HIP(hipMemcpyAsync(out, E.rmax, sizeof(double), hipMemcpyDeviceToHost, st));
+    LM_HIP(hipStreamSynchronize(st));
+    return LM_OK;
+}
+
+// Limited-memory BFGS (two-loop recursion) with a backtracking Armijo line search that also
+// expands a first step of unit length in p.  Every vector operation runs on the GPU; the
+// host keeps the scalars (dot products, step lengths) that decide the next launch.
+lm_status lbfgs_impl(const lm_params* prm, const lm_lbfgs_opts* o, int64_t n, const double* X, const double* Y,
+                     double* x, lm_lbfgs_info* info, EnergyWork& E, Workspace& ws, hipStream_t st)
+{
+    const int64_t m = (int64_t)prm->dim * n;
+    const int hm = o->history > 0 ? o->history : 8;
+    double *g, *d, *xn, *gn, *xt, *gt, *qv, *zeros, *S, *Yh;
+    LM_TRY(ws.get(&xt, m));
+    LM_TRY(ws.get(&gt, m));
+    LM_TRY(ws.get(&g, m));
+    LM_TRY(ws.get(&d, m));
+    LM_TRY(ws.get(&xn, m));
+    LM_TRY(ws.get(&gn, m));
+    LM_TRY(ws.get(&qv, m));
+    LM_TRY(ws.get(&zeros, m));
+    LM_TRY(ws.get(&S, (int64_t)hm * m));
+    LM_TRY(ws.get(&Yh, (int64_t)hm * m));
+    LM_HIP(lm::launch_zero(zeros, m, st));
+    std::vector<double> rho(hm, 0.0), alpha(hm, 0.0);
+    int stored = 0, newest = -1;
+    double f = 0.0, resid = 0.0;
+    LM_TRY(energy_grad_impl(prm, n, X, Y, x, o->lam, o->reg, E, &f, g, nullptr, &resid, st));
+    info->evals = 1;
+    double g0 = 0.0;
+    LM_TRY(maxabs_host(g, m, zeros, E, &g0, st));
+    double gmax = g0;
+    lm_status result = LM_ENOTCONV;
+    int it = 0;
+    for (it = 0;; ++it) {
+        if (!is_finite(f) || !is_finite(gmax)) {
+            result = fail(LM_EDIVERGED, "L-BFGS: non-finite energy or gradient");
+            break;
+        }
+        if (gmax <= o->gtol * g0 || (o->match_tol > 0.0 && resid < o->match_tol)) {
+            result = LM_OK;
+            break;
+        }
+        if (it >= o->max_iter) {
+            result = fail(LM_ENOTCONV, "L-BFGS: %d iterations (max|grad| %.3g, residual %.3g)", it, gmax, resid);
+            break;
+        }
+        // two-loop recursion: d = -H g
+        LM_HIP(hipMemcpyAsync(qv, g, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        for (int k = 0; k < stored; ++k) {
+            const int i = (newest - k + hm) % hm;
+            double sq = 0.0;
+            LM_TRY(dot_host(S + (int64_t)i * m, qv, m, E, &sq, st));
+            alpha[i] = rho[i] * sq;
+            LM_HIP(lm::launch_axpy(qv, qv, -alpha[i], Yh + (int64_t)i * m, m, st));
+        }
+        double gamma;
+        if (stored > 0) {
+            double sy = 0.0, yy = 0.0;
+            LM_TRY(dot_host(S + (int64_t)newest * m, Yh + (int64_t)newest * m, m, E, &sy, st));
+            LM_TRY(dot_host(Yh + (int64_t)newest * m, Yh + (int64_t)newest * m, m, E, &yy, st));
+            gamma = sy / yy;
+        } else {
+            double gg = 0.0;
+            LM_TRY(dot_host(g, g, m, E, &gg, st));
+            gamma = 1.0 / std::sqrt(gg);       // first step: unit length in p
+        }
+        LM_HIP(lm::launch_scale(qv, gamma, qv, m, st));
+        for (int k = stored - 1; k >= 0; --k) {
+            const int i = (newest - k + hm) % hm;
+            double yr = 0.0;
+            LM_TRY(dot_host(Yh + (int64_t)i * m, qv, m, E, &yr, st));
+            const double beta = rho[i] * yr;
+            LM_HIP(lm::launch_axpy(qv, qv, alpha[i] - beta, S + (int64_t)i * m, m, st));
+        }
+        LM_HIP(lm::launch_scale(d, -1.0, qv, m, st));
+        double gd = 0.0;
+        LM_TRY(dot_host(g, d, m, E, &gd, st));
+        if (!(gd < 0.0)) {   // not a descent direction: restart from the scaled gradient
+            stored = 0;
+            double gg = 0.0;
+            LM_TRY(dot_host(g, g, m, E, &gg, st));
+            LM_HIP(lm::launch_scale(d, -1.0 / std::sqrt(gg), g, m, st));
+            gd = -std::sqrt(gg);
+        }
+        // backtracking Armijo (c1 = 1e-4); on the first iteration also expand while it pays
+        double t = 1.0, fn = 0.0, rn = 0.0;
+        bool ok = false;
+        for (int ls = 0; ls < 40; ++ls) {
+            LM_HIP(lm::launch_axpy(xn, x, t, d, m, st));
+            LM_TRY(energy_grad_impl(prm, n, X, Y, xn, o->lam, o->reg, E, &fn, gn, nullptr, &rn, st));
+            ++info->evals;
+            if (is_finite(fn) && fn <= f + 1e-4 * t * gd) {
+                ok = true;
+                break;
+            }
+            t *= 0.5;
+        }
+        if (!ok) {
+            result = fail(LM_ENOTCONV, "L-BFGS: line search failed at iteration %d", it);
+            break;
+        }
+        if (it == 0) {
+            // expansion of the very first step: double t while the energy keeps falling
+            for (int ex = 0; ex < 30; ++ex) {
+                double f2 = 0.0, r2 = 0.0;
+                LM_HIP(lm::launch_axpy(xt, x, 2.0 * t, d, m, st));
+                LM_TRY(energy_grad_impl(prm, n, X, Y, xt, o->lam, o->reg, E, &f2, gt, nullptr, &r2, st));
+                ++info->evals;
+                if (!(is_finite(f2) && f2 < fn)) break;
+                t *= 2.0;
+                fn = f2;
+                rn = r2;
+                std::swap(xn, xt);
+                std::swap(gn, gt);
+            }
+        }
+        // history pair s = xn - x, y = gn - g
+        const int slot = (newest + 1) % hm;
+        double* sv = S + (int64_t)slot * m;
+        double* yv = Yh + (int64_t)slot * m;
+        LM_HIP(lm::launch_sub(sv, xn, x, m, st));
+        LM_HIP(lm::launch_sub(yv, gn, g, m, st));
+        double sy = 0.0;
+        LM_TRY(dot_host(sv, yv, m, E, &sy, st));
+        if (sy > 0.0) {
+            rho[slot] = 1.0 / sy;
+            newest = slot;
+            if (stored < hm) ++stored;
+        }
+        LM_HIP(hipMemcpyAsync(x, xn, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        LM_HIP(hipMemcpyAsync(g, gn, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        f = fn;
+        resid = rn;
+        LM_TRY(maxabs_host(g, m, zeros, E, &gmax, st));
+    }
+    info->iters = it;
+    info->E = f;
+    info->gnorm_inf = gmax;
+    info->resid_inf = resid;
+    return result;
 }
 
 }  // namespace
@@ -1061,54 +1277,40 @@ lm_status lm_shoot_adjoint(const lm_params* prm, int64_t n, const double* q0, co
 }
 
 lm_status lm_energy_grad(const lm_params* prm, int64_t n, const double* X, const double* Y, const double* p0,
-                         double lam, int32_t steps, int32_t ckpt_every, double* E_out, double* grad, double* q1,
-                         void* stream)
+                         double lam, double reg, int32_t steps, int32_t ckpt_every, double* E_out, double* grad,
+                         double* q1, void* stream)
 {
     LM_TRY(check_adjoint_params(prm));
     LM_TRY(check_n(n));
     if (!X || !Y || !p0 || !E_out || !grad) return fail(LM_EINVAL, "NULL pointer");
-    if (!(lam >= 0.0) || !is_finite(lam)) return fail(LM_EINVAL, "lam must be >= 0 and finite");
+    if (!(lam >= 0.0) || !is_finite(lam) || !(reg >= 0.0) || !is_finite(reg))
+        return fail(LM_EINVAL, "lam and reg must be >= 0 and finite");
     if (steps < 1 || ckpt_every < 0) return fail(LM_EINVAL, "bad steps or ckpt_every");
-    const int p0_alias = (grad == p0);
-    if (p0_alias) return fail(LM_EINVAL, "grad must not alias p0");
+    if (grad == p0) return fail(LM_EINVAL, "grad must not alias p0");
     hipStream_t st = (hipStream_t)stream;
-    const int dim = prm->dim;
     Workspace ws(st);
-    AdjointWork W;
-    LM_TRY(W.alloc(ws, prm, n, 1.0, steps, ckpt_every));
-    const int64_t m = W.m;
-    double *v, *red, *dots;
-    LM_TRY(ws.get(&v, m));
-    LM_TRY(ws.get(&red, (int64_t)lm::reduce_blocks(n) * dim));
-    LM_TRY(ws.get(&dots, 2 * dim));
-    // regulariser 1/2 p0^T K(X) p0 and its gradient K(X) p0
-    lm::EpiArgs<double> ev{};
-    ev.kind = lm::EPI_STORE;
-    ev.tau = 0.0;
-    ev.out_q = v;
-    LM_TRY(pair_eval<double>(prm, false, X, p0, n, X, p0, n, ev, W.part, st));
-    LM_HIP(lm::launch_dots(p0, v, n, dim, red, dots, st));
-    // data term lam/2 |q(1) - Y|^2 and its cotangent lam (q(1) - Y)
-    const double* yT = nullptr;
-    LM_TRY(adjoint_forward(prm, n, X, p0, W, &yT, st));
-    if (q1) LM_HIP(hipMemcpyAsync(q1, yT, m * sizeof(double), hipMemcpyDeviceToDevice, st));
-    LM_HIP(lm::launch_sub(W.C0, yT, Y, m, st));
-    LM_HIP(lm::launch_dots(W.C0, W.C0, n, dim, red, dots + dim, st));
-    LM_HIP(lm::launch_scale(W.L0, lam, W.C0, m, st));
-    LM_HIP(lm::launch_zero(W.L0 + m, m, st));
-    const double* lamv = nullptr;
-    LM_TRY(adjoint_reverse(prm, n, W, &lamv, st));
-    LM_HIP(lm::launch_axpy(grad, v, 1.0, lamv + m, m, st));
-    double hd[6] = {0, 0, 0, 0, 0, 0};
-    LM_HIP(hipMemcpyAsync(hd, dots, 2 * dim * sizeof(double), hipMemcpyDeviceToHost, st));
-    LM_HIP(hipStreamSynchronize(st));
-    double e1 = 0.0, e2 = 0.0;
-    for (int c = 0; c < dim; ++c) {
-        e1 += hd[c];
-        e2 += hd[dim + c];
-    }
-    *E_out = 0.5 * e1 + 0.5 * lam * e2;
-    return LM_OK;
+    EnergyWork E;
+    LM_TRY(E.alloc(ws, prm, n, steps, ckpt_every));
+    return energy_grad_impl(prm, n, X, Y, p0, lam, reg, E, E_out, grad, q1, nullptr, st);
+}
+
+lm_status lm_lbfgs_match(const lm_params* prm, const lm_lbfgs_opts* o, int64_t n, const double* X, const double* Y,
+                         double* p0, lm_lbfgs_info* info, void* stream)
+{
+    LM_TRY(check_adjoint_params(prm));
+    LM_TRY(check_n(n));
+    if (!o || !info || !X || !Y || !p0) return fail(LM_EINVAL, "NULL pointer");
+    if (!(o->lam >= 0.0) || !(o->reg >= 0.0) || !is_finite(o->lam) || !is_finite(o->reg))
+        return fail(LM_EINVAL, "lam and reg must be >= 0 and finite");
+    if (o->max_iter < 0 || o->steps < 1 || o->ckpt_every < 0 || o->history < 0 || o->history > 64)
+        return fail(LM_EINVAL, "bad iteration settings");
+    if (!(o->gtol >= 0.0) || !(o->match_tol >= 0.0)) return fail(LM_EINVAL, "tolerances must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    std::memset(info, 0, sizeof *info);
+    Workspace ws(st);
+    EnergyWork EW;
+    LM_TRY(EW.alloc(ws, prm, n, o->steps, o->ckpt_every));
+    return lbfgs_impl(prm, o, n, X, Y, p0, info, EW, ws, st);
 }
 
 }  // extern "C"

@@ -567,3 +567,43 @@ def test_autograd_function_uses_the_adjoint():
     gp1 = 2.0 * host(p1.detach())
     oq, op = oracle.shoot_adjoint(pr.X, pr.p_bench(), gq1, gp1, 1, pr.sigma, 15)
     assert rel_err(host(q0.grad), oq) <= 1e-10 and rel_err(host(p0.grad), op) <= 1e-10
+
+
+# ------------------------------------------------------------------ gradient-based matching
+
+
+@pytest.mark.parametrize("kernel,gtol,tol", [(lm.CONON, 1e-9, 1e-8), (lm.GAUSS, 1e-5, 1e-4)])
+def test_lbfgs_minimiser_has_zero_oracle_gradient(kernel, gtol, tol):
+    """The GPU optimiser's result is checked with the oracle's gradient (an independent
+    evaluation), and against the optimality condition of the continuous problem, under
+    which the final momenta equal -lam (q(1) - Y) (up to the RK4 error).  The Gaussian
+    kernel matrix is far worse conditioned, so its bar is looser."""
+    pr = inputs.config_sphere3d(200, kernel=kernel, sigma=0.3)
+    prm = lm.make_params(3, kernel, pr.sigma)
+    p0 = torch.zeros((3, 200), dtype=torch.float64, device=DEV)
+    st, info = lm.lm_lbfgs_match(prm, dev(pr.X), dev(pr.Y), p0, lam=100.0, steps=20, gtol=gtol, max_iter=1000,
+                                 history=16)
+    print("lbfgs kernel %d: %d its, %d evals, E %.6g, |g| %.2e, resid %.2e" % (
+        kernel, info.iters, info.evals, info.E, info.gnorm_inf, info.resid_inf))
+    assert st == 0
+    E0, g0 = oracle.energy_and_grad(pr.X, pr.Y, np.zeros_like(pr.X), kernel, pr.sigma, 100.0, 20)
+    E, g = oracle.energy_and_grad(pr.X, pr.Y, host(p0), kernel, pr.sigma, 100.0, 20)
+    assert E == pytest.approx(info.E, rel=1e-10)
+    assert np.max(np.abs(g)) <= tol * np.max(np.abs(g0))
+    q1, p1 = oracle.shoot(pr.X, host(p0), kernel, pr.sigma, 20)
+    print("optimality: |p(1) + lam (q(1) - Y)| / |p(1)| = %.2e" % rel_err(p1, -100.0 * (q1 - pr.Y)))
+    if kernel == lm.CONON:   # converged to 1e-9: the condition holds to the RK4 error
+        assert rel_err(p1, -100.0 * (q1 - pr.Y)) <= 1e-4
+
+
+def test_lbfgs_least_squares_reaches_exact_match():
+    """reg = 0 leaves the least-squares shooting objective; its zero is an exact match."""
+    pr = inputs.config_circle_ellipse(64)
+    prm = lm.make_params(2, lm.CONON, pr.sigma)
+    p0 = torch.zeros((2, 64), dtype=torch.float64, device=DEV)
+    st, info = lm.lm_lbfgs_match(prm, dev(pr.X), dev(pr.Y), p0, lam=1.0, reg=0.0, steps=pr.steps, gtol=0.0,
+                                 match_tol=1e-6, max_iter=2000, history=16)
+    print("least squares: %d its, %d evals, resid %.2e" % (info.iters, info.evals, info.resid_inf))
+    assert st == 0 and info.resid_inf < 1e-6
+    q1, _ = oracle.shoot(pr.X, host(p0), 0, pr.sigma, pr.steps)
+    assert np.max(np.abs(q1 - pr.Y)) < 1.1e-6
