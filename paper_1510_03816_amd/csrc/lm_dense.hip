@@ -7,15 +7,16 @@
 // N = 65536 the factor is 34 GB, resident in HBM.
 //
 // Layout: K is row-major n x n (leading dimension n); only the lower triangle is built, read
-// or written (the upper triangle of the diagonal tiles may hold scratch).  Blocked
-// right-looking factorisation with panels of kPanel = 128 columns:
-//   1. lm_potrf_diag_kernel  -- factor the 128 x 128 diagonal block in LDS (one workgroup);
-//   2. lm_trinv_kernel       -- invert that triangular block (kept: the sweeps reuse it);
-//   3. lm_panel_kernel       -- panel rows below: A_ik <- A_ik L_kk^{-T} (one workgroup per
-//                               64 rows, the rows staged in LDS);
-//   4. lm_syrk_kernel        -- trailing update A_ij -= A_ik A_jk^T on 64 x 64 lower tiles,
-//                               FP64 MFMA (v_mfma_f64_16x16x4f64): the only dense
-//                               contraction of the path, N^3/3 flops.
+// or written.  Blocked right-looking factorisation with panels of kPanel = 128 columns, the
+// trailing matrix updated once per block of kOuter panels:
+//   1. lm_potrf_inv_kernel -- factor the 128 x 128 diagonal block in LDS and invert it (the
+//                             inverse is kept: the panel solve and the sweeps reuse it);
+//   2. lm_panel_kernel     -- panel rows below: A_ik <- A_ik L_kk^{-T} (FP64 MFMA);
+//   3. lm_syrk_kernel      -- within a block, the next panel's column strip takes the
+//                             updates of the block's earlier panels (64 x 64 tiles);
+//   4. lm_syrk128_kernel   -- after the block, the trailing update A_ij -= A_ik A_jk^T
+//                             (128 x 128 tiles; 64 x 64 once the trailing matrix is small):
+//                             the only large dense contraction of the path, N^3/3 flops.
 // Solves: blocked forward (L y = b) and backward (L^T x = y) sweeps, one launch per panel;
 // in launch k every workgroup subtracts panel k's contribution from its rows, and the
 // workgroup that owns block k+1 (k-1 backward) then finishes that block with the stored
@@ -29,6 +30,11 @@
 namespace lm {
 
 constexpr int kPanel = 128;
+
+// Panels per trailing update (the update of a block of kOuter panels reads and writes the
+// trailing matrix once; measured on MI355X at N = 65536: 5.8 s for 1 panel, 4.7 s for 2, 4.3 s
+// for 8 with the other kernels then in use).
+constexpr int kOuter = 8;
 
 // ---------------------------------------------------------------------------------------
 // K_ij = G(|X_i - X_j|) (+ tau on the diagonal) for j <= i.  One workgroup per row.
@@ -55,184 +61,326 @@ __global__ __launch_bounds__(256) void lm_kbuild_kernel(const double* __restrict
 }
 
 // ---------------------------------------------------------------------------------------
-// Diagonal block: unblocked right-looking Cholesky of the bs x bs block at (k0, k0), held in
-// LDS in packed lower-triangular form (bs <= 128: 8256 doubles).  A non-positive pivot sets
-// *info = k0 + j + 1 (the factor is then meaningless).
+// Diagonal block, factor and inverse in one pass: the bs x bs block at (k0, k0) is held in
+// LDS as a full 128 x 129 array.  Cholesky is left-looking by columns: for column c, two
+// threads per row r >= c form A_rc - sum_{k<c} L_rk L_ck (even and odd k), the pivot thread
+// takes the square root, and the rows below divide by it.  A non-positive pivot sets
+// *info = k0 + c + 1 (the factor is then meaningless).  The inverse is then formed by
+// forward substitution, two threads per column j of Linv, whose entries (r >= j) are kept in
+// the unused upper triangle at A[j][r + 1].  Outputs: the factor written back over the
+// block, and Linv (kPanel x kPanel, row-major, zero above the diagonal and outside bs).
+// The loops are bound by LDS traffic and latency (about 0.37 ms per block on MI355X, a few
+// per cent of a large factorization).
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; }
-
-__global__ __launch_bounds__(256) void lm_potrf_diag_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
-                                                            int* __restrict__ info)
+__global__ __launch_bounds__(256) void lm_potrf_inv_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
+                                                           double* __restrict__ Linv, int* __restrict__ info)
 {
-    __shared__ double L[kPanel * (kPanel + 1) / 2];
+    __shared__ double A[kPanel][kPanel + 1];
     const int tid = threadIdx.x;
-    const int ne = bs * (bs + 1) / 2;
-    for (int e = tid; e < ne; e += blockDim.x) {
-        // invert the packed index: row r with r(r+1)/2 <= e
-        int r = (int)((__builtin_sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (pk(r + 1, 0) <= e) ++r;
-        while (pk(r, 0) > e) --r;
-        const int c = e - pk(r, 0);
-        L[e] = K[(k0 + r) * n + k0 + c];
+    // global loads are issued in batches of 8 before any is stored (a load-store loop would
+    // wait out the memory latency once per element)
+    for (int e0 = tid; e0 < kPanel * kPanel; e0 += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u, r = e / kPanel, c = e % kPanel;
+            v[u] = (r < bs && c <= r) ? K[(k0 + r) * n + k0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + 256 * u;
+            A[e / kPanel][e % kPanel] = v[u];
+        }
     }
     __syncthreads();
-    for (int j = 0; j < bs; ++j) {
-        const double d = L[pk(j, j)];
-        const bool ok = d > 0.0;
-        const double ljj = ok ? __builtin_sqrt(d) : __builtin_nan("");
-        __syncthreads();
-        if (tid == 0) {
-            L[pk(j, j)] = ljj;
-            if (!ok && *info == 0) *info = (int)(k0 + j + 1);
+    const int h = tid & 1, pr = tid >> 1;
+    for (int c = 0; c < bs; ++c) {
+        const int r = c + pr;
+        double v = 0.0;
+        if (r < bs) {
+            double s0 = 0.0, s1 = 0.0;
+            int k = h;
+            for (; k + 2 < c; k += 4) {
+                s0 = __builtin_fma(A[r][k], A[c][k], s0);
+                s1 = __builtin_fma(A[r][k + 2], A[c][k + 2], s1);
+            }
+            for (; k < c; k += 2) s0 = __builtin_fma(A[r][k], A[c][k], s0);
+            v = s0 + s1;
         }
-        for (int r = j + 1 + tid; r < bs; r += blockDim.x) L[pk(r, j)] /= ljj;
-        __syncthreads();
-        // trailing update of the block: L[r][c] -= L[r][j] L[c][j], j < c <= r
-        const int m = bs - j - 1;
-        const int cnt = m * (m + 1) / 2;
-        for (int e = tid; e < cnt; e += blockDim.x) {
-            int rr = (int)((__builtin_sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-            while (pk(rr + 1, 0) <= e) ++rr;
-            while (pk(rr, 0) > e) --rr;
-            const int cc = e - pk(rr, 0);
-            const int r = j + 1 + rr, c = j + 1 + cc;
-            L[pk(r, c)] -= L[pk(r, j)] * L[pk(c, j)];
+        v += __shfl_xor(v, 1);
+        if (r < bs) v = A[r][c] - v;
+        if (r == c && h == 0) {
+            const bool ok = v > 0.0;
+            A[c][c] = ok ? __builtin_sqrt(v) : __builtin_nan("");
+            if (!ok && *info == 0) *info = (int)(k0 + c + 1);
         }
+        __syncthreads();
+        if (r > c && r < bs && h == 0) A[r][c] = v / A[c][c];
         __syncthreads();
     }
-    for (int e = tid; e < ne; e += blockDim.x) {
-        int r = (int)((__builtin_sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (pk(r + 1, 0) <= e) ++r;
-        while (pk(r, 0) > e) --r;
-        const int c = e - pk(r, 0);
-        K[(k0 + r) * n + k0 + c] = L[e];
+    for (int e = tid; e < kPanel * kPanel; e += blockDim.x) {
+        const int r = e / kPanel, c = e % kPanel;
+        if (r < bs && c <= r) K[(k0 + r) * n + k0 + c] = A[r][c];
+    }
+    // inverse: x_j = 1/L_jj, x_r = -(sum_{l=j}^{r-1} L_rl x_l) / L_rr; both threads of a
+    // pair compute and store every x_r, so each reads back only its own stores
+    const int j = pr;
+    if (j < bs) {
+        A[j][j + 1] = 1.0 / A[j][j];
+        for (int r = j + 1; r < bs; ++r) {
+            double s = 0.0;
+            for (int l = j + h; l < r; l += 2) s = __builtin_fma(A[r][l], A[j][l + 1], s);
+            s += __shfl_xor(s, 1);
+            A[j][r + 1] = -s / A[r][r];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kPanel * kPanel; e += blockDim.x) {
+        const int r = e / kPanel, c = e % kPanel;
+        Linv[e] = (r < bs && c <= r) ? A[c][r + 1] : 0.0;
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// Inverse of the lower-triangular diagonal block at (k0, k0): Linv (kPanel x kPanel,
-// row-major, zero above the diagonal and outside bs).  Thread j computes column j by forward
-// substitution; the block is read from LDS (packed).
+// FP64 MFMA.  Every dense contraction here uses v_mfma_f64_4x4x4f64 (four independent
+// 4x4x4 products per instruction): on gfx950 it sustains about twice the FP64 rate of the
+// 16x16x4 form (measured 73 vs 36 TFLOP/s).  Operand layout (measured): lane l works on
+// block (l/4)%4 with A[l%4][l/16], B[l/16][l%4] and D[l/16][l%4].  A wave that issues the
+// instruction with left operand M[16a + l%16][k] and right operand N[4c + l%4][k] therefore
+// accumulates (M N^T) over rows 16a + 4((l/4)%4) + l/16 and column 4c + l%4.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kPanel) void lm_trinv_kernel(const double* __restrict__ K, int64_t n, int64_t k0, int bs,
-                                                          double* __restrict__ Linv)
+__device__ __forceinline__ double mfma4(double a, double b, double c)
 {
-    __shared__ double L[kPanel * (kPanel + 1) / 2];
-    const int j = threadIdx.x;
-    const int ne = bs * (bs + 1) / 2;
-    for (int e = j; e < ne; e += blockDim.x) {
-        int r = (int)((__builtin_sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (pk(r + 1, 0) <= e) ++r;
-        while (pk(r, 0) > e) --r;
-        const int c = e - pk(r, 0);
-        L[e] = K[(k0 + r) * n + k0 + c];
-    }
-    __syncthreads();
-    for (int r = 0; r < kPanel; ++r) Linv[r * kPanel + j] = 0.0;
-    if (j >= bs) return;
-    // x_r = 0 for r < j ; x_j = 1/L_jj ; x_r = -(sum_{l=j}^{r-1} L_rl x_l)/L_rr
-    Linv[j * kPanel + j] = 1.0 / L[pk(j, j)];
-    for (int r = j + 1; r < bs; ++r) {
-        double s = 0.0;
-        for (int l = j; l < r; ++l) s = __builtin_fma(L[pk(r, l)], Linv[l * kPanel + j], s);
-        Linv[r * kPanel + j] = -s / L[pk(r, r)];
-    }
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ int mfma4_row(int lane) { return 4 * ((lane >> 2) & 3) + (lane >> 4); }
 
 // ---------------------------------------------------------------------------------------
 // Panel below the diagonal block: rows i in [k0+bs, n), columns [k0, k0+bs):
-// A_ik <- A_ik L_kk^{-T}, i.e. A[i][c] = sum_{m <= c} A[i][m] Linv[c][m].  One workgroup per
-// 64 rows; the rows are staged in LDS so the update can be written in place.
+// A_ik <- A_ik L_kk^{-T}, a 64 x 128 by 128 x 128 product per workgroup.  Linv is staged in
+// LDS; wave w holds its 16 rows of A as left operands in registers (all 32 k-steps) before
+// it writes any of them back, so the update is in place.  Columns at or past bs read as zero
+// (Linv is zero there).
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void lm_panel_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
                                                        const double* __restrict__ Linv)
 {
-    __shared__ double rows[64][kPanel + 1];
-    const int64_t r0 = k0 + bs + (int64_t)blockIdx.x * 64;
-    const int nr = (int)((n - r0) < 64 ? (n - r0) : 64);
-    for (int e = threadIdx.x; e < 64 * kPanel; e += blockDim.x) {
-        const int r = e / kPanel, c = e % kPanel;
-        rows[r][c] = (r < nr && c < bs) ? K[(r0 + r) * n + k0 + c] : 0.0;
+    constexpr int LD = kPanel + 4;     // row pitch of the staged Linv
+    __shared__ double Ls[kPanel * LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < kPanel * kPanel; e += blockDim.x) Ls[(e / kPanel) * LD + e % kPanel] = Linv[e];
+    const int64_t rbase = k0 + bs + (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t row = rbase + (lane & 15);
+    const bool okr = row < n;
+    double a[kPanel / 4];
+#pragma unroll
+    for (int s = 0; s < kPanel / 4; ++s) {
+        const int m = 4 * s + (lane >> 4);
+        a[s] = (okr && m < bs) ? K[row * n + k0 + m] : 0.0;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nr * bs; e += blockDim.x) {
-        const int r = e / bs, c = e % bs;
-        const double* li = Linv + c * kPanel;
-        double s = 0.0;
-        for (int m = 0; m <= c; ++m) s = __builtin_fma(rows[r][m], li[m], s);
-        K[(r0 + r) * n + k0 + c] = s;
+    double acc[kPanel / 4];
+#pragma unroll
+    for (int c = 0; c < kPanel / 4; ++c) acc[c] = 0.0;
+    // right operand N[col][m] = Linv[col][m]
+    const double* lrow = Ls + (lane & 3) * LD + (lane >> 4);
+#pragma unroll
+    for (int s = 0; s < kPanel / 4; ++s) {
+#pragma unroll
+        for (int c = 0; c < kPanel / 4; ++c) acc[c] = mfma4(a[s], lrow[4 * c * LD + 4 * s], acc[c]);
+    }
+    const int64_t gi = rbase + mfma4_row(lane);
+#pragma unroll
+    for (int c = 0; c < kPanel / 4; ++c) {
+        const int col = 4 * c + (lane & 3);
+        if (gi < n && col < bs) K[gi * n + k0 + col] = acc[c];
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// Trailing update A_ij -= sum_m A[i][k0+m] A[j][k0+m] over the lower 64 x 64 tiles of the
-// trailing matrix (rows/cols from t0 = k0 + bs).  Workgroup = 4 waves, wave w computes the
-// 32 x 32 quarter (w/2, w%2) as 2 x 2 blocks of v_mfma_f64_16x16x4f64.  Operand layout of
-// that instruction (lane l), as measured on gfx950: A[l%16][l/16] of the 16x4 left block,
-// B[l/16][l%16] of the 4x16 right block, and D[4r + l/16][l%16] in accumulator element r.
+// Trailing update A_ij -= sum_m A[i][k0+m] A[j][k0+m], m < bs, over 64 x 64 lower tiles of the
+// matrix from row/column t0 (t0 = k0 + bs for the trailing matrix).  With strip = 1 the grid
+// covers only the two tile columns of the 128-wide column strip starting at t0 (the update
+// of a panel by the earlier panels of its block).  Wave w computes the 32 x 32 quarter
+// (w/2, w%2).  Operands are staged through LDS 32 columns at a time.
 // ---------------------------------------------------------------------------------------
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(256) void lm_syrk_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs)
+__global__ __launch_bounds__(256) void lm_syrk_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
+                                                      int64_t t0, int strip)
 {
     constexpr int KC = 32;
-    __shared__ double Ai[64][KC + 1];
-    __shared__ double Aj[64][KC + 1];
-    const int64_t t0 = k0 + bs;
-    // linear tile id -> (ti, tj), tj <= ti
+    constexpr int LD = KC + 4;
+    __shared__ double Ai[64 * LD];
+    __shared__ double Aj[64 * LD];
     const int64_t id = blockIdx.x;
-    int64_t ti = (int64_t)((__builtin_sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
-    while ((ti + 1) * (ti + 2) / 2 <= id) ++ti;
-    while (ti * (ti + 1) / 2 > id) --ti;
-    const int64_t tj = id - ti * (ti + 1) / 2;
+    int64_t ti, tj;
+    if (strip) {
+        // tiles (0,0), (1,0), (1,1), (2,0), (2,1), ...
+        ti = (id + 1) / 2;
+        tj = id == 0 ? 0 : (id + 1) % 2;
+    } else {
+        // linear tile id -> (ti, tj), tj <= ti
+        ti = (int64_t)((__builtin_sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= id) ++ti;
+        while (ti * (ti + 1) / 2 > id) --ti;
+        tj = id - ti * (ti + 1) / 2;
+    }
     const int64_t ri = t0 + ti * 64, rj = t0 + tj * 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
 
-    d4 acc[2][2];
+    double acc[2][8];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int c = 0; c < 8; ++c) acc[a][c] = 0.0;
 
+    const double* ai = Ai + (wr * 32 + (lane & 15)) * LD + (lane >> 4);
+    const double* aj = Aj + (wc * 32 + (lane & 3)) * LD + (lane >> 4);
     for (int kc = 0; kc < bs; kc += KC) {
-        // stage 64 x KC of each operand: thread t loads 8 consecutive doubles of one row
+        // thread t loads column t%32 of rows t/32 + 8u, so a wave's load instruction reads two
+        // whole 256-byte row segments
         {
-            const int r = tid >> 2, c0 = (tid & 3) * 8;
+            const int c = tid & 31, r0 = tid >> 5;
+            const bool okc = kc + c < bs;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int c = c0 + u;
-                const bool okc = kc + c < bs;
-                Ai[r][c] = (okc && ri + r < n) ? K[(ri + r) * n + k0 + kc + c] : 0.0;
-                Aj[r][c] = (okc && rj + r < n) ? K[(rj + r) * n + k0 + kc + c] : 0.0;
+                const int r = r0 + 8 * u;
+                Ai[r * LD + c] = (okc && ri + r < n) ? K[(ri + r) * n + k0 + kc + c] : 0.0;
+                Aj[r * LD + c] = (okc && rj + r < n) ? K[(rj + r) * n + k0 + kc + c] : 0.0;
             }
         }
         __syncthreads();
 #pragma unroll
         for (int k4 = 0; k4 < KC; k4 += 4) {
-            double fa[2], fb[2];
+            double fa[2], fb[8];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) fa[a] = Ai[wr * 32 + a * 16 + (lane & 15)][k4 + (lane >> 4)];
+            for (int a = 0; a < 2; ++a) fa[a] = ai[a * 16 * LD + k4];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) fb[b] = Aj[wc * 32 + b * 16 + (lane & 15)][k4 + (lane >> 4)];
+            for (int c = 0; c < 8; ++c) fb[c] = aj[c * 4 * LD + k4];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                for (int c = 0; c < 8; ++c) acc[a][c] = mfma4(fa[a], fb[c], acc[a][c]);
         }
         __syncthreads();
     }
+    // every old value of the tile is read before the first store, so the loads overlap
+    double old[2][8];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 8; ++c) {
+            const int64_t gi = ri + wr * 32 + a * 16 + mfma4_row(lane);
+            const int64_t gj = rj + wc * 32 + c * 4 + (lane & 3);
+            old[a][c] = (gi < n && gj <= gi) ? K[gi * n + gj] : 0.0;
+        }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t gi = ri + wr * 32 + a * 16 + 4 * r + (lane >> 4);
-                const int64_t gj = rj + wc * 32 + b * 16 + (lane & 15);
-                if (gi < n && gj <= gi) K[gi * n + gj] -= acc[a][b][r];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int64_t gi = ri + wr * 32 + a * 16 + mfma4_row(lane);
+            const int64_t gj = rj + wc * 32 + c * 4 + (lane & 3);
+            if (gi < n && gj <= gi) K[gi * n + gj] = old[a][c] - acc[a][c];
+        }
+}
+
+// The same trailing update on 128 x 128 lower tiles, for large trailing matrices: each staged
+// operand row then feeds twice the arithmetic.  Wave w computes the 64 x 64 quarter
+// (w/2, w%2), 4 x 16 instructions per k-step of 4 with 64 accumulators per lane.  Operands go
+// through LDS 32 columns at a time; the next chunk is fetched into registers while the
+// current one is multiplied.
+__global__ __launch_bounds__(256) void lm_syrk128_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
+                                                         int64_t t0)
+{
+    constexpr int KC = 32;
+    constexpr int LD = KC + 4;   // row pitch of the staged operands (spreads rows over banks)
+    __shared__ double Ai[128 * LD];
+    __shared__ double Aj[128 * LD];
+    const int64_t id = blockIdx.x;
+    int64_t ti = (int64_t)((__builtin_sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= id) ++ti;
+    while (ti * (ti + 1) / 2 > id) --ti;
+    const int64_t tj = id - ti * (ti + 1) / 2;
+    const int64_t ri = t0 + ti * 128, rj = t0 + tj * 128;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const bool diag = (ti == tj);
+    const bool active = !(diag && wc > wr);   // the quarter above a diagonal tile's diagonal is not needed
+
+    // staging: thread t holds column t%32 of rows t/32 + 8u (u < 16) of each operand, so one
+    // load instruction of a wave reads two whole 256-byte row segments
+    const int sc = tid & 31, sr = tid >> 5;
+    const double* gi_col = K + (ri + sr) * n + k0 + sc;
+    const double* gj_col = K + (rj + sr) * n + k0 + sc;
+    double pa[16], pb[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const bool okc = sc < bs;
+        pa[u] = (okc && ri + sr + 8 * u < n) ? gi_col[8 * u * n] : 0.0;
+        pb[u] = (okc && rj + sr + 8 * u < n) ? gj_col[8 * u * n] : 0.0;
+    }
+
+    double acc[4][16];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[a][c] = 0.0;
+
+    const double* ai = Ai + (wr * 64 + (lane & 15)) * LD + (lane >> 4);
+    const double* aj = Aj + (wc * 64 + (lane & 3)) * LD + (lane >> 4);
+    for (int kc = 0; kc < bs; kc += KC) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            Ai[(sr + 8 * u) * LD + sc] = pa[u];
+            Aj[(sr + 8 * u) * LD + sc] = pb[u];
+        }
+        __syncthreads();
+        const int kn = kc + KC;
+        if (kn < bs) {
+            const bool okc = kn + sc < bs;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                pa[u] = (okc && ri + sr + 8 * u < n) ? gi_col[8 * u * n + kn] : 0.0;
+                pb[u] = (okc && rj + sr + 8 * u < n) ? gj_col[8 * u * n + kn] : 0.0;
             }
+        }
+        if (active) {
+#pragma unroll
+            for (int k4 = 0; k4 < KC; k4 += 4) {
+                double fa[4], fb[16];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) fa[a] = ai[a * 16 * LD + k4];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) fb[c] = aj[c * 4 * LD + k4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 16; ++c)
+                        acc[a][c] = mfma4(fa[a], fb[c], acc[a][c]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    // read every old value of the tile before the first store, so the 64 loads overlap
+    // (interleaved read-modify-writes would wait for each load in turn)
+    double old[4][16];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int64_t gi = ri + wr * 64 + a * 16 + mfma4_row(lane);
+            const int64_t gj = rj + wc * 64 + c * 4 + (lane & 3);
+            old[a][c] = (gi < n && gj <= gi) ? K[gi * n + gj] : 0.0;
+        }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int64_t gi = ri + wr * 64 + a * 16 + mfma4_row(lane);
+            const int64_t gj = rj + wc * 64 + c * 4 + (lane & 3);
+            if (gi < n && gj <= gi) K[gi * n + gj] = old[a][c] - acc[a][c];
+        }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -400,19 +548,43 @@ hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const
         else
             hipLaunchKernelGGL((lm_kbuild_kernel<3, LM_KERNEL_GAUSS>), dim3((unsigned)n), dim3(256), 0, st, X, n, kq, tau, K);
     }
+    // Panels of kPanel columns are factored one by one, but the trailing matrix is updated once
+    // per block of kOuter panels: within a block, panel s first takes the updates of
+    // the block's earlier panels on its own column strip, and the rest of the matrix takes the
+    // whole block in one pass.  That pass reads and writes the trailing matrix, so its HBM
+    // traffic per flop falls with the block width.
     const int nb = dense_panels(n);
-    for (int b = 0; b < nb; ++b) {
-        const int64_t k0 = (int64_t)b * kPanel;
-        const int bs = (int)((n - k0) < kPanel ? (n - k0) : kPanel);
-        hipLaunchKernelGGL(lm_potrf_diag_kernel, dim3(1), dim3(256), 0, st, K, n, k0, bs, info);
-        hipLaunchKernelGGL(lm_trinv_kernel, dim3(1), dim3(kPanel), 0, st, (const double*)K, n, k0, bs,
-                           Linv + (int64_t)b * kPanel * kPanel);
-        const int64_t rest = n - k0 - bs;
+    for (int b0 = 0; b0 < nb; b0 += kOuter) {
+        const int64_t kb = (int64_t)b0 * kPanel;
+        int64_t kend = kb;
+        for (int b = b0; b < nb && b < b0 + kOuter; ++b) {
+            const int64_t k0 = (int64_t)b * kPanel;
+            const int bs = (int)((n - k0) < kPanel ? (n - k0) : kPanel);
+            if (k0 > kb) {
+                const int64_t nt = (n - k0 + 63) / 64;
+                hipLaunchKernelGGL(lm_syrk_kernel, dim3((unsigned)(2 * nt - 1)), dim3(256), 0, st, K, n, kb,
+                                   (int)(k0 - kb), k0, 1);
+            }
+            double* Lb = Linv + (int64_t)b * kPanel * kPanel;
+            hipLaunchKernelGGL(lm_potrf_inv_kernel, dim3(1), dim3(256), 0, st, K, n, k0, bs, Lb, info);
+            const int64_t below = n - k0 - bs;
+            if (below > 0)
+                hipLaunchKernelGGL(lm_panel_kernel, dim3((unsigned)((below + 63) / 64)), dim3(256), 0, st, K, n, k0,
+                                   bs, (const double*)Lb);
+            kend = k0 + bs;
+        }
+        const int64_t rest = n - kend;
         if (rest <= 0) continue;
-        hipLaunchKernelGGL(lm_panel_kernel, dim3((unsigned)((rest + 63) / 64)), dim3(256), 0, st, K, n, k0, bs,
-                           (const double*)(Linv + (int64_t)b * kPanel * kPanel));
-        const int64_t nt = (rest + 63) / 64;
-        hipLaunchKernelGGL(lm_syrk_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n, k0, bs);
+        const int width = (int)(kend - kb);
+        if (rest >= 1024) {
+            const int64_t nt = (rest + 127) / 128;
+            hipLaunchKernelGGL(lm_syrk128_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n, kb,
+                               width, kend);
+        } else {
+            const int64_t nt = (rest + 63) / 64;
+            hipLaunchKernelGGL(lm_syrk_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n, kb,
+                               width, kend, 0);
+        }
     }
     return hipGetLastError();
 }
