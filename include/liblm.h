@@ -103,6 +103,11 @@ typedef struct lm_match_opts {
     double *resid_hist;   /* HOST, nullable: receives the residual of each shoot */
     int32_t hist_len;     /* capacity of resid_hist */
     int32_t solver;       /* K-solve: LM_SOLVE_AUTO, LM_SOLVE_CG or LM_SOLVE_DENSE */
+    double f32_switch;    /* params->dtype = LM_F32 only.  0: every shoot in single precision.
+                             > 0: single-precision shoots until a residual below f32_switch,
+                             double-precision shoots after; the stopping test then accepts only
+                             a double-precision residual (a single-precision one below tol is
+                             re-shot in double precision before any further update) */
 } lm_match_opts;
 
 /* What a feedback match reports (HOST struct).  GPU times come from HIP events on the
@@ -255,6 +260,71 @@ lm_status lm_lbfgs_match(const lm_params *params, const lm_lbfgs_opts *opts, int
  * q, p: (dim, n); x, u: (dim, m).  Asynchronous. */
 lm_status lm_velocity(const lm_params *params, int64_t n, const void *q, const void *p,
                       int64_t m, const void *x, void *u, void *stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Batches of independent problems.  B problems of uneven size are concatenated in one
+ * component-major array (dim, ntot), ntot = sum of the sizes: problem b owns columns
+ * offs[b] .. offs[b+1]-1, and its particles interact only with each other (each problem is
+ * the N-particle system of its own landmarks).  offs is a HOST array of B + 1 int64 values
+ * with offs[0] = 0 and offs[b] < offs[b+1].  Every RK4 stage of every problem is one launch
+ * over the whole batch: a work list of (problem, 64-target tile, source chunk) items sorted
+ * by cost, walked by a persistent grid.  cutoff must be 0.
+ * --------------------------------------------------------------------------------------- */
+#define LM_BATCH_BUCKETS 4
+
+/* Launch shape of a batch (HOST struct).  Problems fall into size buckets; bucket k holds
+ * the problems with bucket_max[k-1] < N_b <= bucket_max[k] (bucket_max[-1] = 0). */
+typedef struct lm_batch_tuning {
+    int64_t bucket_max[LM_BATCH_BUCKETS]; /* ascending; the last >= every N_b */
+    int32_t split[LM_BATCH_BUCKETS];      /* source chunks per 64-target tile, 1..64
+                                             (1: the item owns all its sources) */
+    int32_t groups;                       /* persistent grid in workgroups of 4 waves;
+                                             0 = one wave per work item */
+    int32_t graph_steps;                  /* RK4 steps per captured hipGraph in a shoot;
+                                             0 = every kernel launched directly */
+    double stage_us;                      /* written by lm_batch_autotune: measured time of
+                                             one stage with this shape (microseconds) */
+} lm_batch_tuning;
+
+/* A launch shape that needs no measurement (HOST only, no GPU call).  Validates offs. */
+lm_status lm_batch_default_tuning(int32_t B, const int64_t *offs, lm_batch_tuning *out);
+
+/* Autotuner: times candidate launch shapes on this batch (right-hand-side evaluations at
+ * (q, p), dim x ntot device arrays of params->dtype, and short graph-replayed shoots) with
+ * HIP events, one parameter at a time from the default (grid size, then each occupied
+ * bucket's source split, then the steps per graph), and writes the fastest to *out.
+ * Synchronous; q and p are not modified. */
+lm_status lm_batch_autotune(const lm_params *params, int32_t B, const int64_t *offs,
+                            const void *q, const void *p, lm_batch_tuning *out, void *stream);
+
+/* lm_rhs for every problem of a batch.  tuning: nullable (NULL = the default shape).
+ * Asynchronous. */
+lm_status lm_rhs_batched(const lm_params *params, int32_t B, const int64_t *offs,
+                         const void *q, const void *p, void *dq, void *dp,
+                         const lm_batch_tuning *tuning, void *stream);
+
+/* lm_shoot for every problem of a batch (the same t1 and steps for all).  With
+ * tuning->graph_steps > 0 the RK4 steps are captured once into a hipGraph and replayed;
+ * the call then returns after the shoot has finished.  Otherwise asynchronous. */
+lm_status lm_shoot_batched(const lm_params *params, int32_t B, const int64_t *offs,
+                           const void *q0, const void *p0, double t1, int32_t steps,
+                           void *q1, void *p1, const lm_batch_tuning *tuning, void *stream);
+
+/* Algorithm 1 for every problem of a batch, all problems iterating together: one batched
+ * shoot per iteration, then for every problem not yet stopped the residual test and the
+ * update p <- p + h (K(X_b) + tau I)^{-1} (Y_b - q_b(1)) with the dense factor of its own
+ * kernel matrix.  A problem stops when its residual passes (stop_rule 0 only), diverges or
+ * has a singular K; the batch runs until every problem has stopped or max_iter updates.
+ * params->dtype = LM_F32 shoots in single precision from FP64 master momenta; residuals,
+ * solves and updates are FP64.  X, Y, p0 (in: guess, out: result), q1 (nullable): FP64
+ * (dim, ntot) device arrays.  info, status: HOST arrays of B entries (per-problem iteration
+ * count, final residual, H at (X, p0), status); the *_ms fields of every entry hold the
+ * batch totals.  Returns LM_OK when every problem converged, else the first of
+ * LM_EDIVERGED, LM_ESINGULAR, LM_ENOTCONV that some problem ended with.  Synchronous. */
+lm_status lm_feedback_match_batched(const lm_params *params, const lm_match_opts *opts, int32_t B,
+                                    const int64_t *offs, const double *X, const double *Y,
+                                    double *p0, double *q1, lm_match_info *info, int32_t *status,
+                                    const lm_batch_tuning *tuning, void *stream);
 
 /* Text describing the last non-OK status returned on the calling thread ("" if none). */
 const char *lm_last_error(void);

@@ -24,7 +24,9 @@ SOLVE_AUTO, SOLVE_CG, SOLVE_DENSE = 0, 1, 2
 # every symbol include/liblm.h declares
 EXPORTS = ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
            "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
-           "lm_lbfgs_match", "lm_last_error", "lm_version"]
+           "lm_lbfgs_match", "lm_batch_default_tuning", "lm_batch_autotune", "lm_rhs_batched",
+           "lm_shoot_batched", "lm_feedback_match_batched", "lm_last_error", "lm_version"]
+BATCH_BUCKETS = 4
 
 
 class LmError(RuntimeError):
@@ -43,7 +45,7 @@ class lm_match_opts(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("steps", ctypes.c_int32), ("stop_rule", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32),
                 ("cg_rtol", ctypes.c_double), ("resid_hist", ctypes.POINTER(ctypes.c_double)),
-                ("hist_len", ctypes.c_int32), ("solver", ctypes.c_int32)]
+                ("hist_len", ctypes.c_int32), ("solver", ctypes.c_int32), ("f32_switch", ctypes.c_double)]
 
 
 class lm_match_info(ctypes.Structure):
@@ -66,6 +68,15 @@ class lm_lbfgs_opts(ctypes.Structure):
 class lm_lbfgs_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("evals", ctypes.c_int32), ("E", ctypes.c_double),
                 ("gnorm_inf", ctypes.c_double), ("resid_inf", ctypes.c_double)]
+
+
+class lm_batch_tuning(ctypes.Structure):
+    _fields_ = [("bucket_max", ctypes.c_int64 * BATCH_BUCKETS), ("split", ctypes.c_int32 * BATCH_BUCKETS),
+                ("groups", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("stage_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"bucket_max": list(self.bucket_max), "split": list(self.split), "groups": self.groups,
+                "graph_steps": self.graph_steps, "stage_us": self.stage_us}
 
 
 _lib = None
@@ -94,9 +105,17 @@ def load():
         L.lm_shoot_adjoint.argtypes = [PP, i64, P, P, d, i32, i32, P, P, P, P, P, P, P]
         L.lm_energy_grad.argtypes = [PP, i64, P, P, P, d, d, i32, i32, ctypes.POINTER(d), P, P, P]
         L.lm_lbfgs_match.argtypes = [PP, ctypes.POINTER(lm_lbfgs_opts), i64, P, P, P, ctypes.POINTER(lm_lbfgs_info), P]
+        PT = ctypes.POINTER(lm_batch_tuning)
+        L.lm_batch_default_tuning.argtypes = [i32, P, PT]
+        L.lm_batch_autotune.argtypes = [PP, i32, P, P, P, PT, P]
+        L.lm_rhs_batched.argtypes = [PP, i32, P, P, P, P, P, PT, P]
+        L.lm_shoot_batched.argtypes = [PP, i32, P, P, P, d, i32, P, P, PT, P]
+        L.lm_feedback_match_batched.argtypes = [PP, ctypes.POINTER(lm_match_opts), i32, P, P, P, P, P,
+                                                ctypes.POINTER(lm_match_info), P, PT, P]
         for name in ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
                      "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
-                     "lm_lbfgs_match"]:
+                     "lm_lbfgs_match", "lm_batch_default_tuning", "lm_batch_autotune", "lm_rhs_batched",
+                     "lm_shoot_batched", "lm_feedback_match_batched"]:
             getattr(L, name).restype = ctypes.c_int
         L.lm_last_error.restype = ctypes.c_char_p
         L.lm_last_error.argtypes = []
@@ -186,9 +205,9 @@ def lm_ksolve(params: lm_params, X, b, x, rtol: float = 1e-13, max_iter: int = 0
 
 def lm_feedback_match(params: lm_params, X, Y, p0, h: float, tol: float, steps: int, max_iter: int = 500,
                       q1=None, stop_rule: int = 0, cg_rtol: float = 0.0, cg_max_iter: int = 0,
-                      hist_len: int = 1024, solver: int = SOLVE_AUTO, stream=None,
+                      hist_len: int = 1024, solver: int = SOLVE_AUTO, f32_switch: float = 0.0, stream=None,
                       raise_on=(LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_EUNSUPPORTED)):
-    """Runs Algorithm 1 in place on p0.  Returns (status, info, residual history).
+    """Runs Algorithm 1 in place on p0.  Returns (status, info, residual of every shoot).
 
     Statuses describing the iteration itself (not converged, diverged, singular K) are
     returned, not raised; argument and runtime errors raise LmError.
@@ -196,16 +215,22 @@ def lm_feedback_match(params: lm_params, X, Y, p0, h: float, tol: float, steps: 
     dim, n = X.shape
     for t, nm in [(X, "X"), (Y, "Y"), (p0, "p0")] + ([(q1, "q1")] if q1 is not None else []):
         _check_tensor(t, params.dim, n, F64, nm)
-    hist = (ctypes.c_double * max(1, hist_len))()
+    nan = float("nan")
+    hist = (ctypes.c_double * max(1, hist_len))(*([nan] * max(1, hist_len)))
     o = lm_match_opts(float(h), float(tol), int(max_iter), int(steps), int(stop_rule), int(cg_max_iter),
-                      float(cg_rtol), ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(hist_len), int(solver))
+                      float(cg_rtol), ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), int(hist_len), int(solver),
+                      float(f32_switch))
     info = lm_match_info()
     st = load().lm_feedback_match(ctypes.byref(params), ctypes.byref(o), n, _ptr(X), _ptr(Y), _ptr(p0),
                                   _ptr(q1), ctypes.byref(info), _stream(stream))
     if st in raise_on:
         raise LmError(st, last_error())
-    k = min(info.iters + 1, hist_len)
-    return st, info, [hist[i] for i in range(k)]
+    shots = []
+    for i in range(hist_len):
+        if hist[i] != hist[i]:
+            break
+        shots.append(hist[i])
+    return st, info, shots
 
 
 def lm_feedback_step(params: lm_params, X, Y, p, h: float, tol: float, steps: int, q1=None,
@@ -286,6 +311,74 @@ def lm_lbfgs_match(params: lm_params, X, Y, p0, lam: float, steps: int, reg: flo
     if st in raise_on:
         raise LmError(st, last_error())
     return st, info
+
+
+# ------------------------------------------------------------------ batches of problems
+
+def _offs_array(offs):
+    """offs: a sequence of B + 1 int64 offsets (host).  Returns (B, ctypes array)."""
+    vals = [int(v) for v in offs]
+    arr = (ctypes.c_int64 * len(vals))(*vals)
+    return len(vals) - 1, arr
+
+
+def _tuning_ptr(tuning):
+    return None if tuning is None else ctypes.byref(tuning)
+
+
+def lm_batch_default_tuning(offs) -> lm_batch_tuning:
+    """Launch shape that needs no measurement (host only: no GPU call)."""
+    B, arr = _offs_array(offs)
+    t = lm_batch_tuning()
+    _check(load().lm_batch_default_tuning(B, arr, ctypes.byref(t)))
+    return t
+
+
+def lm_batch_autotune(params: lm_params, offs, q, p, stream=None) -> lm_batch_tuning:
+    B, arr = _offs_array(offs)
+    for t, nm in [(q, "q"), (p, "p")]:
+        _check_tensor(t, params.dim, arr[B], params.dtype, nm)
+    t = lm_batch_tuning()
+    _check(load().lm_batch_autotune(ctypes.byref(params), B, arr, _ptr(q), _ptr(p), ctypes.byref(t),
+                                    _stream(stream)))
+    return t
+
+
+def lm_rhs_batched(params: lm_params, offs, q, p, dq, dp, tuning=None, stream=None):
+    B, arr = _offs_array(offs)
+    for t, nm in [(q, "q"), (p, "p"), (dq, "dq"), (dp, "dp")]:
+        _check_tensor(t, params.dim, arr[B], params.dtype, nm)
+    return _check(load().lm_rhs_batched(ctypes.byref(params), B, arr, _ptr(q), _ptr(p), _ptr(dq), _ptr(dp),
+                                        _tuning_ptr(tuning), _stream(stream)))
+
+
+def lm_shoot_batched(params: lm_params, offs, q0, p0, t1: float, steps: int, q1, p1, tuning=None, stream=None):
+    B, arr = _offs_array(offs)
+    for t, nm in [(q0, "q0"), (p0, "p0"), (q1, "q1"), (p1, "p1")]:
+        _check_tensor(t, params.dim, arr[B], params.dtype, nm)
+    return _check(load().lm_shoot_batched(ctypes.byref(params), B, arr, _ptr(q0), _ptr(p0), float(t1), int(steps),
+                                          _ptr(q1), _ptr(p1), _tuning_ptr(tuning), _stream(stream)))
+
+
+def lm_feedback_match_batched(params: lm_params, offs, X, Y, p0, h: float, tol: float, steps: int,
+                              max_iter: int = 500, q1=None, tuning=None, f32_switch: float = 0.0, stream=None,
+                              raise_on=(LM_EINVAL, LM_ENOMEM, LM_EHIP, LM_EUNSUPPORTED)):
+    """Algorithm 1 for every problem of a batch, in place on p0.
+
+    Returns (status, infos, statuses): one lm_match_info and one status per problem.
+    """
+    B, arr = _offs_array(offs)
+    for t, nm in [(X, "X"), (Y, "Y"), (p0, "p0")] + ([(q1, "q1")] if q1 is not None else []):
+        _check_tensor(t, params.dim, arr[B], F64, nm)
+    o = lm_match_opts(float(h), float(tol), int(max_iter), int(steps), 0, 0, 0.0, None, 0, SOLVE_DENSE,
+                      float(f32_switch))
+    infos = (lm_match_info * B)()
+    stats = (ctypes.c_int32 * B)()
+    st = load().lm_feedback_match_batched(ctypes.byref(params), ctypes.byref(o), B, arr, _ptr(X), _ptr(Y),
+                                          _ptr(p0), _ptr(q1), infos, stats, _tuning_ptr(tuning), _stream(stream))
+    if st in raise_on:
+        raise LmError(st, last_error())
+    return st, list(infos), list(stats)
 
 
 def lm_version() -> str:

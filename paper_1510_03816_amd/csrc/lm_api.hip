@@ -14,11 +14,14 @@
 #include <string>
 #include <vector>
 
+#include "lm_host.h"
 #include "lm_internal.h"
 
-namespace {
+namespace lmh {
 
+namespace {
 thread_local std::string g_err;
+}
 
 lm_status fail(lm_status st, const char* fmt, ...)
 {
@@ -37,70 +40,7 @@ lm_status fail_hip(hipError_t e, const char* what)
     return fail(LM_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define LM_HIP(expr)                                                  \
-    do {                                                              \
-        hipError_t e_ = (expr);                                       \
-        if (e_ != hipSuccess) return fail_hip(e_, #expr);             \
-    } while (0)
-
-#define LM_TRY(expr)                                                  \
-    do {                                                              \
-        lm_status s_ = (expr);                                        \
-        if (s_ != LM_OK) return s_;                                   \
-    } while (0)
-
-// Stream-ordered device allocations released (on the same stream) when the owner dies.
-class Workspace {
-public:
-    explicit Workspace(hipStream_t st) : st_(st) {}
-    ~Workspace()
-    {
-        for (void* p : ptrs_) (void)hipFreeAsync(p, st_);
-    }
-    Workspace(const Workspace&) = delete;
-    Workspace& operator=(const Workspace&) = delete;
-
-    template <class T>
-    lm_status get(T** out, int64_t count)
-    {
-        void* p = nullptr;
-        size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-        hipError_t e = hipMallocAsync(&p, bytes, st_);
-        if (e != hipSuccess) return fail_hip(e, "hipMallocAsync");
-        ptrs_.push_back(p);
-        *out = (T*)p;
-        return LM_OK;
-    }
-
-private:
-    hipStream_t st_;
-    std::vector<void*> ptrs_;
-};
-
-bool is_finite(double x) { return std::isfinite(x); }
-
-// Four HIP events for phase timings, destroyed with the owner.
-struct EventTimer {
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    lm_status init()
-    {
-        for (auto& e : ev) {
-            hipError_t err = hipEventCreate(&e);
-            if (err != hipSuccess) return fail_hip(err, "hipEventCreate");
-        }
-        return LM_OK;
-    }
-    double ms(int a, int b) const
-    {
-        float t = 0.0f;
-        return hipEventElapsedTime(&t, ev[a], ev[b]) == hipSuccess ? (double)t : -1.0;
-    }
-    ~EventTimer()
-    {
-        for (auto& e : ev)
-            if (e) (void)hipEventDestroy(e);
-    }
-};
+const char* last_error() { return g_err.c_str(); }
 
 lm_status check_params(const lm_params* prm)
 {
@@ -116,15 +56,12 @@ lm_status check_params(const lm_params* prm)
     return LM_OK;
 }
 
-constexpr int64_t kMaxN = (int64_t)1 << 34;
-
-lm_status check_n(int64_t n, const char* name = "n")
+lm_status check_n(int64_t n, const char* name)
 {
     if (n < 1 || n > kMaxN) return fail(LM_EINVAL, "%s must be in [1, 2^34] (got %lld)", name, (long long)n);
     return LM_OK;
 }
 
-// Exponent scale and force constant of the pair bodies.
 void kernel_scales(const lm_params* prm, bool f32, double* kq, double* wscale)
 {
     const double s = prm->sigma;
@@ -138,6 +75,12 @@ void kernel_scales(const lm_params* prm, bool f32, double* kq, double* wscale)
     }
     if (f32) *kq *= log2e;
 }
+
+}  // namespace lmh
+
+namespace {
+
+using namespace lmh;
 
 // Cutoff mode: tile boxes of the sources and of the targets (the same buffer when the
 // targets are the sources) and the squared radius.  box_s == nullptr means every pair.
@@ -423,7 +366,7 @@ lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspa
 lm_status dense_solve(const DenseFactor& f, int dim, const double* b, double* x, hipStream_t st)
 {
     if (x != b) LM_HIP(hipMemcpyAsync(x, b, (size_t)dim * f.n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    LM_HIP(lm::launch_dense_solve(f.L, f.Linv, f.n, dim, x, st));
+    LM_HIP(lm::launch_dense_solve(f.L, f.Linv, f.n, dim, x, f.n, st));
     return LM_OK;
 }
 
@@ -505,6 +448,7 @@ lm_status check_match_args(const lm_match_opts* o, const double* X, const double
     if (o->cg_max_iter < 0 || !(o->cg_rtol >= 0.0)) return fail(LM_EINVAL, "bad CG settings");
     if (o->hist_len < 0 || (o->hist_len > 0 && !o->resid_hist)) return fail(LM_EINVAL, "bad history buffer");
     if (o->solver < LM_SOLVE_AUTO || o->solver > LM_SOLVE_DENSE) return fail(LM_EINVAL, "unknown solver %d", o->solver);
+    if (!(o->f32_switch >= 0.0) || !is_finite(o->f32_switch)) return fail(LM_EINVAL, "f32_switch must be >= 0");
     return LM_OK;
 }
 
@@ -548,14 +492,14 @@ struct FeedbackWork {
             LM_TRY(ws.get(&bpf, m));
             LM_TRY(ws.get(&cqf, m));
             LM_TRY(ws.get(&cpf, m));
-        } else {
-            LM_TRY(ws.get(&aq, m));
-            LM_TRY(ws.get(&ap, m));
-            LM_TRY(ws.get(&bq, m));
-            LM_TRY(ws.get(&bp, m));
-            LM_TRY(ws.get(&cq, m));
-            LM_TRY(ws.get(&cp, m));
         }
+        // double-precision stage buffers (single-precision matches may switch to them)
+        LM_TRY(ws.get(&aq, m));
+        LM_TRY(ws.get(&ap, m));
+        LM_TRY(ws.get(&bq, m));
+        LM_TRY(ws.get(&bp, m));
+        LM_TRY(ws.get(&cq, m));
+        LM_TRY(ws.get(&cp, m));
         if (!ordered) q1 = qd;
         return cg_alloc(ws, prm, n, &cg);
     }
@@ -1034,7 +978,7 @@ lm_status lbfgs_impl(const lm_params* prm, const lm_lbfgs_opts* o, int64_t n, co
 
 extern "C" {
 
-const char* lm_last_error(void) { return g_err.c_str(); }
+const char* lm_last_error(void) { return lmh::last_error(); }
 
 const char* lm_version(void) { return "liblm 0.1 (gfx950)"; }
 
@@ -1133,22 +1077,36 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
 
     lm_status result = LM_OK;
     double r = 0.0, prev_step = INFINITY;
-    int32_t k = 0;
-    for (k = 0;; ++k) {
+    int32_t k = 0;   // momentum updates made
+    // single-precision shoots until the residual drops below f32_switch (if set), then double
+    lm_params p64 = *prm;
+    p64.dtype = LM_F64;
+    const bool may_switch = prm->dtype == LM_F32 && o->f32_switch > 0.0;
+    bool fp64 = prm->dtype == LM_F64;
+    for (int32_t shot = 0;; ++shot) {
         // Algorithm 1, steps 1-2: shoot (X, p) to t = 1, residual r = max |Y - q(1)|
         LM_HIP(hipEventRecord(timer.ev[0], st));
-        LM_TRY(feedback_shoot_residual(prm, o, n, X, Y, p0, w, &r, st, timer.ev[1]));
+        LM_TRY(feedback_shoot_residual(fp64 ? &p64 : prm, o, n, X, Y, p0, w, &r, st, timer.ev[1]));
         info->shoot_ms += timer.ms(0, 1);
-        if (k < o->hist_len) o->resid_hist[k] = r;
+        if (shot < o->hist_len) o->resid_hist[shot] = r;
         if (!is_finite(r)) {
             result = fail(LM_EDIVERGED, "feedback iteration %d: non-finite residual", k);
             break;
         }
-        if (o->stop_rule == 0 ? (r < o->tol) : (k >= 1 && prev_step < o->tol)) break;
+        bool hold = false;   // re-shoot the same momenta in double precision
+        if (may_switch && !fp64) {
+            if (r < o->f32_switch) fp64 = true;
+            if (r < o->tol) {
+                hold = true;
+                fp64 = true;
+            }
+        }
+        if (!hold && (o->stop_rule == 0 ? (r < o->tol) : (k >= 1 && prev_step < o->tol))) break;
         if (k >= o->max_iter) {
             result = fail(LM_ENOTCONV, "feedback: %d updates without reaching tol %.3g (residual %.3g)", k, o->tol, r);
             break;
         }
+        if (hold) continue;
         // steps 3-4: u <- u + h e, i.e. p <- p + h (K + tau I)^{-1} e
         int32_t cgit = 0;
         LM_HIP(hipEventRecord(timer.ev[2], st));
@@ -1162,6 +1120,7 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
         LM_HIP(hipEventSynchronize(timer.ev[3]));
         info->solve_ms += timer.ms(2, 3);
         prev_step = o->h * r;
+        ++k;
     }
     info->iters = k;
     info->resid_inf = r;

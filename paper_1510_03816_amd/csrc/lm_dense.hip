@@ -391,14 +391,14 @@ __global__ __launch_bounds__(256) void lm_syrk128_kernel(double* __restrict__ K,
 // block `blk`, executed by one workgroup of 256 threads.
 template <bool TRANS, int DIM>
 __device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb, int64_t blk,
-                             double* __restrict__ y, double* sh)
+                             double* __restrict__ y, int64_t ldy, double* sh)
 {
     const int64_t b0 = blk * kPanel;
     const int bs = (int)((n - b0) < kPanel ? (n - b0) : kPanel);
     const double* Li = Linv + blk * kPanel * kPanel;
     for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
         const int c = e / kPanel, r = e % kPanel;
-        sh[e] = r < bs ? y[c * n + b0 + r] : 0.0;
+        sh[e] = r < bs ? y[c * ldy + b0 + r] : 0.0;
     }
     __syncthreads();
     double out[3] = {0.0, 0.0, 0.0};
@@ -416,7 +416,7 @@ __device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb,
     }
     __syncthreads();
     if (r < bs)
-        for (int c = 0; c < DIM; ++c) y[c * n + b0 + r] = out[c];
+        for (int c = 0; c < DIM; ++c) y[c * ldy + b0 + r] = out[c];
 }
 
 // Launch k of the forward sweep (k = -1: only finish block 0).  Workgroup 0 owns block k+1:
@@ -424,7 +424,8 @@ __device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb,
 // contribution of y_k from the rows of blocks k+2 .. nb-1, eight rows per wave at a time.
 template <int DIM>
 __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restrict__ L, const double* __restrict__ Linv,
-                                                          int64_t n, int nb, int64_t k, double* __restrict__ y)
+                                                          int64_t n, int nb, int64_t k, double* __restrict__ y,
+                                                          int64_t ldy)
 {
     __shared__ double sh[3 * kPanel];
     __shared__ double yk[3 * kPanel];
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restri
         const int64_t k0 = k * kPanel;
         for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
             const int c = e / kPanel, m = e % kPanel;
-            yk[e] = (k0 + m < n) ? y[c * n + k0 + m] : 0.0;
+            yk[e] = (k0 + m < n) ? y[c * ldy + k0 + m] : 0.0;
         }
         __syncthreads();
         // eight rows per wave at a time: lane l reads 16 consecutive doubles of row (l / 8),
@@ -465,13 +466,13 @@ __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restri
                 for (int o = 4; o > 0; o >>= 1) s[c] += __shfl_xor(s[c], o, 64);
             }
             if (ok && (lane & 7) == 0)
-                for (int c = 0; c < DIM; ++c) y[c * n + r] -= s[c];
+                for (int c = 0; c < DIM; ++c) y[c * ldy + r] -= s[c];
         }
     }
     if (blockIdx.x == 0 && k + 1 < nb) {
         __threadfence_block();
         __syncthreads();
-        finish_block<false, DIM>(Linv, n, nb, k + 1, y, sh);
+        finish_block<false, DIM>(Linv, n, nb, k + 1, y, ldy, sh);
     }
 }
 
@@ -480,7 +481,8 @@ __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restri
 // the columns of blocks 0 .. k-2, one column per thread.
 template <int DIM>
 __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restrict__ L, const double* __restrict__ Linv,
-                                                          int64_t n, int nb, int64_t k, double* __restrict__ y)
+                                                          int64_t n, int nb, int64_t k, double* __restrict__ y,
+                                                          int64_t ldy)
 {
     __shared__ double sh[3 * kPanel];
     __shared__ double xk[3 * kPanel];
@@ -489,7 +491,7 @@ __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restri
         const int bs = (int)((n - k0) < kPanel ? (n - k0) : kPanel);
         for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
             const int c = e / kPanel, m = e % kPanel;
-            xk[e] = m < bs ? y[c * n + k0 + m] : 0.0;
+            xk[e] = m < bs ? y[c * ldy + k0 + m] : 0.0;
         }
         __syncthreads();
         int64_t cbeg, cend, cstep;
@@ -514,14 +516,150 @@ __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restri
 #pragma unroll
                     for (int u = 0; u < 16; ++u) s[c] = __builtin_fma(lv[u], xk[c * kPanel + m0 + u], s[c]);
             }
-            for (int c = 0; c < DIM; ++c) y[c * n + col] -= s[c];
+            for (int c = 0; c < DIM; ++c) y[c * ldy + col] -= s[c];
         }
     }
     if (blockIdx.x == 0 && k - 1 >= 0) {
         __threadfence_block();
         __syncthreads();
-        finish_block<true, DIM>(Linv, n, nb, k - 1, y, sh);
+        finish_block<true, DIM>(Linv, n, nb, k - 1, y, ldy, sh);
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched solves: y_b <- (L_b L_b^T)^{-1} y_b for every flagged problem b of a batch, one
+// workgroup per problem, the problem's vector held in LDS (at most kBatchSolveMax points).
+// Forward, per 128-row block k: s = y_k - L[k, <k] y_<k (rows spread over the waves, lanes
+// striding the columns, four rows at a time), then y_k = Linv_k s.  Backward, per block from
+// the last: t = y_k - L[>k, k]^T x_>k (each wave takes every fourth row below the block, lanes
+// the block's columns; the wave partials are added in wave order), then x_k = Linv_k^T t.
+// L_b: row-major n_b x n_b lower triangle at L + loff[b]; Linv_b at Linv + ioff[b]; y: the
+// batch's (dim, ntot) array, problem b in columns offs[b] .. offs[b+1]-1.
+// ---------------------------------------------------------------------------------------
+constexpr int kBatchSolveMax = 4096;
+
+template <int DIM>
+__global__ __launch_bounds__(256) void lm_batch_solve_kernel(const double* __restrict__ L,
+                                                             const int64_t* __restrict__ loff,
+                                                             const double* __restrict__ Linv,
+                                                             const int64_t* __restrict__ ioff,
+                                                             const int64_t* __restrict__ offs, int64_t ntot,
+                                                             double* __restrict__ y, const int* __restrict__ flag)
+{
+    __shared__ double v[DIM][kBatchSolveMax];
+    __shared__ double tmp[4][DIM][kPanel];
+    const int b = blockIdx.x;
+    if (!flag[b]) return;
+    const int64_t off = offs[b];
+    const int n = (int)(offs[b + 1] - off);
+    const double* Lb = L + loff[b];
+    const double* Ib = Linv + ioff[b];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int c = 0; c < DIM; ++c)
+        for (int i = tid; i < n; i += blockDim.x) v[c][i] = y[c * ntot + off + i];
+    __syncthreads();
+    const int nb = (n + kPanel - 1) / kPanel;
+
+    // forward sweep
+    for (int k = 0; k < nb; ++k) {
+        const int k0 = k * kPanel, bs = (n - k0) < kPanel ? (n - k0) : kPanel;
+        for (int r0 = wave * 4; r0 < bs; r0 += 16) {
+            double acc[4][DIM];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) acc[u][c] = 0.0;
+            for (int j = lane; j < k0; j += 64) {
+                double l[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) l[u] = (r0 + u < bs) ? Lb[(int64_t)(k0 + r0 + u) * n + j] : 0.0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    const double yj = v[c][j];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[u][c] = __builtin_fma(l[u], yj, acc[u][c]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    double a = acc[u][c];
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+                    if (lane == 0 && r0 + u < bs) tmp[0][c][r0 + u] = v[c][k0 + r0 + u] - a;
+                }
+        }
+        __syncthreads();
+        if (tid < bs) {
+            for (int c = 0; c < DIM; ++c) {
+                double s = 0.0;
+                for (int m = 0; m <= tid; ++m) s = __builtin_fma(Ib[(int64_t)k * kPanel * kPanel + tid * kPanel + m], tmp[0][c][m], s);
+                v[c][k0 + tid] = s;
+            }
+        }
+        __syncthreads();
+    }
+
+    // backward sweep
+    for (int k = nb - 1; k >= 0; --k) {
+        const int k0 = k * kPanel, bs = (n - k0) < kPanel ? (n - k0) : kPanel;
+        double acc[2][DIM];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc[h][c] = 0.0;
+        const bool ok0 = lane < bs, ok1 = 64 + lane < bs;
+        for (int j = k0 + bs + wave; j < n; j += 4) {
+            const double* lr = Lb + (int64_t)j * n + k0;
+            const double l0 = ok0 ? lr[lane] : 0.0;
+            const double l1 = ok1 ? lr[64 + lane] : 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const double xj = v[c][j];
+                acc[0][c] = __builtin_fma(l0, xj, acc[0][c]);
+                acc[1][c] = __builtin_fma(l1, xj, acc[1][c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            tmp[wave][c][lane] = acc[0][c];
+            tmp[wave][c][64 + lane] = acc[1][c];
+        }
+        __syncthreads();
+        if (tid < kPanel) {
+            for (int c = 0; c < DIM; ++c) {
+                const double sum = tmp[0][c][tid] + tmp[1][c][tid] + tmp[2][c][tid] + tmp[3][c][tid];
+                tmp[0][c][tid] = (tid < bs) ? v[c][k0 + tid] - sum : 0.0;
+            }
+        }
+        __syncthreads();
+        if (tid < bs) {
+            for (int c = 0; c < DIM; ++c) {
+                double s = 0.0;
+                for (int m = tid; m < bs; ++m) s = __builtin_fma(Ib[(int64_t)k * kPanel * kPanel + m * kPanel + tid], tmp[0][c][m], s);
+                v[c][k0 + tid] = s;
+            }
+        }
+        __syncthreads();
+    }
+    for (int c = 0; c < DIM; ++c)
+        for (int i = tid; i < n; i += blockDim.x) y[c * ntot + off + i] = v[c][i];
+}
+
+int batch_solve_max() { return kBatchSolveMax; }
+
+hipError_t launch_batch_dense_solve(const double* L, const int64_t* loff, const double* Linv, const int64_t* ioff,
+                                    const int64_t* offs, int nprob, int dim, int64_t ntot, double* y, const int* flag,
+                                    hipStream_t st)
+{
+    if (dim == 2)
+        hipLaunchKernelGGL(lm_batch_solve_kernel<2>, dim3(nprob), dim3(256), 0, st, L, loff, Linv, ioff, offs, ntot, y,
+                           flag);
+    else
+        hipLaunchKernelGGL(lm_batch_solve_kernel<3>, dim3(nprob), dim3(256), 0, st, L, loff, Linv, ioff, offs, ntot, y,
+                           flag);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -589,7 +727,8 @@ hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const
     return hipGetLastError();
 }
 
-hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, int dim, double* y, hipStream_t st)
+hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, int dim, double* y, int64_t ldy,
+                              hipStream_t st)
 {
     const int nb = dense_panels(n);
     // enough workgroups to stream a panel at full bandwidth, never more than its rows need
@@ -601,17 +740,17 @@ hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, in
         const int64_t below = n - (k + 2) * kPanel;
         const dim3 g(k < 0 ? 1u : groups(below > 0 ? below : 0, 32));
         if (dim == 2)
-            hipLaunchKernelGGL(lm_trsv_fwd_kernel<2>, g, dim3(256), 0, st, L, Linv, n, nb, k, y);
+            hipLaunchKernelGGL(lm_trsv_fwd_kernel<2>, g, dim3(256), 0, st, L, Linv, n, nb, k, y, ldy);
         else
-            hipLaunchKernelGGL(lm_trsv_fwd_kernel<3>, g, dim3(256), 0, st, L, Linv, n, nb, k, y);
+            hipLaunchKernelGGL(lm_trsv_fwd_kernel<3>, g, dim3(256), 0, st, L, Linv, n, nb, k, y, ldy);
     }
     for (int64_t k = nb; k > 0; --k) {
         const int64_t above = (k - 1) * kPanel;
         const dim3 g(k == nb ? 1u : groups(above, 256));
         if (dim == 2)
-            hipLaunchKernelGGL(lm_trsv_bwd_kernel<2>, g, dim3(256), 0, st, L, Linv, n, nb, k, y);
+            hipLaunchKernelGGL(lm_trsv_bwd_kernel<2>, g, dim3(256), 0, st, L, Linv, n, nb, k, y, ldy);
         else
-            hipLaunchKernelGGL(lm_trsv_bwd_kernel<3>, g, dim3(256), 0, st, L, Linv, n, nb, k, y);
+            hipLaunchKernelGGL(lm_trsv_bwd_kernel<3>, g, dim3(256), 0, st, L, Linv, n, nb, k, y, ldy);
     }
     return hipGetLastError();
 }

@@ -102,6 +102,35 @@ struct VjpArgs {
     AdjEpi epi;
 };
 
+// Batched pair sums (problems concatenated in one (dim, ntot) array; see lm_batch_pair_kernel).
+template <class T>
+struct BatchArgs {
+    const T* q;              // stage input (dim, ntot)
+    const T* p;
+    int64_t ntot;
+    const int64_t* offs;     // problem b owns [offs[b], offs[b+1])
+    const int4* items;       // (problem, first target, chunk, chunks), sorted by cost
+    int32_t nitems;
+    const int64_t* part_off; // split problems: offset of their partials in part (doubles)
+    double* part;
+    double kq;
+    double wscale;
+    EpiArgs<T> epi;          // over the concatenated arrays (n = ntot)
+};
+
+template <class T>
+hipError_t launch_batch_pair(int dim, int kernel, bool force, const BatchArgs<T>& a, const int4* fin, int32_t nfin,
+                             int groups, hipStream_t st);
+template <class TX>
+hipError_t launch_batch_maxabsdiff(const TX* x, const double* y, int dim, int64_t ntot, const int64_t* offs, int nprob,
+                                   double* out, hipStream_t st);
+hipError_t launch_batch_dot(const double* x, const double* y, int dim, int64_t ntot, const int64_t* offs, int nprob,
+                            double* out, hipStream_t st);
+hipError_t launch_batch_axpy(double* p, const double* x, double h, int dim, int64_t ntot, const int64_t* offs,
+                             const int* active, int nprob, hipStream_t st);
+hipError_t launch_batch_copy_f32_to_f64(double* dst, const float* src, int dim, int64_t ntot, const int64_t* offs,
+                                        const int* flag, int nprob, hipStream_t st);
+
 struct PairPlan {
     int64_t itiles;
     int nsplit;
@@ -141,8 +170,16 @@ int dense_panels(int64_t n);
 int64_t dense_linv_elems(int64_t n);
 hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,
                                double* Linv, int* info, hipStream_t st);
-// y <- (L L^T)^{-1} y for dim component vectors, in place.
-hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, int dim, double* y, hipStream_t st);
+// y <- (L L^T)^{-1} y for dim component vectors (component c at y + c * ldy), in place.
+hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, int dim, double* y, int64_t ldy,
+                              hipStream_t st);
+
+// Batched solves, one workgroup per flagged problem (every flagged problem must have at most
+// batch_solve_max() points): y_b <- (L_b L_b^T)^{-1} y_b in the batch's (dim, ntot) layout.
+int batch_solve_max();
+hipError_t launch_batch_dense_solve(const double* L, const int64_t* loff, const double* Linv, const int64_t* ioff,
+                                    const int64_t* offs, int nprob, int dim, int64_t ntot, double* y, const int* flag,
+                                    hipStream_t st);
 
 int64_t tiles_of(int64_t n);     // 64-point tiles covering n points
 int64_t sort_pad(int64_t n);     // power of two >= max(n, 2)

@@ -936,4 +936,224 @@ template hipError_t launch_permute<float, double>(float*, const double*, const i
 template hipError_t launch_permute<double, float>(double*, const float*, const int64_t*, int64_t, int, bool, hipStream_t);
 template hipError_t launch_convert<double, float>(double*, const float*, int64_t, hipStream_t);
 
+// ---------------------------------------------------------------------------------------
+// Batched pair sums: many independent problems of uneven size, concatenated in one
+// component-major array (dim, ntot); problem b owns columns offs[b] .. offs[b+1]-1 and its
+// particles interact only with each other.  The work is a list of items, one wavefront
+// each: (problem, first target of a 64-target tile, source chunk, chunks of the problem).
+// The grid is persistent: every wave walks the list from its global wave id with a stride
+// of all waves in the grid.  The host sorts the list by cost (largest first), so the strided
+// walk hands every wave a mix of large and small items.  An item whose problem is not split
+// (one chunk) runs the epilogue itself; split problems write partial sums that
+// lm_batch_finish_kernel adds in chunk order.  Every sum has a fixed order.
+// ---------------------------------------------------------------------------------------
+
+template <class T, int DIM, int KER, bool FORCE>
+__global__ __launch_bounds__(kTile * kWaves) void lm_batch_pair_kernel(BatchArgs<T> a)
+{
+    const int lane = threadIdx.x & (kTile - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t stride = (int32_t)gridDim.x * kWaves;
+    for (int32_t it = (int32_t)blockIdx.x * kWaves + wave; it < a.nitems; it += stride) {
+        const int4 w = a.items[it];
+        const int64_t off = a.offs[w.x];
+        const int64_t nb = a.offs[w.x + 1] - off;
+        const int64_t il = w.y + lane;
+        const bool live = il < nb;
+        const int64_t ig = off + (live ? il : nb - 1);
+        T qi[DIM], psi[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            qi[c] = a.q[c * a.ntot + ig];
+            psi[c] = FORCE ? (T)(a.wscale * (double)a.p[c * a.ntot + ig]) : (T)0;
+        }
+        const int64_t chunk = (nb + w.w - 1) / w.w;
+        const int64_t j0 = off + (int64_t)w.z * chunk;
+        const int64_t j1 = (j0 + chunk < off + nb) ? (j0 + chunk) : (off + nb);
+        double v[DIM], f[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) { v[c] = 0.0; f[c] = 0.0; }
+        sum_sources<DIM, KER, FORCE>(a.q, a.p, a.ntot, j0, j1, qi, psi, a.kq, v, f);
+        if (!live) continue;
+        if (w.w == 1) {
+            epilogue<T, DIM, FORCE>(a.epi, a.ntot, off + il, v, f);
+        } else {
+            double* pp = a.part + a.part_off[w.x] + (int64_t)w.z * (2 * DIM) * nb;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                pp[c * nb + il] = v[c];
+                pp[(DIM + c) * nb + il] = f[c];
+            }
+        }
+    }
+}
+
+// Finish items (problem, first target of a tile, chunks, -): add the chunk partials of each
+// target in chunk order and run the epilogue.  Same persistent walk as the pair kernel.
+template <class T, int DIM, bool FORCE>
+__global__ __launch_bounds__(kTile * kWaves) void lm_batch_finish_kernel(BatchArgs<T> a, const int4* __restrict__ fin,
+                                                                        int32_t nfin)
+{
+    const int lane = threadIdx.x & (kTile - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t stride = (int32_t)gridDim.x * kWaves;
+    for (int32_t it = (int32_t)blockIdx.x * kWaves + wave; it < nfin; it += stride) {
+        const int4 w = fin[it];
+        const int64_t off = a.offs[w.x];
+        const int64_t nb = a.offs[w.x + 1] - off;
+        const int64_t il = w.y + lane;
+        if (il >= nb) continue;
+        const double* pp = a.part + a.part_off[w.x];
+        double v[DIM], f[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            v[c] = pp[c * nb + il];
+            f[c] = pp[(DIM + c) * nb + il];
+        }
+        for (int s = 1; s < w.z; ++s) {
+            const double* ps = pp + (int64_t)s * (2 * DIM) * nb;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                v[c] += ps[c * nb + il];
+                f[c] += ps[(DIM + c) * nb + il];
+            }
+        }
+        epilogue<T, DIM, FORCE>(a.epi, a.ntot, off + il, v, f);
+    }
+}
+
+template <class T, int DIM, int KER>
+static hipError_t launch_batch_k(bool force, const BatchArgs<T>& a, const int4* fin, int32_t nfin, int groups,
+                                 hipStream_t st)
+{
+    const dim3 blk(kTile * kWaves);
+    if (force)
+        hipLaunchKernelGGL((lm_batch_pair_kernel<T, DIM, KER, true>), dim3(groups), blk, 0, st, a);
+    else
+        hipLaunchKernelGGL((lm_batch_pair_kernel<T, DIM, KER, false>), dim3(groups), blk, 0, st, a);
+    if (nfin > 0) {
+        const int fg = (int)((nfin + kWaves - 1) / kWaves);
+        const int g = fg < groups ? fg : groups;
+        if (force)
+            hipLaunchKernelGGL((lm_batch_finish_kernel<T, DIM, true>), dim3(g), blk, 0, st, a, fin, nfin);
+        else
+            hipLaunchKernelGGL((lm_batch_finish_kernel<T, DIM, false>), dim3(g), blk, 0, st, a, fin, nfin);
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_batch_pair(int dim, int kernel, bool force, const BatchArgs<T>& a, const int4* fin, int32_t nfin,
+                             int groups, hipStream_t st)
+{
+    if (dim == 2)
+        return kernel == LM_KERNEL_CONON ? launch_batch_k<T, 2, LM_KERNEL_CONON>(force, a, fin, nfin, groups, st)
+                                         : launch_batch_k<T, 2, LM_KERNEL_GAUSS>(force, a, fin, nfin, groups, st);
+    return kernel == LM_KERNEL_CONON ? launch_batch_k<T, 3, LM_KERNEL_CONON>(force, a, fin, nfin, groups, st)
+                                     : launch_batch_k<T, 3, LM_KERNEL_GAUSS>(force, a, fin, nfin, groups, st);
+}
+template hipError_t launch_batch_pair<double>(int, int, bool, const BatchArgs<double>&, const int4*, int32_t, int,
+                                              hipStream_t);
+template hipError_t launch_batch_pair<float>(int, int, bool, const BatchArgs<float>&, const int4*, int32_t, int,
+                                             hipStream_t);
+
+// Per-problem reductions over the concatenated layout, one workgroup per problem, in a
+// fixed order (strided partial per thread, then a tree in LDS).
+//   max:  out[b] = max over c, i of |x[c][i] - y[c][i]|   (NaN wins)
+//   dot:  out[b] = sum over c, i of x[c][i] * y[c][i]
+template <class TX, bool MAX>
+__global__ __launch_bounds__(kRedThreads) void lm_batch_reduce_kernel(const TX* __restrict__ x,
+                                                                      const double* __restrict__ y, int dim,
+                                                                      int64_t ntot, const int64_t* __restrict__ offs,
+                                                                      double* __restrict__ out)
+{
+    __shared__ double sh[kRedThreads];
+    const int64_t off = offs[blockIdx.x], nb = offs[blockIdx.x + 1] - off;
+    double r = 0.0;
+    for (int c = 0; c < dim; ++c)
+        for (int64_t i = threadIdx.x; i < nb; i += kRedThreads) {
+            const int64_t k = c * ntot + off + i;
+            if (MAX) {
+                const double d = __builtin_fabs((double)x[k] - y[k]);
+                r = (d > r || d != d) ? d : r;
+            } else {
+                r = __builtin_fma((double)x[k], y[k], r);
+            }
+        }
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            const double b = sh[threadIdx.x + o], av = sh[threadIdx.x];
+            sh[threadIdx.x] = MAX ? ((b > av || b != b) ? b : av) : av + b;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+template <class TX>
+hipError_t launch_batch_maxabsdiff(const TX* x, const double* y, int dim, int64_t ntot, const int64_t* offs, int nprob,
+                                   double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL((lm_batch_reduce_kernel<TX, true>), dim3(nprob), dim3(kRedThreads), 0, st, x, y, dim, ntot, offs,
+                       out);
+    return hipGetLastError();
+}
+template hipError_t launch_batch_maxabsdiff<double>(const double*, const double*, int, int64_t, const int64_t*, int,
+                                                    double*, hipStream_t);
+template hipError_t launch_batch_maxabsdiff<float>(const float*, const double*, int, int64_t, const int64_t*, int,
+                                                   double*, hipStream_t);
+
+hipError_t launch_batch_dot(const double* x, const double* y, int dim, int64_t ntot, const int64_t* offs, int nprob,
+                            double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL((lm_batch_reduce_kernel<double, false>), dim3(nprob), dim3(kRedThreads), 0, st, x, y, dim, ntot,
+                       offs, out);
+    return hipGetLastError();
+}
+
+// p[c][i] += h * x[c][i] for the particles of problems whose flag is set (one workgroup per
+// problem).
+__global__ __launch_bounds__(256) void lm_batch_axpy_kernel(double* __restrict__ p, const double* __restrict__ x,
+                                                            double h, int dim, int64_t ntot,
+                                                            const int64_t* __restrict__ offs,
+                                                            const int* __restrict__ active)
+{
+    if (!active[blockIdx.x]) return;
+    const int64_t off = offs[blockIdx.x], nb = offs[blockIdx.x + 1] - off;
+    for (int c = 0; c < dim; ++c)
+        for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) {
+            const int64_t k = c * ntot + off + i;
+            p[k] = __builtin_fma(h, x[k], p[k]);
+        }
+}
+
+hipError_t launch_batch_axpy(double* p, const double* x, double h, int dim, int64_t ntot, const int64_t* offs,
+                             const int* active, int nprob, hipStream_t st)
+{
+    hipLaunchKernelGGL(lm_batch_axpy_kernel, dim3(nprob), dim3(256), 0, st, p, x, h, dim, ntot, offs, active);
+    return hipGetLastError();
+}
+
+// dst[c][i] = src[c][i] (with type conversion) for the particles of flagged problems.
+template <class TO, class TI>
+__global__ __launch_bounds__(256) void lm_batch_copy_kernel(TO* __restrict__ dst, const TI* __restrict__ src, int dim,
+                                                            int64_t ntot, const int64_t* __restrict__ offs,
+                                                            const int* __restrict__ flag)
+{
+    if (!flag[blockIdx.x]) return;
+    const int64_t off = offs[blockIdx.x], nb = offs[blockIdx.x + 1] - off;
+    for (int c = 0; c < dim; ++c)
+        for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) dst[c * ntot + off + i] = (TO)src[c * ntot + off + i];
+}
+
+hipError_t launch_batch_copy_f32_to_f64(double* dst, const float* src, int dim, int64_t ntot, const int64_t* offs,
+                                        const int* flag, int nprob, hipStream_t st)
+{
+    hipLaunchKernelGGL((lm_batch_copy_kernel<double, float>), dim3(nprob), dim3(256), 0, st, dst, src, dim, ntot, offs,
+                       flag);
+    return hipGetLastError();
+}
+
 }  // namespace lm

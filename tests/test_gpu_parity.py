@@ -281,6 +281,27 @@ def test_feedback_single_precision_shoot():
     assert rel_err(p0, ref.p0) <= 1e-4
 
 
+def test_feedback_single_precision_switches_to_double():
+    """With f32_switch the match shoots in single precision until the residual is below the
+    switch, then in double: it reaches a tolerance single precision cannot, in the oracle's
+    iteration count (or one more), and its last shoot is a double-precision one."""
+    pr = inputs.config_curve2d(700)
+    prm = lm.make_params(2, lm.CONON, pr.sigma, dtype=lm.F32)
+    p0 = torch.zeros((2, pr.n), dtype=torch.float64, device=DEV)
+    q1 = torch.empty_like(p0)
+    st, info, shots = lm.lm_feedback_match(prm, dev(pr.X), dev(pr.Y), p0, h=0.8, tol=1e-9, steps=40, max_iter=200,
+                                           q1=q1, f32_switch=1e-4)
+    ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-9, 40, max_iter=200)
+    print("switch: gpu %d updates, %d shoots, resid %.2e | oracle %d" % (info.iters, len(shots), info.resid_inf,
+                                                                           ref.iters))
+    assert st == 0 and ref.status == 0
+    assert 0 <= info.iters - ref.iters <= 1
+    assert info.iters + 1 <= len(shots) <= info.iters + 2
+    assert info.resid_inf < 1e-9
+    oq, _ = oracle.shoot(pr.X, host(p0), 0, pr.sigma, 40)
+    assert rel_err(host(q1), oq) <= 1e-10
+
+
 def test_feedback_max_iter_reports_not_converged():
     pr = inputs.config_circle_ellipse(64)
     st, info, _, _ = gpu_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, pr.steps, max_iter=3)
