@@ -11,8 +11,14 @@ value       = shooting pair interactions of the step (shoots * 4 * rk4_steps * N
               wall time (factorisation, solves and residuals count against it)
 ms_per_step = time to match.
 Beside them: the dominant kernel's roofline (its average launch time measured live with HIP
-events on the stream it runs on, inside the library), a second time-to-match on the 2-D
-curve workload, and the FP64 oracle timed on the host cores on a bounded sample.
+events on the stream it runs on, inside the library), time-to-match on the 2-D curve (N =
+4096) and circle-to-ellipse (N = 64) workloads, and the FP64 oracle timed on the host cores
+on a bounded sample.
+
+Also reported (not part of value): the 256-problem batch (2-D curves, N_b log-uniform in
+[32, 4096], conical sigma = 0.1, 100 RK4 steps) -- autotuned launch shape, batched shoot
+pair-interactions/s in FP32 and FP64, and batched time-to-match at 1e-6 (FP32 shoots
+switching to FP64 at residual 1e-4, and FP64 throughout).
 
 Default workload: 65536 Fibonacci-sphere landmarks in 3-D, conical kernel sigma = 0.05,
 100 RK4 steps on [0, 1], FP64, h = 0.8; the target is the template moved by a seeded smooth
@@ -115,6 +121,59 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def batched_leg(lm, torch, dev, h: float, tol: float):
+    """The 256-problem batch: autotuned shape, shoot throughput, time-to-match."""
+    import numpy as np
+    import inputs
+
+    sizes, offs, X, Y = inputs.config_batched()
+    steps = 100
+    pairs = float((sizes.astype(np.float64) ** 2).sum())
+    p = np.concatenate([inputs.bench_momentum(X[:, offs[b]:offs[b + 1]], Y[:, offs[b]:offs[b + 1]],
+                                              inputs.curve_kernel_mass(int(sizes[b]), 2 * math.pi, 0.1, 0))
+                        for b in range(len(sizes))], axis=1)
+    Xd, Yd = torch.tensor(X, device=dev), torch.tensor(Y, device=dev)
+    out = {"workload": "batched256_curve2d_conon", "problems": int(len(sizes)), "n_total": int(offs[-1]),
+           "n_min": int(sizes.min()), "n_max": int(sizes.max()), "sum_n2": pairs, "rk4_steps": steps,
+           "sigma": 0.1}
+    tunings = {}
+    for name, dtype, tdt in [("f32", lm.F32, torch.float32), ("f64", lm.F64, torch.float64)]:
+        prm = lm.make_params(2, lm.CONON, 0.1, dtype=dtype)
+        q0, p0 = Xd.to(tdt), torch.tensor(p, dtype=tdt, device=dev)
+        t = lm.lm_batch_autotune(prm, offs, q0, p0)
+        tunings[name] = t
+        q1, p1 = torch.empty_like(q0), torch.empty_like(q0)
+        lm.lm_shoot_batched(prm, offs, q0, p0, 1.0, steps, q1, p1, tuning=t)       # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lm.lm_shoot_batched(prm, offs, q0, p0, 1.0, steps, q1, p1, tuning=t)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["shoot_" + name] = {"ms": dt * 1e3, "pairs_per_s": pairs * 4 * steps / dt, "tuning": t.as_dict()}
+        log("batched shoot %s: %.1f ms, %.3e pairs/s (tuning %s)" % (name, dt * 1e3, pairs * 4 * steps / dt,
+                                                                    t.as_dict()))
+    for name, dtype, sw in [("f32_then_f64", lm.F32, 1e-4), ("f64", lm.F64, 0.0)]:
+        prm = lm.make_params(2, lm.CONON, 0.1, dtype=dtype)
+        pg = torch.zeros_like(Xd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, infos, stats = lm.lm_feedback_match_batched(prm, offs, Xd, Yd, pg, h=h, tol=tol, steps=steps,
+                                                        max_iter=200, tuning=tunings["f32" if dtype == lm.F32
+                                                                                     else "f64"],
+                                                        f32_switch=sw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        its = [i.iters for i in infos]
+        out["time_to_match_" + name] = {
+            "seconds": dt, "status": lm.STATUS_NAMES[st], "converged": sum(1 for s in stats if s == 0),
+            "iters_max": max(its), "iters_mean": sum(its) / len(its),
+            "resid_max": max(i.resid_inf for i in infos), "shoot_ms": infos[0].shoot_ms,
+            "solve_ms": infos[0].solve_ms, "factor_ms": infos[0].factor_ms, "tol": tol, "h": h,
+            "f32_switch": sw}
+        log("batched time to match (%s): %.2f s, %s, iterations max %d" % (name, dt, lm.STATUS_NAMES[st], max(its)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,8 +188,12 @@ def main():
     ap.add_argument("--cg-max-iter", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--match", default="curve2d_conon_f64", choices=sorted(WORKLOADS) + ["none"],
-                    help="second time-to-match measurement (untimed for value)")
+    ap.add_argument("--match", default="curve2d_conon_f64,circle_ellipse_f64",
+                    help="comma-separated workloads whose time-to-match is also reported (outside value), "
+                         "or none")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batch measurements")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 256-problem batch measurements (a diagnostic line, not the benchmark)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -155,6 +218,10 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read, %d MiB written" % (args.calibrate_copy, args.calibrate_copy))
         del src, dst
+
+    if args.batched_only:
+        print(json.dumps({"batched": batched_leg(lm, torch, dev, args.h, args.tol)}), flush=True)
+        return
 
     def setup(name):
         spec, dtype = WORKLOADS[name]
@@ -239,20 +306,27 @@ def main():
     if args.mode == "match":
         ttm = dict(records[-1], workload=args.workload, seconds=elapsed / args.steps, tol=args.tol, h=args.h)
 
-    ttm2 = None
-    if args.match != "none" and args.match != args.workload:
-        mpr, mdtype, mrc, mprm, MX, MY = setup(args.match)
+    extra_matches = {}
+    for mname in ([] if args.match == "none" else args.match.split(",")):
+        if mname == args.workload:
+            continue
+        mpr, mdtype, mrc, mprm, MX, MY = setup(mname)
         run_match(mprm, mpr, MX, MY)                         # warm-up
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         st, minfo, hist = run_match(mprm, mpr, MX, MY)
         torch.cuda.synchronize()
-        ttm2 = {"workload": args.match, "seconds": time.perf_counter() - t1, "status": lm.STATUS_NAMES[st],
-                "iters": minfo.iters, "resid_inf": minfo.resid_inf, "factor_ms": minfo.factor_ms,
-                "shoot_ms": minfo.shoot_ms, "solve_ms": minfo.solve_ms, "cg_iters": minfo.cg_iters,
-                "tol": args.tol, "h": args.h, "paper_H_2H": 2 * minfo.H}
+        extra_matches[mname] = {
+            "workload": mname, "n": mpr.n, "seconds": time.perf_counter() - t1, "status": lm.STATUS_NAMES[st],
+            "iters": minfo.iters, "resid_inf": minfo.resid_inf, "factor_ms": minfo.factor_ms,
+            "shoot_ms": minfo.shoot_ms, "solve_ms": minfo.solve_ms, "cg_iters": minfo.cg_iters,
+            "tol": args.tol, "h": args.h, "paper_H_2H": 2 * minfo.H}
         log("time to match %s: %.3f s, %d iterations, resid %.2e" % (
-            args.match, ttm2["seconds"], minfo.iters, minfo.resid_inf))
+            mname, extra_matches[mname]["seconds"], minfo.iters, minfo.resid_inf))
+    ttm2 = extra_matches.get("curve2d_conon_f64")
+    ttm3 = extra_matches.get("circle_ellipse_f64")
+
+    batched = None if args.no_batched else batched_leg(lm, torch, dev, args.h, args.tol)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(pr, args.cpu_seconds)
 
@@ -278,6 +352,8 @@ def main():
         "cpu_baseline": cpu,
         "time_to_match": ttm,
         "time_to_match_curve2d": ttm2,
+        "time_to_match_circle_ellipse": ttm3,
+        "batched": batched,
         "shoots": shoots,
         "gpu_ms": {"shoot": shoot_ms, "solve": solve_ms, "factor": factor_ms},
         "records": records,

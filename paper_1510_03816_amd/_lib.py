@@ -83,12 +83,19 @@ _lib = None
 
 
 def load():
-    """Load the in-tree liblm.so.  Raises if it has not been built: there is no fallback."""
+    """Load the in-tree liblm.so.  Raises if it has not been built: there is no fallback.
+
+    torch is imported first: its HIP runtime (the one that owns every tensor the binding
+    passes in) must be the one the library binds to.  Loaded the other way round, the
+    library would pull in the system runtime under the same soname and the process would
+    hold two HIP runtimes, each blind to the other's device state.
+    """
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("liblm.so is not built (run __graft_entry__.build() or "
                               "python paper_1510_03816_amd/build.py)")
+        import torch  # noqa: F401  (loads torch's HIP runtime before liblm.so)
         L = ctypes.CDLL(LIB_PATH)
         P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         PP = ctypes.POINTER(lm_params)

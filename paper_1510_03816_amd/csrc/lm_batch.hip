@@ -235,19 +235,31 @@ lm_status batch_steps(const lm_params* prm, const BatchPlan& pl, T* q, T* p, dou
     return LM_OK;
 }
 
-// A captured sequence of RK4 steps, replayable on any stream.
+// A captured sequence of RK4 steps, replayable on any stream.  The executable graph is
+// destroyed only after the stream it was last launched on has drained, also when an error
+// ends the call between two launches.
 struct StepGraph {
     hipStream_t cs = nullptr;
     hipGraph_t g = nullptr;
     hipGraphExec_t x = nullptr;
+    bool launched = false;
+    hipStream_t launch_stream = nullptr;
+    hipError_t launch(hipStream_t st)
+    {
+        launched = true;
+        launch_stream = st;
+        return hipGraphLaunch(x, st);
+    }
     void reset()
     {
+        if (launched) (void)hipStreamSynchronize(launch_stream);
         if (x) (void)hipGraphExecDestroy(x);
         if (g) (void)hipGraphDestroy(g);
         if (cs) (void)hipStreamDestroy(cs);
         x = nullptr;
         g = nullptr;
         cs = nullptr;
+        launched = false;
     }
     ~StepGraph() { reset(); }
 };
@@ -256,6 +268,7 @@ template <class T>
 lm_status capture_steps(const lm_params* prm, const BatchPlan& pl, T* q, T* p, double dt, int32_t count,
                         const ShootBufs<T>& w, StepGraph* sg)
 {
+    sg->reset();
     LM_HIP(hipStreamCreateWithFlags(&sg->cs, hipStreamNonBlocking));
     LM_HIP(hipStreamBeginCapture(sg->cs, hipStreamCaptureModeThreadLocal));
     const lm_status s = batch_steps<T>(prm, pl, q, p, dt, count, w, sg->cs);
@@ -282,7 +295,7 @@ lm_status batch_shoot_inplace(const lm_params* prm, const BatchPlan& pl, T* q, T
     StepGraph* sg = cache ? cache : &local;
     if (!sg->x) LM_TRY(capture_steps<T>(prm, pl, q, p, dt, graph_steps, w, sg));
     const int32_t reps = steps / graph_steps;
-    for (int32_t r = 0; r < reps; ++r) LM_HIP(hipGraphLaunch(sg->x, st));
+    for (int32_t r = 0; r < reps; ++r) LM_HIP(sg->launch(st));
     LM_TRY(batch_steps<T>(prm, pl, q, p, dt, steps - reps * graph_steps, w, st));
     LM_HIP(hipStreamSynchronize(st));
     return LM_OK;

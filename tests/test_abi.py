@@ -8,6 +8,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -112,3 +113,19 @@ def test_package_import_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_one_hip_runtime_whatever_the_import_order(tmp_path):
+    """Importing the package before torch must still leave a single HIP runtime in the
+    process (the one torch loads): liblm.so binds to it instead of the system copy."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1510_03816_amd\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "libs = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
+            "print(len(libs)); print(libs)\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    lines = out.stdout.splitlines()
+    assert lines[0] == "1", lines
