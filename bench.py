@@ -20,6 +20,10 @@ Also reported (not part of value): the 256-problem batch (2-D curves, N_b log-un
 pair-interactions/s in FP32 and FP64, and batched time-to-match at 1e-6 (FP32 shoots
 switching to FP64 at residual 1e-4, and FP64 throughout).
 
+And the differentiation workload (16384 sphere points, Gaussian sigma = 0.1, lambda = 100):
+one energy-and-gradient evaluation, L-BFGS on the energy, and the feedback iteration on the
+same problem (its Gaussian kernel matrix is numerically singular there).
+
 Default workload: 65536 Fibonacci-sphere landmarks in 3-D, conical kernel sigma = 0.05,
 100 RK4 steps on [0, 1], FP64, h = 0.8; the target is the template moved by a seeded smooth
 field.  --mode iteration times single feedback iterations (lm_feedback_step, CG K-solve)
@@ -174,6 +178,51 @@ def batched_leg(lm, torch, dev, h: float, tol: float):
     return out
 
 
+def adjoint_leg(lm, torch, dev, full: bool):
+    """Gradient-based matching on the differentiation workload (16384 Fibonacci-sphere points,
+    Gaussian sigma = 0.1, lambda = 100, 100 RK4 steps, checkpoints every 10 steps) beside the
+    feedback iteration on the same problem."""
+    import inputs
+
+    pr = inputs.config_adjoint3d()
+    lam, ck = pr.extra["lam"], pr.extra["ckpt_every"]
+    prm = lm.make_params(3, lm.GAUSS, pr.sigma)
+    X, Y = torch.tensor(pr.X, device=dev), torch.tensor(pr.Y, device=dev)
+    out = {"workload": "adjoint3d_gauss_f64", "n": pr.n, "sigma": pr.sigma, "lam": lam, "rk4_steps": pr.steps,
+           "ckpt_every": ck}
+    p0, g = torch.zeros_like(X), torch.empty_like(X)
+    lm.lm_energy_grad(prm, X, Y, p0, lam, pr.steps, g, ckpt_every=ck)           # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lm.lm_energy_grad(prm, X, Y, p0, lam, pr.steps, g, ckpt_every=ck)
+    torch.cuda.synchronize()
+    out["energy_grad_s"] = time.perf_counter() - t0
+    runs = [("lbfgs_energy", 1.0, 1e-6, 0.0)]
+    if full:
+        runs.append(("lbfgs_data_term_to_1e-6", 0.0, 0.0, 1e-6))
+    for name, reg, gtol, mtol in runs:
+        p0 = torch.zeros_like(X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = lm.lm_lbfgs_match(prm, X, Y, p0, lam=lam, steps=pr.steps, reg=reg, gtol=gtol, match_tol=mtol,
+                                     max_iter=300, history=16, ckpt_every=ck)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": dt, "status": lm.STATUS_NAMES[st], "iters": info.iters, "evals": info.evals,
+                     "E": info.E, "gnorm_inf": info.gnorm_inf, "resid_inf": info.resid_inf, "reg": reg,
+                     "gtol": gtol, "match_tol": mtol}
+        log("adjoint %s: %s %.1f s, %d iterations, %d evaluations, endpoint error %.2e" % (
+            name, lm.STATUS_NAMES[st], dt, info.iters, info.evals, info.resid_inf))
+    p0 = torch.zeros_like(X)
+    t0 = time.perf_counter()
+    st, info, _ = lm.lm_feedback_match(prm, X, Y, p0, h=0.8, tol=1e-6, steps=pr.steps, max_iter=30,
+                                       solver=lm.SOLVE_DENSE)
+    out["feedback_dense"] = {"seconds": time.perf_counter() - t0, "status": lm.STATUS_NAMES[st],
+                             "message": lm.last_error() if st != 0 else ""}
+    log("adjoint workload, feedback iteration: %s" % lm.STATUS_NAMES[st])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +241,9 @@ def main():
                     help="comma-separated workloads whose time-to-match is also reported (outside value), "
                          "or none")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batch measurements")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient-matching measurements")
+    ap.add_argument("--adjoint-full", action="store_true",
+                    help="also time L-BFGS on the data term alone to max|q(1) - Y| < 1e-6 (about 90 s)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 256-problem batch measurements (a diagnostic line, not the benchmark)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -327,6 +379,7 @@ def main():
     ttm3 = extra_matches.get("circle_ellipse_f64")
 
     batched = None if args.no_batched else batched_leg(lm, torch, dev, args.h, args.tol)
+    adjoint = None if args.no_adjoint else adjoint_leg(lm, torch, dev, args.adjoint_full)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(pr, args.cpu_seconds)
 
@@ -354,6 +407,7 @@ def main():
         "time_to_match_curve2d": ttm2,
         "time_to_match_circle_ellipse": ttm3,
         "batched": batched,
+        "adjoint": adjoint,
         "shoots": shoots,
         "gpu_ms": {"shoot": shoot_ms, "solve": solve_ms, "factor": factor_ms},
         "records": records,

@@ -235,6 +235,48 @@ lm_status batch_steps(const lm_params* prm, const BatchPlan& pl, T* q, T* p, dou
     return LM_OK;
 }
 
+// Side streams that start after the work already on a stream and that the stream then waits
+// for (join).  Destroyed after st has drained.
+constexpr int kFactorStreams = 8;
+
+struct SideStreams {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> e;
+    hipStream_t parent = nullptr;
+    lm_status init(int n, hipStream_t st)
+    {
+        parent = st;
+        hipEvent_t start;
+        LM_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+        e.push_back(start);
+        LM_HIP(hipEventRecord(start, st));
+        for (int i = 0; i < n; ++i) {
+            hipStream_t x;
+            LM_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+            s.push_back(x);
+            LM_HIP(hipStreamWaitEvent(x, start, 0));
+        }
+        return LM_OK;
+    }
+    lm_status join(hipStream_t st)
+    {
+        for (hipStream_t x : s) {
+            hipEvent_t done;
+            LM_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+            e.push_back(done);
+            LM_HIP(hipEventRecord(done, x));
+            LM_HIP(hipStreamWaitEvent(st, done, 0));
+        }
+        return LM_OK;
+    }
+    ~SideStreams()
+    {
+        for (hipStream_t x : s) (void)hipStreamSynchronize(x);
+        for (hipStream_t x : s) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : e) (void)hipEventDestroy(x);
+    }
+};
+
 // A captured sequence of RK4 steps, replayable on any stream.  The executable graph is
 // destroyed only after the stream it was last launched on has drained, also when an error
 // ends the call between two launches.
@@ -490,13 +532,17 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         isum += lm::dense_linv_elems(nb);
         nmax = std::max(nmax, nb);
     }
+    // the factors are independent: they are spread over kFactorStreams side streams (each
+    // with its own copy buffer for X_b), which wait for the allocations on st and are waited
+    // for by st
+    const int ns = std::min<int32_t>(B, kFactorStreams);
     double *L, *Linv, *xb;
     int* finfo;
     int64_t *loff_d, *ioff_d;
     LM_TRY(ws.get(&L, lsum));
     LM_TRY(ws.get(&Linv, isum));
     LM_TRY(ws.get(&finfo, B));
-    LM_TRY(ws.get(&xb, (int64_t)dim * nmax));
+    LM_TRY(ws.get(&xb, (int64_t)ns * dim * nmax));
     LM_TRY(ws.get(&loff_d, B));
     LM_TRY(ws.get(&ioff_d, B));
     LM_HIP(hipMemcpyAsync(loff_d, loff.data(), B * sizeof(int64_t), hipMemcpyHostToDevice, st));
@@ -504,13 +550,20 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
     double kq, wscale;
     kernel_scales(prm, false, &kq, &wscale);
     LM_HIP(hipEventRecord(tm.ev[0], st));
-    for (int32_t b = 0; b < B; ++b) {
-        const int64_t nb = offs[b + 1] - offs[b];
-        for (int c = 0; c < dim; ++c)
-            LM_HIP(hipMemcpyAsync(xb + c * nb, X + c * ntot + offs[b], nb * sizeof(double), hipMemcpyDeviceToDevice,
-                                  st));
-        LM_HIP(lm::launch_dense_factor(dim, prm->kernel, kq, prm->tau, xb, nb, L + loff[b], Linv + ioff[b],
-                                       finfo + b, st));
+    {
+        SideStreams side;
+        LM_TRY(side.init(ns, st));
+        for (int32_t b = 0; b < B; ++b) {
+            const int64_t nb = offs[b + 1] - offs[b];
+            hipStream_t fs = side.s[b % ns];
+            double* x = xb + (int64_t)(b % ns) * dim * nmax;
+            for (int c = 0; c < dim; ++c)
+                LM_HIP(hipMemcpyAsync(x + c * nb, X + c * ntot + offs[b], nb * sizeof(double),
+                                      hipMemcpyDeviceToDevice, fs));
+            LM_HIP(lm::launch_dense_factor(dim, prm->kernel, kq, prm->tau, x, nb, L + loff[b], Linv + ioff[b],
+                                           finfo + b, fs));
+        }
+        LM_TRY(side.join(st));
     }
     LM_HIP(hipEventRecord(tm.ev[1], st));
     std::vector<int> fi((size_t)B);

@@ -302,6 +302,24 @@ def test_feedback_single_precision_switches_to_double():
     assert rel_err(host(q1), oq) <= 1e-10
 
 
+@pytest.mark.parametrize("tau,solver", [(0.05, lm.SOLVE_DENSE), (0.3, lm.SOLVE_DENSE), (0.3, lm.SOLVE_CG)])
+def test_feedback_inexact_matches_oracle(tau, solver):
+    """Inexact matching (eq. N-particle-inexact, Table 5's stopping rule on successive
+    momenta): the same iteration count, momenta and residual history as the oracle."""
+    X, Y = inputs.example2(64)
+    prm = lm.make_params(2, lm.CONON, 1.0, tau=tau)
+    p0 = torch.zeros((2, 64), dtype=torch.float64, device=DEV)
+    st, info, hist = lm.lm_feedback_match(prm, dev(X), dev(Y), p0, h=0.8, tol=1e-3, steps=30, max_iter=300,
+                                          stop_rule=1, solver=solver)
+    ref = oracle.feedback_match(X, Y, 0, 1.0, 0.8, 1e-3, 30, max_iter=300, tau=tau, stop_rule=1)
+    print("inexact tau=%g: gpu %d its resid %.3e | oracle %d its resid %.3e" % (tau, info.iters, info.resid_inf,
+                                                                              ref.iters, ref.resid))
+    assert st == 0 and ref.status == 0
+    assert info.iters == ref.iters
+    assert rel_err(host(p0), ref.p0) <= 1e-8
+    assert np.allclose(hist, ref.hist, rtol=1e-6, atol=1e-12)
+
+
 def test_feedback_max_iter_reports_not_converged():
     pr = inputs.config_circle_ellipse(64)
     st, info, _, _ = gpu_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-6, pr.steps, max_iter=3)

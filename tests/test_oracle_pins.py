@@ -213,6 +213,37 @@ def test_energy_and_angular_momentum_drift_fourth_order(orc, kernel):
         assert 10.0 < d[0] / d[1] < 24.0 and 10.0 < d[1] / d[2] < 24.0
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_inexact_hamiltonian_drift_fourth_order(orc, kernel):
+    """The inexact system (eq. N-particle-inexact) is Hamiltonian with
+    H_tau = H + tau/2 sum |p_i|^2: RK4 conserves it to fourth order."""
+    q = 2.0 * inputs.circle(16, 1.0) + 0.1 * _rand(16, 2, seed=17)[0]
+    p = 0.15 * _rand(16, 2, seed=18)[1]
+    sigma, tau = 0.5, 0.3
+
+    def Htau(qq, pp):
+        return orc.hamiltonian(qq, pp, kernel, sigma) + 0.5 * tau * float(np.sum(pp * pp))
+
+    H0 = Htau(q, p)
+    d = []
+    for n in [5, 10, 20]:
+        q1, p1 = orc.shoot(q, p, kernel, sigma, n, tau=tau)
+        d.append(abs(Htau(q1, p1) - H0))
+    assert 10.0 < d[0] / d[1] < 24.0 and 10.0 < d[1] / d[2] < 24.0
+
+
+def test_inexact_stop_rule_is_the_momentum_step(orc):
+    """stop_rule 1 stops at the first k >= 1 whose last update h max|e^(k-1)| was below tol:
+    the count follows from the residual history of the same iteration run by rule 0."""
+    X, Y = inputs.circle(32, 1.0), inputs.ellipse(32, 1.3, 0.8)
+    h, tol = 0.8, 1e-3
+    full = orc.feedback_match(X, Y, 0, 0.5, h, 1e-12, 20, max_iter=40, tau=0.1)
+    k_want = next(k for k in range(1, len(full.hist)) if h * full.hist[k - 1] < tol)
+    res = orc.feedback_match(X, Y, 0, 0.5, h, tol, 20, max_iter=40, tau=0.1, stop_rule=1)
+    assert res.status == 0 and res.iters == k_want
+    assert np.array_equal(res.hist, full.hist[:k_want + 1])
+
+
 def _rot3(a, b, c):
     Rz = np.array([[math.cos(a), -math.sin(a), 0], [math.sin(a), math.cos(a), 0], [0, 0, 1]])
     Ry = np.array([[math.cos(b), 0, math.sin(b)], [0, 1, 0], [-math.sin(b), 0, math.cos(b)]])
