@@ -129,6 +129,20 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
                         T* bq, T* bp, T* cq, T* cp, double* part, hipStream_t st, double* box = nullptr)
 {
     const double dt = t1 / steps;
+    if (!box && n <= lm::kSmallMax) {
+        // the whole shoot in one launch (one workgroup holds the problem)
+        lm::SmallShootArgs<T> a{};
+        a.q = q;
+        a.p = p;
+        a.ntot = n;
+        a.offs = nullptr;
+        a.dt = dt;
+        a.steps = steps;
+        kernel_scales(prm, sizeof(T) == 4, &a.kq, &a.wscale);
+        a.tau = prm->tau;
+        LM_HIP(lm::launch_small_shoot<T>(prm->dim, prm->kernel, a, 1, st));
+        return LM_OK;
+    }
     lm::EpiArgs<T> e{};
     e.dt = dt;
     e.tau = prm->tau;

@@ -131,6 +131,26 @@ hipError_t launch_batch_axpy(double* p, const double* x, double h, int dim, int6
 hipError_t launch_batch_copy_f32_to_f64(double* dst, const float* src, int dim, int64_t ntot, const int64_t* offs,
                                         const int* flag, int nprob, hipStream_t st);
 
+// Whole shoots of problems of at most kSmallMax points, one workgroup each (see
+// lm_small_shoot_kernel): (q, p) advanced in place by `steps` RK4 steps of size dt.
+constexpr int kSmallMax = 256;
+
+template <class T>
+struct SmallShootArgs {
+    T* q;                    // (dim, ntot), in place
+    T* p;
+    int64_t ntot;
+    const int64_t* offs;     // problem b owns [offs[b], offs[b+1]); null: one problem of ntot
+    double dt;
+    int steps;
+    double kq;
+    double wscale;
+    double tau;
+};
+
+template <class T>
+hipError_t launch_small_shoot(int dim, int kernel, const SmallShootArgs<T>& a, int problems, hipStream_t st);
+
 struct PairPlan {
     int64_t itiles;
     int nsplit;

@@ -1156,4 +1156,172 @@ hipError_t launch_batch_copy_f32_to_f64(double* dst, const float* src, int dim, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// Whole shoots of small problems in one launch.  A problem of at most kSmallMax points fits
+// one workgroup: its stage input lives in LDS, each owner thread keeps its particle's RK4
+// state (step input and running sum, in double precision) in registers, and all
+// 4 x steps stages run inside the kernel with two barriers each.  This removes the one
+// launch per stage that bounds small problems by launch latency.  The four waves split
+// the work as (target tile, source chunk): one tile and four chunks up to 64 points, two
+// and two up to 128, four tiles of all sources up to 256; chunk partials are added in chunk
+// order.  One workgroup per problem: grid = problems (offs non-null) or one problem of
+// ntot points.
+// ---------------------------------------------------------------------------------------
+
+template <int DIM, int KER>
+__device__ __forceinline__ void sum_lds(const double* __restrict__ sq, const double* __restrict__ sp, int j0, int j1,
+                                        const double (&qi)[DIM], const double (&psi)[DIM], double kq,
+                                        double (&v)[DIM], double (&f)[DIM])
+{
+    for (int j = j0; j < j1; ++j) {
+        double qj[DIM], pj[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            qj[c] = sq[c * kSmallMax + j];
+            pj[c] = sp[c * kSmallMax + j];
+        }
+        pair_f64<DIM, KER, true>(qi, psi, qj, pj, kq, v, f);
+    }
+}
+
+// single precision: the chunk (at most 64 sources) is one run summed in float
+template <int DIM, int KER>
+__device__ __forceinline__ void sum_lds(const float* __restrict__ sq, const float* __restrict__ sp, int j0, int j1,
+                                        const float (&qi)[DIM], const float (&psi)[DIM], double kqd,
+                                        double (&v)[DIM], double (&f)[DIM])
+{
+    const float kq = (float)kqd;
+    float vs[DIM], fs[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { vs[c] = 0.0f; fs[c] = 0.0f; }
+    for (int j = j0; j < j1; ++j) {
+        float qj[DIM], pj[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            qj[c] = sq[c * kSmallMax + j];
+            pj[c] = sp[c * kSmallMax + j];
+        }
+        pair_f32<DIM, KER, true>(qi, psi, qj, pj, kq, vs, fs);
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) { v[c] += (double)vs[c]; f[c] += (double)fs[c]; }
+}
+
+template <class T, int DIM, int KER>
+__global__ __launch_bounds__(256) void lm_small_shoot_kernel(SmallShootArgs<T> a)
+{
+    __shared__ T sq[DIM * kSmallMax];
+    __shared__ T sp[DIM * kSmallMax];
+    __shared__ double red[4][2 * DIM][kSmallMax];
+    const int64_t off = a.offs ? a.offs[blockIdx.x] : 0;
+    const int n = a.offs ? (int)(a.offs[blockIdx.x + 1] - off) : (int)a.ntot;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles = (n + 63) / 64;
+    const int tp = tiles <= 1 ? 1 : (tiles <= 2 ? 2 : 4);
+    const int nchunk = 4 / tp;
+    const int tile = wave % tp, chunk = wave / tp;
+    const int i = tile * 64 + lane;
+    const int ic = i < n ? i : n - 1;
+    const bool owner = chunk == 0 && i < n;
+    const int clen = (n + nchunk - 1) / nchunk;
+    const int j0 = chunk * clen < n ? chunk * clen : n;
+    const int j1 = j0 + clen < n ? j0 + clen : n;
+
+    for (int e = threadIdx.x; e < n; e += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            sq[c * kSmallMax + e] = a.q[c * a.ntot + off + e];
+            sp[c * kSmallMax + e] = a.p[c * a.ntot + off + e];
+        }
+    double yq[DIM], yp[DIM], cq[DIM], cp[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        yq[c] = owner ? (double)a.q[c * a.ntot + off + i] : 0.0;
+        yp[c] = owner ? (double)a.p[c * a.ntot + off + i] : 0.0;
+        cq[c] = 0.0;
+        cp[c] = 0.0;
+    }
+    __syncthreads();
+
+    for (int s = 0; s < a.steps; ++s) {
+        for (int k = 0; k < 4; ++k) {
+            T qi[DIM], psi[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                qi[c] = sq[c * kSmallMax + ic];
+                psi[c] = (T)(a.wscale * (double)sp[c * kSmallMax + ic]);
+            }
+            double v[DIM], f[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) { v[c] = 0.0; f[c] = 0.0; }
+            sum_lds<DIM, KER>(sq, sp, j0, j1, qi, psi, a.kq, v, f);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                red[chunk][c][i] = v[c];
+                red[chunk][DIM + c][i] = f[c];
+            }
+            __syncthreads();
+            if (owner) {
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    double sv = red[0][c][i], sf = red[0][DIM + c][i];
+                    for (int ch = 1; ch < nchunk; ++ch) {
+                        sv += red[ch][c][i];
+                        sf += red[ch][DIM + c][i];
+                    }
+                    const double kqc = sv + a.tau * (double)sp[c * kSmallMax + i];
+                    const double kpc = sf;
+                    double nq, np;
+                    if (k == 0) {
+                        cq[c] = kqc;
+                        cp[c] = kpc;
+                        nq = yq[c] + 0.5 * a.dt * kqc;
+                        np = yp[c] + 0.5 * a.dt * kpc;
+                    } else if (k < 3) {
+                        cq[c] += 2.0 * kqc;
+                        cp[c] += 2.0 * kpc;
+                        const double h = (k == 2) ? a.dt : 0.5 * a.dt;
+                        nq = yq[c] + h * kqc;
+                        np = yp[c] + h * kpc;
+                    } else {
+                        const double h6 = a.dt / 6.0;
+                        yq[c] = yq[c] + h6 * (cq[c] + kqc);
+                        yp[c] = yp[c] + h6 * (cp[c] + kpc);
+                        nq = yq[c];
+                        np = yp[c];
+                    }
+                    sq[c * kSmallMax + i] = (T)nq;
+                    sp[c * kSmallMax + i] = (T)np;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (owner)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            a.q[c * a.ntot + off + i] = (T)yq[c];
+            a.p[c * a.ntot + off + i] = (T)yp[c];
+        }
+}
+
+template <class T>
+hipError_t launch_small_shoot(int dim, int kernel, const SmallShootArgs<T>& a, int problems, hipStream_t st)
+{
+    if (dim == 2) {
+        if (kernel == LM_KERNEL_CONON)
+            hipLaunchKernelGGL((lm_small_shoot_kernel<T, 2, LM_KERNEL_CONON>), dim3(problems), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((lm_small_shoot_kernel<T, 2, LM_KERNEL_GAUSS>), dim3(problems), dim3(256), 0, st, a);
+    } else {
+        if (kernel == LM_KERNEL_CONON)
+            hipLaunchKernelGGL((lm_small_shoot_kernel<T, 3, LM_KERNEL_CONON>), dim3(problems), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((lm_small_shoot_kernel<T, 3, LM_KERNEL_GAUSS>), dim3(problems), dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_small_shoot<double>(int, int, const SmallShootArgs<double>&, int, hipStream_t);
+template hipError_t launch_small_shoot<float>(int, int, const SmallShootArgs<float>&, int, hipStream_t);
+
 }  // namespace lm

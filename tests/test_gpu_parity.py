@@ -132,6 +132,25 @@ def test_shoot_matches_oracle(name, make, steps, dtype):
     assert eq <= TOL[dtype] and ep <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 127, 128, 129, 200, 255, 256, 257])
+def test_small_problem_shoot_matches_oracle(n, dtype):
+    """Problems of at most 256 points are shot in one launch (one workgroup, every stage in
+    the kernel); sizes across its tile/chunk splits and the boundary to the stage-per-launch
+    path, with the inexact term, against the oracle."""
+    dim, kernel = (3, lm.GAUSS) if n % 2 else (2, lm.CONON)
+    q0, p0 = inputs.random_state(n, dim, [310, n], box=1.0, pscale=0.3)
+    q0, p0 = rounded(q0, dtype), rounded(p0, dtype)
+    oq, op = oracle.shoot(q0, p0, kernel, 0.4, 25, T=0.9, tau=0.1)
+    prm = lm.make_params(dim, kernel, 0.4, dtype=dtype, tau=0.1)
+    q1, p1 = torch.empty_like(dev(q0, dtype)), torch.empty_like(dev(q0, dtype))
+    lm.lm_shoot(prm, dev(q0, dtype), dev(p0, dtype), 0.9, 25, q1, p1)
+    torch.cuda.synchronize()
+    eq, ep = rel_err(host(q1), oq), rel_err(host(p1), op)
+    print("n=%d dtype=%d: %.2e %.2e" % (n, dtype, eq, ep))
+    assert eq <= TOL[dtype] and ep <= TOL[dtype]
+
+
 def test_shoot_in_place_and_time_span():
     pr = inputs.config_curve2d(300)
     p0 = pr.p_bench()
