@@ -9,8 +9,9 @@
 //
 // Work decomposition as in lm_pair_kernel: 64 targets k per workgroup (one per lane), the
 // sources j split into contiguous chunks per (wave, grid-y), source data wave-uniform (scalar
-// loads of q_j, p_j, a_j, b_j into SGPR operands), wave partials combined in LDS in wave
-// order, grid-y splits by lm_vjp_finish_kernel in split order.  FP64 only.
+// loads of q_j, p_j, a_j, b_j into SGPR operands, from an interleaved copy written by
+// lm_vjp_pack_kernel), wave partials combined in LDS in wave order, grid-y splits by
+// lm_vjp_finish_kernel in split order.  FP64 only.
 //
 // Adjoint of one RK4 step y' = y + dt/6 (k1 + 2k2 + 2k3 + k4), k_s = f(Y_s), given the
 // cotangent abar of y' (stages visited 4, 3, 2, 1):
@@ -26,6 +27,10 @@
 #include "lm_math.h"
 
 namespace lm {
+
+#ifndef LM_VJP_UNROLL
+#define LM_VJP_UNROLL 2
+#endif
 
 constexpr int kTileA = kTile;     // same launch plan as the pair kernel
 constexpr int kWavesA = kWaves;
@@ -136,33 +141,34 @@ __global__ __launch_bounds__(kTileA * kWavesA) void lm_vjp_kernel(VjpArgs A)
     double gq[DIM], gp[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) { gq[c] = 0.0; gp[c] = 0.0; }
-    const double* __restrict__ qs = A.q;
-    const double* __restrict__ ps = A.p;
-    const double* __restrict__ as = A.a;
-    const double* __restrict__ bs = A.b;
+    // sources come from the interleaved copy: one base address, 4 DIM consecutive doubles per
+    // source, so a source is a few wide scalar loads and the loop needs few SGPRs
+    const double* __restrict__ src = A.pack;
     int64_t j = j0;
-    for (; j + 2 <= j1; j += 2) {
+    for (; j + LM_VJP_UNROLL <= j1; j += LM_VJP_UNROLL) {
 #pragma unroll
-        for (int uu = 0; uu < 2; ++uu) {
+        for (int uu = 0; uu < LM_VJP_UNROLL; ++uu) {
+            const double* sj = src + (j + uu) * (4 * DIM);
             double qj[DIM], pj[DIM], aj[DIM], bj[DIM];
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                qj[c] = qs[c * n + j + uu];
-                pj[c] = ps[c * n + j + uu];
-                aj[c] = as[c * n + j + uu];
-                bj[c] = bs[c * n + j + uu];
+                qj[c] = sj[c];
+                pj[c] = sj[DIM + c];
+                aj[c] = sj[2 * DIM + c];
+                bj[c] = sj[3 * DIM + c];
             }
             vjp_pair<DIM, KER>(qk, pk, ak, bk, qj, pj, aj, bj, A.kq, A.c1, A.c2, gq, gp);
         }
     }
     for (; j < j1; ++j) {
+        const double* sj = src + j * (4 * DIM);
         double qj[DIM], pj[DIM], aj[DIM], bj[DIM];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            qj[c] = qs[c * n + j];
-            pj[c] = ps[c * n + j];
-            aj[c] = as[c * n + j];
-            bj[c] = bs[c * n + j];
+            qj[c] = sj[c];
+            pj[c] = sj[DIM + c];
+            aj[c] = sj[2 * DIM + c];
+            bj[c] = sj[3 * DIM + c];
         }
         vjp_pair<DIM, KER>(qk, pk, ak, bk, qj, pj, aj, bj, A.kq, A.c1, A.c2, gq, gp);
     }
@@ -229,9 +235,30 @@ __global__ __launch_bounds__(256) void lm_scale_kernel(double* __restrict__ y, d
         y[i] = alpha * x[i];
 }
 
+// pack[j][0..4 DIM) = (q_j, p_j, a_j, b_j)
+template <int DIM>
+__global__ __launch_bounds__(256) void lm_vjp_pack_kernel(const double* __restrict__ q, const double* __restrict__ p,
+                                                          const double* __restrict__ a, const double* __restrict__ b,
+                                                          int64_t n, double* __restrict__ pack)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        double* o = pack + j * (4 * DIM);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            o[c] = q[c * n + j];
+            o[DIM + c] = p[c * n + j];
+            o[2 * DIM + c] = a[c * n + j];
+            o[3 * DIM + c] = b[c * n + j];
+        }
+    }
+}
+
 template <int DIM, int KER>
 static hipError_t launch_vjp_t(const VjpArgs& a, const PairPlan& pl, hipStream_t st)
 {
+    const int64_t pg = (a.n + 255) / 256;
+    hipLaunchKernelGGL((lm_vjp_pack_kernel<DIM>), dim3((unsigned)(pg < 65536 ? pg : 65536)), dim3(256), 0, st, a.q, a.p,
+                       a.a, a.b, a.n, a.pack);
     hipLaunchKernelGGL((lm_vjp_kernel<DIM, KER>), dim3((unsigned)pl.itiles, (unsigned)pl.nsplit), dim3(kTileA * kWavesA),
                        0, st, a);
     hipError_t err = hipGetLastError();

@@ -121,6 +121,9 @@ int64_t part_elems(const lm_params* prm, int64_t nt, int64_t ns)
     return pl.nsplit > 1 ? (int64_t)pl.nsplit * 2 * prm->dim * nt : 1;
 }
 
+// Workspace of a VJP evaluation: the interleaved source copy, then the split partial sums.
+int64_t vjp_part_elems(const lm_params* prm, int64_t n) { return 4 * (int64_t)prm->dim * n + part_elems(prm, n, n); }
+
 // RK4 shoot of (q, p) in place over [0, t1] with `steps` steps.  a*, b*: stage buffers, c*:
 // the RK4 running sum (dim*n T each); part: the split workspace.  box (non-null in cutoff
 // mode, tiles_of(n)*8 doubles) receives the tile boxes of every stage input.
@@ -616,7 +619,8 @@ lm_status vjp_eval(const lm_params* prm, int64_t n, const double* q, const doubl
         A.c1 = 2.0 / (sg * sg);
         A.c2 = -4.0 / (sg * sg * sg * sg);
     }
-    A.part = part;
+    A.pack = part;
+    A.part = part + 4 * (int64_t)prm->dim * n;
     A.epi = e;
     LM_HIP(lm::launch_vjp(prm->dim, prm->kernel, A, pl, st));
     return LM_OK;
@@ -646,7 +650,7 @@ struct AdjointWork {
         LM_TRY(ws.get(&ckpts, (int64_t)nseg * 2 * m));
         LM_TRY(ws.get(&slots, ((int64_t)ckpt * 4 + 1) * 2 * m));
         LM_TRY(ws.get(&acc, 2 * m));
-        LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+        LM_TRY(ws.get(&part, vjp_part_elems(prm, n)));
         LM_TRY(ws.get(&L0, 2 * m));
         LM_TRY(ws.get(&L1, 2 * m));
         LM_TRY(ws.get(&C0, 2 * m));
@@ -1210,7 +1214,7 @@ lm_status lm_rhs_vjp(const lm_params* prm, int64_t n, const double* q, const dou
     hipStream_t st = (hipStream_t)stream;
     Workspace ws(st);
     double* part;
-    LM_TRY(ws.get(&part, part_elems(prm, n, n)));
+    LM_TRY(ws.get(&part, vjp_part_elems(prm, n)));
     lm::AdjEpi e{};
     e.kind = lm::ADJ_STORE;
     e.cscale = 1.0;

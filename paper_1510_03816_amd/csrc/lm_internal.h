@@ -92,6 +92,7 @@ struct AdjEpi {
 struct VjpArgs {
     const double* q;        // stage input (dim, n)
     const double* p;
+    double* pack;           // 4 dim n doubles: the sources (q_j, p_j, a_j, b_j) interleaved
     const double* a;        // cotangent of dq/dt (dim, n)
     const double* b;        // cotangent of dp/dt
     int64_t n;
