@@ -244,6 +244,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient-matching measurements")
     ap.add_argument("--adjoint-full", action="store_true",
                     help="also time L-BFGS on the data term alone to max|q(1) - Y| < 1e-6 (about 90 s)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the gradient-matching measurements (a diagnostic line, not the benchmark)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 256-problem batch measurements (a diagnostic line, not the benchmark)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -273,6 +275,9 @@ def main():
 
     if args.batched_only:
         print(json.dumps({"batched": batched_leg(lm, torch, dev, args.h, args.tol)}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(lm, torch, dev, args.adjoint_full)}), flush=True)
         return
 
     def setup(name):

@@ -43,7 +43,11 @@ __device__ __forceinline__ void pair_f64(const double (&qi)[DIM], const double (
                                          double kq, double (&v)[DIM], double (&f)[DIM])
 {
     double d[DIM];
-    double s = 0.0;
+    // For the conon the squared distance starts at 1e-300 instead of 0 (an FMA in place of
+    // the first multiply, so it costs nothing): for the self pair (d = 0) this gives
+    // r ~ 1e-150, g = 1 and a finite w that multiplies d = 0, so the pair adds p_j to v and
+    // nothing to f, as the system prescribes; for any other pair s > 1e-284 absorbs it.
+    double s = (KER == LM_KERNEL_CONON) ? 1e-300 : 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         d[c] = qi[c] - qj[c];
@@ -51,12 +55,8 @@ __device__ __forceinline__ void pair_f64(const double (&qi)[DIM], const double (
     }
     double g, w;
     if constexpr (KER == LM_KERNEL_CONON) {
-        // s is clamped away from 0: for the self pair (d = 0) this gives r ~ 1e-150,
-        // g = 1 and a finite w that multiplies d = 0, so the pair adds p_j to v and nothing
-        // to f, as the system prescribes.
-        const double sc = __builtin_fmax(s, 1e-300);
-        const double rho = rsqrt_pos(sc);
-        const double r = sc * rho;
+        const double rho = rsqrt_pos(s);
+        const double r = s * rho;
         g = exp_nonpos(r * kq);
         w = g * rho;
     } else {
@@ -81,7 +81,7 @@ __device__ __forceinline__ void pair_f32(const float (&qi)[DIM], const float (&p
                                          float kq, float (&v)[DIM], float (&f)[DIM])
 {
     float d[DIM];
-    float s = 0.0f;
+    float s = (KER == LM_KERNEL_CONON) ? 1e-30f : 0.0f;   // as in pair_f64
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         d[c] = qi[c] - qj[c];
@@ -89,9 +89,8 @@ __device__ __forceinline__ void pair_f32(const float (&qi)[DIM], const float (&p
     }
     float g, w;
     if constexpr (KER == LM_KERNEL_CONON) {
-        const float sc = __builtin_fmaxf(s, 1e-30f);
-        const float rho = rsqrt_f32(sc);
-        g = exp2_f32(sc * rho * kq);
+        const float rho = rsqrt_f32(s);
+        g = exp2_f32(s * rho * kq);
         w = g * rho;
     } else {
         g = exp2_f32(s * kq);

@@ -173,6 +173,22 @@ def test_single_particle_straight_line():
     assert np.array_equal(host(p1), host(p))
 
 
+def test_time_rescaling_predicts_longer_shoots():
+    """The prediction property (momenta scaled by c reach, at t = 1, the state the unscaled
+    momenta reach at t = c, with momenta scaled by c): shoot(X, c p0, T=1) equals
+    (q, c p) of shoot(X, p0, T=c) with the same step count, on the GPU."""
+    pr = inputs.config_curve2d(500)
+    X, p0 = pr.X, pr.p_bench()
+    prm = lm.make_params(2, lm.CONON, pr.sigma)
+    c = 1.7
+    a = [torch.empty_like(dev(X)) for _ in range(4)]
+    lm.lm_shoot(prm, dev(X), dev(c * p0), 1.0, 60, a[0], a[1])
+    lm.lm_shoot(prm, dev(X), dev(p0), c, 60, a[2], a[3])
+    torch.cuda.synchronize()
+    assert rel_err(host(a[0]), host(a[2])) <= 1e-12
+    assert rel_err(host(a[1]), c * host(a[3])) <= 1e-12
+
+
 def test_shoot_is_deterministic():
     pr = inputs.config_curve2d(2000)
     prm = lm.make_params(2, lm.CONON, pr.sigma)
