@@ -47,6 +47,8 @@ if ROOT not in sys.path:
 # four); fixed before any tuning and never changed, so a faster kernel shows up as a higher
 # fraction of the roofline.
 SLOTS_PER_PAIR = {(3, 0): 46, (2, 0): 41, (3, 1): 32, (2, 1): 27}
+# The symmetric kernel evaluates each unordered pair once, N(N+1)/2 evaluations per launch,
+# and charges the shared part once plus both particles' accumulations: S_pair + 2 dim slots.
 # MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz = 3.93e13 FMA slots/s = 78.6 TFLOP/s
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 PEAK_TFLOPS = 2.0 * PEAK_SLOTS / 1e12
@@ -63,7 +65,8 @@ MEASURED_TRAFFIC = {
 def kernel_source_hash() -> str:
     import hashlib
     csrc = os.path.join(ROOT, "paper_1510_03816_amd", "csrc")
-    data = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("lm_kernels.hip", "lm_math.h"))
+    data = b"".join(open(os.path.join(csrc, f), "rb").read()
+                    for f in ("lm_kernels.hip", "lm_sym.hip", "lm_math.h"))
     return hashlib.sha256(data).hexdigest()[:16]
 
 
@@ -343,8 +346,17 @@ def main():
     value = pairs_per_shoot * shoots / elapsed
     # dominant kernel: the pair-sum kernel, one launch per RK stage
     launch_ms = shoot_ms / (shoots * 4 * pr.steps)
-    slots = SLOTS_PER_PAIR[(dim, pr.kernel)]
-    achieved = n * n * slots * 2.0 / (launch_ms * 1e-3) / 1e12
+    plan = lm.lm_pair_plan(prm, n)
+    kname = "%s,%d,%s,force" % ("double" if dtype == 0 else "float", dim, "conon" if pr.kernel == 0 else "gauss")
+    if plan["symmetric"]:
+        slots = SLOTS_PER_PAIR[(dim, pr.kernel)] + 2 * dim
+        evals = n * (n + 1) // 2
+        kname = "lm_sym_pair_kernel<%s> + lm_finish_kernel" % kname
+    else:
+        slots = SLOTS_PER_PAIR[(dim, pr.kernel)]
+        evals = n * n
+        kname = "lm_pair_kernel<%s>%s" % (kname, " + lm_finish_kernel" if plan["partial_slots"] > 1 else "")
+    achieved = evals * slots * 2.0 / (launch_ms * 1e-3) / 1e12
     if rc > 0.0:
         # with tile skipping the pairs evaluated are fewer than N^2: not a roofline figure
         achieved = None
@@ -354,9 +366,8 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": (achieved / PEAK_TFLOPS) if achieved else None, "traffic": traffic,
                 "traffic_unit": "bytes per launch",
-                "kernel": "lm_pair_kernel<%s,%d,%s,force>" % ("double" if dtype == 0 else "float", dim,
-                                                               "conon" if pr.kernel == 0 else "gauss"),
-                "launch_ms": launch_ms, "pairs_per_launch": n * n, "slots_per_pair": slots,
+                "kernel": kname, "plan": plan,
+                "launch_ms": launch_ms, "pair_evaluations_per_launch": evals, "slots_per_evaluation": slots,
                 "pairs_per_s_in_kernel": n * n / (launch_ms * 1e-3)}
 
     ttm = None

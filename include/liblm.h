@@ -133,6 +133,25 @@ typedef struct lm_match_info {
 lm_status lm_rhs(const lm_params *params, int64_t n, const void *q, const void *p,
                  void *dq, void *dp, void *stream);
 
+/* Launch plan of the pair sums of n points under `params` (host only: no GPU work, no
+ * allocation): the kernel that lm_rhs and every RK4 stage of lm_shoot use, and its shape.
+ * symmetric = 1: each unordered pair is evaluated once and serves both particles (double
+ * precision, every pair, from 192 tiles of 64 points on); 0: the one-sided kernel, one
+ * target per lane.  The environment variable LM_SYM = 0 or 1 overrides that size rule and
+ * LM_SYM_WAVES = 1, 2, 4 or 8 fixes the symmetric kernel's workgroup width (for tuning and
+ * tests; both are read at every launch).  small = 1: shoots of this size (at most 256 points,
+ * no cutoff) run whole inside one workgroup instead.  LM_EINVAL on bad arguments. */
+typedef struct lm_plan_info {
+    int32_t symmetric;
+    int32_t waves;           /* wavefronts per workgroup of the pair-sum launch */
+    int64_t workgroups;      /* workgroups of the pair-sum launch */
+    int32_t partial_slots;   /* partial sums per point added in a fixed order by a second
+                                launch (1: the pair-sum launch finishes the sums itself) */
+    int32_t small;
+} lm_plan_info;
+
+lm_status lm_pair_plan(const lm_params *params, int64_t n, lm_plan_info *info);
+
 /* Shooting map: integrates the N-particle system from (q0, p0) at t = 0 to t = t1 with
  * `steps` steps of the classical fourth-order Runge-Kutta method (the explicit integrator
  * the paper names for evolving the system in Algorithm 1, step 1).  Writes (q(t1), p(t1))

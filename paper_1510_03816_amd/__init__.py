@@ -12,7 +12,7 @@ from ._lib import (  # noqa: F401
     lm_rhs, lm_shoot, lm_hamiltonian, lm_ksolve, lm_feedback_match, lm_feedback_step, lm_velocity,
     lm_version, lm_rhs_vjp, lm_shoot_adjoint, lm_energy_grad, lm_lbfgs_match, lm_lbfgs_opts, lm_lbfgs_info,
     lm_batch_tuning, lm_batch_default_tuning, lm_batch_autotune, lm_rhs_batched, lm_shoot_batched,
-    lm_feedback_match_batched,
+    lm_feedback_match_batched, lm_plan_info, lm_pair_plan,
 )
 
 load()

@@ -25,7 +25,7 @@ SOLVE_AUTO, SOLVE_CG, SOLVE_DENSE = 0, 1, 2
 EXPORTS = ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
            "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
            "lm_lbfgs_match", "lm_batch_default_tuning", "lm_batch_autotune", "lm_rhs_batched",
-           "lm_shoot_batched", "lm_feedback_match_batched", "lm_last_error", "lm_version"]
+           "lm_shoot_batched", "lm_feedback_match_batched", "lm_pair_plan", "lm_last_error", "lm_version"]
 BATCH_BUCKETS = 4
 
 
@@ -52,6 +52,14 @@ class lm_match_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("resid_inf", ctypes.c_double),
                 ("H", ctypes.c_double), ("shoot_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
                 ("factor_ms", ctypes.c_double)]
+
+
+class lm_plan_info(ctypes.Structure):
+    _fields_ = [("symmetric", ctypes.c_int32), ("waves", ctypes.c_int32), ("workgroups", ctypes.c_int64),
+                ("partial_slots", ctypes.c_int32), ("small", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class lm_step_info(ctypes.Structure):
@@ -119,10 +127,11 @@ def load():
         L.lm_shoot_batched.argtypes = [PP, i32, P, P, P, d, i32, P, P, PT, P]
         L.lm_feedback_match_batched.argtypes = [PP, ctypes.POINTER(lm_match_opts), i32, P, P, P, P, P,
                                                 ctypes.POINTER(lm_match_info), P, PT, P]
+        L.lm_pair_plan.argtypes = [PP, i64, ctypes.POINTER(lm_plan_info)]
         for name in ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
                      "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
                      "lm_lbfgs_match", "lm_batch_default_tuning", "lm_batch_autotune", "lm_rhs_batched",
-                     "lm_shoot_batched", "lm_feedback_match_batched"]:
+                     "lm_shoot_batched", "lm_feedback_match_batched", "lm_pair_plan"]:
             getattr(L, name).restype = ctypes.c_int
         L.lm_last_error.restype = ctypes.c_char_p
         L.lm_last_error.argtypes = []
@@ -178,6 +187,14 @@ def lm_rhs(params: lm_params, q, p, dq, dp, stream=None):
     for t, nm in [(q, "q"), (p, "p"), (dq, "dq"), (dp, "dp")]:
         _check_tensor(t, params.dim, n, params.dtype, nm)
     return _check(load().lm_rhs(ctypes.byref(params), n, _ptr(q), _ptr(p), _ptr(dq), _ptr(dp), _stream(stream)))
+
+
+def lm_pair_plan(params: lm_params, n: int) -> dict:
+    """The pair-sum launch plan for n points (host only): symmetric, waves, workgroups,
+    partial_slots, small."""
+    info = lm_plan_info()
+    _check(load().lm_pair_plan(ctypes.byref(params), int(n), ctypes.byref(info)))
+    return info.as_dict()
 
 
 def lm_shoot(params: lm_params, q0, p0, t1: float, steps: int, q1, p1, stream=None):

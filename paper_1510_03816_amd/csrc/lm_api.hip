@@ -96,7 +96,8 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
                     const T* pt, int64_t nt, const lm::EpiArgs<T>& epi, double* part, hipStream_t st,
                     const Cut& cut = Cut())
 {
-    lm::PairPlan pl = lm::plan_pair(nt, ns, cut.box_s != nullptr);
+    const bool sym_ok = sizeof(T) == 8 && qs == qt && ps == pt && ns == nt;
+    lm::PairPlan pl = lm::plan_pair(nt, ns, cut.box_s != nullptr, sym_ok);
     lm::PairArgs<T> a{};
     a.qs = qs;
     a.ps = ps;
@@ -115,10 +116,17 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
     return LM_OK;
 }
 
+// Workspace of the split partial sums: enough for either kernel that pair_eval may choose.
 int64_t part_elems(const lm_params* prm, int64_t nt, int64_t ns)
 {
-    lm::PairPlan pl = lm::plan_pair(nt, ns, false);
-    return pl.nsplit > 1 ? (int64_t)pl.nsplit * 2 * prm->dim * nt : 1;
+    const lm::PairPlan pl = lm::plan_pair(nt, ns, false);
+    int64_t slots = pl.nsplit > 1 ? pl.nsplit : 0;
+    if (nt == ns) {
+        // the symmetric kernel's slots under any setting of LM_SYM (forced or by size)
+        const lm::SymPlan sp = lm::plan_sym(nt, true);
+        if (sp.waves > 0 && sp.nsb + 1 > slots) slots = sp.nsb + 1;
+    }
+    return slots > 0 ? slots * 2 * prm->dim * nt : 1;
 }
 
 // Workspace of a VJP evaluation: the interleaved source copy, then the split partial sums.
@@ -1010,6 +1018,21 @@ lm_status lm_rhs(const lm_params* prm, int64_t n, const void* q, const void* p, 
     if (prm->dtype == LM_F64)
         return rhs_t<double>(prm, n, (const double*)q, (const double*)p, (double*)dq, (double*)dp, st);
     return rhs_t<float>(prm, n, (const float*)q, (const float*)p, (float*)dq, (float*)dp, st);
+}
+
+lm_status lm_pair_plan(const lm_params* prm, int64_t n, lm_plan_info* info)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    if (!info) return fail(LM_EINVAL, "NULL info");
+    const bool cut = prm->cutoff > 0.0;
+    const lm::PairPlan pl = lm::plan_pair(n, n, cut, prm->dtype == LM_F64);
+    info->symmetric = pl.sym_waves > 0;
+    info->waves = pl.sym_waves > 0 ? pl.sym_waves : lm::kWaves;
+    info->workgroups = pl.sym_waves > 0 ? pl.sym_nsb * (pl.sym_nsb + 1) / 2 : pl.itiles * pl.nsplit;
+    info->partial_slots = pl.nsplit;
+    info->small = !cut && n <= lm::kSmallMax;
+    return LM_OK;
 }
 
 lm_status lm_shoot(const lm_params* prm, int64_t n, const void* q0, const void* p0, double t1, int32_t steps,

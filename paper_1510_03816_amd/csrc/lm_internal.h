@@ -154,11 +154,49 @@ hipError_t launch_small_shoot(int dim, int kernel, const SmallShootArgs<T>& a, i
 
 struct PairPlan {
     int64_t itiles;
-    int nsplit;
+    int nsplit;          // partial-sum slots per target (1: none)
     int64_t jchunk;
+    int sym_waves;       // > 0: symmetric kernel (lm_sym.hip) with this many waves per workgroup
+    int64_t sym_nsb;     // its superblock count S (nsplit = S + 1)
 };
 
-PairPlan plan_pair(int64_t nt, int64_t ns, bool cut);
+// sym_ok: the targets are the sources (one point set, every pair, double precision), so the
+// symmetric kernel may be chosen.  The environment variable LM_SYM overrides the size rule:
+// "0" never, "1" always (for tests of small sizes).
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok = false);
+
+// Symmetric pair sums of one point set (lm_sym.hip).
+struct SymArgs {
+    const double* q;     // (dim, n)
+    const double* p;
+    int64_t n;
+    int64_t tiles;       // 64-point tiles
+    int64_t nsb;         // superblocks of 2 * waves tiles
+    double kq;
+    double wscale;
+    double* part;        // (nsb + 1, 2 dim, n) partial sums
+};
+
+struct SymPlan {
+    int waves = 0;       // 0: not worth it (too few wavefronts) or too large
+    int64_t nsb = 0;
+};
+
+// Size rule (measured on MI355X, 3-D conon, FP64, one stage): from 192 tiles (N = 12288)
+// two waves per workgroup, from 768 tiles (N = 49152) four; below, the one-sided kernel.
+// At N = 8192 the two kernels tie (88 vs 89 us); at N = 16384 the symmetric one with two
+// waves takes 298 us against 361, at 32768 997 against 1371, at 65536 (four waves) 3760
+// against 5425.
+constexpr int kSymMaxWaves = 8;
+#ifndef LM_SYM_MIN_TILES
+#define LM_SYM_MIN_TILES 192
+#endif
+constexpr int64_t kSymMinTiles = LM_SYM_MIN_TILES;
+constexpr int64_t kSymWideTiles = 768;
+constexpr int64_t kSymMaxPartBytes = (int64_t)16 << 30;
+
+SymPlan plan_sym(int64_t n, bool force);
+hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs& a, int waves, hipStream_t st);
 
 template <class T>
 hipError_t launch_pair(int dim, int kernel, bool force, const PairArgs<T>& a, const PairPlan& pl,

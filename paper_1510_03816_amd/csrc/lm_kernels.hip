@@ -23,6 +23,7 @@
 // (two when S > 1) and the state never takes a separate pass through memory.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #include "lm_internal.h"
 #include "lm_math.h"
@@ -736,10 +737,24 @@ static inline unsigned blocks_for(int64_t m, int threads, unsigned cap = 8192)
     return (unsigned)(b < (int64_t)cap ? b : cap);
 }
 
-PairPlan plan_pair(int64_t nt, int64_t ns, bool cut)
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok)
 {
-    PairPlan pl;
+    PairPlan pl{};
     pl.itiles = (nt + kTile - 1) / kTile;
+    if (sym_ok && !cut && nt == ns) {
+        const char* e = getenv("LM_SYM");
+        const int mode = e ? atoi(e) : -1;
+        if (mode != 0) {
+            const SymPlan sp = plan_sym(nt, mode == 1);
+            if (sp.waves > 0) {
+                pl.sym_waves = sp.waves;
+                pl.sym_nsb = sp.nsb;
+                pl.nsplit = (int)(sp.nsb + 1);
+                pl.jchunk = ns;
+                return pl;
+            }
+        }
+    }
     // aim for >= LM_MIN_GROUPS workgroups (the targets alone give nt/64; the sources are
     // split over grid-y to make up the rest) while keeping every wave's chunk >= 32 sources
     int64_t s = (LM_MIN_GROUPS + pl.itiles - 1) / pl.itiles;
@@ -761,9 +776,27 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut)
 template <class T, int DIM, int KER, bool FORCE, bool CUT>
 static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStream_t st)
 {
-    dim3 grid((unsigned)pl.itiles, (unsigned)pl.nsplit);
-    hipLaunchKernelGGL((lm_pair_kernel<T, DIM, KER, FORCE, CUT>), grid, dim3(kTile * kWaves), 0, st, a);
-    hipError_t err = hipGetLastError();
+    hipError_t err;
+    if (pl.sym_waves > 0) {
+        if constexpr (sizeof(T) == 8 && !CUT) {
+            SymArgs s{};
+            s.q = a.qs;
+            s.p = a.ps;
+            s.n = a.nt;
+            s.tiles = pl.itiles;
+            s.nsb = pl.sym_nsb;
+            s.kq = a.kq;
+            s.wscale = a.wscale;
+            s.part = a.part;
+            err = launch_sym_pair(DIM, KER, FORCE, s, pl.sym_waves, st);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        dim3 grid((unsigned)pl.itiles, (unsigned)pl.nsplit);
+        hipLaunchKernelGGL((lm_pair_kernel<T, DIM, KER, FORCE, CUT>), grid, dim3(kTile * kWaves), 0, st, a);
+        err = hipGetLastError();
+    }
     if (err != hipSuccess || pl.nsplit == 1) return err;
     hipLaunchKernelGGL((lm_finish_kernel<T, DIM, FORCE>), dim3(blocks_for(a.nt, 256, 1u << 30)), dim3(256), 0, st,
                        (const double*)a.part, pl.nsplit, a.nt, a.epi);

@@ -56,7 +56,7 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"lm_params": _lib.lm_params, "lm_match_opts": _lib.lm_match_opts,
                "lm_match_info": _lib.lm_match_info, "lm_step_info": _lib.lm_step_info,
                "lm_lbfgs_opts": _lib.lm_lbfgs_opts, "lm_lbfgs_info": _lib.lm_lbfgs_info,
-               "lm_batch_tuning": _lib.lm_batch_tuning}
+               "lm_batch_tuning": _lib.lm_batch_tuning, "lm_plan_info": _lib.lm_plan_info}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "liblm.h"', "int main(void) {"]
     for sname, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (sname, sname))

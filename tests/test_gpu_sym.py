@@ -1,0 +1,156 @@
+"""The symmetric pair kernel (each unordered pair evaluated once) against the FP64 oracle
+and against the one-sided kernel, through the C ABI (needs an MI355X).
+
+LM_SYM=1 forces the symmetric kernel at any size and LM_SYM_WAVES fixes its workgroup
+width, so every width and ragged superblocks are covered at sizes the oracle finishes in
+seconds; the size rule alone picks it from N = 12288 on.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+import paper_1510_03816_amd as lm
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+
+
+class _env:
+    """Sets LM_SYM / LM_SYM_WAVES for the duration of a block."""
+
+    def __init__(self, **kv):
+        self.kv = {k: str(v) for k, v in kv.items()}
+
+    def __enter__(self):
+        self.old = {k: os.environ.get(k) for k in self.kv}
+        os.environ.update(self.kv)
+
+    def __exit__(self, *exc):
+        for k, v in self.old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_err(got, want):
+    scale = np.max(np.abs(want))
+    d = np.max(np.abs(got - want))
+    return d / scale if scale > 0 else d
+
+
+def gpu_rhs(q, p, kernel, sigma, tau=0.0):
+    prm = lm.make_params(q.shape[0], kernel, sigma, tau=tau)
+    qd, pd = dev(q), dev(p)
+    dq, dp = torch.empty_like(qd), torch.empty_like(pd)
+    lm.lm_rhs(prm, qd, pd, dq, dp)
+    torch.cuda.synchronize()
+    return host(dq), host(dp)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("n", [1, 2, 64, 65, 700, 3007])
+def test_sym_rhs_matches_oracle(n, dim, kernel, waves):
+    q, p = inputs.random_state(n, dim, seed=[110, n, dim], box=1.0, pscale=0.3)
+    sigma, tau = (0.3 if dim == 3 else 0.25), 0.1
+    dq_o, dp_o = oracle.rhs(q, p, kernel, sigma, tau)
+    print("sym rhs n=%d dim=%d kernel=%d waves=%d" % (n, dim, kernel, waves), flush=True)
+    with _env(LM_SYM=1, LM_SYM_WAVES=waves):
+        dq, dp = gpu_rhs(q, p, kernel, sigma, tau)
+    eq, ep = rel_err(dq, dq_o), rel_err(dp, dp_o)
+    print("  %.2e %.2e" % (eq, ep))
+    assert eq <= 1e-10 and ep <= 1e-10
+    if n == 1:
+        assert np.all(dp == 0.0)
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_sym_coincident_particles(kernel):
+    q, p = inputs.random_state(300, 3, seed=111)
+    q[:, 100:140] = q[:, 0:40]            # coincident distinct particles, across tiles
+    q[:, 200] = q[:, 201]
+    dq_o, dp_o = oracle.rhs(q, p, kernel, 0.4)
+    with _env(LM_SYM=1, LM_SYM_WAVES=2):
+        dq, dp = gpu_rhs(q, p, kernel, 0.4)
+    assert np.all(np.isfinite(dp))
+    assert rel_err(dq, dq_o) <= 1e-10 and rel_err(dp, dp_o) <= 1e-10
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_sym_agrees_with_one_sided_kernel(kernel):
+    """Both kernels on the same input; they differ only in summation order."""
+    q, p = inputs.random_state(5000, 3, seed=112, pscale=0.3)
+    with _env(LM_SYM=0):
+        a = gpu_rhs(q, p, kernel, 0.2)
+    with _env(LM_SYM=1, LM_SYM_WAVES=4):
+        b = gpu_rhs(q, p, kernel, 0.2)
+    assert rel_err(b[0], a[0]) <= 1e-13 and rel_err(b[1], a[1]) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [12289, 30000])
+def test_sym_by_size_rule_sampled(n):
+    """Sizes where the size rule itself picks the symmetric kernel (two waves per workgroup;
+    four are covered at N = 65536 by the full-size tests); sampled rows against the oracle,
+    and the forces sum to zero."""
+    pr = inputs.config_sphere3d(n)
+    q, p = pr.X, pr.p_bench()
+    dq, dp = gpu_rhs(q, p, pr.kernel, pr.sigma)
+    idx = np.sort(np.random.default_rng(113).choice(n, 128, replace=False))
+    idx = np.concatenate([[0, 63, 64, 127, 128, n - 1], idx])
+    rq, rp = oracle.rhs_rows(q, p, idx, pr.kernel, pr.sigma)
+    assert rel_err(dq[:, idx], rq) <= 1e-10 and rel_err(dp[:, idx], rp) <= 1e-10
+    assert np.max(np.abs(dp.sum(axis=1))) <= 1e-9 * np.max(np.abs(dp))
+
+
+def test_sym_shoot_matches_oracle_and_is_deterministic():
+    pr = inputs.config_curve2d(700)
+    oq, op = oracle.shoot(pr.X, pr.p_bench(), pr.kernel, pr.sigma, 40)
+    prm = lm.make_params(2, pr.kernel, pr.sigma)
+    outs = []
+    with _env(LM_SYM=1, LM_SYM_WAVES=2):
+        for _ in range(2):
+            q, p = dev(pr.X), dev(pr.p_bench())
+            q1, p1 = torch.empty_like(q), torch.empty_like(p)
+            lm.lm_shoot(prm, q, p, 1.0, 40, q1, p1)
+            torch.cuda.synchronize()
+            outs.append((host(q1), host(p1)))
+    assert rel_err(outs[0][0], oq) <= 1e-10 and rel_err(outs[0][1], op) <= 1e-10
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_sym_cg_ksolve_matches_cholesky():
+    """The CG solver's products K x run through the velocity-only symmetric kernel."""
+    pr = inputs.config_curve2d(1000)
+    X = pr.X
+    b = np.random.default_rng(114).standard_normal(X.shape)
+    st, L = oracle.cholesky(oracle.kmatrix(X, pr.kernel, pr.sigma))
+    assert st == 0
+    want = np.stack([oracle.cholesky_solve(L, b[c]) for c in range(X.shape[0])])
+    prm = lm.make_params(X.shape[0], pr.kernel, pr.sigma)
+    x = torch.empty((X.shape[0], X.shape[1]), dtype=torch.float64, device=DEV)
+    with _env(LM_SYM=1, LM_SYM_WAVES=4):
+        it = lm.lm_ksolve(prm, dev(X), dev(b), x, rtol=1e-13, solver=lm.SOLVE_CG)
+    print("%d CG iterations, rel err %.2e" % (it, rel_err(host(x), want)))
+    assert rel_err(host(x), want) <= 1e-8

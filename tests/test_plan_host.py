@@ -1,0 +1,79 @@
+"""The pair-sum launch plan (host logic, no GPU): which kernel a size and precision get, the
+symmetric kernel's superblock arithmetic, and the environment overrides."""
+
+import os
+
+import pytest
+
+import paper_1510_03816_amd as lm
+
+
+@pytest.fixture(autouse=True)
+def _clean_env(monkeypatch):
+    monkeypatch.delenv("LM_SYM", raising=False)
+    monkeypatch.delenv("LM_SYM_WAVES", raising=False)
+
+
+def plan(n, dtype=lm.F64, cutoff=0.0, dim=3):
+    prm = lm.make_params(dim, lm.CONON, 0.05, dtype=dtype, cutoff=cutoff)
+    return lm.lm_pair_plan(prm, n)
+
+
+def sym(T, w):
+    """Superblock count, workgroups and partial slots of the symmetric kernel for T tiles."""
+    S = -(-T // (2 * w))
+    return S, S * (S + 1) // 2, S + 1
+
+
+def test_full_size_double_uses_symmetric_kernel_with_four_waves():
+    S, wg, slots = sym(1024, 4)
+    assert plan(65536) == {"symmetric": 1, "waves": 4, "workgroups": wg, "partial_slots": slots, "small": 0}
+    assert (S, wg, slots) == (128, 8256, 129)
+
+
+@pytest.mark.parametrize("n,waves", [(12288, 2), (16384, 2), (49088, 2), (49089, 4), (131072, 4)])
+def test_size_rule(n, waves):
+    p = plan(n)
+    T = -(-n // 64)
+    assert p["symmetric"] == 1 and p["waves"] == waves
+    assert (p["workgroups"], p["partial_slots"]) == sym(T, waves)[1:]
+
+
+@pytest.mark.parametrize("n", [1, 257, 4096, 12224])
+def test_small_sizes_keep_one_sided_kernel(n):
+    p = plan(n)
+    assert p["symmetric"] == 0 and p["waves"] == 4
+    assert p["small"] == (1 if n <= 256 else 0)
+
+
+def test_one_sided_split_rule():
+    # 128 target tiles: 16384 workgroups wanted, capped at 16 source splits from 128 tiles on
+    p = plan(8192)
+    assert p == {"symmetric": 0, "waves": 4, "workgroups": 128 * 16, "partial_slots": 16, "small": 0}
+    # 64 tiles of 2-D points: 256 splits wanted, limited to 64 (and by the 32-source chunk floor)
+    p = plan(4096, dim=2)
+    assert p["workgroups"] == 64 * 32 and p["partial_slots"] == 32
+
+
+def test_single_precision_and_cutoff_keep_one_sided_kernel():
+    assert plan(65536, dtype=lm.F32)["symmetric"] == 0
+    assert plan(65536, cutoff=0.3)["symmetric"] == 0
+    assert plan(100, cutoff=0.3)["small"] == 0
+
+
+def test_environment_overrides(monkeypatch):
+    monkeypatch.setenv("LM_SYM", "0")
+    assert plan(65536)["symmetric"] == 0
+    monkeypatch.setenv("LM_SYM", "1")
+    p = plan(1000)                       # 16 tiles, one wave per workgroup
+    assert p["symmetric"] == 1 and p["waves"] == 1 and p["partial_slots"] == 9 and p["workgroups"] == 36
+    monkeypatch.setenv("LM_SYM_WAVES", "8")
+    p = plan(65536)
+    assert p["waves"] == 8 and (p["workgroups"], p["partial_slots"]) == sym(1024, 8)[1:]
+    monkeypatch.setenv("LM_SYM_WAVES", "3")   # not a width: the size rule applies
+    assert plan(65536)["waves"] == 4
+
+
+def test_invalid_arguments():
+    with pytest.raises(lm.LmError):
+        plan(0)
