@@ -188,6 +188,14 @@ struct SymPlan {
 // waves takes 298 us against 361, at 32768 997 against 1371, at 65536 (four waves) 3760
 // against 5425.
 constexpr int kSymMaxWaves = 8;
+#ifndef LM_SYM_ROWS
+#define LM_SYM_ROWS 2
+#endif
+constexpr int kSymRows = LM_SYM_ROWS;   // 64-point row tiles per wavefront
+#ifndef LM_SYM_OCC
+#define LM_SYM_OCC (LM_SYM_ROWS > 2 ? 3 : 4)
+#endif
+constexpr int kSymOccupancy = LM_SYM_OCC;   // wavefronts per SIMD the register budget allows
 #ifndef LM_SYM_MIN_TILES
 #define LM_SYM_MIN_TILES 192
 #endif

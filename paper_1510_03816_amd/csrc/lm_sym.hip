@@ -163,7 +163,7 @@ __device__ __forceinline__ int sym_mode(bool diag, int64_t I, int64_t J, int64_t
 }
 
 template <int DIM, int KER, bool FORCE>
-__global__ __launch_bounds__(512, 4) void lm_sym_pair_kernel(SymArgs a)
+__global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs a)
 {
     constexpr int E = sym_stride(DIM);           // staged doubles per column point
     constexpr int EC = FORCE ? 2 * DIM : DIM;    // column sums per point
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(512, 4) void lm_sym_pair_kernel(SymArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int64_t side = 2 * (int64_t)nw;
+    const int64_t side = kSymRows * (int64_t)nw;
     double* jbuf = lds;                          // [128][E]
     double* region = lds + 128 * E;              // [nw][EC][128]
 
@@ -193,11 +193,11 @@ __global__ __launch_bounds__(512, 4) void lm_sym_pair_kernel(SymArgs a)
     const bool diag = X == Y;
     const int64_t n = a.n, T = a.tiles;
 
-    int64_t I[2];
-    double qi[2][DIM], pi[2][DIM], v[2][DIM], f[2][DIM];
+    int64_t I[kSymRows];
+    double qi[kSymRows][DIM], pi[kSymRows][DIM], v[kSymRows][DIM], f[kSymRows][DIM];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        I[r] = X * side + 2 * wave + r;
+    for (int r = 0; r < kSymRows; ++r) {
+        I[r] = X * side + kSymRows * wave + r;
         const int64_t i = I[r] * kSymSteps + lane;
         const bool live = i < n;
 #pragma unroll
@@ -220,14 +220,14 @@ __global__ __launch_bounds__(512, 4) void lm_sym_pair_kernel(SymArgs a)
     const int64_t slot_col = diag ? S : X;
     double* pc = a.part + slot_col * (2 * DIM) * n;
     for (int64_t J = J0; J < J1; ++J) {
-        const int m0 = sym_mode(diag, I[0], J, T);
-        const int m1 = sym_mode(diag, I[1], J, T);
-        if (m0 == SYM_BOTH && m1 == SYM_BOTH) {
-            sym_block<DIM, KER, FORCE, 2, true>(qi, pi, jb, a.kq, v, f, acc);
+        // every row tile meets J from both sides, except near the diagonal
+        const bool all = diag ? J > I[kSymRows - 1] : I[kSymRows - 1] < T;
+        if (all) {
+            sym_block<DIM, KER, FORCE, kSymRows, true>(qi, pi, jb, a.kq, v, f, acc);
         } else {
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const int m = r ? m1 : m0;
+            for (int r = 0; r < kSymRows; ++r) {
+                const int m = sym_mode(diag, I[r], J, T);
                 if (m == SYM_SKIP) continue;
                 double q1[1][DIM], p1[1][DIM], v1[1][DIM], f1[1][DIM];
 #pragma unroll
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(512, 4) void lm_sym_pair_kernel(SymArgs a)
 
     double* pr = a.part + Y * (2 * DIM) * n;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < kSymRows; ++r) {
         const int64_t i = I[r] * kSymSteps + lane;
         if (I[r] >= T || i >= n) continue;
 #pragma unroll
@@ -314,7 +314,7 @@ SymPlan plan_sym(int64_t n, bool force)
     // partial sums: (S + 1) slots of up to 6 doubles per point; wider superblocks need
     // fewer, and beyond the cap the one-sided kernel (at most 64 slots) is used instead
     for (;; w *= 2) {
-        const int64_t S = (T + 2 * w - 1) / (2 * w);
+        const int64_t S = (T + kSymRows * w - 1) / (kSymRows * w);
         const bool fits = (S + 1) * 6 * n * (int64_t)sizeof(double) <= kSymMaxPartBytes;
         if (fits && S * (S + 1) / 2 < ((int64_t)1 << 31)) {
             sp.waves = w;
