@@ -68,12 +68,14 @@ __global__ __launch_bounds__(256) void lm_kbuild_kernel(const double* __restrict
 // *info = k0 + c + 1 (the factor is then meaningless).  The inverse is then formed by
 // forward substitution, two threads per column j of Linv, whose entries (r >= j) are kept in
 // the unused upper triangle at A[j][r + 1].  Outputs: the factor written back over the
-// block, and Linv (kPanel x kPanel, row-major, zero above the diagonal and outside bs).
+// block, Linv (kPanel x kPanel, row-major, zero above the diagonal and outside bs) and its
+// transpose LinvT (the triangular sweeps read rows of both).
 // The loops are bound by LDS traffic and latency (about 0.37 ms per block on MI355X, a few
 // per cent of a large factorization).
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void lm_potrf_inv_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
-                                                           double* __restrict__ Linv, int* __restrict__ info)
+                                                           double* __restrict__ Linv, double* __restrict__ LinvT,
+                                                           int* __restrict__ info)
 {
     __shared__ double A[kPanel][kPanel + 1];
     const int tid = threadIdx.x;
@@ -138,6 +140,7 @@ __global__ __launch_bounds__(256) void lm_potrf_inv_kernel(double* __restrict__ 
     for (int e = tid; e < kPanel * kPanel; e += blockDim.x) {
         const int r = e / kPanel, c = e % kPanel;
         Linv[e] = (r < bs && c <= r) ? A[c][r + 1] : 0.0;
+        LinvT[e] = (c < bs && r <= c) ? A[r][c + 1] : 0.0;    // LinvT[r][c] = Linv[c][r]
     }
 }
 
@@ -387,36 +390,40 @@ __global__ __launch_bounds__(256) void lm_syrk128_kernel(double* __restrict__ K,
 // Triangular sweeps for `dim` right-hand sides (component-major vectors of length n).
 // ---------------------------------------------------------------------------------------
 
-// y_blk = Linv_blk * y_blk (forward, TRANS = false) or Linv_blk^T * y_blk (backward), for
-// block `blk`, executed by one workgroup of 256 threads.
+// y_blk <- M y_blk for block blk, with M = Linv_blk (forward, TRANS = false) or Linv_blk^T
+// (backward), by one workgroup of 256 threads.  (M y)_r = sum_m M^T[m][r] y_m reads rows of
+// M^T, which is stored: LinvT for the forward sweep, Linv for the backward one.  Thread
+// (h, r) sums m over half h for output r with 16 loads in flight (each wave load is one
+// 512-byte row segment); the halves are added in order.  part: 3 * kPanel doubles of LDS.
 template <bool TRANS, int DIM>
 __device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb, int64_t blk,
-                             double* __restrict__ y, int64_t ldy, double* sh)
+                             double* __restrict__ y, int64_t ldy, double* sh, double* part)
 {
     const int64_t b0 = blk * kPanel;
     const int bs = (int)((n - b0) < kPanel ? (n - b0) : kPanel);
-    const double* Li = Linv + blk * kPanel * kPanel;
+    const double* Mt = Linv + ((TRANS ? 0 : (int64_t)nb) + blk) * kPanel * kPanel;
     for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
         const int c = e / kPanel, r = e % kPanel;
         sh[e] = r < bs ? y[c * ldy + b0 + r] : 0.0;
     }
     __syncthreads();
-    double out[3] = {0.0, 0.0, 0.0};
-    const int r = threadIdx.x;
-    if (r < bs) {
-        for (int c = 0; c < DIM; ++c) {
-            double s = 0.0;
-            if (!TRANS) {
-                for (int m = 0; m <= r; ++m) s = __builtin_fma(Li[r * kPanel + m], sh[c * kPanel + m], s);
-            } else {
-                for (int m = r; m < bs; ++m) s = __builtin_fma(Li[m * kPanel + r], sh[c * kPanel + m], s);
-            }
-            out[c] = s;
-        }
+    const int r = threadIdx.x & (kPanel - 1), h = threadIdx.x >> 7;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const double* col = Mt + (int64_t)(h * 64) * kPanel + r;
+    for (int m0 = 0; m0 < 64; m0 += 16) {
+        double lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lv[u] = col[(m0 + u) * kPanel];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc[c] = __builtin_fma(lv[u], sh[c * kPanel + h * 64 + m0 + u], acc[c]);
     }
+    if (h == 1)
+        for (int c = 0; c < DIM; ++c) part[c * kPanel + r] = acc[c];
     __syncthreads();
-    if (r < bs)
-        for (int c = 0; c < DIM; ++c) y[c * ldy + b0 + r] = out[c];
+    if (h == 0 && r < bs)
+        for (int c = 0; c < DIM; ++c) y[c * ldy + b0 + r] = acc[c] + part[c * kPanel + r];
 }
 
 // Launch k of the forward sweep (k = -1: only finish block 0).  Workgroup 0 owns block k+1:
@@ -472,13 +479,14 @@ __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restri
     if (blockIdx.x == 0 && k + 1 < nb) {
         __threadfence_block();
         __syncthreads();
-        finish_block<false, DIM>(Linv, n, nb, k + 1, y, ldy, sh);
+        finish_block<false, DIM>(Linv, n, nb, k + 1, y, ldy, sh, yk);
     }
 }
 
 // Launch k of the backward sweep (k = nb: only finish block nb-1).  Workgroup 0 owns block
-// k-1: it subtracts L[block k, block k-1]^T x_k and finishes x_{k-1}; workgroups >= 1 handle
-// the columns of blocks 0 .. k-2, one column per thread.
+// k-1: it subtracts L[block k, block k-1]^T x_k (thread (h, r): column r over row half h,
+// the halves added in order) and finishes x_{k-1}; workgroups >= 1 handle the columns of
+// blocks 0 .. k-2, one column per thread.
 template <int DIM>
 __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restrict__ L, const double* __restrict__ Linv,
                                                           int64_t n, int nb, int64_t k, double* __restrict__ y,
@@ -494,35 +502,50 @@ __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restri
             xk[e] = m < bs ? y[c * ldy + k0 + m] : 0.0;
         }
         __syncthreads();
-        int64_t cbeg, cend, cstep;
         if (blockIdx.x == 0) {
-            cbeg = (k - 1) * kPanel + threadIdx.x;
-            cend = k * kPanel;
-            cstep = blockDim.x;
-        } else {
-            cbeg = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
-            cend = (k - 1) * kPanel;
-            cstep = (int64_t)(gridDim.x - 1) * blockDim.x;
-        }
-        for (int64_t col = cbeg; col < cend; col += cstep) {
+            const int r = threadIdx.x & (kPanel - 1), h = threadIdx.x >> 7;
+            const int64_t col = (k - 1) * kPanel + r;
+            const double* lc = L + (k0 + h * 64) * n + col;
             double s[3] = {0.0, 0.0, 0.0};
-            const double* lc = L + k0 * n + col;
-            // sixteen independent loads in flight per thread (zeros past a ragged block end)
-            for (int m0 = 0; m0 < kPanel; m0 += 16) {
+            for (int m0 = 0; m0 < 64; m0 += 16) {
                 double lv[16];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) lv[u] = (m0 + u < bs) ? lc[(int64_t)(m0 + u) * n] : 0.0;
+                for (int u = 0; u < 16; ++u) {
+                    const int m = h * 64 + m0 + u;
+                    lv[u] = m < bs ? lc[(int64_t)(m0 + u) * n] : 0.0;
+                }
                 for (int c = 0; c < DIM; ++c)
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) s[c] = __builtin_fma(lv[u], xk[c * kPanel + m0 + u], s[c]);
+                    for (int u = 0; u < 16; ++u) s[c] = __builtin_fma(lv[u], xk[c * kPanel + h * 64 + m0 + u], s[c]);
             }
-            for (int c = 0; c < DIM; ++c) y[c * ldy + col] -= s[c];
+            if (h == 1)
+                for (int c = 0; c < DIM; ++c) sh[c * kPanel + r] = s[c];
+            __syncthreads();
+            if (h == 0)
+                for (int c = 0; c < DIM; ++c) y[c * ldy + col] -= s[c] + sh[c * kPanel + r];
+        } else {
+            const int64_t cend = (k - 1) * kPanel;
+            const int64_t cstep = (int64_t)(gridDim.x - 1) * blockDim.x;
+            for (int64_t col = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x; col < cend; col += cstep) {
+                double s[3] = {0.0, 0.0, 0.0};
+                const double* lc = L + k0 * n + col;
+                // sixteen independent loads in flight per thread (zeros past a ragged block end)
+                for (int m0 = 0; m0 < kPanel; m0 += 16) {
+                    double lv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) lv[u] = (m0 + u < bs) ? lc[(int64_t)(m0 + u) * n] : 0.0;
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) s[c] = __builtin_fma(lv[u], xk[c * kPanel + m0 + u], s[c]);
+                }
+                for (int c = 0; c < DIM; ++c) y[c * ldy + col] -= s[c];
+            }
         }
     }
     if (blockIdx.x == 0 && k - 1 >= 0) {
         __threadfence_block();
         __syncthreads();
-        finish_block<true, DIM>(Linv, n, nb, k - 1, y, ldy, sh);
+        finish_block<true, DIM>(Linv, n, nb, k - 1, y, ldy, sh, xk);
     }
 }
 
@@ -669,7 +692,8 @@ hipError_t launch_batch_dense_solve(const double* L, const int64_t* loff, const 
 __global__ void lm_int_zero_kernel(int* p) { if (threadIdx.x == 0) *p = 0; }
 
 int dense_panels(int64_t n) { return (int)((n + kPanel - 1) / kPanel); }
-int64_t dense_linv_elems(int64_t n) { return (int64_t)dense_panels(n) * kPanel * kPanel; }
+// the inverses of the diagonal blocks, then their transposes
+int64_t dense_linv_elems(int64_t n) { return 2 * (int64_t)dense_panels(n) * kPanel * kPanel; }
 
 hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,
                                double* Linv, int* info, hipStream_t st)
@@ -704,7 +728,8 @@ hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const
                                    (int)(k0 - kb), k0, 1);
             }
             double* Lb = Linv + (int64_t)b * kPanel * kPanel;
-            hipLaunchKernelGGL(lm_potrf_inv_kernel, dim3(1), dim3(256), 0, st, K, n, k0, bs, Lb, info);
+            double* LbT = Lb + (int64_t)nb * kPanel * kPanel;
+            hipLaunchKernelGGL(lm_potrf_inv_kernel, dim3(1), dim3(256), 0, st, K, n, k0, bs, Lb, LbT, info);
             const int64_t below = n - k0 - bs;
             if (below > 0)
                 hipLaunchKernelGGL(lm_panel_kernel, dim3((unsigned)((below + 63) / 64)), dim3(256), 0, st, K, n, k0,
