@@ -96,8 +96,8 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
                     const T* pt, int64_t nt, const lm::EpiArgs<T>& epi, double* part, hipStream_t st,
                     const Cut& cut = Cut())
 {
-    const bool sym_ok = sizeof(T) == 8 && qs == qt && ps == pt && ns == nt;
-    lm::PairPlan pl = lm::plan_pair(nt, ns, cut.box_s != nullptr, sym_ok);
+    const bool sym_ok = qs == qt && ps == pt && ns == nt;
+    lm::PairPlan pl = lm::plan_pair(nt, ns, cut.box_s != nullptr, sym_ok, sizeof(T) == 4);
     lm::PairArgs<T> a{};
     a.qs = qs;
     a.ps = ps;
@@ -123,7 +123,7 @@ int64_t part_elems(const lm_params* prm, int64_t nt, int64_t ns)
     int64_t slots = pl.nsplit > 1 ? pl.nsplit : 0;
     if (nt == ns) {
         // the symmetric kernel's slots under any setting of LM_SYM (forced or by size)
-        const lm::SymPlan sp = lm::plan_sym(nt, true);
+        const lm::SymPlan sp = lm::plan_sym(nt, true, prm->dtype == LM_F32);
         if (sp.waves > 0 && sp.nsb + 1 > slots) slots = sp.nsb + 1;
     }
     return slots > 0 ? slots * 2 * prm->dim * nt : 1;
@@ -1026,7 +1026,7 @@ lm_status lm_pair_plan(const lm_params* prm, int64_t n, lm_plan_info* info)
     LM_TRY(check_n(n));
     if (!info) return fail(LM_EINVAL, "NULL info");
     const bool cut = prm->cutoff > 0.0;
-    const lm::PairPlan pl = lm::plan_pair(n, n, cut, prm->dtype == LM_F64);
+    const lm::PairPlan pl = lm::plan_pair(n, n, cut, true, prm->dtype == LM_F32);
     info->symmetric = pl.sym_waves > 0;
     info->waves = pl.sym_waves > 0 ? pl.sym_waves : lm::kWaves;
     info->workgroups = pl.sym_waves > 0 ? pl.sym_nsb * (pl.sym_nsb + 1) / 2 : pl.itiles * pl.nsplit;

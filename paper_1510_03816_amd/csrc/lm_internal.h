@@ -163,12 +163,13 @@ struct PairPlan {
 // sym_ok: the targets are the sources (one point set, every pair, double precision), so the
 // symmetric kernel may be chosen.  The environment variable LM_SYM overrides the size rule:
 // "0" never, "1" always (for tests of small sizes).
-PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok = false);
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok = false, bool f32 = false);
 
 // Symmetric pair sums of one point set (lm_sym.hip).
+template <class T>
 struct SymArgs {
-    const double* q;     // (dim, n)
-    const double* p;
+    const T* q;          // (dim, n)
+    const T* p;
     int64_t n;
     int64_t tiles;       // 64-point tiles
     int64_t nsb;         // superblocks of 2 * waves tiles
@@ -201,10 +202,20 @@ constexpr int kSymOccupancy = LM_SYM_OCC;   // wavefronts per SIMD the register 
 #endif
 constexpr int64_t kSymMinTiles = LM_SYM_MIN_TILES;
 constexpr int64_t kSymWideTiles = 768;
+// Single precision: the size rule never picks the symmetric kernel.  Its shared part (the
+// hardware 2^x and 1/sqrt) is too small a share of a pair for symmetry to pay for the column
+// traffic: 1973 us per stage at N = 65536 against 1996 for the one-sided kernel, slower at
+// every smaller size measured (557 against 519 at 32768, 176 against 144 at 16384).
+#ifndef LM_SYM_MIN_TILES_F32
+#define LM_SYM_MIN_TILES_F32 (int64_t(1) << 40)
+#endif
+constexpr int64_t kSymMinTilesF32 = LM_SYM_MIN_TILES_F32;
+constexpr int64_t kSymWideTilesF32 = 768;
 constexpr int64_t kSymMaxPartBytes = (int64_t)16 << 30;
 
-SymPlan plan_sym(int64_t n, bool force);
-hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs& a, int waves, hipStream_t st);
+SymPlan plan_sym(int64_t n, bool force, bool f32);
+template <class T>
+hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs<T>& a, int waves, hipStream_t st);
 
 template <class T>
 hipError_t launch_pair(int dim, int kernel, bool force, const PairArgs<T>& a, const PairPlan& pl,

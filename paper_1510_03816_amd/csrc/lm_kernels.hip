@@ -737,7 +737,7 @@ static inline unsigned blocks_for(int64_t m, int threads, unsigned cap = 8192)
     return (unsigned)(b < (int64_t)cap ? b : cap);
 }
 
-PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok)
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, bool f32)
 {
     PairPlan pl{};
     pl.itiles = (nt + kTile - 1) / kTile;
@@ -745,7 +745,7 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok)
         const char* e = getenv("LM_SYM");
         const int mode = e ? atoi(e) : -1;
         if (mode != 0) {
-            const SymPlan sp = plan_sym(nt, mode == 1);
+            const SymPlan sp = plan_sym(nt, mode == 1, f32);
             if (sp.waves > 0) {
                 pl.sym_waves = sp.waves;
                 pl.sym_nsb = sp.nsb;
@@ -778,8 +778,8 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
 {
     hipError_t err;
     if (pl.sym_waves > 0) {
-        if constexpr (sizeof(T) == 8 && !CUT) {
-            SymArgs s{};
+        if constexpr (!CUT) {
+            SymArgs<T> s{};
             s.q = a.qs;
             s.p = a.ps;
             s.n = a.nt;
@@ -788,7 +788,7 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
             s.kq = a.kq;
             s.wscale = a.wscale;
             s.part = a.part;
-            err = launch_sym_pair(DIM, KER, FORCE, s, pl.sym_waves, st);
+            err = launch_sym_pair<T>(DIM, KER, FORCE, s, pl.sym_waves, st);
         } else {
             return hipErrorInvalidValue;
         }

@@ -7,9 +7,11 @@
 //     v_i += g p_j,  v_j += g p_i,  f_i += (p_i . p_j) w d,  f_j -= (p_i . p_j) w d,  d = q_i - q_j.
 // The shared part (distance, 1/sqrt, exponential, weight, momentum product) is about three
 // quarters of a pair's work, so a sweep over the N(N+1)/2 unordered pairs costs about 55% of
-// the N^2 ordered ones.  Used for the self-interaction of one point set in double precision
-// (right-hand side, RK4 stages, K x); targets distinct from the sources, tile skipping and
-// single precision keep the one-sided kernel in lm_kernels.hip.
+// the N^2 ordered ones.  Used for the self-interaction of one point set (right-hand side, RK4
+// stages, K x); targets distinct from the sources and tile skipping keep the one-sided
+// kernel in lm_kernels.hip.  In single precision a row point's pairs with one column tile (64
+// steps) are summed in float and those sums in double, as the one-sided kernel sums runs of
+// 64 sources; column-side terms are added in double.
 //
 // Decomposition.  The 64-point tiles are grouped into superblocks of B = 2W tiles; a
 // workgroup of W wavefronts takes one pair (X, Y), X <= Y, of superblocks.  Wave w owns the
@@ -45,76 +47,96 @@ namespace {
 constexpr int kSymSteps = 64;     // column points per tile
 constexpr int kSymUnroll = 8;     // steps per unrolled loop body
 
-// Doubles per staged column point: q and p, padded by one so that the 64 lanes' reads of
-// consecutive entries (stride 14 or 10 words) fall in distinct LDS banks.
+// Values per staged column point: q and p, padded by one so that the 64 lanes' reads of
+// consecutive entries (an odd stride) fall in distinct LDS banks.
 __host__ __device__ constexpr int sym_stride(int dim) { return 2 * dim + 1; }
+
+// Per-precision pieces: FMA, the conon's squared-distance floor (see pair_f64), 1/sqrt and the
+// exponential (in single precision the hardware 2^x, log2 e folded into kq by the caller).
+template <class T>
+struct SymMath;
+template <>
+struct SymMath<double> {
+    static constexpr double kFloor = 1e-300;
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ double rsq(double s) { return rsqrt_pos(s); }
+    static __device__ __forceinline__ double ex(double x) { return exp_nonpos(x); }
+};
+template <>
+struct SymMath<float> {
+    static constexpr float kFloor = 1e-30f;
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ float rsq(float s) { return rsqrt_f32(s); }
+    static __device__ __forceinline__ float ex(float x) { return exp2_f32(x); }
+};
 
 // The symmetric part of a pair: d = q_i - q_j, kernel value g and force weight w (without
 // the constant, which is applied to the sums).
-template <int DIM, int KER>
-__device__ __forceinline__ void sym_pair(const double (&qi)[DIM], const double (&qj)[DIM], double kq,
-                                         double (&d)[DIM], double& g, double& w)
+template <class T, int DIM, int KER>
+__device__ __forceinline__ void sym_pair(const T (&qi)[DIM], const T (&qj)[DIM], T kq, T (&d)[DIM], T& g, T& w)
 {
-    // conon: the squared distance starts at 1e-300 (see pair_f64) so the self pair and
-    // padding points at the same position give a finite weight times d = 0
-    double s = (KER == LM_KERNEL_CONON) ? 1e-300 : 0.0;
+    using M = SymMath<T>;
+    // conon: the squared distance starts at a tiny floor so the self pair and padding points
+    // at the same position give a finite weight times d = 0
+    T s = (KER == LM_KERNEL_CONON) ? M::kFloor : (T)0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         d[c] = qi[c] - qj[c];
-        s = __builtin_fma(d[c], d[c], s);
+        s = M::fma(d[c], d[c], s);
     }
     if constexpr (KER == LM_KERNEL_CONON) {
-        const double rho = rsqrt_pos(s);
-        g = exp_nonpos(s * rho * kq);
+        const T rho = M::rsq(s);
+        g = M::ex(s * rho * kq);
         w = g * rho;
     } else {
-        g = exp_nonpos(s * kq);
+        g = M::ex(s * kq);
         w = g;
     }
 }
 
 // One step: the ROWS row points of this lane against column entry `src` (q then p).  With
 // JSIDE the column-side terms are added into the wave's column array at `acc` (component c
-// at acc[c * 128]).
-template <int DIM, int KER, bool FORCE, int ROWS, bool JSIDE>
-__device__ __forceinline__ void sym_step(const double (&qi)[ROWS][DIM], const double (&pi)[ROWS][DIM],
-                                         const double* __restrict__ src, double kq, double (&v)[ROWS][DIM],
-                                         double (&f)[ROWS][DIM], double* __restrict__ acc)
+// at acc[c * 128]).  The column arrays are double in both precisions: ds_add_f64 runs at
+// full rate, while single-precision LDS atomic adds measured 16 times slower for the kernel.
+template <class T, int DIM, int KER, bool FORCE, int ROWS, bool JSIDE>
+__device__ __forceinline__ void sym_step(const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM], const T* __restrict__ src,
+                                         T kq, T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc)
 {
-    double qj[DIM], pj[DIM];
+    using M = SymMath<T>;
+    T qj[DIM], pj[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         qj[c] = src[c];
         pj[c] = src[DIM + c];
     }
-    double tv[DIM], tf[DIM];
+    T tv[DIM], tf[DIM];
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
-        double d[DIM], g, w;
-        sym_pair<DIM, KER>(qi[r], qj, kq, d, g, w);
+        T d[DIM], g, w;
+        sym_pair<T, DIM, KER>(qi[r], qj, kq, d, g, w);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            v[r][c] = __builtin_fma(g, pj[c], v[r][c]);
-            if (JSIDE) tv[c] = (r == 0) ? g * pi[r][c] : __builtin_fma(g, pi[r][c], tv[c]);
+            v[r][c] = M::fma(g, pj[c], v[r][c]);
+            if (JSIDE) tv[c] = (r == 0) ? g * pi[r][c] : M::fma(g, pi[r][c], tv[c]);
         }
         if constexpr (FORCE) {
-            double pp = pi[r][0] * pj[0];
+            T pp = pi[r][0] * pj[0];
 #pragma unroll
-            for (int c = 1; c < DIM; ++c) pp = __builtin_fma(pi[r][c], pj[c], pp);
-            const double cw = pp * w;
+            for (int c = 1; c < DIM; ++c) pp = M::fma(pi[r][c], pj[c], pp);
+            const T cw = pp * w;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                f[r][c] = __builtin_fma(cw, d[c], f[r][c]);
-                if (JSIDE) tf[c] = (r == 0) ? -cw * d[c] : __builtin_fma(-cw, d[c], tf[c]);
+                f[r][c] = M::fma(cw, d[c], f[r][c]);
+                if (JSIDE) tf[c] = (r == 0) ? -cw * d[c] : M::fma(-cw, d[c], tf[c]);
             }
         }
     }
     if constexpr (JSIDE) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            __hip_atomic_fetch_add(acc + c * 128, tv[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(acc + c * 128, (double)tv[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (FORCE)
-                __hip_atomic_fetch_add(acc + (DIM + c) * 128, tf[c], __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(acc + (DIM + c) * 128, (double)tf[c], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
@@ -122,30 +144,30 @@ __device__ __forceinline__ void sym_step(const double (&qi)[ROWS][DIM], const do
 
 // All 64 steps of one (row tile(s), column tile) block.  jb = this lane's first column entry
 // (jbuf + lane * sym_stride(DIM)), acc = this lane's first word of the wave's column array.
-template <int DIM, int KER, bool FORCE, int ROWS, bool JSIDE>
-__device__ __forceinline__ void sym_block(const double (&qi)[ROWS][DIM], const double (&pi)[ROWS][DIM],
-                                          const double* __restrict__ jb, double kq, double (&v)[ROWS][DIM],
-                                          double (&f)[ROWS][DIM], double* __restrict__ acc)
+template <class T, int DIM, int KER, bool FORCE, int ROWS, bool JSIDE>
+__device__ __forceinline__ void sym_block(const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM], const T* __restrict__ jb,
+                                          T kq, T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc)
 {
     constexpr int E = sym_stride(DIM);
     for (int k0 = 0; k0 < kSymSteps; k0 += kSymUnroll) {
 #pragma unroll
         for (int u = 0; u < kSymUnroll; ++u)
-            sym_step<DIM, KER, FORCE, ROWS, JSIDE>(qi, pi, jb + (k0 + u) * E, kq, v, f, acc + k0 + u);
+            sym_step<T, DIM, KER, FORCE, ROWS, JSIDE>(qi, pi, jb + (k0 + u) * E, kq, v, f, acc + k0 + u);
     }
 }
 
 // Loads column tile J into jbuf: entry e (0..127) holds point J*64 + (e mod 64), its q then
-// its p (the pad word is never read); points past n are zero (zero momentum: they add exactly nothing to real points).
-template <int DIM>
-__device__ __forceinline__ void sym_stage(double* __restrict__ jbuf, const double* __restrict__ q,
-                                          const double* __restrict__ p, int64_t n, int64_t J)
+// its p (the pad word is never read); points past n are zero (zero momentum: they add
+// exactly nothing to real points).
+template <class T, int DIM>
+__device__ __forceinline__ void sym_stage(T* __restrict__ jbuf, const T* __restrict__ q, const T* __restrict__ p,
+                                          int64_t n, int64_t J)
 {
     constexpr int E = sym_stride(DIM);
     for (int t = threadIdx.x; t < kSymSteps * 2 * DIM; t += blockDim.x) {
         const int c = t >> 6, l = t & 63;
         const int64_t j = J * kSymSteps + l;
-        double x = 0.0;
+        T x = (T)0;
         if (j < n) x = (c < DIM) ? q[c * n + j] : p[(c - DIM) * n + j];
         jbuf[l * E + c] = x;
         jbuf[(l + 64) * E + c] = x;
@@ -162,18 +184,56 @@ __device__ __forceinline__ int sym_mode(bool diag, int64_t I, int64_t J, int64_t
     return I == J ? SYM_ONE : SYM_SKIP;
 }
 
-template <int DIM, int KER, bool FORCE>
-__global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs a)
+// The row tiles of this wave against column tile J (staged at jb), sums added to (v, f): both
+// rows symmetrically in one pass when they allow it, else row by row by mode.
+template <class T, int DIM, int KER, bool FORCE, class A>
+__device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[kSymRows], int64_t J, int64_t NT,
+                                         const T (&qi)[kSymRows][DIM], const T (&pi)[kSymRows][DIM],
+                                         const T* __restrict__ jb, T kq, A (&v)[kSymRows][DIM], A (&f)[kSymRows][DIM],
+                                         double* __restrict__ acc)
 {
-    constexpr int E = sym_stride(DIM);           // staged doubles per column point
+    // every row tile meets J from both sides, except near the diagonal
+    const bool all = diag ? J > I[kSymRows - 1] : I[kSymRows - 1] < NT;
+    if (all) {
+        sym_block<T, DIM, KER, FORCE, kSymRows, true>(qi, pi, jb, kq, v, f, acc);
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < kSymRows; ++r) {
+        const int m = sym_mode(diag, I[r], J, NT);
+        if (m == SYM_SKIP) continue;
+        T q1[1][DIM], p1[1][DIM], v1[1][DIM], f1[1][DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            q1[0][c] = qi[r][c];
+            p1[0][c] = pi[r][c];
+            v1[0][c] = v[r][c];
+            f1[0][c] = f[r][c];
+        }
+        if (m == SYM_BOTH)
+            sym_block<T, DIM, KER, FORCE, 1, true>(q1, p1, jb, kq, v1, f1, acc);
+        else
+            sym_block<T, DIM, KER, FORCE, 1, false>(q1, p1, jb, kq, v1, f1, acc);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            v[r][c] = v1[0][c];
+            f[r][c] = f1[0][c];
+        }
+    }
+}
+
+template <class T, int DIM, int KER, bool FORCE>
+__global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs<T> a)
+{
+    constexpr int E = sym_stride(DIM);           // staged values per column point
     constexpr int EC = FORCE ? 2 * DIM : DIM;    // column sums per point
-    extern __shared__ double lds[];
+    extern __shared__ double lds_words[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const int64_t side = kSymRows * (int64_t)nw;
-    double* jbuf = lds;                          // [128][E]
-    double* region = lds + 128 * E;              // [nw][EC][128]
+    double* region = lds_words;                                // [nw][EC][128]
+    T* jbuf = reinterpret_cast<T*>(region + nw * EC * 128);    // [128][E]
 
     // superblock pair: off-diagonal pairs (X < Y) first, numbered Y(Y-1)/2 + X, then the
     // diagonal ones, which carry half the work
@@ -191,10 +251,13 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
         X = Y = b - noff;
     }
     const bool diag = X == Y;
-    const int64_t n = a.n, T = a.tiles;
+    const int64_t n = a.n, NT = a.tiles;
+    const T kq = (T)a.kq;
 
+    // row points in registers; their sums over one column tile in T, over all tiles in double
     int64_t I[kSymRows];
-    double qi[kSymRows][DIM], pi[kSymRows][DIM], v[kSymRows][DIM], f[kSymRows][DIM];
+    T qi[kSymRows][DIM], pi[kSymRows][DIM];
+    double vs[kSymRows][DIM], fs[kSymRows][DIM];
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r) {
         I[r] = X * side + kSymRows * wave + r;
@@ -202,54 +265,46 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
         const bool live = i < n;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            qi[r][c] = live ? a.q[c * n + i] : 0.0;
-            pi[r][c] = live ? a.p[c * n + i] : 0.0;
-            v[r][c] = 0.0;
-            f[r][c] = 0.0;
+            qi[r][c] = live ? a.q[c * n + i] : (T)0;
+            pi[r][c] = live ? a.p[c * n + i] : (T)0;
+            vs[r][c] = 0.0;
+            fs[r][c] = 0.0;
         }
     }
 
     for (int t = threadIdx.x; t < nw * EC * 128; t += blockDim.x) region[t] = 0.0;
     const int64_t J0 = Y * side;
-    const int64_t J1 = (J0 + side < T) ? (J0 + side) : T;
-    sym_stage<DIM>(jbuf, a.q, a.p, n, J0);
+    const int64_t J1 = (J0 + side < NT) ? (J0 + side) : NT;
+    sym_stage<T, DIM>(jbuf, a.q, a.p, n, J0);
     __syncthreads();
 
-    const double* jb = jbuf + lane * E;
+    const T* jb = jbuf + lane * E;
     double* acc = region + wave * EC * 128 + lane;
     const int64_t slot_col = diag ? S : X;
     double* pc = a.part + slot_col * (2 * DIM) * n;
     for (int64_t J = J0; J < J1; ++J) {
-        // every row tile meets J from both sides, except near the diagonal
-        const bool all = diag ? J > I[kSymRows - 1] : I[kSymRows - 1] < T;
-        if (all) {
-            sym_block<DIM, KER, FORCE, kSymRows, true>(qi, pi, jb, a.kq, v, f, acc);
+        if constexpr (sizeof(T) == sizeof(double)) {
+            sym_tile<T, DIM, KER, FORCE>(diag, I, J, NT, qi, pi, jb, kq, vs, fs, acc);
         } else {
+            T v[kSymRows][DIM], f[kSymRows][DIM];
 #pragma unroll
-            for (int r = 0; r < kSymRows; ++r) {
-                const int m = sym_mode(diag, I[r], J, T);
-                if (m == SYM_SKIP) continue;
-                double q1[1][DIM], p1[1][DIM], v1[1][DIM], f1[1][DIM];
+            for (int r = 0; r < kSymRows; ++r)
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
-                    q1[0][c] = qi[r][c];
-                    p1[0][c] = pi[r][c];
-                    v1[0][c] = v[r][c];
-                    f1[0][c] = f[r][c];
+                    v[r][c] = (T)0;
+                    f[r][c] = (T)0;
                 }
-                if (m == SYM_BOTH)
-                    sym_block<DIM, KER, FORCE, 1, true>(q1, p1, jb, a.kq, v1, f1, acc);
-                else
-                    sym_block<DIM, KER, FORCE, 1, false>(q1, p1, jb, a.kq, v1, f1, acc);
+            sym_tile<T, DIM, KER, FORCE>(diag, I, J, NT, qi, pi, jb, kq, v, f, acc);
+#pragma unroll
+            for (int r = 0; r < kSymRows; ++r)
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
-                    v[r][c] = v1[0][c];
-                    f[r][c] = f1[0][c];
+                    vs[r][c] += (double)v[r][c];
+                    fs[r][c] += (double)f[r][c];
                 }
-            }
         }
         __syncthreads();
-        // column sums of tile J: the waves in order, each wave's two halves in order
+        // column sums of tile J, in double: the waves in order, each wave's two halves in order
         for (int t = threadIdx.x; t < EC * 64; t += blockDim.x) {
             const int c = t >> 6, l = t & 63;
             double s = 0.0;
@@ -263,7 +318,7 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
             const int64_t j = J * kSymSteps + l;
             if (j < n) pc[c * n + j] = (c < DIM) ? s : s * a.wscale;
         }
-        if (J + 1 < J1) sym_stage<DIM>(jbuf, a.q, a.p, n, J + 1);
+        if (J + 1 < J1) sym_stage<T, DIM>(jbuf, a.q, a.p, n, J + 1);
         __syncthreads();
     }
 
@@ -271,29 +326,29 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r) {
         const int64_t i = I[r] * kSymSteps + lane;
-        if (I[r] >= T || i >= n) continue;
+        if (I[r] >= NT || i >= n) continue;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            pr[c * n + i] = v[r][c];
-            if (FORCE) pr[(DIM + c) * n + i] = f[r][c] * a.wscale;
+            pr[c * n + i] = vs[r][c];
+            if (FORCE) pr[(DIM + c) * n + i] = fs[r][c] * a.wscale;
         }
     }
 }
 
-template <int DIM, int KER, bool FORCE>
-hipError_t launch_sym_t(const SymArgs& a, int waves, hipStream_t st)
+template <class T, int DIM, int KER, bool FORCE>
+hipError_t launch_sym_t(const SymArgs<T>& a, int waves, hipStream_t st)
 {
     constexpr int EC = FORCE ? 2 * DIM : DIM;
-    const size_t lds = (size_t)(128 * sym_stride(DIM) + waves * EC * 128) * sizeof(double);
+    const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
     const int64_t S = a.nsb;
-    hipLaunchKernelGGL((lm_sym_pair_kernel<DIM, KER, FORCE>), dim3((unsigned)(S * (S + 1) / 2)),
+    hipLaunchKernelGGL((lm_sym_pair_kernel<T, DIM, KER, FORCE>), dim3((unsigned)(S * (S + 1) / 2)),
                        dim3(64 * waves), lds, st, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-SymPlan plan_sym(int64_t n, bool force)
+SymPlan plan_sym(int64_t n, bool force, bool f32)
 {
     SymPlan sp{};
     const int64_t T = tiles_of(n);
@@ -303,9 +358,9 @@ SymPlan plan_sym(int64_t n, bool force)
     int w = 0;
     if (fixed == 1 || fixed == 2 || fixed == 4 || fixed == 8) {
         w = fixed;
-    } else if (T >= kSymWideTiles) {
+    } else if (T >= (f32 ? kSymWideTilesF32 : kSymWideTiles) && T >= (f32 ? kSymMinTilesF32 : kSymMinTiles)) {
         w = 4;
-    } else if (T >= kSymMinTiles) {
+    } else if (T >= (f32 ? kSymMinTilesF32 : kSymMinTiles)) {
         w = 2;
     } else if (force) {
         w = 1;
@@ -325,20 +380,24 @@ SymPlan plan_sym(int64_t n, bool force)
     }
 }
 
-hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs& a, int waves, hipStream_t st)
+template <class T>
+hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs<T>& a, int waves, hipStream_t st)
 {
     if (dim == 2) {
         if (kernel == LM_KERNEL_CONON)
-            return force ? launch_sym_t<2, LM_KERNEL_CONON, true>(a, waves, st)
-                         : launch_sym_t<2, LM_KERNEL_CONON, false>(a, waves, st);
-        return force ? launch_sym_t<2, LM_KERNEL_GAUSS, true>(a, waves, st)
-                     : launch_sym_t<2, LM_KERNEL_GAUSS, false>(a, waves, st);
+            return force ? launch_sym_t<T, 2, LM_KERNEL_CONON, true>(a, waves, st)
+                         : launch_sym_t<T, 2, LM_KERNEL_CONON, false>(a, waves, st);
+        return force ? launch_sym_t<T, 2, LM_KERNEL_GAUSS, true>(a, waves, st)
+                     : launch_sym_t<T, 2, LM_KERNEL_GAUSS, false>(a, waves, st);
     }
     if (kernel == LM_KERNEL_CONON)
-        return force ? launch_sym_t<3, LM_KERNEL_CONON, true>(a, waves, st)
-                     : launch_sym_t<3, LM_KERNEL_CONON, false>(a, waves, st);
-    return force ? launch_sym_t<3, LM_KERNEL_GAUSS, true>(a, waves, st)
-                 : launch_sym_t<3, LM_KERNEL_GAUSS, false>(a, waves, st);
+        return force ? launch_sym_t<T, 3, LM_KERNEL_CONON, true>(a, waves, st)
+                     : launch_sym_t<T, 3, LM_KERNEL_CONON, false>(a, waves, st);
+    return force ? launch_sym_t<T, 3, LM_KERNEL_GAUSS, true>(a, waves, st)
+                 : launch_sym_t<T, 3, LM_KERNEL_GAUSS, false>(a, waves, st);
 }
+
+template hipError_t launch_sym_pair<double>(int, int, bool, const SymArgs<double>&, int, hipStream_t);
+template hipError_t launch_sym_pair<float>(int, int, bool, const SymArgs<float>&, int, hipStream_t);
 
 }  // namespace lm

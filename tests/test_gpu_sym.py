@@ -45,12 +45,20 @@ class _env:
                 os.environ[k] = v
 
 
-def dev(a):
-    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+TOL = {lm.F64: 1e-10, lm.F32: 1e-4}
+
+
+def dev(a, dtype=lm.F64):
+    tdt = torch.float64 if dtype == lm.F64 else torch.float32
+    return torch.tensor(np.ascontiguousarray(a), dtype=tdt, device=DEV)
 
 
 def host(t):
-    return t.detach().cpu().numpy()
+    return t.detach().double().cpu().numpy()
+
+
+def rounded(a, dtype):
+    return a.astype(np.float32).astype(np.float64) if dtype == lm.F32 else a
 
 
 def rel_err(got, want):
@@ -59,29 +67,31 @@ def rel_err(got, want):
     return d / scale if scale > 0 else d
 
 
-def gpu_rhs(q, p, kernel, sigma, tau=0.0):
-    prm = lm.make_params(q.shape[0], kernel, sigma, tau=tau)
-    qd, pd = dev(q), dev(p)
+def gpu_rhs(q, p, kernel, sigma, tau=0.0, dtype=lm.F64):
+    prm = lm.make_params(q.shape[0], kernel, sigma, tau=tau, dtype=dtype)
+    qd, pd = dev(q, dtype), dev(p, dtype)
     dq, dp = torch.empty_like(qd), torch.empty_like(pd)
     lm.lm_rhs(prm, qd, pd, dq, dp)
     torch.cuda.synchronize()
     return host(dq), host(dp)
 
 
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
 @pytest.mark.parametrize("waves", [1, 2, 4, 8])
 @pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("n", [1, 2, 64, 65, 700, 3007])
-def test_sym_rhs_matches_oracle(n, dim, kernel, waves):
+def test_sym_rhs_matches_oracle(n, dim, kernel, waves, dtype):
     q, p = inputs.random_state(n, dim, seed=[110, n, dim], box=1.0, pscale=0.3)
+    q, p = rounded(q, dtype), rounded(p, dtype)
     sigma, tau = (0.3 if dim == 3 else 0.25), 0.1
     dq_o, dp_o = oracle.rhs(q, p, kernel, sigma, tau)
-    print("sym rhs n=%d dim=%d kernel=%d waves=%d" % (n, dim, kernel, waves), flush=True)
+    print("sym rhs n=%d dim=%d kernel=%d waves=%d dtype=%d" % (n, dim, kernel, waves, dtype), flush=True)
     with _env(LM_SYM=1, LM_SYM_WAVES=waves):
-        dq, dp = gpu_rhs(q, p, kernel, sigma, tau)
+        dq, dp = gpu_rhs(q, p, kernel, sigma, tau, dtype)
     eq, ep = rel_err(dq, dq_o), rel_err(dp, dp_o)
     print("  %.2e %.2e" % (eq, ep))
-    assert eq <= 1e-10 and ep <= 1e-10
+    assert eq <= TOL[dtype] and ep <= TOL[dtype]
     if n == 1:
         assert np.all(dp == 0.0)
 
@@ -124,19 +134,21 @@ def test_sym_by_size_rule_sampled(n):
     assert np.max(np.abs(dp.sum(axis=1))) <= 1e-9 * np.max(np.abs(dp))
 
 
-def test_sym_shoot_matches_oracle_and_is_deterministic():
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+def test_sym_shoot_matches_oracle_and_is_deterministic(dtype):
     pr = inputs.config_curve2d(700)
-    oq, op = oracle.shoot(pr.X, pr.p_bench(), pr.kernel, pr.sigma, 40)
-    prm = lm.make_params(2, pr.kernel, pr.sigma)
+    X, P = rounded(pr.X, dtype), rounded(pr.p_bench(), dtype)
+    oq, op = oracle.shoot(X, P, pr.kernel, pr.sigma, 40)
+    prm = lm.make_params(2, pr.kernel, pr.sigma, dtype=dtype)
     outs = []
     with _env(LM_SYM=1, LM_SYM_WAVES=2):
         for _ in range(2):
-            q, p = dev(pr.X), dev(pr.p_bench())
+            q, p = dev(X, dtype), dev(P, dtype)
             q1, p1 = torch.empty_like(q), torch.empty_like(p)
             lm.lm_shoot(prm, q, p, 1.0, 40, q1, p1)
             torch.cuda.synchronize()
             outs.append((host(q1), host(p1)))
-    assert rel_err(outs[0][0], oq) <= 1e-10 and rel_err(outs[0][1], op) <= 1e-10
+    assert rel_err(outs[0][0], oq) <= TOL[dtype] and rel_err(outs[0][1], op) <= TOL[dtype]
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
