@@ -53,12 +53,13 @@ SLOTS_PER_PAIR = {(3, 0): 46, (2, 0): 41, (3, 1): 32, (2, 1): 27}
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 PEAK_TFLOPS = 2.0 * PEAK_SLOTS / 1e12
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
+# HBM bytes per RK stage of the dominant kernel (the pair-sum launch and the launch that adds
+# its partial sums) from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
 # each scaled by the reading of a plain device copy of known size (fetch x2.000, write x1.000),
 # recorded with the hash of the kernel sources they were taken on; a changed kernel reports
 # null until the counters are taken again.
 MEASURED_TRAFFIC = {
-    "sphere3d_conon_f64": ("a4522bd12cee5990", 9.772e7),
+    "sphere3d_conon_f64": ("ee4c413d4a0ae20f", 9.490e8),
 }
 
 
@@ -365,7 +366,7 @@ def main():
         traffic = MEASURED_TRAFFIC[args.workload][1]
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": (achieved / PEAK_TFLOPS) if achieved else None, "traffic": traffic,
-                "traffic_unit": "bytes per launch",
+                "traffic_unit": "HBM bytes per RK stage (pair-sum and finish launches)",
                 "kernel": kname, "plan": plan,
                 "launch_ms": launch_ms, "pair_evaluations_per_launch": evals, "slots_per_evaluation": slots,
                 "pairs_per_s_in_kernel": n * n / (launch_ms * 1e-3)}
