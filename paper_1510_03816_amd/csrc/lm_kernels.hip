@@ -14,7 +14,7 @@
 // and used directly as VALU operands, with no LDS traffic and no per-lane address math.
 // The W partial sums of a workgroup are combined in LDS in wave order; when the grid is
 // split along y (S > 1, used when the targets alone cannot fill 256 CUs), each split
-// writes its partial sums to a workspace and lm_finish_kernel adds them in split order.
+// writes its partial sums to a workspace and lm_finish_kernel adds them in a fixed order.
 // Every sum therefore has a fixed order: results are bitwise reproducible run to run.
 //
 // Epilogues.  The thread that owns target i after the reduction also performs the
@@ -352,25 +352,56 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
     epilogue<T, DIM, FORCE>(a.epi, a.nt, i, v, f);
 }
 
-// Adds the S split partials of each target in split order, then runs the epilogue.
+// Adds the partial sums of each target in a fixed order, then runs the epilogue.  A stage
+// has only N threads' worth of targets, too few to hide memory latency one thread per target
+// (one workgroup per CU at N = 65536), so a workgroup takes 64 targets and its four waves
+// split the slots: wave w adds slots w, w + 4, w + 8, ... in increasing order, four loads in
+// flight per value, and wave 0 adds the four wave sums in wave order.
 template <class T, int DIM, bool FORCE>
 __global__ __launch_bounds__(256) void lm_finish_kernel(const double* __restrict__ part, int nsplit,
                                                         int64_t nt, EpiArgs<T> e)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nt) return;
+    constexpr int NV = FORCE ? 2 * DIM : DIM;
+    __shared__ double red[3][NV][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = i < nt;
+    const int64_t slot = (int64_t)(2 * DIM) * nt;
+    double acc[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+    if (live) {
+        const double* ps = part + i;
+        int s = wave;
+        for (; s + 12 < nsplit; s += 16) {
+            double x[4][NV];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) x[u][c] = ps[(s + 4 * u) * slot + c * nt];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) acc[c] += x[u][c];
+        }
+        for (; s < nsplit; s += 4)
+#pragma unroll
+            for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) red[wave - 1][c][lane] = acc[c];
+    __syncthreads();
+    if (wave != 0 || !live) return;
     double v[DIM], f[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        v[c] = part[c * nt + i];
-        f[c] = part[(DIM + c) * nt + i];
-    }
-    for (int s = 1; s < nsplit; ++s) {
-        const double* ps = part + (int64_t)s * (2 * DIM) * nt;
+        v[c] = acc[c];
+        f[c] = FORCE ? acc[DIM + c] : 0.0;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            v[c] += ps[c * nt + i];
-            f[c] += ps[(DIM + c) * nt + i];
+        for (int w = 0; w < 3; ++w) {
+            v[c] += red[w][c][lane];
+            if (FORCE) f[c] += red[w][DIM + c][lane];
         }
     }
     epilogue<T, DIM, FORCE>(e, nt, i, v, f);
@@ -798,7 +829,7 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
         err = hipGetLastError();
     }
     if (err != hipSuccess || pl.nsplit == 1) return err;
-    hipLaunchKernelGGL((lm_finish_kernel<T, DIM, FORCE>), dim3(blocks_for(a.nt, 256, 1u << 30)), dim3(256), 0, st,
+    hipLaunchKernelGGL((lm_finish_kernel<T, DIM, FORCE>), dim3(blocks_for(a.nt, 64, 1u << 30)), dim3(256), 0, st,
                        (const double*)a.part, pl.nsplit, a.nt, a.epi);
     return hipGetLastError();
 }

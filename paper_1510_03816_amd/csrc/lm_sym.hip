@@ -31,7 +31,7 @@
 // Partial sums.  A point of superblock Z receives one partial from each superblock pair that
 // contains Z: from (Z, Y), Y > Z, as a row (slot Y); from (Y, Z), Y < Z, as a column (slot Y);
 // from (Z, Z) both (row: slot Z, column: slot S).  Every one of the S + 1 slots of a point is
-// written exactly once per launch, and lm_finish_kernel adds them in slot order, so the
+// written exactly once per launch, and lm_finish_kernel adds them in a fixed order, so the
 // result is bitwise reproducible.  The force constant is applied when a partial is written.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
