@@ -11,7 +11,8 @@
 // sources j split into contiguous chunks per (wave, grid-y), source data wave-uniform (scalar
 // loads of q_j, p_j, a_j, b_j into SGPR operands, from an interleaved copy written by
 // lm_vjp_pack_kernel), wave partials combined in LDS in wave order, grid-y splits by
-// lm_vjp_finish_kernel in split order.  FP64 only.
+// lm_vjp_finish_kernel in a fixed order.  FP64 only.  From the size where the forward sums
+// use the symmetric kernel, the VJP does too (lm_sym_vjp.hip: each unordered pair once).
 //
 // Adjoint of one RK4 step y' = y + dt/6 (k1 + 2k2 + 2k3 + k4), k_s = f(Y_s), given the
 // cotangent abar of y' (stages visited 4, 3, 2, 1):
@@ -205,24 +206,54 @@ __global__ __launch_bounds__(kTileA * kWavesA) void lm_vjp_kernel(VjpArgs A)
     adj_epilogue<DIM>(A.epi, n, k, gq, gp);
 }
 
+// Adds the partial sums of each target in a fixed order (as lm_finish_kernel: four waves per
+// 64 targets, wave w taking slots w, w + 4, ..., the wave sums added in wave order), then
+// runs the adjoint epilogue.
 template <int DIM>
 __global__ __launch_bounds__(256) void lm_vjp_finish_kernel(const double* __restrict__ part, int nsplit, int64_t n,
                                                             AdjEpi e)
 {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    constexpr int NV = 2 * DIM;
+    __shared__ double red[3][NV][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = k < n;
+    const int64_t slot = (int64_t)NV * n;
+    double acc[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+    if (live) {
+        const double* ps = part + k;
+        int s = wave;
+        for (; s + 12 < nsplit; s += 16) {
+            double x[4][NV];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) x[u][c] = ps[(s + 4 * u) * slot + c * n];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) acc[c] += x[u][c];
+        }
+        for (; s < nsplit; s += 4)
+#pragma unroll
+            for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * n];
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) red[wave - 1][c][lane] = acc[c];
+    __syncthreads();
+    if (wave != 0 || !live) return;
     double gq[DIM], gp[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        gq[c] = part[c * n + k];
-        gp[c] = part[(DIM + c) * n + k];
-    }
-    for (int s = 1; s < nsplit; ++s) {
-        const double* ps = part + (int64_t)s * (2 * DIM) * n;
+        gq[c] = acc[c];
+        gp[c] = acc[DIM + c];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            gq[c] += ps[c * n + k];
-            gp[c] += ps[(DIM + c) * n + k];
+        for (int w = 0; w < 3; ++w) {
+            gq[c] += red[w][c][lane];
+            gp[c] += red[w][DIM + c][lane];
         }
     }
     adj_epilogue<DIM>(e, n, k, gq, gp);
@@ -256,14 +287,19 @@ __global__ __launch_bounds__(256) void lm_vjp_pack_kernel(const double* __restri
 template <int DIM, int KER>
 static hipError_t launch_vjp_t(const VjpArgs& a, const PairPlan& pl, hipStream_t st)
 {
-    const int64_t pg = (a.n + 255) / 256;
-    hipLaunchKernelGGL((lm_vjp_pack_kernel<DIM>), dim3((unsigned)(pg < 65536 ? pg : 65536)), dim3(256), 0, st, a.q, a.p,
-                       a.a, a.b, a.n, a.pack);
-    hipLaunchKernelGGL((lm_vjp_kernel<DIM, KER>), dim3((unsigned)pl.itiles, (unsigned)pl.nsplit), dim3(kTileA * kWavesA),
-                       0, st, a);
-    hipError_t err = hipGetLastError();
+    hipError_t err;
+    if (pl.sym_waves > 0) {
+        err = launch_sym_vjp(DIM, KER, a, pl.sym_waves, pl.sym_nsb, st);
+    } else {
+        const int64_t pg = (a.n + 255) / 256;
+        hipLaunchKernelGGL((lm_vjp_pack_kernel<DIM>), dim3((unsigned)(pg < 65536 ? pg : 65536)), dim3(256), 0, st, a.q,
+                           a.p, a.a, a.b, a.n, a.pack);
+        hipLaunchKernelGGL((lm_vjp_kernel<DIM, KER>), dim3((unsigned)pl.itiles, (unsigned)pl.nsplit),
+                           dim3(kTileA * kWavesA), 0, st, a);
+        err = hipGetLastError();
+    }
     if (err != hipSuccess || pl.nsplit == 1) return err;
-    const unsigned g = (unsigned)((a.n + 255) / 256);
+    const unsigned g = (unsigned)((a.n + 63) / 64);
     hipLaunchKernelGGL((lm_vjp_finish_kernel<DIM>), dim3(g), dim3(256), 0, st, (const double*)a.part, pl.nsplit, a.n,
                        a.epi);
     return hipGetLastError();

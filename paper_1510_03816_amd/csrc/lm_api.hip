@@ -97,7 +97,7 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
                     const Cut& cut = Cut())
 {
     const bool sym_ok = qs == qt && ps == pt && ns == nt;
-    lm::PairPlan pl = lm::plan_pair(nt, ns, cut.box_s != nullptr, sym_ok, sizeof(T) == 4);
+    lm::PairPlan pl = lm::plan_pair(nt, ns, cut.box_s != nullptr, sym_ok, sizeof(T) == 4 ? lm::SYM_F32 : lm::SYM_F64);
     lm::PairArgs<T> a{};
     a.qs = qs;
     a.ps = ps;
@@ -123,14 +123,21 @@ int64_t part_elems(const lm_params* prm, int64_t nt, int64_t ns)
     int64_t slots = pl.nsplit > 1 ? pl.nsplit : 0;
     if (nt == ns) {
         // the symmetric kernel's slots under any setting of LM_SYM (forced or by size)
-        const lm::SymPlan sp = lm::plan_sym(nt, true, prm->dtype == LM_F32);
+        const lm::SymPlan sp = lm::plan_sym(nt, true, prm->dtype == LM_F32 ? lm::SYM_F32 : lm::SYM_F64);
         if (sp.waves > 0 && sp.nsb + 1 > slots) slots = sp.nsb + 1;
     }
     return slots > 0 ? slots * 2 * prm->dim * nt : 1;
 }
 
-// Workspace of a VJP evaluation: the interleaved source copy, then the split partial sums.
-int64_t vjp_part_elems(const lm_params* prm, int64_t n) { return 4 * (int64_t)prm->dim * n + part_elems(prm, n, n); }
+// Workspace of a VJP evaluation: the interleaved source copy, then the partial sums of either
+// VJP kernel (and of the forward sums, which share the buffer in the adjoint).
+int64_t vjp_part_elems(const lm_params* prm, int64_t n)
+{
+    int64_t m = part_elems(prm, n, n);
+    const lm::SymPlan sp = lm::plan_sym(n, true, lm::SYM_VJP);
+    if (sp.waves > 0 && (sp.nsb + 1) * 2 * prm->dim * n > m) m = (sp.nsb + 1) * 2 * prm->dim * n;
+    return 4 * (int64_t)prm->dim * n + m;
+}
 
 // RK4 shoot of (q, p) in place over [0, t1] with `steps` steps.  a*, b*: stage buffers, c*:
 // the RK4 running sum (dim*n T each); part: the split workspace.  box (non-null in cutoff
@@ -609,7 +616,7 @@ lm_status feedback_update(const lm_params* prm, const lm_match_opts* o, int64_t 
 lm_status vjp_eval(const lm_params* prm, int64_t n, const double* q, const double* p, const double* a,
                    const double* b, const lm::AdjEpi& e, double* part, hipStream_t st)
 {
-    lm::PairPlan pl = lm::plan_pair(n, n, false);
+    lm::PairPlan pl = lm::plan_pair(n, n, false, true, lm::SYM_VJP);
     lm::VjpArgs A{};
     A.q = q;
     A.p = p;
@@ -1026,7 +1033,7 @@ lm_status lm_pair_plan(const lm_params* prm, int64_t n, lm_plan_info* info)
     LM_TRY(check_n(n));
     if (!info) return fail(LM_EINVAL, "NULL info");
     const bool cut = prm->cutoff > 0.0;
-    const lm::PairPlan pl = lm::plan_pair(n, n, cut, true, prm->dtype == LM_F32);
+    const lm::PairPlan pl = lm::plan_pair(n, n, cut, true, prm->dtype == LM_F32 ? lm::SYM_F32 : lm::SYM_F64);
     info->symmetric = pl.sym_waves > 0;
     info->waves = pl.sym_waves > 0 ? pl.sym_waves : lm::kWaves;
     info->workgroups = pl.sym_waves > 0 ? pl.sym_nsb * (pl.sym_nsb + 1) / 2 : pl.itiles * pl.nsplit;

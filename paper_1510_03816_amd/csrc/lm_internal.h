@@ -163,7 +163,11 @@ struct PairPlan {
 // sym_ok: the targets are the sources (one point set, every pair, double precision), so the
 // symmetric kernel may be chosen.  The environment variable LM_SYM overrides the size rule:
 // "0" never, "1" always (for tests of small sizes).
-PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok = false, bool f32 = false);
+// What a symmetric launch computes (its size rule differs): double- or single-precision sums,
+// or their vector-Jacobian product (double).
+enum SymKind : int { SYM_F64 = 0, SYM_F32 = 1, SYM_VJP = 2 };
+
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok = false, int kind = SYM_F64);
 
 // Symmetric pair sums of one point set (lm_sym.hip).
 template <class T>
@@ -210,10 +214,14 @@ constexpr int64_t kSymWideTiles = 768;
 #define LM_SYM_MIN_TILES_F32 (int64_t(1) << 40)
 #endif
 constexpr int64_t kSymMinTilesF32 = LM_SYM_MIN_TILES_F32;
-constexpr int64_t kSymWideTilesF32 = 768;
+// The VJP (heavier pairs, 154-162 VGPRs) gains from 128 tiles on: at N = 8192 one wave per
+// workgroup 136 us against 158 one-sided, at 16384 two waves 415 against 545, at 65536 two
+// waves 6436 against 9632 (four: 6594).
+constexpr int64_t kSymVjpMinTiles = 128;
+constexpr int64_t kSymVjpTwoWaveTiles = 192;
 constexpr int64_t kSymMaxPartBytes = (int64_t)16 << 30;
 
-SymPlan plan_sym(int64_t n, bool force, bool f32);
+SymPlan plan_sym(int64_t n, bool force, int kind);
 template <class T>
 hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs<T>& a, int waves, hipStream_t st);
 
@@ -224,6 +232,9 @@ hipError_t launch_pair(int dim, int kernel, bool force, const PairArgs<T>& a, co
 int reduce_blocks(int64_t m);
 
 hipError_t launch_vjp(int dim, int kernel, const VjpArgs& a, const PairPlan& pl, hipStream_t st);
+// The symmetric form (lm_sym_vjp.hip): partial sums in (nsb + 1) slots of a.part, without the
+// epilogue (launch_vjp adds them).
+hipError_t launch_sym_vjp(int dim, int kernel, const VjpArgs& a, int waves, int64_t nsb, hipStream_t st);
 hipError_t launch_scale(double* y, double alpha, const double* x, int64_t m, hipStream_t st);
 
 template <class TA, class TB>

@@ -768,7 +768,7 @@ static inline unsigned blocks_for(int64_t m, int threads, unsigned cap = 8192)
     return (unsigned)(b < (int64_t)cap ? b : cap);
 }
 
-PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, bool f32)
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, int kind)
 {
     PairPlan pl{};
     pl.itiles = (nt + kTile - 1) / kTile;
@@ -776,7 +776,7 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, bool f32)
         const char* e = getenv("LM_SYM");
         const int mode = e ? atoi(e) : -1;
         if (mode != 0) {
-            const SymPlan sp = plan_sym(nt, mode == 1, f32);
+            const SymPlan sp = plan_sym(nt, mode == 1, kind);
             if (sp.waves > 0) {
                 pl.sym_waves = sp.waves;
                 pl.sym_nsb = sp.nsb;

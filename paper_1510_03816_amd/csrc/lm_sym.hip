@@ -39,13 +39,11 @@
 
 #include "lm_internal.h"
 #include "lm_math.h"
+#include "lm_sym.h"
 
 namespace lm {
 
 namespace {
-
-constexpr int kSymSteps = 64;     // column points per tile
-constexpr int kSymUnroll = 8;     // steps per unrolled loop body
 
 // Values per staged column point: q and p, padded by one so that the 64 lanes' reads of
 // consecutive entries (an odd stride) fall in distinct LDS banks.
@@ -174,16 +172,6 @@ __device__ __forceinline__ void sym_stage(T* __restrict__ jbuf, const T* __restr
     }
 }
 
-enum SymMode : int { SYM_SKIP = 0, SYM_ONE = 1, SYM_BOTH = 2 };
-
-// What row tile I does with column tile J in superblock pair (X, Y).
-__device__ __forceinline__ int sym_mode(bool diag, int64_t I, int64_t J, int64_t T)
-{
-    if (I >= T) return SYM_SKIP;
-    if (!diag || I < J) return SYM_BOTH;
-    return I == J ? SYM_ONE : SYM_SKIP;
-}
-
 // The row tiles of this wave against column tile J (staged at jb), sums added to (v, f): both
 // rows symmetrically in one pass when they allow it, else row by row by mode.
 template <class T, int DIM, int KER, bool FORCE, class A>
@@ -235,21 +223,9 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
     double* region = lds_words;                                // [nw][EC][128]
     T* jbuf = reinterpret_cast<T*>(region + nw * EC * 128);    // [128][E]
 
-    // superblock pair: off-diagonal pairs (X < Y) first, numbered Y(Y-1)/2 + X, then the
-    // diagonal ones, which carry half the work
     const int64_t S = a.nsb;
-    const int64_t noff = S * (S - 1) / 2;
-    const int64_t b = blockIdx.x;
     int64_t X, Y;
-    if (b < noff) {
-        int64_t y = (int64_t)(0.5 * (1.0 + __builtin_sqrt(1.0 + 8.0 * (double)b)));
-        while (y * (y - 1) / 2 > b) --y;
-        while ((y + 1) * y / 2 <= b) ++y;
-        Y = y;
-        X = b - y * (y - 1) / 2;
-    } else {
-        X = Y = b - noff;
-    }
+    sym_superblocks(blockIdx.x, S, X, Y);
     const bool diag = X == Y;
     const int64_t n = a.n, NT = a.tiles;
     const T kq = (T)a.kq;
@@ -348,7 +324,7 @@ hipError_t launch_sym_t(const SymArgs<T>& a, int waves, hipStream_t st)
 
 }  // namespace
 
-SymPlan plan_sym(int64_t n, bool force, bool f32)
+SymPlan plan_sym(int64_t n, bool force, int kind)
 {
     SymPlan sp{};
     const int64_t T = tiles_of(n);
@@ -358,13 +334,14 @@ SymPlan plan_sym(int64_t n, bool force, bool f32)
     int w = 0;
     if (fixed == 1 || fixed == 2 || fixed == 4 || fixed == 8) {
         w = fixed;
-    } else if (T >= (f32 ? kSymWideTilesF32 : kSymWideTiles) && T >= (f32 ? kSymMinTilesF32 : kSymMinTiles)) {
+    } else if (kind == SYM_VJP) {
+        w = T >= kSymVjpTwoWaveTiles ? 2 : T >= kSymVjpMinTiles ? 1 : 0;
+    } else if (kind == SYM_F64 && T >= kSymWideTiles) {
         w = 4;
-    } else if (T >= (f32 ? kSymMinTilesF32 : kSymMinTiles)) {
+    } else if (T >= (kind == SYM_F32 ? kSymMinTilesF32 : kSymMinTiles)) {
         w = 2;
-    } else if (force) {
-        w = 1;
     }
+    if (w == 0 && force) w = 1;
     if (w == 0) return sp;
     // partial sums: (S + 1) slots of up to 6 doubles per point; wider superblocks need
     // fewer, and beyond the cap the one-sided kernel (at most 64 slots) is used instead

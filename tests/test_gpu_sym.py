@@ -166,3 +166,65 @@ def test_sym_cg_ksolve_matches_cholesky():
         it = lm.lm_ksolve(prm, dev(X), dev(b), x, rtol=1e-13, solver=lm.SOLVE_CG)
     print("%d CG iterations, rel err %.2e" % (it, rel_err(host(x), want)))
     assert rel_err(host(x), want) <= 1e-8
+
+
+# ------------------------------------------------------------------ reverse mode
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("n", [1, 65, 700, 3007])
+def test_sym_vjp_matches_oracle(n, dim, kernel, waves):
+    q, p = inputs.random_state(n, dim, seed=[115, n, dim], pscale=0.3)
+    rng = np.random.default_rng([116, n])
+    a, b = rng.standard_normal(q.shape), rng.standard_normal(q.shape)
+    q[:, n // 2] = q[:, 0]                 # a coincident pair (for n > 2)
+    prm = lm.make_params(dim, kernel, 0.3, tau=0.2)
+    aq, ap = torch.empty((dim, n), dtype=torch.float64, device=DEV), torch.empty((dim, n), dtype=torch.float64, device=DEV)
+    print("sym vjp n=%d dim=%d kernel=%d waves=%d" % (n, dim, kernel, waves), flush=True)
+    with _env(LM_SYM=1, LM_SYM_WAVES=waves):
+        lm.lm_rhs_vjp(prm, dev(q), dev(p), dev(a), dev(b), aq, ap)
+        torch.cuda.synchronize()
+    oq, op = oracle.rhs_vjp(q, p, a, b, kernel, 0.3, 0.2)
+    eq, ep = rel_err(host(aq), oq), rel_err(host(ap), op)
+    print("  %.2e %.2e" % (eq, ep))
+    assert eq <= 1e-10 and ep <= 1e-10
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_sym_vjp_agrees_with_one_sided_kernel(kernel):
+    q, p = inputs.random_state(6000, 3, seed=117, pscale=0.3)
+    rng = np.random.default_rng(118)
+    a, b = rng.standard_normal(q.shape), rng.standard_normal(q.shape)
+    prm = lm.make_params(3, kernel, 0.2)
+    out = []
+    for env in ({"LM_SYM": 0}, {"LM_SYM": 1, "LM_SYM_WAVES": 4}):
+        aq, ap = torch.empty((3, 6000), dtype=torch.float64, device=DEV), torch.empty((3, 6000), dtype=torch.float64, device=DEV)
+        with _env(**env):
+            lm.lm_rhs_vjp(prm, dev(q), dev(p), dev(a), dev(b), aq, ap)
+            torch.cuda.synchronize()
+        out.append((host(aq), host(ap)))
+    assert rel_err(out[1][0], out[0][0]) <= 1e-13 and rel_err(out[1][1], out[0][1]) <= 1e-13
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_sym_shoot_adjoint_and_energy_gradient_match_oracle(kernel):
+    """Forward stages and VJP stages both symmetric (forced), through the checkpointed adjoint."""
+    pr = inputs.config_sphere3d(500, kernel=kernel, sigma=0.2)
+    q0, p0 = pr.X, 0.3 * pr.p_bench()
+    rng = np.random.default_rng(119)
+    gq1, gp1 = rng.standard_normal(q0.shape), rng.standard_normal(q0.shape)
+    oq, op = oracle.shoot_adjoint(q0, p0, gq1, gp1, kernel, pr.sigma, 10, T=0.8, tau=0.1)
+    E_o, g_o = oracle.energy_and_grad(pr.X, pr.Y, p0, kernel, pr.sigma, 100.0, 10)
+    with _env(LM_SYM=1, LM_SYM_WAVES=2):
+        prm = lm.make_params(3, kernel, pr.sigma, tau=0.1)
+        gq0, gp0 = torch.empty((3, 500), dtype=torch.float64, device=DEV), torch.empty((3, 500), dtype=torch.float64, device=DEV)
+        lm.lm_shoot_adjoint(prm, dev(q0), dev(p0), 0.8, 10, 3, dev(gq1), dev(gp1), gq0, gp0)
+        prm0 = lm.make_params(3, kernel, pr.sigma)
+        g = torch.empty((3, 500), dtype=torch.float64, device=DEV)
+        E = lm.lm_energy_grad(prm0, dev(pr.X), dev(pr.Y), dev(p0), 100.0, 10, g, ckpt_every=3)
+        torch.cuda.synchronize()
+    assert rel_err(host(gq0), oq) <= 1e-10 and rel_err(host(gp0), op) <= 1e-10
+    assert E == pytest.approx(E_o, rel=1e-11)
+    assert rel_err(host(g), g_o) <= 1e-10
