@@ -301,6 +301,11 @@ typedef struct lm_batch_tuning {
                                              0 = one wave per work item */
     int32_t graph_steps;                  /* RK4 steps per captured hipGraph in a shoot;
                                              0 = every kernel launched directly */
+    int32_t sym_min;                      /* double precision: problems of at least sym_min
+                                             points evaluate each unordered pair once (the
+                                             symmetric kernel, one superblock pair per
+                                             workgroup); 0 = never */
+    int32_t sym_waves;                    /* its wavefronts per workgroup: 1, 2, 4 or 8 */
     double stage_us;                      /* written by lm_batch_autotune: measured time of
                                              one stage with this shape (microseconds) */
 } lm_batch_tuning;
@@ -311,7 +316,8 @@ lm_status lm_batch_default_tuning(int32_t B, const int64_t *offs, lm_batch_tunin
 /* Autotuner: times candidate launch shapes on this batch (right-hand-side evaluations at
  * (q, p), dim x ntot device arrays of params->dtype, and short graph-replayed shoots) with
  * HIP events, one parameter at a time from the default (grid size, then each occupied
- * bucket's source split, then the steps per graph), and writes the fastest to *out.
+ * bucket's source split, then in double precision the symmetric threshold and width, then the
+ * steps per graph), and writes the fastest to *out.
  * Synchronous; q and p are not modified. */
 lm_status lm_batch_autotune(const lm_params *params, int32_t B, const int64_t *offs,
                             const void *q, const void *p, lm_batch_tuning *out, void *stream);

@@ -80,11 +80,13 @@ class lm_lbfgs_info(ctypes.Structure):
 
 class lm_batch_tuning(ctypes.Structure):
     _fields_ = [("bucket_max", ctypes.c_int64 * BATCH_BUCKETS), ("split", ctypes.c_int32 * BATCH_BUCKETS),
-                ("groups", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("stage_us", ctypes.c_double)]
+                ("groups", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("sym_min", ctypes.c_int32),
+                ("sym_waves", ctypes.c_int32), ("stage_us", ctypes.c_double)]
 
     def as_dict(self):
         return {"bucket_max": list(self.bucket_max), "split": list(self.split), "groups": self.groups,
-                "graph_steps": self.graph_steps, "stage_us": self.stage_us}
+                "graph_steps": self.graph_steps, "sym_min": self.sym_min, "sym_waves": self.sym_waves,
+                "stage_us": self.stage_us}
 
 
 _lib = None

@@ -22,6 +22,10 @@
 
 namespace {
 
+// Default size from which a batch's double-precision problems use the symmetric kernel (the
+// autotuner's choice on the 256-curve workload: 256, two waves per workgroup).
+constexpr int32_t kDefaultSymMin = 256;
+
 using namespace lmh;
 
 lm_status check_offs(int32_t B, const int64_t* offs, int64_t* ntot, int64_t* nmax)
@@ -54,6 +58,9 @@ lm_status check_tuning(const lm_batch_tuning* t, int64_t nmax)
                     LM_BATCH_BUCKETS - 1, (long long)t->bucket_max[LM_BATCH_BUCKETS - 1], (long long)nmax);
     if (t->groups < 0 || t->groups > (1 << 20)) return fail(LM_EINVAL, "tuning groups must be in 0..2^20");
     if (t->graph_steps < 0) return fail(LM_EINVAL, "tuning graph_steps must be >= 0");
+    if (t->sym_min < 0) return fail(LM_EINVAL, "tuning sym_min must be >= 0");
+    if (t->sym_waves != 1 && t->sym_waves != 2 && t->sym_waves != 4 && t->sym_waves != 8)
+        return fail(LM_EINVAL, "tuning sym_waves must be 1, 2, 4 or 8");
     return LM_OK;
 }
 
@@ -68,6 +75,8 @@ void default_tuning(lm_batch_tuning* t, int64_t nmax)
     t->bucket_max[LM_BATCH_BUCKETS - 1] = std::max<int64_t>(nmax, 2049);
     t->groups = 0;
     t->graph_steps = 10;
+    t->sym_min = kDefaultSymMin;
+    t->sym_waves = 2;
     t->stage_us = 0.0;
 }
 
@@ -80,6 +89,9 @@ int bucket_of(const lm_batch_tuning& t, int64_t nb)
 
 // Work list of a batch for one launch shape, on the device.
 struct BatchPlan {
+    int4* sym_items_d = nullptr;   // symmetric problems' superblock pairs, largest first
+    int32_t nsym = 0;
+    int sym_waves = 1;
     int32_t B = 0;
     int64_t ntot = 0;
     int dim = 0;
@@ -96,19 +108,34 @@ struct BatchPlan {
 // Builds the work list on the host and uploads it (the host vectors are copied before this
 // returns: the copies are synchronous with respect to the host).
 lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs_d, const lm_batch_tuning& t,
-                    Workspace& ws, BatchPlan* pl, hipStream_t st, const std::vector<int>* include = nullptr)
+                    Workspace& ws, BatchPlan* pl, hipStream_t st, bool f64, const std::vector<int>* include = nullptr)
 {
     struct Item {
         int4 w;
         int64_t cost;
     };
-    std::vector<Item> items;
+    std::vector<Item> items, sym;
     std::vector<int4> fin;
     std::vector<int64_t> part_off((size_t)B, -1);
     int64_t part_elems = 0;
+    const int64_t side = (int64_t)lm::kSymRows * t.sym_waves;   // tiles per superblock
     for (int32_t b = 0; b < B; ++b) {
         if (include && !(*include)[b]) continue;
         const int64_t nb = offs[b + 1] - offs[b];
+        if (f64 && t.sym_min > 0 && nb >= t.sym_min) {
+            // symmetric: one item per superblock pair (X <= Y), S + 1 partial-sum slots
+            const int64_t nt = (nb + 63) / 64;
+            const int64_t S = (nt + side - 1) / side;
+            part_off[b] = part_elems;
+            part_elems += (S + 1) * 2 * dim * nb;
+            for (int64_t Y = 0; Y < S; ++Y)
+                for (int64_t X = 0; X <= Y; ++X) {
+                    const int64_t rows = std::min(side, nt - X * side), cols = std::min(side, nt - Y * side);
+                    sym.push_back({make_int4(b, (int)X, (int)Y, (int)S), X == Y ? rows * (rows + 1) / 2 : rows * cols});
+                }
+            for (int64_t t0 = 0; t0 < nb; t0 += 64) fin.push_back(make_int4(b, (int)t0, (int)(S + 1), 0));
+            continue;
+        }
         const int32_t S = (int32_t)std::min<int64_t>(t.split[bucket_of(t, nb)], nb);
         const int64_t chunk = (nb + S - 1) / S;
         if (S > 1) {
@@ -124,9 +151,17 @@ lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs
         }
     }
     if (items.size() > (size_t)INT32_MAX) return fail(LM_EINVAL, "batch has too many work items");
+    if (sym.size() > (size_t)INT32_MAX) return fail(LM_EINVAL, "batch has too many symmetric work items");
     std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
-    std::vector<int4> w(items.size());
+    std::stable_sort(sym.begin(), sym.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    std::vector<int4> w(items.size()), ws_sym(sym.size());
     for (size_t k = 0; k < items.size(); ++k) w[k] = items[k].w;
+    for (size_t k = 0; k < sym.size(); ++k) ws_sym[k] = sym[k].w;
+    pl->nsym = (int32_t)ws_sym.size();
+    pl->sym_waves = t.sym_waves;
+    LM_TRY(ws.get(&pl->sym_items_d, std::max<int32_t>(pl->nsym, 1)));
+    if (pl->nsym > 0)
+        LM_HIP(hipMemcpyAsync(pl->sym_items_d, ws_sym.data(), ws_sym.size() * sizeof(int4), hipMemcpyHostToDevice, st));
 
     pl->B = B;
     pl->ntot = offs[B];
@@ -136,7 +171,7 @@ lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs
     pl->nfin = (int32_t)fin.size();
     const int32_t natural = (pl->nitems + lm::kWaves - 1) / lm::kWaves;
     pl->groups = t.groups > 0 ? std::min(t.groups, natural) : natural;
-    LM_TRY(ws.get(&pl->items_d, pl->nitems));
+    LM_TRY(ws.get(&pl->items_d, std::max<int32_t>(pl->nitems, 1)));
     LM_TRY(ws.get(&pl->fin_d, std::max<int32_t>(pl->nfin, 1)));
     LM_TRY(ws.get(&pl->part_off_d, B));
     LM_TRY(ws.get(&pl->part, std::max<int64_t>(part_elems, 1)));
@@ -172,6 +207,9 @@ lm_status batch_eval(const lm_params* prm, const BatchPlan& pl, const T* q, cons
     a.nitems = pl.nitems;
     a.part_off = pl.part_off_d;
     a.part = pl.part;
+    a.sym_items = pl.sym_items_d;
+    a.nsym = pl.nsym;
+    a.sym_waves = pl.sym_waves;
     kernel_scales(prm, sizeof(T) == 4, &a.kq, &a.wscale);
     a.epi = e;
     LM_HIP(lm::launch_batch_pair<T>(prm->dim, prm->kernel, true, a, pl.fin_d, pl.nfin, pl.groups, st));
@@ -351,7 +389,7 @@ lm_status shoot_batched_t(const lm_params* prm, int32_t B, const int64_t* offs, 
     int64_t* offs_d;
     LM_TRY(upload_offs(B, offs, ws, &offs_d, st));
     BatchPlan pl;
-    LM_TRY(make_plan(prm->dim, B, offs, offs_d, tun, ws, &pl, st));
+    LM_TRY(make_plan(prm->dim, B, offs, offs_d, tun, ws, &pl, st, sizeof(T) == 8));
     const int64_t m = (int64_t)prm->dim * pl.ntot;
     if (q1 != q0) LM_HIP(hipMemcpyAsync(q1, q0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
     if (p1 != p0) LM_HIP(hipMemcpyAsync(p1, p0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
@@ -428,7 +466,7 @@ lm_status autotune_t(const lm_params* prm, int32_t B, const int64_t* offs, const
     auto stage_time = [&](const lm_batch_tuning& t, double* ms) -> lm_status {
         Workspace pws(st);
         BatchPlan pl;
-        LM_TRY(make_plan(prm->dim, B, offs, offs_d, t, pws, &pl, st));
+        LM_TRY(make_plan(prm->dim, B, offs, offs_d, t, pws, &pl, st, sizeof(T) == 8));
         return time_ms([&]() { return batch_rhs<T>(prm, pl, q, p, dq, dp, st); }, 5, st, ms);
     };
     double cur;
@@ -450,6 +488,31 @@ lm_status autotune_t(const lm_params* prm, int32_t B, const int64_t* offs, const
         if (ms < cur) {
             cur = ms;
             *best = t;
+        }
+    }
+    // double precision: the size from which problems go symmetric (0 = none), then its width
+    if (sizeof(T) == 8) {
+        for (int sm : {0, 512, 1024, 2048, 4096}) {   // the default, 256, is the starting point
+            lm_batch_tuning t = *best;
+            t.sym_min = sm;
+            double ms;
+            LM_TRY(stage_time(t, &ms));
+            if (ms < cur) {
+                cur = ms;
+                *best = t;
+            }
+        }
+        if (best->sym_min > 0) {
+            for (int sw : {1, 4}) {
+                lm_batch_tuning t = *best;
+                t.sym_waves = sw;
+                double ms;
+                LM_TRY(stage_time(t, &ms));
+                if (ms < cur) {
+                    cur = ms;
+                    *best = t;
+                }
+            }
         }
     }
     // source splits of each occupied bucket, largest problems first
@@ -474,7 +537,7 @@ lm_status autotune_t(const lm_params* prm, int32_t B, const int64_t* offs, const
     {
         Workspace pws(st);
         BatchPlan pl;
-        LM_TRY(make_plan(prm->dim, B, offs, offs_d, *best, pws, &pl, st));
+        LM_TRY(make_plan(prm->dim, B, offs, offs_d, *best, pws, &pl, st, sizeof(T) == 8));
         double bt = 0.0;
         int bg = 0;
         for (int gs : {0, 1, 5, 20}) {
@@ -620,13 +683,13 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         if (any64 && want64 != in64) {
             g64.reset();
             pws64.reset(new Workspace(st));
-            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws64, &pl64, st, &want64));
+            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws64, &pl64, st, true, &want64));
             in64 = want64;
         }
         if (any32 && want32 != in32) {
             g32.reset();
             pws32.reset(new Workspace(st));
-            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws32, &pl32, st, &want32));
+            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws32, &pl32, st, false, &want32));
             in32 = want32;
         }
 
@@ -724,7 +787,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
     {
         Workspace hws(st);
         BatchPlan pl;
-        LM_TRY(make_plan(dim, B, offs, offs_d, tun, hws, &pl, st));
+        LM_TRY(make_plan(dim, B, offs, offs_d, tun, hws, &pl, st, true));
         lm::EpiArgs<double> ev{};
         ev.kind = lm::EPI_STORE;
         ev.tau = prm->tau;
@@ -801,7 +864,7 @@ lm_status lm_rhs_batched(const lm_params* prm, int32_t B, const int64_t* offs, c
     int64_t* offs_d;
     LM_TRY(upload_offs(B, offs, ws, &offs_d, st));
     BatchPlan pl;
-    LM_TRY(make_plan(prm->dim, B, offs, offs_d, t, ws, &pl, st));
+    LM_TRY(make_plan(prm->dim, B, offs, offs_d, t, ws, &pl, st, prm->dtype == LM_F64));
     if (prm->dtype == LM_F32)
         return batch_rhs<float>(prm, pl, (const float*)q, (const float*)p, (float*)dq, (float*)dp, st);
     return batch_rhs<double>(prm, pl, (const double*)q, (const double*)p, (double*)dq, (double*)dp, st);

@@ -117,11 +117,18 @@ struct BatchArgs {
     double kq;
     double wscale;
     EpiArgs<T> epi;          // over the concatenated arrays (n = ntot)
+    const int4* sym_items;   // symmetric problems: (problem, X, Y, S) superblock pairs, one per
+    int32_t nsym;            //   workgroup of sym_waves waves (lm_batch_sym_kernel)
+    int sym_waves;
 };
 
 template <class T>
 hipError_t launch_batch_pair(int dim, int kernel, bool force, const BatchArgs<T>& a, const int4* fin, int32_t nfin,
                              int groups, hipStream_t st);
+// The symmetric items of a batch (lm_sym.hip); their partial sums are added by the batch's
+// finish launch.
+template <class T>
+hipError_t launch_batch_sym(int dim, int kernel, bool force, const BatchArgs<T>& a, hipStream_t st);
 template <class TX>
 hipError_t launch_batch_maxabsdiff(const TX* x, const double* y, int dim, int64_t ntot, const int64_t* offs, int nprob,
                                    double* out, hipStream_t st);

@@ -1093,13 +1093,20 @@ static hipError_t launch_batch_k(bool force, const BatchArgs<T>& a, const int4* 
                                  hipStream_t st)
 {
     const dim3 blk(kTile * kWaves);
-    if (force)
-        hipLaunchKernelGGL((lm_batch_pair_kernel<T, DIM, KER, true>), dim3(groups), blk, 0, st, a);
-    else
-        hipLaunchKernelGGL((lm_batch_pair_kernel<T, DIM, KER, false>), dim3(groups), blk, 0, st, a);
+    if (a.nitems > 0) {
+        if (force)
+            hipLaunchKernelGGL((lm_batch_pair_kernel<T, DIM, KER, true>), dim3(groups), blk, 0, st, a);
+        else
+            hipLaunchKernelGGL((lm_batch_pair_kernel<T, DIM, KER, false>), dim3(groups), blk, 0, st, a);
+    }
+    if (a.nsym > 0) {
+        const hipError_t err = launch_batch_sym<T>(DIM, KER, force, a, st);
+        if (err != hipSuccess) return err;
+    }
     if (nfin > 0) {
         const int fg = (int)((nfin + kWaves - 1) / kWaves);
-        const int g = fg < groups ? fg : groups;
+        const int cap = groups > 1024 ? groups : 1024;
+        const int g = fg < cap ? fg : cap;
         if (force)
             hipLaunchKernelGGL((lm_batch_finish_kernel<T, DIM, true>), dim3(g), blk, 0, st, a, fin, nfin);
         else

@@ -49,6 +49,8 @@ namespace {
 // consecutive entries (an odd stride) fall in distinct LDS banks.
 __host__ __device__ constexpr int sym_stride(int dim) { return 2 * dim + 1; }
 
+__device__ __forceinline__ int64_t tiles_of_dev(int64_t n) { return (n + kSymSteps - 1) / kSymSteps; }
+
 // Per-precision pieces: FMA, the conon's squared-distance floor (see pair_f64), 1/sqrt and the
 // exponential (in single precision the hardware 2^x, log2 e folded into kq by the caller).
 template <class T>
@@ -159,14 +161,14 @@ __device__ __forceinline__ void sym_block(const T (&qi)[ROWS][DIM], const T (&pi
 // exactly nothing to real points).
 template <class T, int DIM>
 __device__ __forceinline__ void sym_stage(T* __restrict__ jbuf, const T* __restrict__ q, const T* __restrict__ p,
-                                          int64_t n, int64_t J)
+                                          int64_t ld, int64_t n, int64_t J)
 {
     constexpr int E = sym_stride(DIM);
     for (int t = threadIdx.x; t < kSymSteps * 2 * DIM; t += blockDim.x) {
         const int c = t >> 6, l = t & 63;
         const int64_t j = J * kSymSteps + l;
         T x = (T)0;
-        if (j < n) x = (c < DIM) ? q[c * n + j] : p[(c - DIM) * n + j];
+        if (j < n) x = (c < DIM) ? q[c * ld + j] : p[(c - DIM) * ld + j];
         jbuf[l * E + c] = x;
         jbuf[(l + 64) * E + c] = x;
     }
@@ -210,8 +212,13 @@ __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[kSymRows]
     }
 }
 
+// One workgroup's superblock pair (X, Y) of a point set of n points: component c of point i at
+// q[c * ld + i] (ld = n for one problem, the batch's total for a batched one); partial sums in
+// part, (S + 1) slots of 2 dim x n doubles.
 template <class T, int DIM, int KER, bool FORCE>
-__global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs<T> a)
+__device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, const T* __restrict__ p, int64_t ld,
+                                                    int64_t n, int64_t S, int64_t X, int64_t Y, double kqd,
+                                                    double wscale, double* __restrict__ part)
 {
     constexpr int E = sym_stride(DIM);           // staged values per column point
     constexpr int EC = FORCE ? 2 * DIM : DIM;    // column sums per point
@@ -223,12 +230,9 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
     double* region = lds_words;                                // [nw][EC][128]
     T* jbuf = reinterpret_cast<T*>(region + nw * EC * 128);    // [128][E]
 
-    const int64_t S = a.nsb;
-    int64_t X, Y;
-    sym_superblocks(blockIdx.x, S, X, Y);
     const bool diag = X == Y;
-    const int64_t n = a.n, NT = a.tiles;
-    const T kq = (T)a.kq;
+    const int64_t NT = tiles_of_dev(n);
+    const T kq = (T)kqd;
 
     // row points in registers; their sums over one column tile in T, over all tiles in double
     int64_t I[kSymRows];
@@ -241,8 +245,8 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
         const bool live = i < n;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            qi[r][c] = live ? a.q[c * n + i] : (T)0;
-            pi[r][c] = live ? a.p[c * n + i] : (T)0;
+            qi[r][c] = live ? q[c * ld + i] : (T)0;
+            pi[r][c] = live ? p[c * ld + i] : (T)0;
             vs[r][c] = 0.0;
             fs[r][c] = 0.0;
         }
@@ -251,13 +255,13 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
     for (int t = threadIdx.x; t < nw * EC * 128; t += blockDim.x) region[t] = 0.0;
     const int64_t J0 = Y * side;
     const int64_t J1 = (J0 + side < NT) ? (J0 + side) : NT;
-    sym_stage<T, DIM>(jbuf, a.q, a.p, n, J0);
+    sym_stage<T, DIM>(jbuf, q, p, ld, n, J0);
     __syncthreads();
 
     const T* jb = jbuf + lane * E;
     double* acc = region + wave * EC * 128 + lane;
     const int64_t slot_col = diag ? S : X;
-    double* pc = a.part + slot_col * (2 * DIM) * n;
+    double* pc = part + slot_col * (2 * DIM) * n;
     for (int64_t J = J0; J < J1; ++J) {
         if constexpr (sizeof(T) == sizeof(double)) {
             sym_tile<T, DIM, KER, FORCE>(diag, I, J, NT, qi, pi, jb, kq, vs, fs, acc);
@@ -292,13 +296,13 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
                 rg[l + 64] = 0.0;
             }
             const int64_t j = J * kSymSteps + l;
-            if (j < n) pc[c * n + j] = (c < DIM) ? s : s * a.wscale;
+            if (j < n) pc[c * n + j] = (c < DIM) ? s : s * wscale;
         }
-        if (J + 1 < J1) sym_stage<T, DIM>(jbuf, a.q, a.p, n, J + 1);
+        if (J + 1 < J1) sym_stage<T, DIM>(jbuf, q, p, ld, n, J + 1);
         __syncthreads();
     }
 
-    double* pr = a.part + Y * (2 * DIM) * n;
+    double* pr = part + Y * (2 * DIM) * n;
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r) {
         const int64_t i = I[r] * kSymSteps + lane;
@@ -306,9 +310,29 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             pr[c * n + i] = vs[r][c];
-            if (FORCE) pr[(DIM + c) * n + i] = fs[r][c] * a.wscale;
+            if (FORCE) pr[(DIM + c) * n + i] = fs[r][c] * wscale;
         }
     }
+}
+
+template <class T, int DIM, int KER, bool FORCE>
+__global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs<T> a)
+{
+    int64_t X, Y;
+    sym_superblocks(blockIdx.x, a.nsb, X, Y);
+    sym_superblock_pair<T, DIM, KER, FORCE>(a.q, a.p, a.n, a.n, a.nsb, X, Y, a.kq, a.wscale, a.part);
+}
+
+// Batched: workgroup b takes item sym_items[b] = (problem, X, Y, S) of the concatenated
+// (dim, ntot) arrays; the problem's partial sums start at part + part_off[problem].
+template <class T, int DIM, int KER, bool FORCE>
+__global__ __launch_bounds__(512, kSymOccupancy) void lm_batch_sym_kernel(BatchArgs<T> a)
+{
+    const int4 w = a.sym_items[blockIdx.x];
+    const int64_t off = a.offs[w.x];
+    const int64_t nb = a.offs[w.x + 1] - off;
+    sym_superblock_pair<T, DIM, KER, FORCE>(a.q + off, a.p + off, a.ntot, nb, w.w, w.y, w.z, a.kq, a.wscale,
+                                            a.part + a.part_off[w.x]);
 }
 
 template <class T, int DIM, int KER, bool FORCE>
@@ -375,6 +399,37 @@ hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs<T>& a,
 }
 
 template hipError_t launch_sym_pair<double>(int, int, bool, const SymArgs<double>&, int, hipStream_t);
+
+template <class T, int DIM, int KER, bool FORCE>
+static hipError_t launch_batch_sym_t(const BatchArgs<T>& a, hipStream_t st)
+{
+    constexpr int EC = FORCE ? 2 * DIM : DIM;
+    const int waves = a.sym_waves;
+    const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
+    hipLaunchKernelGGL((lm_batch_sym_kernel<T, DIM, KER, FORCE>), dim3((unsigned)a.nsym), dim3(64 * waves), lds, st, a);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_batch_sym(int dim, int kernel, bool force, const BatchArgs<T>& a, hipStream_t st)
+{
+    if (a.nsym == 0) return hipSuccess;
+    if (dim == 2) {
+        if (kernel == LM_KERNEL_CONON)
+            return force ? launch_batch_sym_t<T, 2, LM_KERNEL_CONON, true>(a, st)
+                         : launch_batch_sym_t<T, 2, LM_KERNEL_CONON, false>(a, st);
+        return force ? launch_batch_sym_t<T, 2, LM_KERNEL_GAUSS, true>(a, st)
+                     : launch_batch_sym_t<T, 2, LM_KERNEL_GAUSS, false>(a, st);
+    }
+    if (kernel == LM_KERNEL_CONON)
+        return force ? launch_batch_sym_t<T, 3, LM_KERNEL_CONON, true>(a, st)
+                     : launch_batch_sym_t<T, 3, LM_KERNEL_CONON, false>(a, st);
+    return force ? launch_batch_sym_t<T, 3, LM_KERNEL_GAUSS, true>(a, st)
+                 : launch_batch_sym_t<T, 3, LM_KERNEL_GAUSS, false>(a, st);
+}
+
+template hipError_t launch_batch_sym<double>(int, int, bool, const BatchArgs<double>&, hipStream_t);
+template hipError_t launch_batch_sym<float>(int, int, bool, const BatchArgs<float>&, hipStream_t);
 template hipError_t launch_sym_pair<float>(int, int, bool, const SymArgs<float>&, int, hipStream_t);
 
 }  // namespace lm

@@ -18,6 +18,7 @@ def test_default_tuning_covers_the_256_problem_workload():
     bm = list(t.bucket_max)
     assert bm == sorted(bm) and bm[-1] >= sizes.max()
     assert all(s == 1 for s in t.split) and t.groups >= 0 and t.graph_steps >= 0
+    assert t.sym_min > 0 and t.sym_waves in (1, 2, 4, 8)
 
 
 @pytest.mark.parametrize("offs", [[], [1, 5], [0, 0, 3], [0, 4, 3], [0, 5, 5]])
@@ -54,6 +55,13 @@ def test_bad_tuning_rejected_before_any_launch():
     t = _lib.lm_batch_default_tuning(offs)
     t.groups = -1
     assert _rhs_batched_rc(offs, t) == _lib.LM_EINVAL
+    t = _lib.lm_batch_default_tuning(offs)
+    t.sym_min = -1
+    assert _rhs_batched_rc(offs, t) == _lib.LM_EINVAL
+    for bad in (0, 3, 16):
+        t = _lib.lm_batch_default_tuning(offs)
+        t.sym_waves = bad
+        assert _rhs_batched_rc(offs, t) == _lib.LM_EINVAL
 
 
 def test_cutoff_and_inexact_stop_rule_unsupported_for_batches():

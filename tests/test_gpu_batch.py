@@ -297,3 +297,91 @@ def test_full_batch_sampled_rhs(dtype):
         oq, op = oracle.rhs(q[:, s], p[:, s], lm.CONON, 0.1)
         assert rel_err(host(dq)[:, s], oq) <= TOL[dtype], (b, sizes[b])
         assert rel_err(host(dp)[:, s], op) <= TOL[dtype], (b, sizes[b])
+
+
+# ------------------------------------------------------------------ symmetric problems
+
+
+def _sym_tuning(offs, sym_min, waves, split=1):
+    t = lm.lm_batch_default_tuning(offs)
+    t.sym_min = sym_min
+    t.sym_waves = waves
+    for k in range(len(t.split)):
+        t.split[k] = split
+    return t
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+@pytest.mark.parametrize("dim,kernel,tau", [(2, lm.CONON, 0.0), (3, lm.CONON, 0.1), (2, lm.GAUSS, 0.2),
+                                            (3, lm.GAUSS, 0.0)])
+def test_batched_symmetric_rhs_matches_oracle(dim, kernel, tau, waves):
+    """Every problem symmetric (sym_min = 1), at every width: ragged tiles and superblocks,
+    one-point and one-tile problems."""
+    offs, q, p = ragged_batch(SIZES + [1100], dim, seed=304)
+    prm = lm.make_params(dim, kernel, 0.3, tau=tau)
+    dq, dp = torch.empty_like(dev(q)), torch.empty_like(dev(q))
+    lm.lm_rhs_batched(prm, offs, dev(q), dev(p), dq, dp, tuning=_sym_tuning(offs, 1, waves))
+    torch.cuda.synchronize()
+    gq, gp = host(dq), host(dp)
+    for b in range(len(offs) - 1):
+        s = slice(offs[b], offs[b + 1])
+        oq, op = oracle.rhs(q[:, s], p[:, s], kernel, 0.3, tau)
+        assert rel_err(gq[:, s], oq) <= 1e-10, (b, rel_err(gq[:, s], oq))
+        if offs[b + 1] - offs[b] > 1:
+            assert rel_err(gp[:, s], op) <= 1e-10, (b, rel_err(gp[:, s], op))
+        else:
+            assert np.all(gp[:, s] == 0.0)
+
+
+def test_batched_mixed_symmetric_and_split_problems():
+    """Problems from 200 points symmetric, the smaller ones one-sided with split sums, in the
+    same stage; single precision ignores the threshold."""
+    offs, q, p = ragged_batch(SIZES + [1100], 2, seed=305)
+    for dtype in (lm.F64, lm.F32):
+        qq, pp = rounded(q, dtype), rounded(p, dtype)
+        prm = lm.make_params(2, lm.CONON, 0.25, dtype=dtype)
+        dq, dp = torch.empty_like(dev(qq, dtype)), torch.empty_like(dev(qq, dtype))
+        lm.lm_rhs_batched(prm, offs, dev(qq, dtype), dev(pp, dtype), dq, dp, tuning=_sym_tuning(offs, 200, 2, 4))
+        torch.cuda.synchronize()
+        for b in range(len(offs) - 1):
+            s = slice(offs[b], offs[b + 1])
+            oq, op = oracle.rhs(qq[:, s], pp[:, s], lm.CONON, 0.25)
+            assert rel_err(host(dq)[:, s], oq) <= TOL[dtype], (dtype, b)
+            if offs[b + 1] - offs[b] > 1:
+                assert rel_err(host(dp)[:, s], op) <= TOL[dtype], (dtype, b)
+
+
+def test_batched_symmetric_shoot_graph_replays_and_oracle():
+    offs, q, p = ragged_batch([40, 300, 1029, 7, 513], 2, seed=306, pscale=0.3)
+    prm = lm.make_params(2, lm.CONON, 0.2)
+    t = _sym_tuning(offs, 100, 2)
+    out = []
+    for gs in [0, 3, 0]:
+        t.graph_steps = gs
+        q1, p1 = torch.empty_like(dev(q)), torch.empty_like(dev(q))
+        lm.lm_shoot_batched(prm, offs, dev(q), dev(p), 0.9, 7, q1, p1, tuning=t)
+        torch.cuda.synchronize()
+        out.append((host(q1), host(p1)))
+    for gq, gp in out[1:]:
+        assert np.array_equal(gq, out[0][0]) and np.array_equal(gp, out[0][1])
+    for b in range(len(offs) - 1):
+        s = slice(offs[b], offs[b + 1])
+        oq, op = oracle.shoot(q[:, s], p[:, s], lm.CONON, 0.2, 7, T=0.9)
+        assert rel_err(out[0][0][:, s], oq) <= 1e-10 and rel_err(out[0][1][:, s], op) <= 1e-10
+
+
+def test_batched_symmetric_feedback_matches_oracle_per_problem():
+    sizes, offs, X, Y = curve_batch(5, 300)
+    prm = lm.make_params(2, lm.CONON, 0.1)
+    p0 = torch.zeros((2, int(offs[-1])), dtype=torch.float64, device=DEV)
+    q1 = torch.empty_like(p0)
+    st, infos, stats = lm.lm_feedback_match_batched(prm, offs, dev(X), dev(Y), p0, h=0.8, tol=1e-6, steps=20,
+                                                    max_iter=200, q1=q1, tuning=_sym_tuning(offs, 1, 1))
+    assert st == lm.LM_OK and all(s == lm.LM_OK for s in stats)
+    gp, gq = host(p0), host(q1)
+    for b in range(len(sizes)):
+        s = slice(offs[b], offs[b + 1])
+        ref = oracle.feedback_match(X[:, s], Y[:, s], lm.CONON, 0.1, 0.8, 1e-6, 20, max_iter=200)
+        assert infos[b].iters == ref.iters, (b, infos[b].iters, ref.iters)
+        assert rel_err(gp[:, s], ref.p0) <= 1e-8
+        assert rel_err(gq[:, s], ref.q1) <= 1e-10
