@@ -194,11 +194,11 @@ struct SymPlan {
     int64_t nsb = 0;
 };
 
-// Size rule (measured on MI355X, 3-D conon, FP64, one stage): from 192 tiles (N = 12288)
-// two waves per workgroup, from 768 tiles (N = 49152) four; below, the one-sided kernel.
-// At N = 8192 the two kernels tie (88 vs 89 us); at N = 16384 the symmetric one with two
-// waves takes 298 us against 361, at 32768 997 against 1371, at 65536 (four waves) 3760
-// against 5425.
+// Size rule (measured on MI355X, 3-D conon, FP64, one stage): from 128 tiles (N = 8192) one
+// wave per workgroup, from 192 tiles (N = 12288) two, from 768 tiles (N = 49152) four; below,
+// the one-sided kernel.
+// At N = 16384 the symmetric kernel with two waves takes 298 us against 361, at 32768 997
+// against 1371, at 65536 (four waves) 3760 against 5425.
 constexpr int kSymMaxWaves = 8;
 #ifndef LM_SYM_ROWS
 #define LM_SYM_ROWS 2
@@ -213,6 +213,9 @@ constexpr int kSymOccupancy = LM_SYM_OCC;   // wavefronts per SIMD the register 
 #endif
 constexpr int64_t kSymMinTiles = LM_SYM_MIN_TILES;
 constexpr int64_t kSymWideTiles = 768;
+// one wave per workgroup from 128 tiles (N = 8192: 3-D conon 92 against 101 us, 3-D Gaussian 79
+// against 80, 2-D conon 78 against 86)
+constexpr int64_t kSymOneWaveTiles = 128;
 // Single precision: the size rule never picks the symmetric kernel.  Its shared part (the
 // hardware 2^x and 1/sqrt) is too small a share of a pair for symmetry to pay for the column
 // traffic: 1973 us per stage at N = 65536 against 1996 for the one-sided kernel, slower at

@@ -768,42 +768,6 @@ static inline unsigned blocks_for(int64_t m, int threads, unsigned cap = 8192)
     return (unsigned)(b < (int64_t)cap ? b : cap);
 }
 
-PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, int kind)
-{
-    PairPlan pl{};
-    pl.itiles = (nt + kTile - 1) / kTile;
-    if (sym_ok && !cut && nt == ns) {
-        const char* e = getenv("LM_SYM");
-        const int mode = e ? atoi(e) : -1;
-        if (mode != 0) {
-            const SymPlan sp = plan_sym(nt, mode == 1, kind);
-            if (sp.waves > 0) {
-                pl.sym_waves = sp.waves;
-                pl.sym_nsb = sp.nsb;
-                pl.nsplit = (int)(sp.nsb + 1);
-                pl.jchunk = ns;
-                return pl;
-            }
-        }
-    }
-    // aim for >= LM_MIN_GROUPS workgroups (the targets alone give nt/64; the sources are
-    // split over grid-y to make up the rest) while keeping every wave's chunk >= 32 sources
-    int64_t s = (LM_MIN_GROUPS + pl.itiles - 1) / pl.itiles;
-    int64_t smax = ns / (kWaves * 32);
-    if (smax < 1) smax = 1;
-    if (s > smax) s = smax;
-    if (s > 64) s = 64;
-    // from 128 target tiles (N = 8192) on, more than 16 splits only shortens the chunks:
-    // measured at N = 16384, 3-D, FP64, 16 splits beat 64 by 12% (Gaussian) and 4% (conon)
-    if (pl.itiles >= 128 && s > 16) s = 16;
-    if (s < 1) s = 1;
-    pl.nsplit = (int)s;
-    int64_t chunks = (int64_t)pl.nsplit * kWaves;
-    pl.jchunk = (ns + chunks - 1) / chunks;
-    if (cut) pl.jchunk = (pl.jchunk + kTile - 1) / kTile * kTile;   // chunks start on tile boundaries
-    return pl;
-}
-
 template <class T, int DIM, int KER, bool FORCE, bool CUT>
 static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStream_t st)
 {

@@ -1,0 +1,81 @@
+// lm_plan.hip -- launch plans of the pair sums (host code): how many source splits the
+// one-sided kernel gets, and whether and how wide the symmetric kernels run.
+#include <stdint.h>
+#include <stdlib.h>
+
+#include "lm_internal.h"
+
+namespace lm {
+
+PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, int kind)
+{
+    PairPlan pl{};
+    pl.itiles = (nt + kTile - 1) / kTile;
+    if (sym_ok && !cut && nt == ns) {
+        const char* e = getenv("LM_SYM");
+        const int mode = e ? atoi(e) : -1;
+        if (mode != 0) {
+            const SymPlan sp = plan_sym(nt, mode == 1, kind);
+            if (sp.waves > 0) {
+                pl.sym_waves = sp.waves;
+                pl.sym_nsb = sp.nsb;
+                pl.nsplit = (int)(sp.nsb + 1);
+                pl.jchunk = ns;
+                return pl;
+            }
+        }
+    }
+    // aim for >= LM_MIN_GROUPS workgroups (the targets alone give nt/64; the sources are
+    // split over grid-y to make up the rest) while keeping every wave's chunk >= 32 sources
+    int64_t s = (LM_MIN_GROUPS + pl.itiles - 1) / pl.itiles;
+    int64_t smax = ns / (kWaves * 32);
+    if (smax < 1) smax = 1;
+    if (s > smax) s = smax;
+    if (s > 64) s = 64;
+    // from 128 target tiles (N = 8192) on, more than 16 splits only shortens the chunks:
+    // measured at N = 16384, 3-D, FP64, 16 splits beat 64 by 12% (Gaussian) and 4% (conon)
+    if (pl.itiles >= 128 && s > 16) s = 16;
+    if (s < 1) s = 1;
+    pl.nsplit = (int)s;
+    int64_t chunks = (int64_t)pl.nsplit * kWaves;
+    pl.jchunk = (ns + chunks - 1) / chunks;
+    if (cut) pl.jchunk = (pl.jchunk + kTile - 1) / kTile * kTile;   // chunks start on tile boundaries
+    return pl;
+}
+
+SymPlan plan_sym(int64_t n, bool force, int kind)
+{
+    SymPlan sp{};
+    const int64_t T = tiles_of(n);
+    // LM_SYM_WAVES fixes the workgroup width (tuning runs, tests of every width)
+    const char* env = getenv("LM_SYM_WAVES");
+    const int fixed = env ? atoi(env) : 0;
+    int w = 0;
+    if (fixed == 1 || fixed == 2 || fixed == 4 || fixed == 8) {
+        w = fixed;
+    } else if (kind == SYM_VJP) {
+        w = T >= kSymVjpTwoWaveTiles ? 2 : T >= kSymVjpMinTiles ? 1 : 0;
+    } else if (kind == SYM_F64 && T >= kSymWideTiles) {
+        w = 4;
+    } else if (T >= (kind == SYM_F32 ? kSymMinTilesF32 : kSymMinTiles)) {
+        w = 2;
+    } else if (kind == SYM_F64 && T >= kSymOneWaveTiles) {
+        w = 1;
+    }
+    if (w == 0 && force) w = 1;
+    if (w == 0) return sp;
+    // partial sums: (S + 1) slots of up to 6 doubles per point; wider superblocks need
+    // fewer, and beyond the cap the one-sided kernel (at most 64 slots) is used instead
+    for (;; w *= 2) {
+        const int64_t S = (T + kSymRows * w - 1) / (kSymRows * w);
+        const bool fits = (S + 1) * 6 * n * (int64_t)sizeof(double) <= kSymMaxPartBytes;
+        if (fits && S * (S + 1) / 2 < ((int64_t)1 << 31)) {
+            sp.waves = w;
+            sp.nsb = S;
+            return sp;
+        }
+        if (w >= kSymMaxWaves || fixed) return sp;
+    }
+}
+
+}  // namespace lm

@@ -348,39 +348,6 @@ hipError_t launch_sym_t(const SymArgs<T>& a, int waves, hipStream_t st)
 
 }  // namespace
 
-SymPlan plan_sym(int64_t n, bool force, int kind)
-{
-    SymPlan sp{};
-    const int64_t T = tiles_of(n);
-    // LM_SYM_WAVES fixes the workgroup width (tuning runs, tests of every width)
-    const char* env = getenv("LM_SYM_WAVES");
-    const int fixed = env ? atoi(env) : 0;
-    int w = 0;
-    if (fixed == 1 || fixed == 2 || fixed == 4 || fixed == 8) {
-        w = fixed;
-    } else if (kind == SYM_VJP) {
-        w = T >= kSymVjpTwoWaveTiles ? 2 : T >= kSymVjpMinTiles ? 1 : 0;
-    } else if (kind == SYM_F64 && T >= kSymWideTiles) {
-        w = 4;
-    } else if (T >= (kind == SYM_F32 ? kSymMinTilesF32 : kSymMinTiles)) {
-        w = 2;
-    }
-    if (w == 0 && force) w = 1;
-    if (w == 0) return sp;
-    // partial sums: (S + 1) slots of up to 6 doubles per point; wider superblocks need
-    // fewer, and beyond the cap the one-sided kernel (at most 64 slots) is used instead
-    for (;; w *= 2) {
-        const int64_t S = (T + kSymRows * w - 1) / (kSymRows * w);
-        const bool fits = (S + 1) * 6 * n * (int64_t)sizeof(double) <= kSymMaxPartBytes;
-        if (fits && S * (S + 1) / 2 < ((int64_t)1 << 31)) {
-            sp.waves = w;
-            sp.nsb = S;
-            return sp;
-        }
-        if (w >= kSymMaxWaves || fixed) return sp;
-    }
-}
-
 template <class T>
 hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs<T>& a, int waves, hipStream_t st)
 {

@@ -3,7 +3,7 @@ and against the one-sided kernel, through the C ABI (needs an MI355X).
 
 LM_SYM=1 forces the symmetric kernel at any size and LM_SYM_WAVES fixes its workgroup
 width, so every width and ragged superblocks are covered at sizes the oracle finishes in
-seconds; the size rule alone picks it from N = 12288 on.
+seconds; the size rule alone picks it from N = 8192 on.
 """
 
 import os

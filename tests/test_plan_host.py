@@ -31,7 +31,8 @@ def test_full_size_double_uses_symmetric_kernel_with_four_waves():
     assert (S, wg, slots) == (128, 8256, 129)
 
 
-@pytest.mark.parametrize("n,waves", [(12288, 2), (16384, 2), (49088, 2), (49089, 4), (131072, 4)])
+@pytest.mark.parametrize("n,waves", [(8129, 1), (8192, 1), (12224, 1), (12288, 2), (16384, 2), (49088, 2),
+                                     (49089, 4), (131072, 4)])
 def test_size_rule(n, waves):
     p = plan(n)
     T = -(-n // 64)
@@ -39,17 +40,19 @@ def test_size_rule(n, waves):
     assert (p["workgroups"], p["partial_slots"]) == sym(T, waves)[1:]
 
 
-@pytest.mark.parametrize("n", [1, 257, 4096, 12224])
+@pytest.mark.parametrize("n", [1, 257, 4096, 8128])
 def test_small_sizes_keep_one_sided_kernel(n):
     p = plan(n)
     assert p["symmetric"] == 0 and p["waves"] == 4
     assert p["small"] == (1 if n <= 256 else 0)
 
 
-def test_one_sided_split_rule():
+def test_one_sided_split_rule(monkeypatch):
     # 128 target tiles: 16384 workgroups wanted, capped at 16 source splits from 128 tiles on
+    monkeypatch.setenv("LM_SYM", "0")
     p = plan(8192)
     assert p == {"symmetric": 0, "waves": 4, "workgroups": 128 * 16, "partial_slots": 16, "small": 0}
+    monkeypatch.delenv("LM_SYM")
     # 64 tiles of 2-D points: 256 splits wanted, limited to 64 (and by the 32-source chunk floor)
     p = plan(4096, dim=2)
     assert p["workgroups"] == 64 * 32 and p["partial_slots"] == 32
