@@ -556,10 +556,44 @@ __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restri
 // striding the columns, four rows at a time), then y_k = Linv_k s.  Backward, per block from
 // the last: t = y_k - L[>k, k]^T x_>k (each wave takes every fourth row below the block, lanes
 // the block's columns; the wave partials are added in wave order), then x_k = Linv_k^T t.
-// L_b: row-major n_b x n_b lower triangle at L + loff[b]; Linv_b at Linv + ioff[b]; y: the
+// Both block finishes read rows (of LinvT, of Linv) with two threads per output.
+// L_b: row-major n_b x n_b lower triangle at L + loff[b]; Linv_b at Linv + ioff[b] (the
+// transposes after the problem's panels of inverses, as launch_dense_factor stores them); y: the
 // batch's (dim, ntot) array, problem b in columns offs[b] .. offs[b+1]-1.
 // ---------------------------------------------------------------------------------------
 constexpr int kBatchSolveMax = 4096;
+
+// v[k0 + r] <- (M t)_r for r < bs, M^T stored at Mt (128 x 128 rows): thread (h, r) sums its
+// half of the rows of Mt, the halves added in order (part: scratch, one panel per component).
+// t must be zero past bs.
+template <int DIM>
+__device__ __forceinline__ void batch_finish(const double* __restrict__ Mt, int bs, int k0,
+                                             const double (*t)[kPanel], double (*part)[kPanel],
+                                             double (*v)[kBatchSolveMax])
+{
+    const int tid = threadIdx.x, r = tid & (kPanel - 1), h = tid >> 7;
+    double acc[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
+    const double* col = Mt + (int64_t)(h * 64) * kPanel + r;
+    for (int m0 = 0; m0 < 64; m0 += 16) {
+        double lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lv[u] = col[(m0 + u) * kPanel];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc[c] = __builtin_fma(lv[u], t[c][h * 64 + m0 + u], acc[c]);
+    }
+    if (h == 1)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) part[c][r] = acc[c];
+    __syncthreads();
+    if (h == 0 && r < bs)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) v[c][k0 + r] = acc[c] + part[c][r];
+    __syncthreads();
+}
 
 template <int DIM>
 __global__ __launch_bounds__(256) void lm_batch_solve_kernel(const double* __restrict__ L,
@@ -613,15 +647,12 @@ __global__ __launch_bounds__(256) void lm_batch_solve_kernel(const double* __res
                     if (lane == 0 && r0 + u < bs) tmp[0][c][r0 + u] = v[c][k0 + r0 + u] - a;
                 }
         }
+        // zero the staged vector past a ragged last block (the finish multiplies every entry)
+        for (int e = bs + tid; e < kPanel; e += blockDim.x)
+            for (int c = 0; c < DIM; ++c) tmp[0][c][e] = 0.0;
         __syncthreads();
-        if (tid < bs) {
-            for (int c = 0; c < DIM; ++c) {
-                double s = 0.0;
-                for (int m = 0; m <= tid; ++m) s = __builtin_fma(Ib[(int64_t)k * kPanel * kPanel + tid * kPanel + m], tmp[0][c][m], s);
-                v[c][k0 + tid] = s;
-            }
-        }
-        __syncthreads();
+        // y_k = Linv_k t: rows of the stored transpose LinvT
+        batch_finish<DIM>(Ib + ((int64_t)nb + k) * kPanel * kPanel, bs, k0, tmp[0], tmp[1], v);
     }
 
     // backward sweep
@@ -657,14 +688,8 @@ __global__ __launch_bounds__(256) void lm_batch_solve_kernel(const double* __res
             }
         }
         __syncthreads();
-        if (tid < bs) {
-            for (int c = 0; c < DIM; ++c) {
-                double s = 0.0;
-                for (int m = tid; m < bs; ++m) s = __builtin_fma(Ib[(int64_t)k * kPanel * kPanel + m * kPanel + tid], tmp[0][c][m], s);
-                v[c][k0 + tid] = s;
-            }
-        }
-        __syncthreads();
+        // x_k = Linv_k^T t: rows of Linv
+        batch_finish<DIM>(Ib + (int64_t)k * kPanel * kPanel, bs, k0, tmp[0], tmp[1], v);
     }
     for (int c = 0; c < DIM; ++c)
         for (int i = tid; i < n; i += blockDim.x) y[c * ntot + off + i] = v[c][i];
