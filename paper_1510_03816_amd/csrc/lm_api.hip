@@ -120,13 +120,17 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
 int64_t part_elems(const lm_params* prm, int64_t nt, int64_t ns)
 {
     const lm::PairPlan pl = lm::plan_pair(nt, ns, false);
-    int64_t slots = pl.nsplit > 1 ? pl.nsplit : 0;
+    int64_t m = pl.nsplit > 1 ? (int64_t)pl.nsplit * 2 * prm->dim * nt : 1;
     if (nt == ns) {
-        // the symmetric kernel's slots under any setting of LM_SYM (forced or by size)
+        // the symmetric kernel's slots under any setting of LM_SYM (forced or by size), and its
+        // superblock-pair flags in tile-skipping mode
         const lm::SymPlan sp = lm::plan_sym(nt, true, prm->dtype == LM_F32 ? lm::SYM_F32 : lm::SYM_F64);
-        if (sp.waves > 0 && sp.nsb + 1 > slots) slots = sp.nsb + 1;
+        if (sp.waves > 0) {
+            const int64_t ms = (sp.nsb + 1) * 2 * prm->dim * nt + lm::sym_flag_elems(sp.nsb);
+            if (ms > m) m = ms;
+        }
     }
-    return slots > 0 ? slots * 2 * prm->dim * nt : 1;
+    return m;
 }
 
 // Workspace of a VJP evaluation: the interleaved source copy, then the partial sums of either

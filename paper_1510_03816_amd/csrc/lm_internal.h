@@ -187,7 +187,14 @@ struct SymArgs {
     double kq;
     double wscale;
     double* part;        // (nsb + 1, 2 dim, n) partial sums
+    const double* box;   // tile skipping: tile boxes (8 doubles per 64-point tile), else null
+    double rc2;          // cutoff radius squared
+    uint8_t* flags;      // tile skipping: one byte per superblock pair, 0 = nothing written
 };
+
+// Bytes of the superblock-pair flags that follow the partial sums of a symmetric launch with
+// tile skipping, in doubles.
+inline int64_t sym_flag_elems(int64_t nsb) { return (nsb * (nsb + 1) / 2 + 7) / 8; }
 
 struct SymPlan {
     int waves = 0;       // 0: not worth it (too few wavefronts) or too large
@@ -216,6 +223,10 @@ constexpr int64_t kSymWideTiles = 768;
 // one wave per workgroup from 128 tiles (N = 8192: 3-D conon 92 against 101 us, 3-D Gaussian 79
 // against 80, 2-D conon 78 against 86)
 constexpr int64_t kSymOneWaveTiles = 128;
+// With tile skipping (3-D Gaussian, cutoff where the kernel is 1e-16): at N = 65536 the
+// symmetric kernel takes 502 us per stage against 574 one-sided (conon: 3784 against 5542),
+// at N = 16384 149 against 120.
+constexpr int64_t kSymCutTiles = 768;
 // Single precision: the size rule never picks the symmetric kernel.  Its shared part (the
 // hardware 2^x and 1/sqrt) is too small a share of a pair for symmetry to pay for the column
 // traffic: 1973 us per stage at N = 65536 against 1996 for the one-sided kernel, slower at

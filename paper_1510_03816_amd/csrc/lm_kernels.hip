@@ -357,9 +357,12 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
 // (one workgroup per CU at N = 65536), so a workgroup takes 64 targets and its four waves
 // split the slots: wave w adds slots w, w + 4, w + 8, ... in increasing order, four loads in
 // flight per value, and wave 0 adds the four wave sums in wave order.
+// flags (the symmetric kernel with tile skipping, else null): slot s of a target in superblock
+// Z (sbp points each) came from superblock pair {Z, s}; a pair flagged 0 wrote nothing there.
 template <class T, int DIM, bool FORCE>
 __global__ __launch_bounds__(256) void lm_finish_kernel(const double* __restrict__ part, int nsplit,
-                                                        int64_t nt, EpiArgs<T> e)
+                                                        int64_t nt, EpiArgs<T> e, const uint8_t* __restrict__ flags,
+                                                        int64_t sbp)
 {
     constexpr int NV = FORCE ? 2 * DIM : DIM;
     __shared__ double red[3][NV][64];
@@ -367,6 +370,13 @@ __global__ __launch_bounds__(256) void lm_finish_kernel(const double* __restrict
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     const bool live = i < nt;
     const int64_t slot = (int64_t)(2 * DIM) * nt;
+    // the workgroup's 64 targets form one tile, so they share one superblock Z
+    const int64_t Z = (int64_t)blockIdx.x * 64 / sbp;
+    auto written = [&](int s) -> bool {
+        if (flags == nullptr || s >= nsplit - 1 || s == Z) return true;
+        const int64_t X = s < Z ? s : Z, Y = s < Z ? Z : s;
+        return flags[Y * (Y - 1) / 2 + X] != 0;
+    };
     double acc[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[c] = 0.0;
@@ -376,17 +386,20 @@ __global__ __launch_bounds__(256) void lm_finish_kernel(const double* __restrict
         for (; s + 12 < nsplit; s += 16) {
             double x[4][NV];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) {
+                const bool w = written(s + 4 * u);
 #pragma unroll
-                for (int c = 0; c < NV; ++c) x[u][c] = ps[(s + 4 * u) * slot + c * nt];
+                for (int c = 0; c < NV; ++c) x[u][c] = w ? ps[(s + 4 * u) * slot + c * nt] : 0.0;
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int c = 0; c < NV; ++c) acc[c] += x[u][c];
         }
         for (; s < nsplit; s += 4)
+            if (written(s))
 #pragma unroll
-            for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
+                for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
     }
     if (wave > 0)
 #pragma unroll
@@ -772,8 +785,10 @@ template <class T, int DIM, int KER, bool FORCE, bool CUT>
 static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStream_t st)
 {
     hipError_t err;
+    uint8_t* flags = nullptr;   // symmetric with tile skipping: which superblock pairs wrote
+    int64_t sbp = kTile;
     if (pl.sym_waves > 0) {
-        if constexpr (!CUT) {
+        {
             SymArgs<T> s{};
             s.q = a.qs;
             s.p = a.ps;
@@ -783,9 +798,15 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
             s.kq = a.kq;
             s.wscale = a.wscale;
             s.part = a.part;
+            if (CUT) {
+                if (a.box_t != a.box_s) return hipErrorInvalidValue;   // one point set
+                s.box = a.box_s;
+                s.rc2 = a.rc2;
+                s.flags = (uint8_t*)(a.part + (int64_t)pl.nsplit * (2 * DIM) * a.nt);
+                flags = s.flags;
+                sbp = (int64_t)kTile * kSymRows * pl.sym_waves;
+            }
             err = launch_sym_pair<T>(DIM, KER, FORCE, s, pl.sym_waves, st);
-        } else {
-            return hipErrorInvalidValue;
         }
     } else {
         dim3 grid((unsigned)pl.itiles, (unsigned)pl.nsplit);
@@ -794,7 +815,7 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
     }
     if (err != hipSuccess || pl.nsplit == 1) return err;
     hipLaunchKernelGGL((lm_finish_kernel<T, DIM, FORCE>), dim3(blocks_for(a.nt, 64, 1u << 30)), dim3(256), 0, st,
-                       (const double*)a.part, pl.nsplit, a.nt, a.epi);
+                       (const double*)a.part, pl.nsplit, a.nt, a.epi, (const uint8_t*)flags, sbp);
     return hipGetLastError();
 }
 

@@ -11,10 +11,14 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, int kind)
 {
     PairPlan pl{};
     pl.itiles = (nt + kTile - 1) / kTile;
-    if (sym_ok && !cut && nt == ns) {
+    // tile skipping runs symmetric in double precision only, and by the size rule only from
+    // kSymCutTiles tiles: with much skipped, the symmetric kernel's fixed costs (superblock
+    // tests, the flags, the finish) need a large N to pay off
+    if (sym_ok && nt == ns && (!cut || kind == SYM_F64)) {
         const char* e = getenv("LM_SYM");
         const int mode = e ? atoi(e) : -1;
-        if (mode != 0) {
+        const bool small_cut = cut && mode != 1 && pl.itiles < kSymCutTiles;
+        if (mode != 0 && !small_cut) {
             const SymPlan sp = plan_sym(nt, mode == 1, kind);
             if (sp.waves > 0) {
                 pl.sym_waves = sp.waves;

@@ -176,21 +176,44 @@ __device__ __forceinline__ void sym_stage(T* __restrict__ jbuf, const T* __restr
 
 // The row tiles of this wave against column tile J (staged at jb), sums added to (v, f): both
 // rows symmetrically in one pass when they allow it, else row by row by mode.
-template <class T, int DIM, int KER, bool FORCE, class A>
+// Whether the bounding boxes of tiles a and b (8 doubles each: lo[4], hi[4]) lie farther apart
+// than sqrt(rc2), so that every pair between them does.
+template <int DIM>
+__device__ __forceinline__ bool sym_tiles_far(const double* __restrict__ a, const double* __restrict__ b, double rc2)
+{
+    double g2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double gap = __builtin_fmax(__builtin_fmax(a[c] - b[4 + c], b[c] - a[4 + c]), 0.0);
+        g2 = __builtin_fma(gap, gap, g2);
+    }
+    return g2 > rc2;
+}
+
+// CUT: a row tile whose box lies farther than the cutoff from column tile J's box skips it
+// (both directions of its pairs: the block is evaluated once, here or nowhere).
+template <class T, int DIM, int KER, bool FORCE, bool CUT, class A>
 __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[kSymRows], int64_t J, int64_t NT,
                                          const T (&qi)[kSymRows][DIM], const T (&pi)[kSymRows][DIM],
                                          const T* __restrict__ jb, T kq, A (&v)[kSymRows][DIM], A (&f)[kSymRows][DIM],
-                                         double* __restrict__ acc)
+                                         double* __restrict__ acc, const double* __restrict__ box, double rc2)
 {
-    // every row tile meets J from both sides, except near the diagonal
-    const bool all = diag ? J > I[kSymRows - 1] : I[kSymRows - 1] < NT;
+    bool far[kSymRows];
+    bool any_far = false;
+#pragma unroll
+    for (int r = 0; r < kSymRows; ++r) {
+        far[r] = CUT && I[r] < NT && sym_tiles_far<DIM>(box + I[r] * 8, box + J * 8, rc2);
+        any_far = any_far || far[r];
+    }
+    // every row tile meets J from both sides, except near the diagonal (and skipped tiles)
+    const bool all = (diag ? J > I[kSymRows - 1] : I[kSymRows - 1] < NT) && !any_far;
     if (all) {
         sym_block<T, DIM, KER, FORCE, kSymRows, true>(qi, pi, jb, kq, v, f, acc);
         return;
     }
 #pragma unroll
     for (int r = 0; r < kSymRows; ++r) {
-        const int m = sym_mode(diag, I[r], J, NT);
+        const int m = far[r] ? SYM_SKIP : sym_mode(diag, I[r], J, NT);
         if (m == SYM_SKIP) continue;
         T q1[1][DIM], p1[1][DIM], v1[1][DIM], f1[1][DIM];
 #pragma unroll
@@ -214,11 +237,15 @@ __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[kSymRows]
 
 // One workgroup's superblock pair (X, Y) of a point set of n points: component c of point i at
 // q[c * ld + i] (ld = n for one problem, the batch's total for a batched one); partial sums in
-// part, (S + 1) slots of 2 dim x n doubles.
-template <class T, int DIM, int KER, bool FORCE>
+// part, (S + 1) slots of 2 dim x n doubles.  CUT: flags[b] (b = the pair's number) says
+// whether the pair wrote its slots; a pair whose tiles are all farther apart than the cutoff
+// writes nothing else (lm_finish_kernel skips its slots).
+template <class T, int DIM, int KER, bool FORCE, bool CUT>
 __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, const T* __restrict__ p, int64_t ld,
                                                     int64_t n, int64_t S, int64_t X, int64_t Y, double kqd,
-                                                    double wscale, double* __restrict__ part)
+                                                    double wscale, double* __restrict__ part,
+                                                    const double* __restrict__ box, double rc2,
+                                                    uint8_t* __restrict__ flags, int64_t b)
 {
     constexpr int E = sym_stride(DIM);           // staged values per column point
     constexpr int EC = FORCE ? 2 * DIM : DIM;    // column sums per point
@@ -233,6 +260,20 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     const bool diag = X == Y;
     const int64_t NT = tiles_of_dev(n);
     const T kq = (T)kqd;
+
+    if constexpr (CUT) {
+        int near = diag;
+        if (!diag) {
+            const int64_t I0 = X * side, I1 = (I0 + side < NT) ? I0 + side : NT;
+            const int64_t J0 = Y * side, J1 = (J0 + side < NT) ? J0 + side : NT;
+            const int64_t w = J1 - J0;
+            for (int64_t t = threadIdx.x; t < (I1 - I0) * w; t += blockDim.x)
+                if (!sym_tiles_far<DIM>(box + (I0 + t / w) * 8, box + (J0 + t % w) * 8, rc2)) near = 1;
+        }
+        near = __syncthreads_or(near);
+        if (threadIdx.x == 0) flags[b] = (uint8_t)(near != 0);
+        if (!near) return;
+    }
 
     // row points in registers; their sums over one column tile in T, over all tiles in double
     int64_t I[kSymRows];
@@ -264,7 +305,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     double* pc = part + slot_col * (2 * DIM) * n;
     for (int64_t J = J0; J < J1; ++J) {
         if constexpr (sizeof(T) == sizeof(double)) {
-            sym_tile<T, DIM, KER, FORCE>(diag, I, J, NT, qi, pi, jb, kq, vs, fs, acc);
+            sym_tile<T, DIM, KER, FORCE, CUT>(diag, I, J, NT, qi, pi, jb, kq, vs, fs, acc, box, rc2);
         } else {
             T v[kSymRows][DIM], f[kSymRows][DIM];
 #pragma unroll
@@ -274,7 +315,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
                     v[r][c] = (T)0;
                     f[r][c] = (T)0;
                 }
-            sym_tile<T, DIM, KER, FORCE>(diag, I, J, NT, qi, pi, jb, kq, v, f, acc);
+            sym_tile<T, DIM, KER, FORCE, CUT>(diag, I, J, NT, qi, pi, jb, kq, v, f, acc, box, rc2);
 #pragma unroll
             for (int r = 0; r < kSymRows; ++r)
 #pragma unroll
@@ -315,12 +356,13 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     }
 }
 
-template <class T, int DIM, int KER, bool FORCE>
+template <class T, int DIM, int KER, bool FORCE, bool CUT>
 __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs<T> a)
 {
     int64_t X, Y;
     sym_superblocks(blockIdx.x, a.nsb, X, Y);
-    sym_superblock_pair<T, DIM, KER, FORCE>(a.q, a.p, a.n, a.n, a.nsb, X, Y, a.kq, a.wscale, a.part);
+    sym_superblock_pair<T, DIM, KER, FORCE, CUT>(a.q, a.p, a.n, a.n, a.nsb, X, Y, a.kq, a.wscale, a.part, a.box,
+                                                 a.rc2, a.flags, blockIdx.x);
 }
 
 // Batched: workgroup b takes item sym_items[b] = (problem, X, Y, S) of the concatenated
@@ -331,8 +373,8 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_batch_sym_kernel(BatchA
     const int4 w = a.sym_items[blockIdx.x];
     const int64_t off = a.offs[w.x];
     const int64_t nb = a.offs[w.x + 1] - off;
-    sym_superblock_pair<T, DIM, KER, FORCE>(a.q + off, a.p + off, a.ntot, nb, w.w, w.y, w.z, a.kq, a.wscale,
-                                            a.part + a.part_off[w.x]);
+    sym_superblock_pair<T, DIM, KER, FORCE, false>(a.q + off, a.p + off, a.ntot, nb, w.w, w.y, w.z, a.kq, a.wscale,
+                                                   a.part + a.part_off[w.x], nullptr, 0.0, nullptr, 0);
 }
 
 template <class T, int DIM, int KER, bool FORCE>
@@ -341,8 +383,15 @@ hipError_t launch_sym_t(const SymArgs<T>& a, int waves, hipStream_t st)
     constexpr int EC = FORCE ? 2 * DIM : DIM;
     const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
     const int64_t S = a.nsb;
-    hipLaunchKernelGGL((lm_sym_pair_kernel<T, DIM, KER, FORCE>), dim3((unsigned)(S * (S + 1) / 2)),
-                       dim3(64 * waves), lds, st, a);
+    const dim3 grid((unsigned)(S * (S + 1) / 2)), block(64 * waves);
+    if (a.box == nullptr) {
+        hipLaunchKernelGGL((lm_sym_pair_kernel<T, DIM, KER, FORCE, false>), grid, block, lds, st, a);
+    } else if constexpr (sizeof(T) == sizeof(double) && FORCE) {
+        // tile skipping: double-precision sums with forces (the shoot's stages)
+        hipLaunchKernelGGL((lm_sym_pair_kernel<T, DIM, KER, FORCE, true>), grid, block, lds, st, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -228,3 +228,77 @@ def test_sym_shoot_adjoint_and_energy_gradient_match_oracle(kernel):
     assert rel_err(host(gq0), oq) <= 1e-10 and rel_err(host(gp0), op) <= 1e-10
     assert E == pytest.approx(E_o, rel=1e-11)
     assert rel_err(host(g), g_o) <= 1e-10
+
+
+# ------------------------------------------------------------------ tile skipping
+
+
+def _morton_sorted(X):
+    lo, hi = X.min(axis=1, keepdims=True), X.max(axis=1, keepdims=True)
+    g = np.clip(((X - lo) / (hi - lo) * 1023).astype(np.int64), 0, 1023)
+    key = np.zeros(X.shape[1], dtype=np.int64)
+    for b in range(10):
+        for c in range(X.shape[0]):
+            key |= ((g[c] >> b) & 1) << (X.shape[0] * b + c)
+    return np.argsort(key, kind="stable")
+
+
+@pytest.mark.parametrize("waves", [1, 4])
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_sym_cutoff_at_negligible_radius_meets_exact_parity(kernel, waves):
+    pr = inputs.config_sphere3d(6000, kernel=kernel, sigma=0.05)
+    perm = _morton_sorted(pr.X)
+    q, p = pr.X[:, perm], pr.p_bench()[:, perm]
+    rc = pr.sigma * (36.9 if kernel == 0 else 36.9 ** 0.5)
+    dq_o, dp_o = oracle.rhs(q, p, kernel, pr.sigma)
+    prm = lm.make_params(3, kernel, pr.sigma, cutoff=rc)
+    qd, pd = dev(q), dev(p)
+    dq, dp = torch.empty_like(qd), torch.empty_like(pd)
+    with _env(LM_SYM=1, LM_SYM_WAVES=waves):
+        lm.lm_rhs(prm, qd, pd, dq, dp)
+        torch.cuda.synchronize()
+    assert rel_err(host(dq), dq_o) <= 1e-10 and rel_err(host(dp), dp_o) <= 1e-10
+
+
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_sym_cutoff_error_within_certified_bound_and_matches_one_sided(kernel):
+    """At a radius that drops pairs, the symmetric kernel skips exactly the tile pairs the
+    one-sided kernel skips: the same pairs are dropped, so both stay within the certified
+    bound and agree to rounding."""
+    pr = inputs.config_sphere3d(8000, kernel=kernel, sigma=0.05)
+    perm = _morton_sorted(pr.X)
+    q, p = pr.X[:, perm], pr.p_bench()[:, perm]
+    rc = 3.0 * pr.sigma
+    dq_o, dp_o = oracle.rhs(q, p, kernel, pr.sigma)
+    prm = lm.make_params(3, kernel, pr.sigma, cutoff=rc)
+    out = []
+    for env in ({"LM_SYM": 0}, {"LM_SYM": 1, "LM_SYM_WAVES": 2}):
+        qd, pd = dev(q), dev(p)
+        dq, dp = torch.empty_like(qd), torch.empty_like(pd)
+        with _env(**env):
+            lm.lm_rhs(prm, qd, pd, dq, dp)
+            torch.cuda.synchronize()
+        out.append((host(dq), host(dp)))
+    G = np.exp(-rc / pr.sigma) if kernel == 0 else np.exp(-(rc / pr.sigma) ** 2)
+    dG = G / pr.sigma if kernel == 0 else 2 * rc / pr.sigma ** 2 * G
+    pn = np.sqrt(np.sum(p * p, axis=0))
+    bv, bf = G * pn.sum(), dG * pn * pn.sum()
+    slack = 1e-12 * max(np.max(np.abs(dq_o)), np.max(np.abs(dp_o)))
+    dqs, dps = out[1]
+    assert np.all(np.sqrt(np.sum((dqs - dq_o) ** 2, axis=0)) <= bv + slack)
+    assert np.all(np.sqrt(np.sum((dps - dp_o) ** 2, axis=0)) <= bf + slack)
+    assert rel_err(dqs, out[0][0]) <= 1e-12 and rel_err(dps, out[0][1]) <= 1e-12
+    assert np.max(np.abs(dqs - dq_o)) > 0.0      # something was skipped
+
+
+def test_sym_cutoff_shoot_matches_oracle():
+    pr = inputs.config_sphere3d(3000, kernel=lm.GAUSS, sigma=0.1)
+    q0, p0 = pr.X, pr.p_bench()
+    oq, op = oracle.shoot(q0, p0, lm.GAUSS, pr.sigma, 8)
+    prm = lm.make_params(3, lm.GAUSS, pr.sigma, cutoff=pr.sigma * 36.9 ** 0.5)
+    with _env(LM_SYM=1, LM_SYM_WAVES=2):
+        q, p = dev(q0), dev(p0)
+        q1, p1 = torch.empty_like(q), torch.empty_like(p)
+        lm.lm_shoot(prm, q, p, 1.0, 8, q1, p1)
+        torch.cuda.synchronize()
+    assert rel_err(host(q1), oq) <= 1e-10 and rel_err(host(p1), op) <= 1e-10

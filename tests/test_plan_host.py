@@ -58,9 +58,12 @@ def test_one_sided_split_rule(monkeypatch):
     assert p["workgroups"] == 64 * 32 and p["partial_slots"] == 32
 
 
-def test_single_precision_and_cutoff_keep_one_sided_kernel():
+def test_single_precision_keeps_one_sided_kernel_and_cutoff_runs_symmetric_in_double():
     assert plan(65536, dtype=lm.F32)["symmetric"] == 0
-    assert plan(65536, cutoff=0.3)["symmetric"] == 0
+    assert plan(65536, cutoff=0.3)["symmetric"] == 1
+    assert plan(49088, cutoff=0.3)["symmetric"] == 0        # 768 tiles needed with tile skipping
+    assert plan(49152, cutoff=0.3)["symmetric"] == 1
+    assert plan(65536, dtype=lm.F32, cutoff=0.3)["symmetric"] == 0
     assert plan(100, cutoff=0.3)["small"] == 0
 
 
