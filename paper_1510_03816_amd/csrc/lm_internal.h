@@ -182,8 +182,7 @@ struct SymArgs {
     const T* q;          // (dim, n)
     const T* p;
     int64_t n;
-    int64_t tiles;       // 64-point tiles
-    int64_t nsb;         // superblocks of 2 * waves tiles
+    int64_t nsb;         // superblocks of kSymRows * waves tiles
     double kq;
     double wscale;
     double* part;        // (nsb + 1, 2 dim, n) partial sums

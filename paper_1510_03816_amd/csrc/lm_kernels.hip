@@ -6,6 +6,10 @@
 // evaluated once per Runge-Kutta stage.  It is bound by vector ALU issue (a pair costs
 // about 45 VALU instructions in double precision and touches no memory), not by HBM, and
 // it is not a dense contraction, so it runs on the vector units rather than on MFMA.
+// This file holds the one-sided kernel (each target sums over all sources), used in single
+// precision, with targets other than the sources, and for double-precision sets below the
+// symmetric kernel's size rule (lm_sym.hip evaluates each unordered pair once); the finish
+// kernel that adds either kernel's partial sums; the batched kernels; reductions and sorts.
 //
 // Work decomposition.  A workgroup owns a tile of 64 targets i, one per lane, and
 // W = 4 wavefronts; the sources j of the tile are split into W * S contiguous chunks,
@@ -793,7 +797,6 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
             s.q = a.qs;
             s.p = a.ps;
             s.n = a.nt;
-            s.tiles = pl.itiles;
             s.nsb = pl.sym_nsb;
             s.kq = a.kq;
             s.wscale = a.wscale;
