@@ -148,6 +148,8 @@ typedef struct lm_plan_info {
     int32_t partial_slots;   /* partial sums per point added in a fixed order by a second
                                 launch (1: the pair-sum launch finishes the sums itself) */
     int32_t small;
+    int32_t rows;            /* symmetric: 64-point row tiles per wavefront (2, or 4 in the
+                                widest tier); one-sided: 1 (one target per lane) */
 } lm_plan_info;
 
 lm_status lm_pair_plan(const lm_params *params, int64_t n, lm_plan_info *info);

@@ -56,7 +56,7 @@ class lm_match_info(ctypes.Structure):
 
 class lm_plan_info(ctypes.Structure):
     _fields_ = [("symmetric", ctypes.c_int32), ("waves", ctypes.c_int32), ("workgroups", ctypes.c_int64),
-                ("partial_slots", ctypes.c_int32), ("small", ctypes.c_int32)]
+                ("partial_slots", ctypes.c_int32), ("small", ctypes.c_int32), ("rows", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -193,7 +193,7 @@ def lm_rhs(params: lm_params, q, p, dq, dp, stream=None):
 
 def lm_pair_plan(params: lm_params, n: int) -> dict:
     """The pair-sum launch plan for n points (host only): symmetric, waves, workgroups,
-    partial_slots, small."""
+    partial_slots, small, rows."""
     info = lm_plan_info()
     _check(load().lm_pair_plan(ctypes.byref(params), int(n), ctypes.byref(info)))
     return info.as_dict()

@@ -124,10 +124,12 @@ int64_t part_elems(const lm_params* prm, int64_t nt, int64_t ns)
     if (nt == ns) {
         // the symmetric kernel's slots under any setting of LM_SYM (forced or by size), and its
         // superblock-pair flags in tile-skipping mode
-        const lm::SymPlan sp = lm::plan_sym(nt, true, prm->dtype == LM_F32 ? lm::SYM_F32 : lm::SYM_F64);
-        if (sp.waves > 0) {
-            const int64_t ms = (sp.nsb + 1) * 2 * prm->dim * nt + lm::sym_flag_elems(sp.nsb);
-            if (ms > m) m = ms;
+        for (int cut = 0; cut < 2; ++cut) {
+            const lm::SymPlan sp = lm::plan_sym(nt, true, prm->dtype == LM_F32 ? lm::SYM_F32 : lm::SYM_F64, cut == 1);
+            if (sp.waves > 0) {
+                const int64_t ms = (sp.nsb + 1) * 2 * prm->dim * nt + lm::sym_flag_elems(sp.nsb);
+                if (ms > m) m = ms;
+            }
         }
     }
     return m;
@@ -1043,6 +1045,7 @@ lm_status lm_pair_plan(const lm_params* prm, int64_t n, lm_plan_info* info)
     info->workgroups = pl.sym_waves > 0 ? pl.sym_nsb * (pl.sym_nsb + 1) / 2 : pl.itiles * pl.nsplit;
     info->partial_slots = pl.nsplit;
     info->small = !cut && n <= lm::kSmallMax;
+    info->rows = pl.sym_waves > 0 ? pl.sym_rows : 1;
     return LM_OK;
 }
 

@@ -164,6 +164,7 @@ struct PairPlan {
     int nsplit;          // partial-sum slots per target (1: none)
     int64_t jchunk;
     int sym_waves;       // > 0: symmetric kernel (lm_sym.hip) with this many waves per workgroup
+    int sym_rows;        // and this many row tiles per wave
     int64_t sym_nsb;     // its superblock count S (nsplit = S + 1)
 };
 
@@ -182,7 +183,8 @@ struct SymArgs {
     const T* q;          // (dim, n)
     const T* p;
     int64_t n;
-    int64_t nsb;         // superblocks of kSymRows * waves tiles
+    int64_t nsb;         // superblocks of rows * waves tiles
+    int rows;            // row tiles per wave: kSymRows, or kSymRowsWide (double, forces, no cutoff)
     double kq;
     double wscale;
     double* part;        // (nsb + 1, 2 dim, n) partial sums
@@ -197,6 +199,7 @@ inline int64_t sym_flag_elems(int64_t nsb) { return (nsb * (nsb + 1) / 2 + 7) / 
 
 struct SymPlan {
     int waves = 0;       // 0: not worth it (too few wavefronts) or too large
+    int rows = 2;        // row tiles per wave
     int64_t nsb = 0;
 };
 
@@ -214,6 +217,8 @@ constexpr int kSymRows = LM_SYM_ROWS;   // 64-point row tiles per wavefront
 #define LM_SYM_OCC (LM_SYM_ROWS > 2 ? 3 : 4)
 #endif
 constexpr int kSymOccupancy = LM_SYM_OCC;   // wavefronts per SIMD the register budget allows
+constexpr int kSymRowsWide = 4;             // the widest tier (lm_sym_pair_wide_kernel)
+constexpr int kSymOccupancyWide = 3;
 #ifndef LM_SYM_MIN_TILES
 #define LM_SYM_MIN_TILES 192
 #endif
@@ -241,7 +246,8 @@ constexpr int64_t kSymVjpMinTiles = 128;
 constexpr int64_t kSymVjpTwoWaveTiles = 192;
 constexpr int64_t kSymMaxPartBytes = (int64_t)16 << 30;
 
-SymPlan plan_sym(int64_t n, bool force, int kind);
+// cut: tile skipping (the wide tier has no tile skipping)
+SymPlan plan_sym(int64_t n, bool force, int kind, bool cut = false);
 template <class T>
 hipError_t launch_sym_pair(int dim, int kernel, bool force, const SymArgs<T>& a, int waves, hipStream_t st);
 

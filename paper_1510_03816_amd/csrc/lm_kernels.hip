@@ -798,6 +798,7 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
             s.p = a.ps;
             s.n = a.nt;
             s.nsb = pl.sym_nsb;
+            s.rows = pl.sym_rows;
             s.kq = a.kq;
             s.wscale = a.wscale;
             s.part = a.part;
@@ -807,7 +808,7 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
                 s.rc2 = a.rc2;
                 s.flags = (uint8_t*)(a.part + (int64_t)pl.nsplit * (2 * DIM) * a.nt);
                 flags = s.flags;
-                sbp = (int64_t)kTile * kSymRows * pl.sym_waves;
+                sbp = (int64_t)kTile * pl.sym_rows * pl.sym_waves;
             }
             err = launch_sym_pair<T>(DIM, KER, FORCE, s, pl.sym_waves, st);
         }

@@ -19,9 +19,10 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, int kind)
         const int mode = e ? atoi(e) : -1;
         const bool small_cut = cut && mode != 1 && pl.itiles < kSymCutTiles;
         if (mode != 0 && !small_cut) {
-            const SymPlan sp = plan_sym(nt, mode == 1, kind);
+            const SymPlan sp = plan_sym(nt, mode == 1, kind, cut);
             if (sp.waves > 0) {
                 pl.sym_waves = sp.waves;
+                pl.sym_rows = sp.rows;
                 pl.sym_nsb = sp.nsb;
                 pl.nsplit = (int)(sp.nsb + 1);
                 pl.jchunk = ns;
@@ -47,20 +48,29 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, int kind)
     return pl;
 }
 
-SymPlan plan_sym(int64_t n, bool force, int kind)
+SymPlan plan_sym(int64_t n, bool force, int kind, bool cut)
 {
     SymPlan sp{};
     const int64_t T = tiles_of(n);
-    // LM_SYM_WAVES fixes the workgroup width (tuning runs, tests of every width)
+    // LM_SYM_WAVES fixes the workgroup width and LM_SYM_ROWS the row tiles per wave (tuning
+    // runs, tests of every shape); four rows exist for double-precision sums without cutoff
     const char* env = getenv("LM_SYM_WAVES");
     const int fixed = env ? atoi(env) : 0;
+    const char* env_rows = getenv("LM_SYM_ROWS");
+    const int fixed_rows = env_rows ? atoi(env_rows) : 0;
+    const bool wide_ok = kind == SYM_F64 && !cut;
+    int rows = kSymRows;
     int w = 0;
     if (fixed == 1 || fixed == 2 || fixed == 4 || fixed == 8) {
         w = fixed;
+        // (at most four waves: sums without forces fall back to two rows and twice the waves)
+        if (wide_ok && fixed_rows == kSymRowsWide && fixed <= 4) rows = kSymRowsWide;
     } else if (kind == SYM_VJP) {
         w = T >= kSymVjpTwoWaveTiles ? 2 : T >= kSymVjpMinTiles ? 1 : 0;
     } else if (kind == SYM_F64 && T >= kSymWideTiles) {
-        w = 4;
+        // superblocks of 8 tiles: four rows and two waves, or (with tile skipping) two and four
+        rows = (wide_ok && fixed_rows != kSymRows) ? kSymRowsWide : kSymRows;
+        w = 8 / rows;
     } else if (T >= (kind == SYM_F32 ? kSymMinTilesF32 : kSymMinTiles)) {
         w = 2;
     } else if (kind == SYM_F64 && T >= kSymOneWaveTiles) {
@@ -71,10 +81,11 @@ SymPlan plan_sym(int64_t n, bool force, int kind)
     // partial sums: (S + 1) slots of up to 6 doubles per point; wider superblocks need
     // fewer, and beyond the cap the one-sided kernel (at most 64 slots) is used instead
     for (;; w *= 2) {
-        const int64_t S = (T + kSymRows * w - 1) / (kSymRows * w);
+        const int64_t S = (T + rows * w - 1) / (rows * w);
         const bool fits = (S + 1) * 6 * n * (int64_t)sizeof(double) <= kSymMaxPartBytes;
         if (fits && S * (S + 1) / 2 < ((int64_t)1 << 31)) {
             sp.waves = w;
+            sp.rows = rows;
             sp.nsb = S;
             return sp;
         }

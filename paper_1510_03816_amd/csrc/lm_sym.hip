@@ -192,27 +192,27 @@ __device__ __forceinline__ bool sym_tiles_far(const double* __restrict__ a, cons
 
 // CUT: a row tile whose box lies farther than the cutoff from column tile J's box skips it
 // (both directions of its pairs: the block is evaluated once, here or nowhere).
-template <class T, int DIM, int KER, bool FORCE, bool CUT, class A>
-__device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[kSymRows], int64_t J, int64_t NT,
-                                         const T (&qi)[kSymRows][DIM], const T (&pi)[kSymRows][DIM],
-                                         const T* __restrict__ jb, T kq, A (&v)[kSymRows][DIM], A (&f)[kSymRows][DIM],
+template <class T, int DIM, int KER, bool FORCE, bool CUT, int ROWS, class A>
+__device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[ROWS], int64_t J, int64_t NT,
+                                         const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM],
+                                         const T* __restrict__ jb, T kq, A (&v)[ROWS][DIM], A (&f)[ROWS][DIM],
                                          double* __restrict__ acc, const double* __restrict__ box, double rc2)
 {
-    bool far[kSymRows];
+    bool far[ROWS];
     bool any_far = false;
 #pragma unroll
-    for (int r = 0; r < kSymRows; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
         far[r] = CUT && I[r] < NT && sym_tiles_far<DIM>(box + I[r] * 8, box + J * 8, rc2);
         any_far = any_far || far[r];
     }
     // every row tile meets J from both sides, except near the diagonal (and skipped tiles)
-    const bool all = (diag ? J > I[kSymRows - 1] : I[kSymRows - 1] < NT) && !any_far;
+    const bool all = (diag ? J > I[ROWS - 1] : I[ROWS - 1] < NT) && !any_far;
     if (all) {
-        sym_block<T, DIM, KER, FORCE, kSymRows, true>(qi, pi, jb, kq, v, f, acc);
+        sym_block<T, DIM, KER, FORCE, ROWS, true>(qi, pi, jb, kq, v, f, acc);
         return;
     }
 #pragma unroll
-    for (int r = 0; r < kSymRows; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
         const int m = far[r] ? SYM_SKIP : sym_mode(diag, I[r], J, NT);
         if (m == SYM_SKIP) continue;
         T q1[1][DIM], p1[1][DIM], v1[1][DIM], f1[1][DIM];
@@ -240,7 +240,7 @@ __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[kSymRows]
 // part, (S + 1) slots of 2 dim x n doubles.  CUT: flags[b] (b = the pair's number) says
 // whether the pair wrote its slots; a pair whose tiles are all farther apart than the cutoff
 // writes nothing else (lm_finish_kernel skips its slots).
-template <class T, int DIM, int KER, bool FORCE, bool CUT>
+template <class T, int DIM, int KER, bool FORCE, bool CUT, int ROWS>
 __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, const T* __restrict__ p, int64_t ld,
                                                     int64_t n, int64_t S, int64_t X, int64_t Y, double kqd,
                                                     double wscale, double* __restrict__ part,
@@ -253,7 +253,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int64_t side = kSymRows * (int64_t)nw;
+    const int64_t side = ROWS * (int64_t)nw;
     double* region = lds_words;                                // [nw][EC][128]
     T* jbuf = reinterpret_cast<T*>(region + nw * EC * 128);    // [128][E]
 
@@ -276,12 +276,12 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     }
 
     // row points in registers; their sums over one column tile in T, over all tiles in double
-    int64_t I[kSymRows];
-    T qi[kSymRows][DIM], pi[kSymRows][DIM];
-    double vs[kSymRows][DIM], fs[kSymRows][DIM];
+    int64_t I[ROWS];
+    T qi[ROWS][DIM], pi[ROWS][DIM];
+    double vs[ROWS][DIM], fs[ROWS][DIM];
 #pragma unroll
-    for (int r = 0; r < kSymRows; ++r) {
-        I[r] = X * side + kSymRows * wave + r;
+    for (int r = 0; r < ROWS; ++r) {
+        I[r] = X * side + ROWS * wave + r;
         const int64_t i = I[r] * kSymSteps + lane;
         const bool live = i < n;
 #pragma unroll
@@ -305,19 +305,19 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     double* pc = part + slot_col * (2 * DIM) * n;
     for (int64_t J = J0; J < J1; ++J) {
         if constexpr (sizeof(T) == sizeof(double)) {
-            sym_tile<T, DIM, KER, FORCE, CUT>(diag, I, J, NT, qi, pi, jb, kq, vs, fs, acc, box, rc2);
+            sym_tile<T, DIM, KER, FORCE, CUT, ROWS>(diag, I, J, NT, qi, pi, jb, kq, vs, fs, acc, box, rc2);
         } else {
-            T v[kSymRows][DIM], f[kSymRows][DIM];
+            T v[ROWS][DIM], f[ROWS][DIM];
 #pragma unroll
-            for (int r = 0; r < kSymRows; ++r)
+            for (int r = 0; r < ROWS; ++r)
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
                     v[r][c] = (T)0;
                     f[r][c] = (T)0;
                 }
-            sym_tile<T, DIM, KER, FORCE, CUT>(diag, I, J, NT, qi, pi, jb, kq, v, f, acc, box, rc2);
+            sym_tile<T, DIM, KER, FORCE, CUT, ROWS>(diag, I, J, NT, qi, pi, jb, kq, v, f, acc, box, rc2);
 #pragma unroll
-            for (int r = 0; r < kSymRows; ++r)
+            for (int r = 0; r < ROWS; ++r)
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
                     vs[r][c] += (double)v[r][c];
@@ -345,7 +345,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
 
     double* pr = part + Y * (2 * DIM) * n;
 #pragma unroll
-    for (int r = 0; r < kSymRows; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
         const int64_t i = I[r] * kSymSteps + lane;
         if (I[r] >= NT || i >= n) continue;
 #pragma unroll
@@ -361,8 +361,22 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_sym_pair_kernel(SymArgs
 {
     int64_t X, Y;
     sym_superblocks(blockIdx.x, a.nsb, X, Y);
-    sym_superblock_pair<T, DIM, KER, FORCE, CUT>(a.q, a.p, a.n, a.n, a.nsb, X, Y, a.kq, a.wscale, a.part, a.box,
-                                                 a.rc2, a.flags, blockIdx.x);
+    sym_superblock_pair<T, DIM, KER, FORCE, CUT, kSymRows>(a.q, a.p, a.n, a.n, a.nsb, X, Y, a.kq, a.wscale, a.part,
+                                                           a.box, a.rc2, a.flags, blockIdx.x);
+}
+
+// The widest tier (double precision with forces, every pair, large N): four row tiles per
+// wave, so each staged column entry and each column-array add serves four pairs instead of
+// two, at 143-185 VGPRs (three waves per SIMD).  Measured at N = 65536 (two waves per
+// workgroup, superblocks of 8 tiles as with two rows and four waves): conon 3613 us per stage
+// against 3748, Gaussian 2841 against 2969; at N = 131072 13861 against 14576.
+template <class T, int DIM, int KER>
+__global__ __launch_bounds__(512, kSymOccupancyWide) void lm_sym_pair_wide_kernel(SymArgs<T> a)
+{
+    int64_t X, Y;
+    sym_superblocks(blockIdx.x, a.nsb, X, Y);
+    sym_superblock_pair<T, DIM, KER, true, false, kSymRowsWide>(a.q, a.p, a.n, a.n, a.nsb, X, Y, a.kq, a.wscale,
+                                                               a.part, nullptr, 0.0, nullptr, blockIdx.x);
 }
 
 // Batched: workgroup b takes item sym_items[b] = (problem, X, Y, S) of the concatenated
@@ -373,17 +387,33 @@ __global__ __launch_bounds__(512, kSymOccupancy) void lm_batch_sym_kernel(BatchA
     const int4 w = a.sym_items[blockIdx.x];
     const int64_t off = a.offs[w.x];
     const int64_t nb = a.offs[w.x + 1] - off;
-    sym_superblock_pair<T, DIM, KER, FORCE, false>(a.q + off, a.p + off, a.ntot, nb, w.w, w.y, w.z, a.kq, a.wscale,
-                                                   a.part + a.part_off[w.x], nullptr, 0.0, nullptr, 0);
+    sym_superblock_pair<T, DIM, KER, FORCE, false, kSymRows>(a.q + off, a.p + off, a.ntot, nb, w.w, w.y, w.z, a.kq,
+                                                             a.wscale, a.part + a.part_off[w.x], nullptr, 0.0, nullptr,
+                                                             0);
 }
 
 template <class T, int DIM, int KER, bool FORCE>
 hipError_t launch_sym_t(const SymArgs<T>& a, int waves, hipStream_t st)
 {
     constexpr int EC = FORCE ? 2 * DIM : DIM;
-    const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
     const int64_t S = a.nsb;
-    const dim3 grid((unsigned)(S * (S + 1) / 2)), block(64 * waves);
+    const dim3 grid((unsigned)(S * (S + 1) / 2));
+    if (a.rows == kSymRowsWide) {
+        if constexpr (sizeof(T) == sizeof(double) && FORCE) {
+            if (a.box == nullptr) {
+                const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
+                hipLaunchKernelGGL((lm_sym_pair_wide_kernel<T, DIM, KER>), grid, dim3(64 * waves), lds, st, a);
+                return hipGetLastError();
+            }
+        }
+        // the same superblocks with two row tiles per wave and twice the waves (velocity-only
+        // sums, e.g. the K x of a CG solve, run the two-row kernel)
+        waves = waves * kSymRowsWide / kSymRows;
+    } else if (a.rows != kSymRows) {
+        return hipErrorInvalidValue;
+    }
+    const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
+    const dim3 block(64 * waves);
     if (a.box == nullptr) {
         hipLaunchKernelGGL((lm_sym_pair_kernel<T, DIM, KER, FORCE, false>), grid, block, lds, st, a);
     } else if constexpr (sizeof(T) == sizeof(double) && FORCE) {

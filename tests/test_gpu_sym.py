@@ -28,7 +28,7 @@ def _gpu():
 
 
 class _env:
-    """Sets LM_SYM / LM_SYM_WAVES for the duration of a block."""
+    """Sets LM_SYM / LM_SYM_WAVES / LM_SYM_ROWS for the duration of a block."""
 
     def __init__(self, **kv):
         self.kv = {k: str(v) for k, v in kv.items()}
@@ -94,6 +94,40 @@ def test_sym_rhs_matches_oracle(n, dim, kernel, waves, dtype):
     assert eq <= TOL[dtype] and ep <= TOL[dtype]
     if n == 1:
         assert np.all(dp == 0.0)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4])
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("n", [1, 65, 700, 3007])
+def test_sym_wide_rows_match_oracle(n, dim, kernel, waves):
+    """Four row tiles per wave (the widest tier's kernel), forced at small sizes: the sums
+    with forces run it, the velocity-only K x of a CG solve falls back to two rows."""
+    q, p = inputs.random_state(n, dim, seed=[120, n, dim], box=1.0, pscale=0.3)
+    sigma, tau = (0.3 if dim == 3 else 0.25), 0.1
+    dq_o, dp_o = oracle.rhs(q, p, kernel, sigma, tau)
+    with _env(LM_SYM=1, LM_SYM_WAVES=waves, LM_SYM_ROWS=4):
+        dq, dp = gpu_rhs(q, p, kernel, sigma, tau)
+    assert rel_err(dq, dq_o) <= 1e-10 and rel_err(dp, dp_o) <= 1e-10
+
+
+def test_sym_wide_rows_shoot_and_velocity_only_products():
+    pr = inputs.config_curve2d(1000)
+    oq, op = oracle.shoot(pr.X, pr.p_bench(), pr.kernel, pr.sigma, 10)
+    X = pr.X
+    b = np.random.default_rng(121).standard_normal(X.shape)
+    st, L = oracle.cholesky(oracle.kmatrix(X, pr.kernel, pr.sigma))
+    want = np.stack([oracle.cholesky_solve(L, b[c]) for c in range(2)])
+    prm = lm.make_params(2, pr.kernel, pr.sigma)
+    with _env(LM_SYM=1, LM_SYM_WAVES=4, LM_SYM_ROWS=4):
+        q, p = dev(pr.X), dev(pr.p_bench())
+        q1, p1 = torch.empty_like(q), torch.empty_like(p)
+        lm.lm_shoot(prm, q, p, 1.0, 10, q1, p1)
+        x = torch.empty_like(q)
+        lm.lm_ksolve(prm, dev(X), dev(b), x, rtol=1e-13, solver=lm.SOLVE_CG)
+        torch.cuda.synchronize()
+    assert rel_err(host(q1), oq) <= 1e-10 and rel_err(host(p1), op) <= 1e-10
+    assert rel_err(host(x), want) <= 1e-8
 
 
 @pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])

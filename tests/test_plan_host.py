@@ -12,6 +12,7 @@ import paper_1510_03816_amd as lm
 def _clean_env(monkeypatch):
     monkeypatch.delenv("LM_SYM", raising=False)
     monkeypatch.delenv("LM_SYM_WAVES", raising=False)
+    monkeypatch.delenv("LM_SYM_ROWS", raising=False)
 
 
 def plan(n, dtype=lm.F64, cutoff=0.0, dim=3):
@@ -19,31 +20,33 @@ def plan(n, dtype=lm.F64, cutoff=0.0, dim=3):
     return lm.lm_pair_plan(prm, n)
 
 
-def sym(T, w):
+def sym(T, w, rows=2):
     """Superblock count, workgroups and partial slots of the symmetric kernel for T tiles."""
-    S = -(-T // (2 * w))
+    S = -(-T // (rows * w))
     return S, S * (S + 1) // 2, S + 1
 
 
-def test_full_size_double_uses_symmetric_kernel_with_four_waves():
-    S, wg, slots = sym(1024, 4)
-    assert plan(65536) == {"symmetric": 1, "waves": 4, "workgroups": wg, "partial_slots": slots, "small": 0}
+def test_full_size_double_uses_the_wide_symmetric_tier():
+    """Four row tiles per wave, two waves per workgroup: superblocks of 8 tiles."""
+    S, wg, slots = sym(1024, 2, 4)
+    assert plan(65536) == {"symmetric": 1, "waves": 2, "workgroups": wg, "partial_slots": slots, "small": 0,
+                           "rows": 4}
     assert (S, wg, slots) == (128, 8256, 129)
 
 
-@pytest.mark.parametrize("n,waves", [(8129, 1), (8192, 1), (12224, 1), (12288, 2), (16384, 2), (49088, 2),
-                                     (49089, 4), (131072, 4)])
-def test_size_rule(n, waves):
+@pytest.mark.parametrize("n,waves,rows", [(8129, 1, 2), (8192, 1, 2), (12224, 1, 2), (12288, 2, 2), (16384, 2, 2),
+                                          (49088, 2, 2), (49089, 2, 4), (131072, 2, 4)])
+def test_size_rule(n, waves, rows):
     p = plan(n)
     T = -(-n // 64)
-    assert p["symmetric"] == 1 and p["waves"] == waves
-    assert (p["workgroups"], p["partial_slots"]) == sym(T, waves)[1:]
+    assert p["symmetric"] == 1 and p["waves"] == waves and p["rows"] == rows
+    assert (p["workgroups"], p["partial_slots"]) == sym(T, waves, rows)[1:]
 
 
 @pytest.mark.parametrize("n", [1, 257, 4096, 8128])
 def test_small_sizes_keep_one_sided_kernel(n):
     p = plan(n)
-    assert p["symmetric"] == 0 and p["waves"] == 4
+    assert p["symmetric"] == 0 and p["waves"] == 4 and p["rows"] == 1
     assert p["small"] == (1 if n <= 256 else 0)
 
 
@@ -51,7 +54,7 @@ def test_one_sided_split_rule(monkeypatch):
     # 128 target tiles: 16384 workgroups wanted, capped at 16 source splits from 128 tiles on
     monkeypatch.setenv("LM_SYM", "0")
     p = plan(8192)
-    assert p == {"symmetric": 0, "waves": 4, "workgroups": 128 * 16, "partial_slots": 16, "small": 0}
+    assert p == {"symmetric": 0, "waves": 4, "workgroups": 128 * 16, "partial_slots": 16, "small": 0, "rows": 1}
     monkeypatch.delenv("LM_SYM")
     # 64 tiles of 2-D points: 256 splits wanted, limited to 64 (and by the 32-source chunk floor)
     p = plan(4096, dim=2)
@@ -60,7 +63,8 @@ def test_one_sided_split_rule(monkeypatch):
 
 def test_single_precision_keeps_one_sided_kernel_and_cutoff_runs_symmetric_in_double():
     assert plan(65536, dtype=lm.F32)["symmetric"] == 0
-    assert plan(65536, cutoff=0.3)["symmetric"] == 1
+    p = plan(65536, cutoff=0.3)                 # tile skipping: two rows, four waves, same superblocks
+    assert p["symmetric"] == 1 and p["rows"] == 2 and p["waves"] == 4 and p["partial_slots"] == 129
     assert plan(49088, cutoff=0.3)["symmetric"] == 0        # 768 tiles needed with tile skipping
     assert plan(49152, cutoff=0.3)["symmetric"] == 1
     assert plan(65536, dtype=lm.F32, cutoff=0.3)["symmetric"] == 0
@@ -75,9 +79,19 @@ def test_environment_overrides(monkeypatch):
     assert p["symmetric"] == 1 and p["waves"] == 1 and p["partial_slots"] == 9 and p["workgroups"] == 36
     monkeypatch.setenv("LM_SYM_WAVES", "8")
     p = plan(65536)
-    assert p["waves"] == 8 and (p["workgroups"], p["partial_slots"]) == sym(1024, 8)[1:]
+    assert p["waves"] == 8 and p["rows"] == 2 and (p["workgroups"], p["partial_slots"]) == sym(1024, 8)[1:]
+    monkeypatch.setenv("LM_SYM_ROWS", "4")
+    assert plan(65536)["rows"] == 2                   # four rows take at most four waves
+    monkeypatch.setenv("LM_SYM_WAVES", "4")
+    p = plan(65536)
+    assert p["waves"] == 4 and p["rows"] == 4 and (p["workgroups"], p["partial_slots"]) == sym(1024, 4, 4)[1:]
+    assert plan(65536, dtype=lm.F32)["rows"] == 2     # four rows: double precision only
+    monkeypatch.delenv("LM_SYM_ROWS")
     monkeypatch.setenv("LM_SYM_WAVES", "3")   # not a width: the size rule applies
-    assert plan(65536)["waves"] == 4
+    assert plan(65536)["waves"] == 2 and plan(65536)["rows"] == 4
+    monkeypatch.delenv("LM_SYM_WAVES")
+    monkeypatch.setenv("LM_SYM_ROWS", "2")    # two rows in the wide tier: four waves
+    assert plan(65536)["waves"] == 4 and plan(65536)["rows"] == 2
 
 
 def test_invalid_arguments():
