@@ -352,7 +352,8 @@ def main():
     if plan["symmetric"]:
         slots = SLOTS_PER_PAIR[(dim, pr.kernel)] + 2 * dim
         evals = n * (n + 1) // 2
-        kname = "lm_sym_pair_kernel<%s> + lm_finish_kernel" % kname
+        kname = "%s<%s> + lm_finish_kernel" % ("lm_sym_pair_wide_kernel" if plan["rows"] == 4 else "lm_sym_pair_kernel",
+                                               kname)
     else:
         slots = SLOTS_PER_PAIR[(dim, pr.kernel)]
         evals = n * n
