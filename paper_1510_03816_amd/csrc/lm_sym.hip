@@ -8,15 +8,16 @@
 // The shared part (distance, 1/sqrt, exponential, weight, momentum product) is about three
 // quarters of a pair's work, so a sweep over the N(N+1)/2 unordered pairs costs about 55% of
 // the N^2 ordered ones.  Used for the self-interaction of one point set (right-hand side, RK4
-// stages, K x); targets distinct from the sources and tile skipping keep the one-sided
-// kernel in lm_kernels.hip.  In single precision a row point's pairs with one column tile (64
-// steps) are summed in float and those sums in double, as the one-sided kernel sums runs of
-// 64 sources; column-side terms are added in double.
+// stages, K x, with or without tile skipping, and a batch's larger problems); targets distinct
+// from the sources keep the one-sided kernel in lm_kernels.hip.  In single precision a row
+// point's pairs with one column tile (64 steps) are summed in float and those sums in double,
+// as the one-sided kernel sums runs of 64 sources; column-side terms are added in double.
 //
-// Decomposition.  The 64-point tiles are grouped into superblocks of B = 2W tiles; a
+// Decomposition.  The 64-point tiles are grouped into superblocks of B = R W tiles; a
 // workgroup of W wavefronts takes one pair (X, Y), X <= Y, of superblocks.  Wave w owns the
-// two row tiles X*B + 2w and X*B + 2w + 1 (one point of each per lane, in registers, with
-// their row sums) and the W waves walk the B column tiles of superblock Y together:
+// R row tiles X*B + R w ... X*B + R w + R - 1 (R = 2, or 4 in the widest tier: one point of
+// each per lane, in registers, with their row sums) and the W waves walk the B column tiles
+// of superblock Y together:
 //   - the column tile (q, p interleaved) is staged in LDS twice in a row, so that at step k
 //     lane l reads entry l + k -- point (l + k) mod 64 -- at an immediate offset, and over 64
 //     steps every lane meets every point of the tile once;
@@ -31,8 +32,9 @@
 // Partial sums.  A point of superblock Z receives one partial from each superblock pair that
 // contains Z: from (Z, Y), Y > Z, as a row (slot Y); from (Y, Z), Y < Z, as a column (slot Y);
 // from (Z, Z) both (row: slot Z, column: slot S).  Every one of the S + 1 slots of a point is
-// written exactly once per launch, and lm_finish_kernel adds them in a fixed order, so the
-// result is bitwise reproducible.  The force constant is applied when a partial is written.
+// written exactly once per launch (with tile skipping, or flagged empty), and lm_finish_kernel
+// adds them in a fixed order, so the result is bitwise reproducible.  The force constant is
+// applied when a partial is written.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -174,8 +176,6 @@ __device__ __forceinline__ void sym_stage(T* __restrict__ jbuf, const T* __restr
     }
 }
 
-// The row tiles of this wave against column tile J (staged at jb), sums added to (v, f): both
-// rows symmetrically in one pass when they allow it, else row by row by mode.
 // Whether the bounding boxes of tiles a and b (8 doubles each: lo[4], hi[4]) lie farther apart
 // than sqrt(rc2), so that every pair between them does.
 template <int DIM>
@@ -190,8 +190,10 @@ __device__ __forceinline__ bool sym_tiles_far(const double* __restrict__ a, cons
     return g2 > rc2;
 }
 
-// CUT: a row tile whose box lies farther than the cutoff from column tile J's box skips it
-// (both directions of its pairs: the block is evaluated once, here or nowhere).
+// The ROWS row tiles of this wave against column tile J (staged at jb), sums added to (v, f):
+// all rows symmetrically in one pass when they allow it, else row by row by mode.  CUT: a row
+// tile whose box lies farther than the cutoff from column tile J's box skips it (both
+// directions of its pairs: the block is evaluated once, here or nowhere).
 template <class T, int DIM, int KER, bool FORCE, bool CUT, int ROWS, class A>
 __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[ROWS], int64_t J, int64_t NT,
                                          const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM],
