@@ -376,6 +376,7 @@ struct DenseFactor {
 // Whether the dense factor of an n-point problem fits in half the free device memory.
 bool dense_fits(int64_t n)
 {
+    if (n >= lm::kDenseMaxN) return false;
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return false;
     const double need = 8.0 * (double)n * (double)n + 8.0 * (double)lm::dense_linv_elems(n);

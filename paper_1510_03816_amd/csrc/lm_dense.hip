@@ -291,9 +291,25 @@ __global__ __launch_bounds__(256) void lm_syrk_kernel(double* __restrict__ K, in
 // operand row then feeds twice the arithmetic.  Wave w computes the 64 x 64 quarter
 // (w/2, w%2), 4 x 16 instructions per k-step of 4 with 64 accumulators per lane.  Operands go
 // through LDS 32 columns at a time; the next chunk is fetched into registers while the
-// current one is multiplied.
-__global__ __launch_bounds__(256) void lm_syrk128_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
-                                                         int64_t t0)
+// current one is multiplied.  A wave stays within 256 registers (246: 128 accumulators, 64
+// staged values, one k-step's operands) so that two workgroups share a CU and one multiplies
+// while the other stages its next chunk: the fetches are buffer loads from the tile's first
+// row with one 32-bit lane offset (rows past n fall outside the buffer's range and read as
+// zero) instead of a live pointer per staged row, the k-steps are not unrolled, and the
+// epilogue works on a quarter of the tile at a time.  With one workgroup per CU (384
+// registers) the N = 65536 factorization took 2.66 s, with two 2.04 s (MI355X).
+constexpr int kSyrkRsrcWord3 = 0x00020000;   // raw buffer, 32-bit elements (gfx9 encoding)
+
+__device__ __forceinline__ double syrk_load(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+// A lane whose column lies past the block width loads from 2^31 bytes on, outside every
+// operand buffer (at most 2^31 - 1 bytes), which reads as zero without a branch.
+__device__ __forceinline__ unsigned syrk_col_off(unsigned off, bool in_block) { return in_block ? off : 0x80000000u; }
+
+__global__ __launch_bounds__(256, 2) void lm_syrk128_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
+                                                            int64_t t0)
 {
     constexpr int KC = 32;
     constexpr int LD = KC + 4;   // row pitch of the staged operands (spreads rows over banks)
@@ -310,17 +326,26 @@ __global__ __launch_bounds__(256) void lm_syrk128_kernel(double* __restrict__ K,
     const bool diag = (ti == tj);
     const bool active = !(diag && wc > wr);   // the quarter above a diagonal tile's diagonal is not needed
 
-    // staging: thread t holds column t%32 of rows t/32 + 8u (u < 16) of each operand, so one
-    // load instruction of a wave reads two whole 256-byte row segments
-    const int sc = tid & 31, sr = tid >> 5;
-    const double* gi_col = K + (ri + sr) * n + k0 + sc;
-    const double* gj_col = K + (rj + sr) * n + k0 + sc;
-    double pa[16], pb[16];
+    // staging: thread t holds column t%KC of rows t/KC + RS u (u < NU) of each operand, so one
+    // load instruction of a wave reads whole row segments of KC doubles.  Byte offsets from
+    // (row ri or rj, column k0): row r, column c at 8 (r n + c); the buffer holds the tile's
+    // rows below n.  128 n 8 bytes fit the 31-bit range for n below 2^21.
+    constexpr int RS = 256 / KC, NU = 128 / RS;
+    const int sc = tid % KC, sr = tid / KC;
+    const int64_t rows_i = (n - ri) < 128 ? (n - ri) : 128;
+    const int64_t rows_j = (n - rj) < 128 ? (n - rj) : 128;
+    const __amdgpu_buffer_rsrc_t bi =
+        __builtin_amdgcn_make_buffer_rsrc(K + ri * n + k0, (short)0, (int)(rows_i * n * 8), kSyrkRsrcWord3);
+    const __amdgpu_buffer_rsrc_t bj =
+        __builtin_amdgcn_make_buffer_rsrc(K + rj * n + k0, (short)0, (int)(rows_j * n * 8), kSyrkRsrcWord3);
+    const unsigned rowstep = (unsigned)(RS * n * 8);   // RS rows, in bytes
+    const unsigned lane_off = (unsigned)((sr * n + sc) * 8);
+    double pa[NU], pb[NU];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const bool okc = sc < bs;
-        pa[u] = (okc && ri + sr + 8 * u < n) ? gi_col[8 * u * n] : 0.0;
-        pb[u] = (okc && rj + sr + 8 * u < n) ? gj_col[8 * u * n] : 0.0;
+    for (int u = 0; u < NU; ++u) {
+        const unsigned off = syrk_col_off(lane_off, sc < bs);
+        pa[u] = syrk_load(bi, off + u * rowstep);
+        pb[u] = syrk_load(bj, off + u * rowstep);
     }
 
     double acc[4][16];
@@ -333,22 +358,22 @@ __global__ __launch_bounds__(256) void lm_syrk128_kernel(double* __restrict__ K,
     const double* aj = Aj + (wc * 64 + (lane & 3)) * LD + (lane >> 4);
     for (int kc = 0; kc < bs; kc += KC) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            Ai[(sr + 8 * u) * LD + sc] = pa[u];
-            Aj[(sr + 8 * u) * LD + sc] = pb[u];
+        for (int u = 0; u < NU; ++u) {
+            Ai[(sr + RS * u) * LD + sc] = pa[u];
+            Aj[(sr + RS * u) * LD + sc] = pb[u];
         }
         __syncthreads();
         const int kn = kc + KC;
         if (kn < bs) {
-            const bool okc = kn + sc < bs;
+            const unsigned off = syrk_col_off(lane_off + (unsigned)kn * 8, kn + sc < bs);
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                pa[u] = (okc && ri + sr + 8 * u < n) ? gi_col[8 * u * n + kn] : 0.0;
-                pb[u] = (okc && rj + sr + 8 * u < n) ? gj_col[8 * u * n + kn] : 0.0;
+            for (int u = 0; u < NU; ++u) {
+                pa[u] = syrk_load(bi, off + u * rowstep);
+                pb[u] = syrk_load(bj, off + u * rowstep);
             }
         }
         if (active) {
-#pragma unroll
+#pragma unroll 1
             for (int k4 = 0; k4 < KC; k4 += 4) {
                 double fa[4], fb[16];
 #pragma unroll
@@ -365,25 +390,24 @@ __global__ __launch_bounds__(256) void lm_syrk128_kernel(double* __restrict__ K,
         __syncthreads();
     }
     if (!active) return;
-    // read every old value of the tile before the first store, so the 64 loads overlap
-    // (interleaved read-modify-writes would wait for each load in turn)
-    double old[4][16];
+    // read-modify-write in four groups of 16 values: each group's loads are all issued before
+    // its first store (one load in flight at a time would serialise them), and a group's 32
+    // registers fit beside the accumulators within the two-wave budget
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const int64_t gi = ri + wr * 64 + a * 16 + mfma4_row(lane);
-            const int64_t gj = rj + wc * 64 + c * 4 + (lane & 3);
-            old[a][c] = (gi < n && gj <= gi) ? K[gi * n + gj] : 0.0;
-        }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+        const int64_t gi = ri + wr * 64 + a * 16 + mfma4_row(lane);
+        double old[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            const int64_t gi = ri + wr * 64 + a * 16 + mfma4_row(lane);
             const int64_t gj = rj + wc * 64 + c * 4 + (lane & 3);
-            if (gi < n && gj <= gi) K[gi * n + gj] = old[a][c] - acc[a][c];
+            old[c] = (gi < n && gj <= gi) ? K[gi * n + gj] : 0.0;
         }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int64_t gj = rj + wc * 64 + c * 4 + (lane & 3);
+            if (gi < n && gj <= gi) K[gi * n + gj] = old[c] - acc[a][c];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -723,6 +747,7 @@ int64_t dense_linv_elems(int64_t n) { return 2 * (int64_t)dense_panels(n) * kPan
 hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,
                                double* Linv, int* info, hipStream_t st)
 {
+    if (n <= 0 || n >= kDenseMaxN) return hipErrorInvalidValue;
     hipLaunchKernelGGL(lm_int_zero_kernel, dim3(1), dim3(64), 0, st, info);
     if (dim == 2) {
         if (kernel == LM_KERNEL_CONON)

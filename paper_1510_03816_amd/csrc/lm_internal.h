@@ -281,6 +281,9 @@ hipError_t launch_convert(TO* y, const TI* x, int64_t m, hipStream_t st);
 
 // Dense K(X) = L L^T (lower triangle of a row-major n x n buffer) with the inverses of the
 // 128 x 128 diagonal blocks (dense_linv_elems doubles); *info != 0 flags a non-positive pivot.
+// n must stay below kDenseMaxN: the trailing update addresses 128 rows of the matrix with
+// 31-bit byte offsets (a factor that size would need 35 TB anyway).
+constexpr int64_t kDenseMaxN = (int64_t)1 << 21;
 int dense_panels(int64_t n);
 int64_t dense_linv_elems(int64_t n);
 hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,

@@ -515,6 +515,21 @@ def test_dense_ksolve_matches_cholesky(n, dim, kernel, sigma, tau):
     assert err <= max(1e-12, 1e-15 * cond)
 
 
+def test_dense_ksolve_several_trailing_updates_matches_cg():
+    """N = 5000: three trailing updates on 128 x 128 tiles (the last tile row ragged), checked
+    against conjugate gradients on the same system (matrix-free, through the pair kernel)."""
+    n = 5000
+    X = inputs.fibonacci_sphere(n)
+    b = np.random.default_rng([113, n]).standard_normal(X.shape)
+    prm = lm.make_params(3, lm.CONON, 0.15, tau=0.1)
+    xd, xc = (torch.empty((3, n), dtype=torch.float64, device=DEV) for _ in range(2))
+    assert lm.lm_ksolve(prm, dev(X), dev(b), xd, solver=lm.SOLVE_DENSE) == 0
+    it = lm.lm_ksolve(prm, dev(X), dev(b), xc, solver=lm.SOLVE_CG, rtol=1e-13, max_iter=5000)
+    err = rel_err(host(xd), host(xc))
+    print("n=%d dense vs CG (%d iterations) rel diff %.2e" % (n, it, err))
+    assert err <= 1e-9
+
+
 def test_dense_ksolve_reports_singular_kernel_matrix():
     X = np.zeros((2, 300))          # every point at the origin: K is the all-ones matrix
     X[0, :] = np.linspace(0, 1e-9, 300)
