@@ -62,18 +62,16 @@ lm_status check_n(int64_t n, const char* name)
     return LM_OK;
 }
 
-void kernel_scales(const lm_params* prm, bool f32, double* kq, double* wscale)
+void kernel_scales(const lm_params* prm, double* kq, double* wscale)
 {
     const double s = prm->sigma;
-    const double log2e = 1.4426950408889634;
     if (prm->kernel == LM_KERNEL_CONON) {
-        *kq = -1.0 / s;
+        *kq = -kLog2e / s;
         *wscale = 1.0 / s;
     } else {
-        *kq = -1.0 / (s * s);
+        *kq = -kLog2e / (s * s);
         *wscale = 2.0 / (s * s);
     }
-    if (f32) *kq *= log2e;
 }
 
 }  // namespace lmh
@@ -106,7 +104,7 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
     a.nt = nt;
     a.ns = ns;
     a.jchunk = pl.jchunk;
-    kernel_scales(prm, sizeof(T) == 4, &a.kq, &a.wscale);
+    kernel_scales(prm, &a.kq, &a.wscale);
     a.part = part;
     a.box_s = cut.box_s;
     a.box_t = cut.box_t;
@@ -162,7 +160,7 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
         a.offs = nullptr;
         a.dt = dt;
         a.steps = steps;
-        kernel_scales(prm, sizeof(T) == 4, &a.kq, &a.wscale);
+        kernel_scales(prm, &a.kq, &a.wscale);
         a.tau = prm->tau;
         LM_HIP(lm::launch_small_shoot<T>(prm->dim, prm->kernel, a, 1, st));
         return LM_OK;
@@ -391,7 +389,7 @@ lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspa
     LM_TRY(ws.get(&f->Linv, lm::dense_linv_elems(n)));
     LM_TRY(ws.get(&f->info, 1));
     double kq, wscale;
-    kernel_scales(prm, false, &kq, &wscale);
+    kernel_scales(prm, &kq, &wscale);
     LM_HIP(lm::launch_dense_factor(prm->dim, prm->kernel, kq, prm->tau, X, n, f->L, f->Linv, f->info, st));
     int info = 0;
     LM_HIP(hipMemcpyAsync(&info, f->info, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -633,11 +631,11 @@ lm_status vjp_eval(const lm_params* prm, int64_t n, const double* q, const doubl
     A.jchunk = pl.jchunk;
     const double sg = prm->sigma;
     if (prm->kernel == LM_KERNEL_CONON) {
-        A.kq = -1.0 / sg;
+        A.kq = -lmh::kLog2e / sg;
         A.c1 = 1.0 / sg;
         A.c2 = 0.0;
     } else {
-        A.kq = -1.0 / (sg * sg);
+        A.kq = -lmh::kLog2e / (sg * sg);
         A.c1 = 2.0 / (sg * sg);
         A.c2 = -4.0 / (sg * sg * sg * sg);
     }

@@ -210,7 +210,7 @@ lm_status batch_eval(const lm_params* prm, const BatchPlan& pl, const T* q, cons
     a.sym_items = pl.sym_items_d;
     a.nsym = pl.nsym;
     a.sym_waves = pl.sym_waves;
-    kernel_scales(prm, sizeof(T) == 4, &a.kq, &a.wscale);
+    kernel_scales(prm, &a.kq, &a.wscale);
     a.epi = e;
     LM_HIP(lm::launch_batch_pair<T>(prm->dim, prm->kernel, true, a, pl.fin_d, pl.nfin, pl.groups, st));
     return LM_OK;
@@ -611,7 +611,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
     LM_HIP(hipMemcpyAsync(loff_d, loff.data(), B * sizeof(int64_t), hipMemcpyHostToDevice, st));
     LM_HIP(hipMemcpyAsync(ioff_d, ioff.data(), B * sizeof(int64_t), hipMemcpyHostToDevice, st));
     double kq, wscale;
-    kernel_scales(prm, false, &kq, &wscale);
+    kernel_scales(prm, &kq, &wscale);
     LM_HIP(hipEventRecord(tm.ev[0], st));
     {
         SideStreams side;

@@ -87,7 +87,9 @@ constexpr int64_t kMaxN = (int64_t)1 << 34;
 
 lm_status check_params(const lm_params* prm);
 lm_status check_n(int64_t n, const char* name = "n");
-// Exponent scale and force constant of the pair bodies.
-void kernel_scales(const lm_params* prm, bool f32, double* kq, double* wscale);
+// Exponent scale and force constant of the pair bodies.  The pair bodies evaluate the kernel
+// as 2^(kq t) (t = r for the conon, r^2 for the Gaussian), so kq carries the factor log2(e).
+constexpr double kLog2e = 1.4426950408889634;
+void kernel_scales(const lm_params* prm, double* kq, double* wscale);
 
 }  // namespace lmh

@@ -58,7 +58,7 @@ struct PairArgs {
     const T* pt;
     int64_t nt, ns;
     int64_t jchunk;    // sources per wave chunk
-    double kq;         // exponent scale: conon -1/sigma, Gaussian -1/sigma^2 (x log2 e in f32)
+    double kq;         // base-2 exponent scale: conon -log2(e)/sigma, Gaussian -log2(e)/sigma^2
     double wscale;     // force-weight constant: conon 1/sigma, Gaussian 2/sigma^2
     double* part;      // split partial sums (nsplit, 2 dim, nt), used when nsplit > 1
     const double* box_s;   // cutoff mode: source tile boxes (8 doubles per 64-point tile), else null
@@ -97,7 +97,7 @@ struct VjpArgs {
     const double* b;        // cotangent of dp/dt
     int64_t n;
     int64_t jchunk;
-    double kq;              // exponent scale (conon -1/sigma, Gaussian -1/sigma^2)
+    double kq;              // base-2 exponent scale (conon -log2(e)/sigma, Gaussian -log2(e)/sigma^2)
     double c1, c2;          // conon: c1 = 1/sigma; Gaussian: c1 = 2/sigma^2, c2 = -4/sigma^4
     double* part;
     AdjEpi epi;

@@ -36,10 +36,11 @@ namespace lm {
 
 
 // ---------------------------------------------------------------------------------------
-// Pair bodies.  `kq` holds the kernel-argument scale: for the conon -1/sigma, for the
-// Gaussian -1/sigma^2 (double); in single precision the factor log2(e) is folded in so the
-// exponential is the hardware 2^x.  The force weight's constant (1/sigma for the conon,
-// 2/sigma^2 for the Gaussian) is folded into the target momentum `psi` by the caller.
+// Pair bodies.  `kq` holds the kernel-argument scale in base 2: for the conon
+// -log2(e)/sigma, for the Gaussian -log2(e)/sigma^2, so the kernel value is 2^(kq r) or
+// 2^(kq r^2) (exp2_nonpos in double, the hardware 2^x in single precision).  The force
+// weight's constant (1/sigma for the conon, 2/sigma^2 for the Gaussian) is folded into the
+// target momentum `psi` by the caller.
 // ---------------------------------------------------------------------------------------
 
 template <int DIM, int KER, bool FORCE>
@@ -62,10 +63,10 @@ __device__ __forceinline__ void pair_f64(const double (&qi)[DIM], const double (
     if constexpr (KER == LM_KERNEL_CONON) {
         const double rho = rsqrt_pos(s);
         const double r = s * rho;
-        g = exp_nonpos(r * kq);
+        g = exp2_nonpos(r * kq);
         w = g * rho;
     } else {
-        g = exp_nonpos(s * kq);
+        g = exp2_nonpos(s * kq);
         w = g;
     }
 #pragma unroll

@@ -1,14 +1,19 @@
 // lm_math.h -- device math for the pair kernels (gfx950).
 //
 // The pair kernels need exp of a non-positive argument and 1/sqrt of a positive one, in
-// double and in single precision.  There is no double-precision exp instruction; the one
-// here follows Cody & Waite's argument reduction (W. J. Cody and W. Waite, "Software
-// Manual for the Elementary Functions", 1980): x = k ln2 + r with integer k and
-// |r| <= ln2/2, then exp(x) = 2^k P(r) with P a degree-10 polynomial.  The constants were
-// derived for this library by gen_exp_coeffs.py (Chebyshev interpolation of exp on
-// [-ln2/2, ln2/2] at 60 digits, rounded to double): the rounded polynomial is within
-// 3.3e-16 of exp on that interval (degree 11 would give 1.7e-17 for one more FMA per pair;
-// the difference is far below the parity bar and the sums' own rounding).
+// double and in single precision.  Both precisions take the exponential in base 2: the
+// caller folds log2(e) into the kernel's scale constant, so the argument x = y log2(e) of
+// 2^x arrives with the one rounding of the product that forms it.  There is no
+// double-precision exp instruction; the one here reduces the argument after Cody & Waite
+// (W. J. Cody and W. Waite, "Software Manual for the Elementary Functions", 1980), in base 2
+// so that the reduction is exact: k = rint(x), f = x - k in [-1/2, 1/2], 2^x = 2^k P(f) with
+// P a degree-10 polynomial.  The constants were derived for this library by
+// gen_exp_coeffs.py (Chebyshev interpolation of 2^f on [-1/2, 1/2] at 60 digits, rounded to
+// double): the rounded polynomial is within 3.1e-16 of 2^f on that interval (degree 11 would
+// give 2.0e-17 for one more FMA per pair; the difference is far below the parity bar and the
+// sums' own rounding).  Against the natural-base reduction it saves the second half of the
+// split ln 2 (one FMA per pair) at the same accuracy: either way the argument carries the
+// relative rounding error of the products that form it.
 //
 // The reciprocal square root starts from the hardware estimate v_rsq_f64 (relative error
 // 5.2e-8 = 2^-24.2, measured on gfx950 over 2^20 arguments in [2^-20, 2^20]) and applies one
@@ -20,33 +25,28 @@
 
 namespace lm {
 
-constexpr double kLog2e = 1.4426950408889634;       // 1/ln 2
-constexpr double kLn2Hi = 0.6931471805599453;       // ln 2 rounded to double
-constexpr double kLn2Lo = 2.3190468138462996e-17;   // ln 2 - kLn2Hi
-
-// exp(x) for x <= 0.  Arguments below -1000 return 0 (exp underflows far earlier); the
-// clamp also keeps the reduction finite for huge |x|.  k = round(x / ln2) comes from adding
-// and subtracting 1.5 * 2^52 (one FMA and one subtraction): the low word of kd then holds k
-// as a 32-bit integer for the final scaling, so no separate rounding or conversion is needed.
-__device__ __forceinline__ double exp_nonpos(double x)
+// 2^x for x <= 0.  Arguments below -1500 return 0 (2^x underflows below -1075); the clamp
+// also keeps the reduction finite for huge |x|.  k = rint(x) comes from adding and
+// subtracting 1.5 * 2^52: the low word of kd then holds k as a 32-bit integer for the final
+// scaling, so no separate rounding or conversion is needed, and f = x - k is exact.
+__device__ __forceinline__ double exp2_nonpos(double x)
 {
-    x = __builtin_fmax(x, -1000.0);
-    const double kd = __builtin_fma(x, kLog2e, 0x1.8p52);
+    x = __builtin_fmax(x, -1500.0);
+    const double kd = x + 0x1.8p52;
     const double k = kd - 0x1.8p52;
     const int ki = (int)(unsigned)__builtin_bit_cast(unsigned long long, kd);
-    double r = __builtin_fma(k, -kLn2Hi, x);
-    r = __builtin_fma(k, -kLn2Lo, r);
-    double p = 0x1.28a2c0a7209fbp-22;
-    p = __builtin_fma(p, r, 0x1.72faf024b693bp-19);
-    p = __builtin_fma(p, r, 0x1.a019a66a75dd4p-16);
-    p = __builtin_fma(p, r, 0x1.a01978c6baf81p-13);
-    p = __builtin_fma(p, r, 0x1.6c16c17f43a58p-10);
-    p = __builtin_fma(p, r, 0x1.1111112dd67c5p-7);
-    p = __builtin_fma(p, r, 0x1.55555555520afp-5);
-    p = __builtin_fma(p, r, 0x1.555555554b757p-3);
-    p = __builtin_fma(p, r, 0x1.0000000000005p-1);
-    p = __builtin_fma(p, r, 0x1.000000000001ep+0);
-    p = __builtin_fma(p, r, 1.0);
+    const double f = x - k;
+    double p = 0x1.e6063f7217bc6p-28;
+    p = __builtin_fma(p, f, 0x1.b675bca4eeebbp-24);
+    p = __builtin_fma(p, f, 0x1.62bfd47773353p-20);
+    p = __builtin_fma(p, f, 0x1.ffcb54062e698p-17);
+    p = __builtin_fma(p, f, 0x1.430913096fd9fp-13);
+    p = __builtin_fma(p, f, 0x1.5d87fe9d7a584p-10);
+    p = __builtin_fma(p, f, 0x1.3b2ab6fba1ddap-7);
+    p = __builtin_fma(p, f, 0x1.c6b08d703ce49p-5);
+    p = __builtin_fma(p, f, 0x1.ebfbdff82c598p-3);
+    p = __builtin_fma(p, f, 0x1.62e42fefa3a19p-1);
+    p = __builtin_fma(p, f, 1.0);
     return __builtin_ldexp(p, ki);
 }
 

@@ -54,7 +54,7 @@ __host__ __device__ constexpr int sym_stride(int dim) { return 2 * dim + 1; }
 __device__ __forceinline__ int64_t tiles_of_dev(int64_t n) { return (n + kSymSteps - 1) / kSymSteps; }
 
 // Per-precision pieces: FMA, the conon's squared-distance floor (see pair_f64), 1/sqrt and the
-// exponential (in single precision the hardware 2^x, log2 e folded into kq by the caller).
+// exponential 2^x (kq carries log2 e; in single precision the hardware 2^x).
 template <class T>
 struct SymMath;
 template <>
@@ -62,7 +62,7 @@ struct SymMath<double> {
     static constexpr double kFloor = 1e-300;
     static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
     static __device__ __forceinline__ double rsq(double s) { return rsqrt_pos(s); }
-    static __device__ __forceinline__ double ex(double x) { return exp_nonpos(x); }
+    static __device__ __forceinline__ double ex(double x) { return exp2_nonpos(x); }
 };
 template <>
 struct SymMath<float> {

@@ -52,12 +52,12 @@ __device__ __forceinline__ void vjp_shared(const double (&qk)[DIM], const double
         // w = G/(sigma r), u = w'/r = -w rho (rho + 1/sigma) with rho = 1/r; c1 = 1/sigma
         const double sc = __builtin_fmax(s, 1e-200);
         const double rho = rsqrt_pos(sc);
-        g = exp_nonpos(sc * rho * kq);
+        g = exp2_nonpos(sc * rho * kq);
         w = g * rho * c1;
         u = -w * rho * (rho + c1);
     } else {
         // w = 2G/sigma^2, u = -4G/sigma^4; c1 = 2/sigma^2, c2 = -4/sigma^4
-        g = exp_nonpos(s * kq);
+        g = exp2_nonpos(s * kq);
         w = g * c1;
         u = g * c2;
     }
