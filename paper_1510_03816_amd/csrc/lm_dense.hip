@@ -163,7 +163,9 @@ __device__ __forceinline__ int mfma4_row(int lane) { return 4 * ((lane >> 2) & 3
 // A_ik <- A_ik L_kk^{-T}, a 64 x 128 by 128 x 128 product per workgroup.  Linv is staged in
 // LDS; wave w holds its 16 rows of A as left operands in registers (all 32 k-steps) before
 // it writes any of them back, so the update is in place.  Columns at or past bs read as zero
-// (Linv is zero there).
+// (Linv is zero there).  Each finished entry L_ik is also stored at (k, i), in the upper
+// triangle, which nothing else uses: the forward sweep then reads panel k as 128 contiguous
+// rows instead of one 1 KiB segment from each of n - k0 rows 8 n bytes apart.
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void lm_panel_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
                                                        const double* __restrict__ Linv)
@@ -196,7 +198,10 @@ __global__ __launch_bounds__(256) void lm_panel_kernel(double* __restrict__ K, i
 #pragma unroll
     for (int c = 0; c < kPanel / 4; ++c) {
         const int col = 4 * c + (lane & 3);
-        if (gi < n && col < bs) K[gi * n + k0 + col] = acc[c];
+        if (gi < n && col < bs) {
+            K[gi * n + k0 + col] = acc[c];
+            K[(k0 + col) * n + gi] = acc[c];   // transposed copy in the unused upper triangle
+        }
     }
 }
 
@@ -450,9 +455,13 @@ __device__ void finish_block(const double* __restrict__ Linv, int64_t n, int nb,
         for (int c = 0; c < DIM; ++c) y[c * ldy + b0 + r] = acc[c] + part[c * kPanel + r];
 }
 
-// Launch k of the forward sweep (k = -1: only finish block 0).  Workgroup 0 owns block k+1:
-// it subtracts L[block k+1, block k] y_k and finishes y_{k+1}; workgroups >= 1 subtract the
-// contribution of y_k from the rows of blocks k+2 .. nb-1, eight rows per wave at a time.
+// Launch k of the forward sweep (k = -1: only finish block 0): y_r -= sum_m L[r][k0 + m]
+// y_k[m] for every row r past block k, reading panel k from its transposed copy, row k0 + m
+// of the upper triangle (LT[m][r] = L[r][k0 + m], contiguous in r).  A workgroup takes 64
+// consecutive rows r, one per lane; wave w sums m over [32 w, 32 w + 32) (each wave load is
+// one 512-byte segment of a row of LT) and the four wave sums are added in wave order.
+// Workgroup 0 owns block k+1 (its two 64-row halves, then the block's finish with the
+// stored inverse); workgroups >= 1 take the rows of blocks k+2 .. nb-1, 64 at a time.
 template <int DIM>
 __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restrict__ L, const double* __restrict__ Linv,
                                                           int64_t n, int nb, int64_t k, double* __restrict__ y,
@@ -460,6 +469,7 @@ __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restri
 {
     __shared__ double sh[3 * kPanel];
     __shared__ double yk[3 * kPanel];
+    __shared__ double red[4][3][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (k >= 0) {
         const int64_t k0 = k * kPanel;
@@ -468,36 +478,36 @@ __global__ __launch_bounds__(256) void lm_trsv_fwd_kernel(const double* __restri
             yk[e] = (k0 + m < n) ? y[c * ldy + k0 + m] : 0.0;
         }
         __syncthreads();
-        // eight rows per wave at a time: lane l reads 16 consecutive doubles of row (l / 8),
-        // so each row's 128 panel entries come in as one coalesced 1 KiB segment
-        const int sub = lane >> 3, seg = (lane & 7) * 16;
         int64_t rbeg, rend, rstep;
         if (blockIdx.x == 0) {
-            rbeg = (k + 1) * kPanel + wave * 8;
+            rbeg = (k + 1) * kPanel;
             rend = (k + 2) * kPanel < n ? (k + 2) * kPanel : n;
-            rstep = 32;
+            rstep = 64;
         } else {
-            rbeg = (k + 2) * kPanel + ((int64_t)(blockIdx.x - 1) * 4 + wave) * 8;
+            rbeg = (k + 2) * kPanel + (int64_t)(blockIdx.x - 1) * 64;
             rend = n;
-            rstep = (int64_t)(gridDim.x - 1) * 32;
+            rstep = (int64_t)(gridDim.x - 1) * 64;
         }
+        const int m0 = wave * 32;
         for (int64_t rb = rbeg; rb < rend; rb += rstep) {
-            const int64_t r = rb + sub;
+            const int64_t r = rb + lane;
             const bool ok = r < rend;
-            const double* lr = L + (ok ? r : rb) * n + k0 + seg;
-            double lv[16];
+            const double* lt = L + (k0 + m0) * n + (ok ? r : rb);
+            double lv[32];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) lv[u] = lr[u];
+            for (int u = 0; u < 32; ++u) lv[u] = lt[(int64_t)u * n];
             double s[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) {
+            for (int c = 0; c < DIM; ++c)
 #pragma unroll
-                for (int u = 0; u < 16; ++u) s[c] = __builtin_fma(lv[u], yk[c * kPanel + seg + u], s[c]);
+                for (int u = 0; u < 32; ++u) s[c] = __builtin_fma(lv[u], yk[c * kPanel + m0 + u], s[c]);
 #pragma unroll
-                for (int o = 4; o > 0; o >>= 1) s[c] += __shfl_xor(s[c], o, 64);
-            }
-            if (ok && (lane & 7) == 0)
-                for (int c = 0; c < DIM; ++c) y[c * ldy + r] -= s[c];
+            for (int c = 0; c < DIM; ++c) red[wave][c][lane] = s[c];
+            __syncthreads();
+            if (wave == 0 && ok)
+                for (int c = 0; c < DIM; ++c)
+                    y[c * ldy + r] -= ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
+            __syncthreads();
         }
     }
     if (blockIdx.x == 0 && k + 1 < nb) {
@@ -813,7 +823,7 @@ hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, in
     };
     for (int64_t k = -1; k < nb - 1; ++k) {
         const int64_t below = n - (k + 2) * kPanel;
-        const dim3 g(k < 0 ? 1u : groups(below > 0 ? below : 0, 32));
+        const dim3 g(k < 0 ? 1u : groups(below > 0 ? below : 0, 64));
         if (dim == 2)
             hipLaunchKernelGGL(lm_trsv_fwd_kernel<2>, g, dim3(256), 0, st, L, Linv, n, nb, k, y, ldy);
         else
