@@ -20,7 +20,8 @@
 // Solves: blocked forward (L y = b) and backward (L^T x = y) sweeps, one launch per panel;
 // in launch k every workgroup subtracts panel k's contribution from its rows, and the
 // workgroup that owns block k+1 (k-1 backward) then finishes that block with the stored
-// inverse of its diagonal block.
+// inverse of its diagonal block.  The panel kernel also writes each panel transposed into
+// the unused upper triangle, where the forward sweep reads it as contiguous rows.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
