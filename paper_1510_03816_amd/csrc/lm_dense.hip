@@ -63,22 +63,24 @@ __global__ __launch_bounds__(256) void lm_kbuild_kernel(const double* __restrict
 
 // ---------------------------------------------------------------------------------------
 // Diagonal block, factor and inverse in one pass: the bs x bs block at (k0, k0) is held in
-// LDS as a full 128 x 129 array.  Cholesky is left-looking by columns: for column c, two
-// threads per row r >= c form A_rc - sum_{k<c} L_rk L_ck (even and odd k), the pivot thread
-// takes the square root, and the rows below divide by it.  A non-positive pivot sets
-// *info = k0 + c + 1 (the factor is then meaningless).  The inverse is then formed by
-// forward substitution, two threads per column j of Linv, whose entries (r >= j) are kept in
-// the unused upper triangle at A[j][r + 1].  Outputs: the factor written back over the
-// block, Linv (kPanel x kPanel, row-major, zero above the diagonal and outside bs) and its
-// transpose LinvT (the triangular sweeps read rows of both).
-// The loops are bound by LDS traffic and latency (about 0.37 ms per block on MI355X, a few
-// per cent of a large factorization).
+// LDS as a full 128 x 129 array.  Cholesky is left-looking by columns: for column c, a group
+// of threads per row r >= c (2 while more than 64 rows remain, up to 64 for the last few)
+// forms A_rc - sum_{k<c} L_rk L_ck, the pivot thread takes the square root, and the rows
+// below divide by it.  A non-positive pivot sets *info = k0 + c + 1 (the factor is then
+// meaningless).  The inverse is then formed by forward substitution, two threads per column
+// j of Linv, whose entries (r >= j) are kept in the unused upper triangle at A[j][r + 1].
+// Outputs: the factor written back over the block, Linv (kPanel x kPanel, row-major, zero
+// above the diagonal and outside bs) and its transpose LinvT (the triangular sweeps read rows
+// of both).  The dot products keep eight LDS loads in flight (one at a time left every
+// iteration waiting out the LDS latency: 0.36 ms per block, now 0.23 ms on MI355X); the
+// kernel stays bound by the latency of its dependent column steps.
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void lm_potrf_inv_kernel(double* __restrict__ K, int64_t n, int64_t k0, int bs,
                                                            double* __restrict__ Linv, double* __restrict__ LinvT,
                                                            int* __restrict__ info)
 {
     __shared__ double A[kPanel][kPanel + 1];
+    __shared__ double rdiag[kPanel];
     const int tid = threadIdx.x;
     // global loads are issued in batches of 8 before any is stored (a load-store loop would
     // wait out the memory latency once per element)
@@ -96,21 +98,30 @@ __global__ __launch_bounds__(256) void lm_potrf_inv_kernel(double* __restrict__ 
         }
     }
     __syncthreads();
-    const int h = tid & 1, pr = tid >> 1;
     for (int c = 0; c < bs; ++c) {
-        const int r = c + pr;
+        // tpr threads per row r >= c (as many as the 256 threads cover, 2 to 64), thread h of a
+        // row summing k = h, h + tpr, ... with eight loads in flight and four accumulators
+        const int rows = bs - c;
+        const int tpr = rows > 64 ? 2 : rows > 32 ? 4 : rows > 16 ? 8 : rows > 8 ? 16 : rows > 4 ? 32 : 64;
+        const int h = tid & (tpr - 1), r = c + tid / tpr;
         double v = 0.0;
         if (r < bs) {
-            double s0 = 0.0, s1 = 0.0;
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
             int k = h;
-            for (; k + 2 < c; k += 4) {
-                s0 = __builtin_fma(A[r][k], A[c][k], s0);
-                s1 = __builtin_fma(A[r][k + 2], A[c][k + 2], s1);
+            for (; k + 7 * tpr < c; k += 8 * tpr) {
+                double x[8], y[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    x[u] = A[r][k + u * tpr];
+                    y[u] = A[c][k + u * tpr];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s4[u & 3] = __builtin_fma(x[u], y[u], s4[u & 3]);
             }
-            for (; k < c; k += 2) s0 = __builtin_fma(A[r][k], A[c][k], s0);
-            v = s0 + s1;
+            for (; k < c; k += tpr) s4[0] = __builtin_fma(A[r][k], A[c][k], s4[0]);
+            v = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         }
-        v += __shfl_xor(v, 1);
+        for (int o = 1; o < tpr; o <<= 1) v += __shfl_xor(v, o);
         if (r < bs) v = A[r][c] - v;
         if (r == c && h == 0) {
             const bool ok = v > 0.0;
@@ -125,16 +136,31 @@ __global__ __launch_bounds__(256) void lm_potrf_inv_kernel(double* __restrict__ 
         const int r = e / kPanel, c = e % kPanel;
         if (r < bs && c <= r) K[(k0 + r) * n + k0 + c] = A[r][c];
     }
-    // inverse: x_j = 1/L_jj, x_r = -(sum_{l=j}^{r-1} L_rl x_l) / L_rr; both threads of a
-    // pair compute and store every x_r, so each reads back only its own stores
-    const int j = pr;
+    // inverse: x_j = 1/L_jj, x_r = -(sum_{l=j}^{r-1} L_rl x_l) / L_rr, two threads per
+    // column j (l = j + h, j + h + 2, ...; eight loads in flight, four accumulators).  Both
+    // threads of a pair compute and store every x_r, so each reads back only its own stores.
+    if (tid < bs) rdiag[tid] = 1.0 / A[tid][tid];
+    __syncthreads();
+    const int h = tid & 1, j = tid >> 1;
     if (j < bs) {
-        A[j][j + 1] = 1.0 / A[j][j];
+        A[j][j + 1] = rdiag[j];
         for (int r = j + 1; r < bs; ++r) {
-            double s = 0.0;
-            for (int l = j + h; l < r; l += 2) s = __builtin_fma(A[r][l], A[j][l + 1], s);
+            double s4[4] = {0.0, 0.0, 0.0, 0.0};
+            int l = j + h;
+            for (; l + 14 < r; l += 16) {
+                double x[8], y[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    x[u] = A[r][l + 2 * u];
+                    y[u] = A[j][l + 2 * u + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s4[u & 3] = __builtin_fma(x[u], y[u], s4[u & 3]);
+            }
+            for (; l < r; l += 2) s4[0] = __builtin_fma(A[r][l], A[j][l + 1], s4[0]);
+            double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             s += __shfl_xor(s, 1);
-            A[j][r + 1] = -s / A[r][r];
+            A[j][r + 1] = -s * rdiag[r];
         }
     }
     __syncthreads();
