@@ -619,7 +619,9 @@ __global__ __launch_bounds__(256) void lm_trsv_bwd_kernel(const double* __restri
 // striding the columns, four rows at a time), then y_k = Linv_k s.  Backward, per block from
 // the last: t = y_k - L[>k, k]^T x_>k (each wave takes every fourth row below the block, lanes
 // the block's columns; the wave partials are added in wave order), then x_k = Linv_k^T t.
-// Both block finishes read rows (of LinvT, of Linv) with two threads per output.
+// Both block finishes read rows (of LinvT, of Linv) with two threads per output.  One
+// workgroup sweeps a problem's whole factor, so the loops keep 16 loads in flight per wave
+// (with one to four, the 4065-point problem's sweeps took 11.1 ms, latency-bound).
 // L_b: row-major n_b x n_b lower triangle at L + loff[b]; Linv_b at Linv + ioff[b] (the
 // transposes after the problem's panels of inverses, as launch_dense_factor stores them); y: the
 // batch's (dim, ntot) array, problem b in columns offs[b] .. offs[b+1]-1.
@@ -689,7 +691,26 @@ __global__ __launch_bounds__(256) void lm_batch_solve_kernel(const double* __res
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) acc[u][c] = 0.0;
-            for (int j = lane; j < k0; j += 64) {
+            // four 64-column chunks per iteration (16 loads in flight), then single chunks;
+            // every row's terms are added in increasing j either way
+            int j = lane;
+            for (; j + 192 < k0; j += 256) {
+                double l[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        l[q][u] = (r0 + u < bs) ? Lb[(int64_t)(k0 + r0 + u) * n + j + 64 * q] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        const double yj = v[c][j + 64 * q];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[u][c] = __builtin_fma(l[q][u], yj, acc[u][c]);
+                    }
+            }
+            for (; j < k0; j += 64) {
                 double l[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) l[u] = (r0 + u < bs) ? Lb[(int64_t)(k0 + r0 + u) * n + j] : 0.0;
@@ -727,7 +748,27 @@ __global__ __launch_bounds__(256) void lm_batch_solve_kernel(const double* __res
 #pragma unroll
             for (int c = 0; c < DIM; ++c) acc[h][c] = 0.0;
         const bool ok0 = lane < bs, ok1 = 64 + lane < bs;
-        for (int j = k0 + bs + wave; j < n; j += 4) {
+        // eight of the wave's rows per iteration (16 loads in flight), then single rows; the
+        // terms are added in increasing j either way
+        int j = k0 + bs + wave;
+        for (; j + 28 < n; j += 32) {
+            double l0[8], l1[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double* lr = Lb + (int64_t)(j + 4 * q) * n + k0;
+                l0[q] = ok0 ? lr[lane] : 0.0;
+                l1[q] = ok1 ? lr[64 + lane] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    const double xj = v[c][j + 4 * q];
+                    acc[0][c] = __builtin_fma(l0[q], xj, acc[0][c]);
+                    acc[1][c] = __builtin_fma(l1[q], xj, acc[1][c]);
+                }
+        }
+        for (; j < n; j += 4) {
             const double* lr = Lb + (int64_t)j * n + k0;
             const double l0 = ok0 ? lr[lane] : 0.0;
             const double l1 = ok1 ? lr[64 + lane] : 0.0;
