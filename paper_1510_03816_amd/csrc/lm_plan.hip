@@ -37,9 +37,11 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, int kind)
     if (smax < 1) smax = 1;
     if (s > smax) s = smax;
     if (s > 64) s = 64;
-    // from 128 target tiles (N = 8192) on, more than 16 splits only shortens the chunks:
-    // measured at N = 16384, 3-D, FP64, 16 splits beat 64 by 12% (Gaussian) and 4% (conon)
-    if (pl.itiles >= 128 && s > 16) s = 16;
+    // from 80 target tiles (N = 5120) on, more than 16 splits only shortens the chunks and
+    // lengthens the finish: measured at N = 16384, 3-D, FP64, 16 splits beat 64 by 12%
+    // (Gaussian) and 4% (conon); at N = 6000 (94 tiles) 16 beat 46 by 10%, while at N = 4096
+    // (64 tiles, 2-D) 32 beat 16 by 3%
+    if (pl.itiles >= 80 && s > 16) s = 16;
     if (s < 1) s = 1;
     pl.nsplit = (int)s;
     int64_t chunks = (int64_t)pl.nsplit * kWaves;

@@ -59,6 +59,11 @@ def test_one_sided_split_rule(monkeypatch):
     # 64 tiles of 2-D points: 256 splits wanted, limited to 64 (and by the 32-source chunk floor)
     p = plan(4096, dim=2)
     assert p["workgroups"] == 64 * 32 and p["partial_slots"] == 32
+    # 94 tiles: 16 splits from 80 tiles on
+    p = plan(6000)
+    assert p["symmetric"] == 0 and p["workgroups"] == 94 * 16 and p["partial_slots"] == 16
+    p = plan(5056)          # 79 tiles: 39 splits (the 32-source chunk floor)
+    assert p["workgroups"] == 79 * 39 and p["partial_slots"] == 39
 
 
 def test_single_precision_keeps_one_sided_kernel_and_cutoff_runs_symmetric_in_double():
