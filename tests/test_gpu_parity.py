@@ -540,6 +540,19 @@ def test_dense_ksolve_reports_singular_kernel_matrix():
     assert e.value.status == lm.LM_ESINGULAR
 
 
+def test_dense_ksolve_refuses_sizes_beyond_the_factor_limit():
+    """n = 2^21 points: the trailing update addresses 128 rows of the factor with 31-bit byte
+    offsets, so a forced dense solve is refused (LM_ENOMEM) before anything is allocated or
+    launched; nothing is read from the inputs."""
+    n = 1 << 21
+    prm = lm.make_params(2, lm.CONON, 0.1)
+    X = torch.zeros((2, n), dtype=torch.float64, device=DEV)
+    x = torch.empty_like(X)
+    with pytest.raises(lm.LmError) as e:
+        lm.lm_ksolve(prm, X, X, x, solver=lm.SOLVE_DENSE)
+    assert e.value.status == lm.LM_ENOMEM
+
+
 def test_feedback_with_cg_solver_matches_dense():
     pr = inputs.config_circle_ellipse(64)
     prm = lm.make_params(2, lm.CONON, pr.sigma)
