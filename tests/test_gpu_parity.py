@@ -540,6 +540,21 @@ def test_dense_ksolve_reports_singular_kernel_matrix():
     assert e.value.status == lm.LM_ESINGULAR
 
 
+def test_dense_ksolve_at_16384_matches_cg():
+    """N = 16384 on the 3-D sphere workload (sigma 0.05): 128 panels, 16 trailing updates on
+    128 x 128 tiles, the forward sweep on the transposed panel copies; against conjugate
+    gradients on the same system."""
+    pr = inputs.config_sphere3d(16384)
+    prm = lm.make_params(3, lm.CONON, pr.sigma)
+    b = np.random.default_rng([114, pr.n]).standard_normal(pr.X.shape)
+    xd, xc = (torch.empty((3, pr.n), dtype=torch.float64, device=DEV) for _ in range(2))
+    assert lm.lm_ksolve(prm, dev(pr.X), dev(b), xd, solver=lm.SOLVE_DENSE) == 0
+    it = lm.lm_ksolve(prm, dev(pr.X), dev(b), xc, solver=lm.SOLVE_CG, rtol=1e-13, max_iter=5000)
+    err = rel_err(host(xd), host(xc))
+    print("n=%d dense vs CG (%d iterations) rel diff %.2e" % (pr.n, it, err))
+    assert err <= 1e-9
+
+
 def test_dense_ksolve_refuses_sizes_beyond_the_factor_limit():
     """n = 2^21 points: the trailing update addresses 128 rows of the factor with 31-bit byte
     offsets, so a forced dense solve is refused (LM_ENOMEM) before anything is allocated or
