@@ -53,17 +53,15 @@ __device__ __forceinline__ void vjp_shared(const double (&qk)[DIM], const double
         const double sc = __builtin_fmax(s, 1e-200);
         const double rho = rsqrt_pos(sc);
         g = exp2_nonpos(sc * rho * kq);
-        w = g * rho * c1;
+        const double gm = s > 0.0 ? g : 0.0;   // coincident particles: w = u = 0
+        w = gm * rho * c1;
         u = -w * rho * (rho + c1);
     } else {
         // w = 2G/sigma^2, u = -4G/sigma^4; c1 = 2/sigma^2, c2 = -4/sigma^4
         g = exp2_nonpos(s * kq);
-        w = g * c1;
-        u = g * c2;
-    }
-    if (!(s > 0.0)) {
-        w = 0.0;
-        u = 0.0;
+        const double gm = s > 0.0 ? g : 0.0;   // coincident particles: w = u = 0
+        w = gm * c1;
+        u = gm * c2;
     }
     double ed = 0.0, apj = 0.0, pp = 0.0;
 #pragma unroll
