@@ -233,7 +233,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1, help="timed steps (whole matches)")
     ap.add_argument("--warmup", type=int, default=1, help="untimed steps before")
     ap.add_argument("--workload", default="sphere3d_conon_f64", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="match", choices=["match", "iteration"])
+    ap.add_argument("--mode", default="match", choices=["match", "iteration", "shoot"],
+                    help="a step is one whole match, one feedback iteration, or one forward shoot from the "
+                         "workload's benchmark momenta")
     ap.add_argument("--h", type=float, default=0.8, help="search length of Algorithm 1")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=100)
@@ -306,9 +308,22 @@ def main():
         "f64" if dtype == 0 else "f32", rc, args.mode))
 
     p_iter = torch.zeros_like(X)
+    if args.mode == "shoot":
+        sdt = torch.float64 if dtype == 0 else torch.float32
+        q_sh = X.to(sdt)
+        p_sh = torch.tensor(pr.p_bench(), device=dev, dtype=sdt)
+        q1_sh, p1_sh = torch.empty_like(q_sh), torch.empty_like(q_sh)
 
     def step():
         """Returns (shoots, shoot_ms, solve_ms, factor_ms, record)."""
+        if args.mode == "shoot":
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = lm.lm_shoot(prm, q_sh, p_sh, 1.0, pr.steps, q1_sh, p1_sh)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3
+            log("shoot: %s %.1f ms" % (lm.STATUS_NAMES[st], ms))
+            return 1, ms, 0.0, 0.0, {"status": lm.STATUS_NAMES[st], "shoot_ms": ms}
         if args.mode == "match":
             st, info, hist = run_match(prm, pr, X, Y)
             rec = {"status": lm.STATUS_NAMES[st], "iters": info.iters, "resid_inf": info.resid_inf,
@@ -417,8 +432,9 @@ def main():
         "config": {"workload": args.workload, "n": n, "dim": dim,
                    "kernel": "conon" if pr.kernel == 0 else "gauss", "sigma": pr.sigma,
                    "rk4_steps": pr.steps, "h": args.h, "tol": args.tol, "cutoff": rc,
-                   "step": ("one whole feedback match from p = 0 to max|q(1) - Y| < tol"
-                            if args.mode == "match" else "one feedback iteration (CG K-solve)")},
+                   "step": {"match": "one whole feedback match from p = 0 to max|q(1) - Y| < tol",
+                            "iteration": "one feedback iteration (CG K-solve)",
+                            "shoot": "one forward shoot of the RK4 steps from X with the benchmark momenta"}[args.mode]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_match": ttm,
