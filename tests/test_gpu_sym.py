@@ -325,6 +325,34 @@ def test_sym_cutoff_error_within_certified_bound_and_matches_one_sided(kernel):
     assert np.max(np.abs(dqs - dq_o)) > 0.0      # something was skipped
 
 
+@pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
+def test_sym_cutoff_full_size_sampled_rows(kernel):
+    """N = 65536 with tile skipping in the default launch shape (two row tiles, two waves,
+    4-tile superblocks) at the radius where the kernel falls to 1e-16, Morton-ordered as
+    lm_shoot orders it: sampled rows (both ends of a tile and the last point included)
+    against the oracle, which computes rows one by one over all pairs."""
+    n = 65536
+    pr = inputs.config_sphere3d(n, kernel=kernel, sigma=0.05)
+    perm = _morton_sorted(pr.X)
+    q, p = pr.X[:, perm], pr.p_bench()[:, perm]
+    L = np.log(1e16)
+    rc = pr.sigma * (L if kernel == 0 else np.sqrt(L))
+    prm = lm.make_params(3, kernel, pr.sigma, cutoff=rc)
+    plan = lm.lm_pair_plan(prm, n)
+    assert plan["symmetric"] == 1 and plan["rows"] == 2 and plan["waves"] == 2
+    qd, pd = dev(q), dev(p)
+    dq, dp = torch.empty_like(qd), torch.empty_like(pd)
+    lm.lm_rhs(prm, qd, pd, dq, dp)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(77).choice(n, 192, replace=False))
+    idx = np.concatenate([[0, 63, 64, n - 1], idx])
+    rq, rp = oracle.rhs_rows(q, p, idx, kernel, pr.sigma)
+    eq = np.max(np.abs(host(dq)[:, idx] - rq)) / np.max(np.abs(rq))
+    ep = np.max(np.abs(host(dp)[:, idx] - rp)) / np.max(np.abs(rp))
+    print("cutoff full-size sampled kernel=%d: %.2e %.2e" % (kernel, eq, ep))
+    assert eq <= 1e-10 and ep <= 1e-10
+
+
 def test_sym_cutoff_shoot_matches_oracle():
     pr = inputs.config_sphere3d(3000, kernel=lm.GAUSS, sigma=0.1)
     q0, p0 = pr.X, pr.p_bench()

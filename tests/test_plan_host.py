@@ -68,8 +68,8 @@ def test_one_sided_split_rule(monkeypatch):
 
 def test_single_precision_keeps_one_sided_kernel_and_cutoff_runs_symmetric_in_double():
     assert plan(65536, dtype=lm.F32)["symmetric"] == 0
-    p = plan(65536, cutoff=0.3)                 # tile skipping: two rows, four waves, same superblocks
-    assert p["symmetric"] == 1 and p["rows"] == 2 and p["waves"] == 4 and p["partial_slots"] == 129
+    p = plan(65536, cutoff=0.3)                 # tile skipping: two rows, two waves, 4-tile superblocks
+    assert p["symmetric"] == 1 and p["rows"] == 2 and p["waves"] == 2 and p["partial_slots"] == 257
     assert plan(49088, cutoff=0.3)["symmetric"] == 0        # 768 tiles needed with tile skipping
     assert plan(49152, cutoff=0.3)["symmetric"] == 1
     assert plan(65536, dtype=lm.F32, cutoff=0.3)["symmetric"] == 0
