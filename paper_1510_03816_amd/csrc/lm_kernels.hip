@@ -364,8 +364,14 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
 // the four wave sums in wave order.
 // flags (the symmetric kernel with tile skipping, else null): slot s of a target in superblock
 // Z (sbp points each) came from superblock pair {Z, s}; a pair flagged 0 wrote nothing there.
+// Slots up to which the flagged finish lists the written slots in LDS (beyond: it tests
+// every slot's flag as it goes).
+constexpr int kFinishListSlots = 2048;
+
+// (At most 128 VGPRs: four workgroups per CU, so the 1024 workgroups of an N = 65536 stage
+// run in one round.)
 template <class T, int DIM, bool FORCE>
-__global__ __launch_bounds__(256) void lm_finish_kernel(const double* __restrict__ part, int nsplit,
+__global__ __launch_bounds__(256, 4) void lm_finish_kernel(const double* __restrict__ part, int nsplit,
                                                         int64_t nt, EpiArgs<T> e, const uint8_t* __restrict__ flags,
                                                         int64_t sbp)
 {
@@ -385,30 +391,63 @@ __global__ __launch_bounds__(256) void lm_finish_kernel(const double* __restrict
     double acc[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[c] = 0.0;
-    if (live && flags == nullptr) {
+    if (flags == nullptr) {
         // every slot written: a plain strided loop (the compiler keeps the loads in flight;
         // 89 against 94 us per stage at N = 65536 for the explicit four-slot batches below)
+        if (live) {
+            const double* ps = part + i;
+            for (int s = wave; s < nsplit; s += 4)
+#pragma unroll
+                for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
+        }
+    } else if (nsplit <= kFinishListSlots) {
+        // with tile skipping most slots hold nothing: the workgroup marks the written slots
+        // in a bit mask (one flag per thread), each wave lists its own slots (s = wave mod 4,
+        // increasing) in LDS and adds only those, four slots' loads in flight
+        __shared__ uint64_t mask[kFinishListSlots / 64];
+        __shared__ int list[4][kFinishListSlots / 4];
+        for (int base = 0; base < nsplit; base += 256) {
+            const int s = base + (int)threadIdx.x;
+            const uint64_t b = __ballot(s < nsplit && written(s));
+            if (lane == 0) mask[(base >> 6) + wave] = b;
+        }
+        __syncthreads();
+        const uint64_t own = 0x1111111111111111ull << wave;   // bits b with b = wave mod 4
+        int cnt = 0;
+        for (int k = 0; k < (nsplit + 63) >> 6; ++k) {
+            const uint64_t m = mask[k] & own;
+            if ((m >> lane) & 1ull) list[wave][cnt + __popcll(m & ((1ull << lane) - 1ull))] = 64 * k + lane;
+            cnt += __popcll(m);
+        }
+        __syncthreads();
+        if (live) {
+            const double* ps = part + i;
+            const int* ls = list[wave];
+            int j = 0;
+            for (; j + 3 < cnt; j += 4) {
+                double x[4][NV];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t s = ls[j + u];
+#pragma unroll
+                    for (int c = 0; c < NV; ++c) x[u][c] = ps[s * slot + c * nt];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int c = 0; c < NV; ++c) acc[c] += x[u][c];
+            }
+            for (; j < cnt; ++j) {
+                const int64_t s = ls[j];
+#pragma unroll
+                for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
+            }
+        }
+    } else if (live) {
+        // (more slots than the list holds: the partial-sum cap keeps the symmetric plans
+        // below it, so this plain loop is a fallback)
         const double* ps = part + i;
         for (int s = wave; s < nsplit; s += 4)
-#pragma unroll
-            for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
-    } else if (live) {
-        const double* ps = part + i;
-        int s = wave;
-        for (; s + 12 < nsplit; s += 16) {
-            double x[4][NV];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const bool w = written(s + 4 * u);
-#pragma unroll
-                for (int c = 0; c < NV; ++c) x[u][c] = w ? ps[(s + 4 * u) * slot + c * nt] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int c = 0; c < NV; ++c) acc[c] += x[u][c];
-        }
-        for (; s < nsplit; s += 4)
             if (written(s))
 #pragma unroll
                 for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
