@@ -263,18 +263,28 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     const int64_t NT = tiles_of_dev(n);
     const T kq = (T)kqd;
 
+    // CUT: bit k of `need` says whether column tile Y * side + k lies within the cutoff of some
+    // row tile of the superblock; the others are neither staged nor evaluated (their column
+    // sums are written as zeros), and a pair with no such tile writes only its flag
+    uint32_t need = ~0u;
+    static_assert(!CUT || ROWS <= 2, "with tile skipping a superblock has at most 2 x 16 tiles (one bit each)");
     if constexpr (CUT) {
-        int near = diag;
+        __shared__ uint32_t need_bits;
+        if (threadIdx.x == 0) need_bits = diag ? ~0u : 0u;
+        __syncthreads();
         if (!diag) {
             const int64_t I0 = X * side, I1 = (I0 + side < NT) ? I0 + side : NT;
             const int64_t J0 = Y * side, J1 = (J0 + side < NT) ? J0 + side : NT;
             const int64_t w = J1 - J0;
+            uint32_t m = 0;
             for (int64_t t = threadIdx.x; t < (I1 - I0) * w; t += blockDim.x)
-                if (!sym_tiles_far<DIM>(box + (I0 + t / w) * 8, box + (J0 + t % w) * 8, rc2)) near = 1;
+                if (!sym_tiles_far<DIM>(box + (I0 + t / w) * 8, box + (J0 + t % w) * 8, rc2)) m |= 1u << (t % w);
+            if (m) atomicOr(&need_bits, m);
         }
-        near = __syncthreads_or(near);
-        if (threadIdx.x == 0) flags[b] = (uint8_t)(near != 0);
-        if (!near) return;
+        __syncthreads();
+        need = need_bits;
+        if (threadIdx.x == 0) flags[b] = (uint8_t)(need != 0);
+        if (need == 0) return;
     }
 
     // row points in registers; their sums over one column tile in T, over all tiles in double
@@ -298,7 +308,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     for (int t = threadIdx.x; t < nw * EC * 128; t += blockDim.x) region[t] = 0.0;
     const int64_t J0 = Y * side;
     const int64_t J1 = (J0 + side < NT) ? (J0 + side) : NT;
-    sym_stage<T, DIM>(jbuf, q, p, ld, n, J0);
+    if (need & 1u) sym_stage<T, DIM>(jbuf, q, p, ld, n, J0);
     __syncthreads();
 
     const T* jb = jbuf + lane * E;
@@ -341,7 +351,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
             const int64_t j = J * kSymSteps + l;
             if (j < n) pc[c * n + j] = (c < DIM) ? s : s * wscale;
         }
-        if (J + 1 < J1) sym_stage<T, DIM>(jbuf, q, p, ld, n, J + 1);
+        if (J + 1 < J1 && ((need >> (J + 1 - J0)) & 1u)) sym_stage<T, DIM>(jbuf, q, p, ld, n, J + 1);
         __syncthreads();
     }
 
