@@ -1,33 +1,34 @@
 #!/usr/bin/env python3
 """Benchmark: pair-interactions/s of RK4 shooting and time-to-match of the feedback iteration.
 
-A step is one whole match through the C ABI (lm_feedback_match): Algorithm 1 from p = 0 (the
-paper's initial guess) until max|q(1) - Y| < 1e-6 -- the factorisation of K(X) once, then
-per iteration an RK4 shoot of the N-particle system (every stage one pass of the O(N^2)
-pair sums, the stage bookkeeping fused in), the max-norm residual and the momentum update
-p <- p + h K(X)^{-1} e.  Every row of the hot path runs inside the timed region.
+A step is one forward shoot through the C ABI (lm_shoot) of the headline workload: 65536
+Fibonacci-sphere landmarks in 3-D, conical kernel sigma = 0.05, FP64, 100 RK4 steps on
+[0, 1] from the template X with the workload's throughput momenta (a Jacobi estimate of the
+first feedback momenta, so the kernel runs on realistic operands).  Every RK stage is one
+pass of the O(N^2) pair sums with the stage bookkeeping fused in (equation "N-particle",
+Algorithm 1 step 1).
 
-value       = shooting pair interactions of the step (shoots * 4 * rk4_steps * N^2) / its
-              wall time (factorisation, solves and residuals count against it)
-ms_per_step = time to match.
-Beside them: the dominant kernel's roofline (its average launch time measured live with HIP
-events on the stream it runs on, inside the library), time-to-match on the 2-D curve (N =
-4096) and circle-to-ellipse (N = 64) workloads, and the FP64 oracle timed on the host cores
-on a bounded sample.
+value       = pair interactions of the timed shoots (steps * 4 * rk4_steps * N^2) / wall time
+ms_per_step = wall time of one shoot.
 
-Also reported (not part of value): the 256-problem batch (2-D curves, N_b log-uniform in
-[32, 4096], conical sigma = 0.1, 100 RK4 steps) -- autotuned launch shape, batched shoot
-pair-interactions/s in FP32 and FP64, and batched time-to-match at 1e-6 (FP32 shoots
-switching to FP64 at residual 1e-4, and FP64 throughout).
+Outside the timed loop, in this order, each only while the run's wall-clock budget
+(--budget-s, counted from the start of the process) has room for it:
+  - the dominant kernel's roofline (the RK stage, its time from HIP events recorded on the
+    stream the library launches on, around every timed shoot);
+  - the FP64 oracle timed on the host cores on a bounded sample (cpu_baseline);
+  - time-to-match of the headline workload: Algorithm 1 from p = 0 until
+    max|q(1) - Y| < 1e-6 (dense factor of K(X), shoots, solves), measured once;
+  - the single-precision form: the same shoot in FP32 (its stage time and roofline) and its
+    error against the FP64 oracle's stored shoot, with the FP64 shoot's error beside it;
+  - time-to-match of the 2-D curve (N = 4096, 200 RK4 steps, FP64, and FP32 switching to FP64)
+    and of the circle -> ellipse (N = 64), and the FP32 curve shoot's error against the oracle;
+  - the 256-problem batch (autotuned shape, batched shoots, batched Algorithm 1);
+  - the differentiation workload (16384 sphere points, Gaussian sigma = 0.1, lambda = 100:
+    energy gradient, L-BFGS, and the feedback iteration on the same problem).
+A leg that does not fit is reported as skipped; the JSON line is always printed.
 
-And the differentiation workload (16384 sphere points, Gaussian sigma = 0.1, lambda = 100):
-one energy-and-gradient evaluation, L-BFGS on the energy, and the feedback iteration on the
-same problem (its Gaussian kernel matrix is numerically singular there).
-
-Default workload: 65536 Fibonacci-sphere landmarks in 3-D, conical kernel sigma = 0.05,
-100 RK4 steps on [0, 1], FP64, h = 0.8; the target is the template moved by a seeded smooth
-field.  --mode iteration times single feedback iterations (lm_feedback_step, CG K-solve)
-instead, for workloads whose kernel matrix is singular (the Gaussian at these widths).
+--mode match or iteration makes a step one whole match or one feedback iteration instead
+(diagnostics; the headline is the shoot).
 """
 
 from __future__ import annotations
@@ -39,9 +40,13 @@ import os
 import sys
 import time
 
+T_START = time.time()
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 # FP64 VALU issue slots charged per pair (an FMA is one slot, a quarter-rate transcendental
 # four); fixed before any tuning and never changed, so a faster kernel shows up as a higher
@@ -52,6 +57,11 @@ SLOTS_PER_PAIR = {(3, 0): 46, (2, 0): 41, (3, 1): 32, (2, 1): 27}
 # MI355X: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz = 3.93e13 FMA slots/s = 78.6 TFLOP/s
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 PEAK_TFLOPS = 2.0 * PEAK_SLOTS / 1e12
+# Single precision: the arithmetic of the FP64 charge plus v_exp_f32 (4 slots, with its
+# range step 5) and, for the conon, v_rsq_f32 (4 slots, no Newton step at the FP32 bar),
+# charged against MI355X's FP32 vector peak of 157.3 TFLOP/s (twice the FP64 lane rate).
+SLOTS_PER_PAIR_F32 = {(3, 0): 28, (2, 0): 23, (3, 1): 22, (2, 1): 17}
+PEAK_TFLOPS_F32 = 157.3
 
 # HBM bytes per RK stage of the dominant kernel (the pair-sum launch and the launch that adds
 # its partial sums) from rocprofv3 FETCH_SIZE and WRITE_SIZE runs,
@@ -61,6 +71,11 @@ PEAK_TFLOPS = 2.0 * PEAK_SLOTS / 1e12
 MEASURED_TRAFFIC = {
     "sphere3d_conon_f64": ("f6c3a5cf97caf2d9", 1.0588e9),
 }
+
+# Estimated seconds of each optional leg on MI355X (a leg runs only if the budget left
+# covers it), refined in the run by what the headline shoot measured.
+LEG_SECONDS = {"cpu_baseline": 20.0, "time_to_match": 40.0, "fp32": 15.0, "curve2d": 20.0,
+               "batched": 90.0, "adjoint": 60.0}
 
 
 def kernel_source_hash() -> str:
@@ -103,13 +118,30 @@ def cutoff_radius(spec) -> float:
     return spec["sigma"] * (L if spec["kernel"] == 0 else math.sqrt(L))
 
 
-def cpu_baseline(pr, target_s: float):
+class Budget:
+    """Wall-clock budget of the whole run, counted from the start of the process."""
+
+    def __init__(self, seconds: float):
+        self.seconds = seconds
+        self.skipped = []
+
+    def left(self) -> float:
+        return self.seconds - (time.time() - T_START)
+
+    def allows(self, leg: str, estimate: float) -> bool:
+        if self.left() >= estimate:
+            return True
+        self.skipped.append(leg)
+        log("budget: skipping %s (%.0f s left, needs about %.0f s)" % (leg, self.left(), estimate))
+        return False
+
+
+def cpu_baseline(pr, p, target_s: float):
     """The FP64 oracle on the host cores: rows of one RHS evaluation of the same workload."""
     import numpy as np
     import oracle
 
     n = pr.n
-    p = pr.p_bench()
     rows = 64
     while True:
         idx = np.linspace(0, n - 1, rows).astype(np.int64)
@@ -127,6 +159,141 @@ def cpu_baseline(pr, target_s: float):
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def stored_oracle(name: str, pr, p0):
+    """The oracle's stored shoot of a workload (written by tests/golden/make_oracle_shoots.py),
+    or None when it is absent or was made from other inputs."""
+    import numpy as np
+    path = os.path.join(GOLDEN, "oracle_shoot_%s.npz" % name)
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    idx = z["idx"]
+    if int(z["n"]) != pr.n or not (np.allclose(z["X"], pr.X[:, idx], rtol=0, atol=1e-14)
+                                   and np.allclose(z["p0"], p0[:, idx], rtol=0, atol=1e-14)):
+        return None
+    return z
+
+
+def rel_err(got, want) -> float:
+    import numpy as np
+    return float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+
+
+def timed_shoots(lm, torch, prm, q0, p0, t1, steps, q1, p1, count):
+    """Runs `count` shoots; returns (wall seconds, GPU milliseconds per shoot from HIP events
+    recorded on the stream the library launches on)."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(count)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        st = lm.lm_shoot(prm, q0, p0, t1, steps, q1, p1)
+        b.record()
+        if st != 0:
+            raise RuntimeError("lm_shoot: %s" % lm.STATUS_NAMES[st])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in evs]
+
+
+def pair_roofline(lm, prm, n, dim, kernel, dtype, stage_ms, cutoff=0.0):
+    """Roofline entry of one RK stage (pair-sum launch plus the launch adding its partials)."""
+    plan = lm.lm_pair_plan(prm, n)
+    kname = "%s,%d,%s,force" % ("double" if dtype == 0 else "float", dim, "conon" if kernel == 0 else "gauss")
+    if dtype == 0:
+        peak, table = PEAK_TFLOPS, SLOTS_PER_PAIR
+    else:
+        peak, table = PEAK_TFLOPS_F32, SLOTS_PER_PAIR_F32
+    if plan["symmetric"]:
+        slots = table[(dim, kernel)] + 2 * dim
+        evals = n * (n + 1) // 2
+        kname = "%s<%s> + lm_finish_kernel" % ("lm_sym_pair_wide_kernel" if plan["rows"] == 4 else "lm_sym_pair_kernel",
+                                               kname)
+    else:
+        slots = table[(dim, kernel)]
+        evals = n * n
+        kname = "lm_pair_kernel<%s>%s" % (kname, " + lm_finish_kernel" if plan["partial_slots"] > 1 else "")
+    achieved = evals * slots * 2.0 / (stage_ms * 1e-3) / 1e12
+    if cutoff > 0.0:
+        achieved = None          # with tile skipping fewer than N^2 pairs are evaluated
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": (achieved / peak) if achieved else None, "traffic": None,
+            "kernel": kname, "plan": plan, "launch_ms": stage_ms, "pair_evaluations_per_launch": evals,
+            "slots_per_evaluation": slots, "pairs_per_s_in_kernel": n * n / (stage_ms * 1e-3)}
+
+
+def match_record(lm, st, info, seconds, tol, h):
+    return {"seconds": seconds, "status": lm.STATUS_NAMES[st], "iters": info.iters, "resid_inf": info.resid_inf,
+            "factor_ms": info.factor_ms, "shoot_ms": info.shoot_ms, "solve_ms": info.solve_ms,
+            "cg_iters": info.cg_iters, "tol": tol, "h": h, "paper_H_2H": 2 * info.H}
+
+
+def fp32_leg(lm, torch, dev, pr, p_np, q64_gpu, p64_gpu):
+    """The headline shoot in single precision: stage time, roofline, and its error against the
+    oracle's stored FP64 shoot (and the FP64 GPU shoot's error beside it)."""
+    prm = lm.make_params(pr.dim, pr.kernel, pr.sigma, dtype=lm.F32)
+    q0 = torch.tensor(pr.X, device=dev, dtype=torch.float32)
+    p0 = torch.tensor(p_np, device=dev, dtype=torch.float32)
+    q1, p1 = torch.empty_like(q0), torch.empty_like(q0)
+    timed_shoots(lm, torch, prm, q0, p0, 1.0, pr.steps, q1, p1, 1)                    # warm-up
+    wall, ev = timed_shoots(lm, torch, prm, q0, p0, 1.0, pr.steps, q1, p1, 2)
+    stage_ms = sum(ev) / (len(ev) * 4 * pr.steps)
+    out = {"workload": "sphere3d_conon_f32", "shoot_ms": wall * 1e3 / 2,
+           "pairs_per_s": 4 * pr.steps * pr.n ** 2 * 2 / wall,
+           "roofline": pair_roofline(lm, prm, pr.n, pr.dim, pr.kernel, 1, stage_ms)}
+    q32, p32 = q1.double().cpu().numpy(), p1.double().cpu().numpy()
+    q64, p64 = q64_gpu.cpu().numpy(), p64_gpu.cpu().numpy()
+    out["err_vs_gpu_f64"] = {"q": rel_err(q32, q64), "p": rel_err(p32, p64)}
+    z = stored_oracle("sphere3d_conon_100steps", pr, p_np)
+    if z is not None:
+        idx = z["idx"]
+        out["err_vs_oracle"] = {"q": rel_err(q32[:, idx], z["q1"]), "p": rel_err(p32[:, idx], z["p1"]),
+                                "rows": int(len(idx)), "bar": 1e-4}
+        out["f64_err_vs_oracle"] = {"q": rel_err(q64[:, idx], z["q1"]), "p": rel_err(p64[:, idx], z["p1"]),
+                                    "rows": int(len(idx)), "bar": 1e-10}
+    log("fp32 shoot: %.1f ms, stage %.3f ms, err vs FP64 gpu q %.2e p %.2e%s" % (
+        out["shoot_ms"], stage_ms, out["err_vs_gpu_f64"]["q"], out["err_vs_gpu_f64"]["p"],
+        (", vs oracle q %.2e p %.2e" % (out["err_vs_oracle"]["q"], out["err_vs_oracle"]["p"]))
+        if "err_vs_oracle" in out else ""))
+    return out
+
+
+def curve2d_leg(lm, torch, dev, h, tol, setup, run_match):
+    """2-D curve (N = 4096, 200 RK4 steps) and circle -> ellipse (N = 64) time-to-match, and the
+    curve's FP32 and FP64 shoots against the oracle's stored shoot."""
+    out = {}
+    for mname, sw in [("curve2d_conon_f64", 0.0), ("curve2d_conon_f32", 1e-4), ("circle_ellipse_f64", 0.0)]:
+        mpr, mdtype, mrc, mprm, MX, MY = setup(mname)
+        run_match(mprm, mpr, MX, MY, sw)                     # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, minfo, _ = run_match(mprm, mpr, MX, MY, sw)
+        torch.cuda.synchronize()
+        rec = match_record(lm, st, minfo, time.perf_counter() - t1, tol, h)
+        rec.update(workload=mname, n=mpr.n, f32_switch=sw)
+        out[mname] = rec
+        log("time to match %s: %.3f s, %d iterations, resid %.2e" % (mname, rec["seconds"], minfo.iters,
+                                                                      minfo.resid_inf))
+    pr = make_problem(WORKLOADS["curve2d_conon_f64"][0])
+    p_np = pr.p_bench()
+    z = stored_oracle("curve2d_conon_200steps", pr, p_np)
+    if z is not None:
+        idx = z["idx"]
+        errs = {}
+        for name, dt_ in [("f64", torch.float64), ("f32", torch.float32)]:
+            prm = lm.make_params(2, pr.kernel, pr.sigma, dtype=lm.F64 if dt_ == torch.float64 else lm.F32)
+            q0 = torch.tensor(pr.X, device=dev, dtype=dt_)
+            p0 = torch.tensor(p_np, device=dev, dtype=dt_)
+            q1, p1 = torch.empty_like(q0), torch.empty_like(q0)
+            lm.lm_shoot(prm, q0, p0, 1.0, pr.steps, q1, p1)
+            q, p = q1.double().cpu().numpy()[:, idx], p1.double().cpu().numpy()[:, idx]
+            errs[name] = {"q": rel_err(q, z["q1"]), "p": rel_err(p, z["p1"])}
+        out["shoot_err_vs_oracle"] = dict(errs, rows=int(len(idx)), bars={"f64": 1e-10, "f32": 1e-4})
+        log("curve2d shoot vs oracle: f64 q %.2e p %.2e, f32 q %.2e p %.2e" % (
+            errs["f64"]["q"], errs["f64"]["p"], errs["f32"]["q"], errs["f32"]["p"]))
+    return out
 
 
 def batched_leg(lm, torch, dev, h: float, tol: float):
@@ -227,15 +394,18 @@ def adjoint_leg(lm, torch, dev, full: bool):
     return out
 
 
-def main():
+def parse_args(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1, help="timed steps (whole matches)")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed steps before")
+    ap.add_argument("--steps", type=int, default=10, help="timed steps (forward shoots)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed steps before")
     ap.add_argument("--workload", default="sphere3d_conon_f64", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="match", choices=["match", "iteration", "shoot"],
-                    help="a step is one whole match, one feedback iteration, or one forward shoot from the "
-                         "workload's benchmark momenta")
+    ap.add_argument("--mode", default="shoot", choices=["shoot", "match", "iteration"],
+                    help="a step is one forward shoot from the workload's benchmark momenta (default), one "
+                         "whole match, or one feedback iteration")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock budget of the whole run from process start; the legs after the timed "
+                         "steps are skipped when it has no room for them")
     ap.add_argument("--h", type=float, default=0.8, help="search length of Algorithm 1")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=100)
@@ -243,9 +413,9 @@ def main():
     ap.add_argument("--cg-max-iter", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--match", default="curve2d_conon_f64,circle_ellipse_f64",
-                    help="comma-separated workloads whose time-to-match is also reported (outside value), "
-                         "or none")
+    ap.add_argument("--no-match", action="store_true", help="skip the headline workload's time-to-match")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the single-precision shoot")
+    ap.add_argument("--no-curve2d", action="store_true", help="skip the 2-D curve and circle workloads")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-problem batch measurements")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient-matching measurements")
     ap.add_argument("--adjoint-full", action="store_true",
@@ -256,7 +426,11 @@ def main():
                     help="only the 256-problem batch measurements (a diagnostic line, not the benchmark)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
-    args = ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def main():
+    args = parse_args()
 
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; the pair sums would shard by target rows with one "
@@ -267,6 +441,7 @@ def main():
 
     import paper_1510_03816_amd as lm
 
+    budget = Budget(args.budget_s)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
@@ -295,10 +470,11 @@ def main():
         Y = torch.tensor(pr.Y, device=dev)
         return pr, dtype, rc, prm, X, Y
 
-    def run_match(prm, pr, X, Y):
+    def run_match(prm, pr, X, Y, f32_switch=0.0):
         p = torch.zeros_like(X)
         return lm.lm_feedback_match(prm, X, Y, p, h=args.h, tol=args.tol, steps=pr.steps,
-                                    max_iter=args.max_iter, cg_max_iter=args.cg_max_iter, solver=args.solver)
+                                    max_iter=args.max_iter, cg_max_iter=args.cg_max_iter, solver=args.solver,
+                                    f32_switch=f32_switch)
 
     pr, dtype, rc, prm, X, Y = setup(args.workload)
     n, dim = pr.n, pr.dim
@@ -307,114 +483,112 @@ def main():
         args.workload, n, dim, "conon" if pr.kernel == 0 else "gauss", pr.sigma, pr.steps,
         "f64" if dtype == 0 else "f32", rc, args.mode))
 
+    sdt = torch.float64 if dtype == 0 else torch.float32
+    p_np = pr.p_bench()
+    q_sh = X.to(sdt)
+    p_sh = torch.tensor(p_np, device=dev, dtype=sdt)
+    q1_sh, p1_sh = torch.empty_like(q_sh), torch.empty_like(q_sh)
     p_iter = torch.zeros_like(X)
-    if args.mode == "shoot":
-        sdt = torch.float64 if dtype == 0 else torch.float32
-        q_sh = X.to(sdt)
-        p_sh = torch.tensor(pr.p_bench(), device=dev, dtype=sdt)
-        q1_sh, p1_sh = torch.empty_like(q_sh), torch.empty_like(q_sh)
-
-    def step():
-        """Returns (shoots, shoot_ms, solve_ms, factor_ms, record)."""
-        if args.mode == "shoot":
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            st = lm.lm_shoot(prm, q_sh, p_sh, 1.0, pr.steps, q1_sh, p1_sh)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t) * 1e3
-            log("shoot: %s %.1f ms" % (lm.STATUS_NAMES[st], ms))
-            return 1, ms, 0.0, 0.0, {"status": lm.STATUS_NAMES[st], "shoot_ms": ms}
-        if args.mode == "match":
-            st, info, hist = run_match(prm, pr, X, Y)
-            rec = {"status": lm.STATUS_NAMES[st], "iters": info.iters, "resid_inf": info.resid_inf,
-                   "cg_iters": info.cg_iters, "factor_ms": info.factor_ms, "shoot_ms": info.shoot_ms,
-                   "solve_ms": info.solve_ms, "paper_H_2H": 2 * info.H}
-            log("match: %s %d iterations, resid %.3e, factor %.0f ms, shoots %.0f ms, solves %.0f ms" % (
-                rec["status"], info.iters, info.resid_inf, info.factor_ms, info.shoot_ms, info.solve_ms))
-            return info.iters + 1, info.shoot_ms, info.solve_ms, info.factor_ms, rec
-        st, info = lm.lm_feedback_step(prm, X, Y, p_iter, h=args.h, tol=args.tol, steps=pr.steps,
-                                       cg_max_iter=args.cg_max_iter, solver=lm.SOLVE_CG)
-        rec = {"status": lm.STATUS_NAMES[st], "resid_inf": info.resid_inf, "cg_iters": info.cg_iters,
-               "shoot_ms": info.shoot_ms, "solve_ms": info.solve_ms}
-        log("iteration: %s resid %.3e shoot %.0f ms solve %.0f ms (%d CG)" % (
-            rec["status"], info.resid_inf, info.shoot_ms, info.solve_ms, info.cg_iters))
-        return 1, info.shoot_ms, info.solve_ms, 0.0, rec
-
-    for _ in range(args.warmup):
-        step()
-    p_iter.zero_()
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    shoots = 0
-    shoot_ms = solve_ms = factor_ms = 0.0
     records = []
-    for _ in range(args.steps):
-        s, a, b, c, rec = step()
-        shoots += s
-        shoot_ms += a
-        solve_ms += b
-        factor_ms += c
-        records.append(rec)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    gpu_ms = {"shoot": 0.0, "solve": 0.0, "factor": 0.0}
+
+    if args.mode == "shoot":
+        if args.warmup > 0:
+            timed_shoots(lm, torch, prm, q_sh, p_sh, 1.0, pr.steps, q1_sh, p1_sh, args.warmup)
+        elapsed, ev_ms = timed_shoots(lm, torch, prm, q_sh, p_sh, 1.0, pr.steps, q1_sh, p1_sh, args.steps)
+        shoots = args.steps
+        gpu_ms["shoot"] = sum(ev_ms)
+        records = [{"shoot_ms_gpu": t} for t in ev_ms]
+        log("timed %d shoots: %.1f ms each (wall), GPU %.1f .. %.1f ms" % (
+            shoots, elapsed * 1e3 / shoots, min(ev_ms), max(ev_ms)))
+    else:
+        def step():
+            if args.mode == "match":
+                st, info, _ = run_match(prm, pr, X, Y)
+                rec = {"status": lm.STATUS_NAMES[st], "iters": info.iters, "resid_inf": info.resid_inf,
+                       "factor_ms": info.factor_ms, "shoot_ms": info.shoot_ms, "solve_ms": info.solve_ms}
+                return info.iters + 1, info.shoot_ms, info.solve_ms, info.factor_ms, rec
+            st, info = lm.lm_feedback_step(prm, X, Y, p_iter, h=args.h, tol=args.tol, steps=pr.steps,
+                                           cg_max_iter=args.cg_max_iter, solver=lm.SOLVE_CG)
+            rec = {"status": lm.STATUS_NAMES[st], "resid_inf": info.resid_inf, "cg_iters": info.cg_iters,
+                   "shoot_ms": info.shoot_ms, "solve_ms": info.solve_ms}
+            return 1, info.shoot_ms, info.solve_ms, 0.0, rec
+
+        for _ in range(args.warmup):
+            step()
+        p_iter.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        shoots = 0
+        for _ in range(args.steps):
+            s, a, b, c, rec = step()
+            shoots += s
+            gpu_ms["shoot"] += a
+            gpu_ms["solve"] += b
+            gpu_ms["factor"] += c
+            records.append(rec)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
 
     value = pairs_per_shoot * shoots / elapsed
-    # dominant kernel: the pair-sum kernel, one launch per RK stage
-    launch_ms = shoot_ms / (shoots * 4 * pr.steps)
-    plan = lm.lm_pair_plan(prm, n)
-    kname = "%s,%d,%s,force" % ("double" if dtype == 0 else "float", dim, "conon" if pr.kernel == 0 else "gauss")
-    if plan["symmetric"]:
-        slots = SLOTS_PER_PAIR[(dim, pr.kernel)] + 2 * dim
-        evals = n * (n + 1) // 2
-        kname = "%s<%s> + lm_finish_kernel" % ("lm_sym_pair_wide_kernel" if plan["rows"] == 4 else "lm_sym_pair_kernel",
-                                               kname)
-    else:
-        slots = SLOTS_PER_PAIR[(dim, pr.kernel)]
-        evals = n * n
-        kname = "lm_pair_kernel<%s>%s" % (kname, " + lm_finish_kernel" if plan["partial_slots"] > 1 else "")
-    achieved = evals * slots * 2.0 / (launch_ms * 1e-3) / 1e12
-    if rc > 0.0:
-        # with tile skipping the pairs evaluated are fewer than N^2: not a roofline figure
-        achieved = None
-    traffic = None
+    stage_ms = gpu_ms["shoot"] / (shoots * 4 * pr.steps)
+    roofline = pair_roofline(lm, prm, n, dim, pr.kernel, dtype, stage_ms, rc)
     if args.workload in MEASURED_TRAFFIC and MEASURED_TRAFFIC[args.workload][0] == kernel_source_hash():
-        traffic = MEASURED_TRAFFIC[args.workload][1]
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_TFLOPS) if achieved else None, "traffic": traffic,
-                "traffic_unit": "HBM bytes per RK stage (pair-sum and finish launches)",
-                "kernel": kname, "plan": plan,
-                "launch_ms": launch_ms, "pair_evaluations_per_launch": evals, "slots_per_evaluation": slots,
-                "pairs_per_s_in_kernel": n * n / (launch_ms * 1e-3)}
+        roofline["traffic"] = MEASURED_TRAFFIC[args.workload][1]
+    roofline["traffic_unit"] = "HBM bytes per RK stage (pair-sum and finish launches)"
+    roofline["timing"] = "HIP events on the library's stream around every timed shoot / (4 x RK4 steps)"
+    shoot_s = elapsed / max(shoots, 1)
+    log("roofline: %.3f ms per stage, %.1f TFLOP/s, frac %.3f" % (
+        stage_ms, roofline["achieved"] or 0.0, roofline["frac"] or 0.0))
+
+    legs = {}
+
+    def leg(name, fn, estimate):
+        if not budget.allows(name, estimate):
+            legs[name] = {"skipped": "wall-clock budget"}
+            return None
+        t = time.time()
+        try:
+            r = fn()
+        except Exception as e:              # report the leg's failure and keep the line
+            log("%s failed: %r" % (name, e))
+            r = {"error": repr(e)}
+        log("%s leg: %.1f s" % (name, time.time() - t))
+        return r
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = leg("cpu_baseline", lambda: cpu_baseline(pr, p_np, args.cpu_seconds), args.cpu_seconds * 1.5 + 5)
 
     ttm = None
-    if args.mode == "match":
+    if not args.no_match and args.mode == "shoot" and rc == 0.0:
+        def ttm_fn():
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, info, _ = run_match(prm, pr, X, Y)
+            torch.cuda.synchronize()
+            r = match_record(lm, st, info, time.perf_counter() - t1, args.tol, args.h)
+            r.update(workload=args.workload, shoots=info.iters + 1)
+            log("time to match %s: %.2f s, %d iterations, resid %.2e" % (args.workload, r["seconds"], info.iters,
+                                                                          info.resid_inf))
+            return r
+        ttm = leg("time_to_match", ttm_fn, max(LEG_SECONDS["time_to_match"], 22 * shoot_s))
+    elif args.mode == "match":
         ttm = dict(records[-1], workload=args.workload, seconds=elapsed / args.steps, tol=args.tol, h=args.h)
 
-    extra_matches = {}
-    for mname in ([] if args.match == "none" else args.match.split(",")):
-        if mname == args.workload:
-            continue
-        mpr, mdtype, mrc, mprm, MX, MY = setup(mname)
-        run_match(mprm, mpr, MX, MY)                         # warm-up
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        st, minfo, hist = run_match(mprm, mpr, MX, MY)
-        torch.cuda.synchronize()
-        extra_matches[mname] = {
-            "workload": mname, "n": mpr.n, "seconds": time.perf_counter() - t1, "status": lm.STATUS_NAMES[st],
-            "iters": minfo.iters, "resid_inf": minfo.resid_inf, "factor_ms": minfo.factor_ms,
-            "shoot_ms": minfo.shoot_ms, "solve_ms": minfo.solve_ms, "cg_iters": minfo.cg_iters,
-            "tol": args.tol, "h": args.h, "paper_H_2H": 2 * minfo.H}
-        log("time to match %s: %.3f s, %d iterations, resid %.2e" % (
-            mname, extra_matches[mname]["seconds"], minfo.iters, minfo.resid_inf))
-    ttm2 = extra_matches.get("curve2d_conon_f64")
-    ttm3 = extra_matches.get("circle_ellipse_f64")
+    fp32 = None
+    if not args.no_fp32 and args.workload == "sphere3d_conon_f64" and args.mode == "shoot":
+        fp32 = leg("fp32", lambda: fp32_leg(lm, torch, dev, pr, p_np, q1_sh, p1_sh),
+                   max(LEG_SECONDS["fp32"], 4 * shoot_s))
 
-    batched = None if args.no_batched else batched_leg(lm, torch, dev, args.h, args.tol)
-    adjoint = None if args.no_adjoint else adjoint_leg(lm, torch, dev, args.adjoint_full)
-
-    cpu = None if args.no_cpu_baseline else cpu_baseline(pr, args.cpu_seconds)
+    curves = None
+    if not args.no_curve2d:
+        curves = leg("curve2d", lambda: curve2d_leg(lm, torch, dev, args.h, args.tol, setup, run_match),
+                     LEG_SECONDS["curve2d"])
+    batched = None if args.no_batched else leg("batched", lambda: batched_leg(lm, torch, dev, args.h, args.tol),
+                                               LEG_SECONDS["batched"])
+    adjoint = None if args.no_adjoint else leg("adjoint", lambda: adjoint_leg(lm, torch, dev, args.adjoint_full),
+                                               LEG_SECONDS["adjoint"] + (90.0 if args.adjoint_full else 0.0))
 
     out = {
         "metric": "pair-interactions/s (RK4 shooting) + time-to-match at endpoint err 1e-6",
@@ -432,18 +606,20 @@ def main():
         "config": {"workload": args.workload, "n": n, "dim": dim,
                    "kernel": "conon" if pr.kernel == 0 else "gauss", "sigma": pr.sigma,
                    "rk4_steps": pr.steps, "h": args.h, "tol": args.tol, "cutoff": rc,
-                   "step": {"match": "one whole feedback match from p = 0 to max|q(1) - Y| < tol",
-                            "iteration": "one feedback iteration (CG K-solve)",
-                            "shoot": "one forward shoot of the RK4 steps from X with the benchmark momenta"}[args.mode]},
+                   "step": {"shoot": "one forward shoot of the RK4 steps from X with the benchmark momenta",
+                            "match": "one whole feedback match from p = 0 to max|q(1) - Y| < tol",
+                            "iteration": "one feedback iteration (CG K-solve)"}[args.mode]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_match": ttm,
-        "time_to_match_curve2d": ttm2,
-        "time_to_match_circle_ellipse": ttm3,
+        "fp32": fp32,
+        "curve2d": curves,
         "batched": batched,
         "adjoint": adjoint,
+        "legs_skipped": budget.skipped,
+        "wall_s": time.time() - T_START,
         "shoots": shoots,
-        "gpu_ms": {"shoot": shoot_ms, "solve": solve_ms, "factor": factor_ms},
+        "gpu_ms": gpu_ms,
         "records": records,
     }
     print(json.dumps(out), flush=True)

@@ -13,10 +13,19 @@ from . import _lib
 
 
 class ShootFunction(torch.autograd.Function):
-    """(q1, p1) = shoot(q0, p0) over [0, t1] with `steps` RK4 steps (double precision)."""
+    """(q1, p1) = shoot(q0, p0) over [0, t1] with `steps` RK4 steps.
+
+    The backward pass (the discrete adjoint) exists for double precision and every pair
+    (params.dtype == F64, params.cutoff == 0): when an input requires a gradient under other
+    settings, forward raises before any GPU work rather than after the shoot."""
 
     @staticmethod
     def forward(ctx, q0, p0, params, t1: float, steps: int, ckpt_every: int = 10):
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            if params.dtype != _lib.F64 or params.cutoff > 0.0:
+                raise _lib.LmError(_lib.LM_EUNSUPPORTED,
+                                   "the shooting adjoint needs dtype F64 and cutoff 0 (got dtype %d, cutoff %g)"
+                                   % (params.dtype, params.cutoff))
         q0 = q0.contiguous()
         p0 = p0.contiguous()
         q1 = torch.empty_like(q0)

@@ -788,9 +788,11 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         Workspace hws(st);
         BatchPlan pl;
         LM_TRY(make_plan(dim, B, offs, offs_d, tun, hws, &pl, st, true));
+        // H is the kernel form alone (equation "H"): the inexact advection weight tau is not
+        // part of it, so the velocities are summed with tau = 0
         lm::EpiArgs<double> ev{};
         ev.kind = lm::EPI_STORE;
-        ev.tau = prm->tau;
+        ev.tau = 0.0;
         ev.in_p = p;
         ev.out_q = e;
         ev.out_p = qd;   // forces are not needed; written to scratch

@@ -129,3 +129,18 @@ def test_one_hip_runtime_whatever_the_import_order(tmp_path):
     assert out.returncode == 0, out.stderr
     lines = out.stdout.splitlines()
     assert lines[0] == "1", lines
+
+
+@pytest.mark.parametrize("dtype,cutoff", [(1, 0.0), (0, 0.3)])
+def test_autograd_shoot_refuses_unsupported_settings_before_the_shoot(dtype, cutoff):
+    """The shooting adjoint exists for double precision with every pair: asking for a gradient
+    under single precision or tile skipping fails in the forward pass, before any GPU work
+    (the tensors here are host tensors, which the library would reject if it got them)."""
+    import torch
+    from paper_1510_03816_amd import _lib
+    from paper_1510_03816_amd.autograd import shoot
+    q = torch.zeros((2, 4), dtype=torch.float64, requires_grad=True)
+    p = torch.zeros((2, 4), dtype=torch.float64)
+    with pytest.raises(_lib.LmError) as ei:
+        shoot(q, p, _params(dtype=dtype, cutoff=cutoff), 1.0, 10)
+    assert ei.value.status == _lib.LM_EUNSUPPORTED

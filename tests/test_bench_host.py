@@ -44,3 +44,24 @@ def test_workload_sizes():
     assert all(v == (65536, 100) for k, v in sizes.items() if k.startswith("sphere3d"))
     assert all(v == (4096, 200) for k, v in sizes.items() if k.startswith("curve2d"))
     assert bench.WORKLOADS["circle_ellipse_f64"][0]["n"] == 64
+
+
+def test_default_step_is_one_forward_shoot_of_the_sphere():
+    a = bench.parse_args([])
+    assert a.mode == "shoot" and a.workload == "sphere3d_conon_f64" and a.gpus == 1
+    spec, dtype = bench.WORKLOADS[a.workload]
+    assert (spec["n"], spec["kernel"], spec["sigma"], spec["steps"], dtype) == (65536, 0, 0.05, 100, 0)
+
+
+def test_budget_skips_legs_that_do_not_fit():
+    b = bench.Budget(bench.time.time() - bench.T_START + 30.0)
+    assert b.allows("short", 5.0)
+    assert not b.allows("long", 1000.0)
+    assert b.skipped == ["long"]
+
+
+def test_fp32_charges_are_at_most_the_fp64_charges():
+    """Single precision drops the exponential's and the square root's refinement steps, so its
+    charge per pair is below the double-precision one for every kernel and dimension."""
+    for key, s64 in bench.SLOTS_PER_PAIR.items():
+        assert bench.SLOTS_PER_PAIR_F32[key] < s64

@@ -191,6 +191,30 @@ def test_batched_feedback_matches_oracle_per_problem():
         assert abs(infos[b].H - ref.H) <= 1e-9 * abs(ref.H)
 
 
+def test_batched_inexact_feedback_matches_oracle_per_problem():
+    """The inexact system (tau > 0: the tau p_i advection term and the (K + tau I) update,
+    equation "N-particle-inexact") through batched Algorithm 1: per problem the oracle's
+    iteration count, momenta, q(1), and H of equation "H" (the kernel form alone, without tau)."""
+    tau = 0.05
+    sizes, offs, X, Y = curve_batch(5, 300)
+    prm = lm.make_params(2, lm.CONON, 0.1, tau=tau)
+    p0 = torch.zeros((2, int(offs[-1])), dtype=torch.float64, device=DEV)
+    q1 = torch.empty_like(p0)
+    st, infos, stats = lm.lm_feedback_match_batched(prm, offs, dev(X), dev(Y), p0, h=0.8, tol=1e-6, steps=20,
+                                                    max_iter=200, q1=q1)
+    assert st == lm.LM_OK and all(s == lm.LM_OK for s in stats)
+    gp, gq = host(p0), host(q1)
+    for b in range(len(sizes)):
+        s = slice(offs[b], offs[b + 1])
+        ref = oracle.feedback_match(X[:, s], Y[:, s], lm.CONON, 0.1, 0.8, 1e-6, 20, max_iter=200, tau=tau)
+        assert ref.status == 0
+        assert infos[b].iters == ref.iters, (b, infos[b].iters, ref.iters)
+        assert rel_err(gp[:, s], ref.p0) <= 1e-8
+        assert rel_err(gq[:, s], ref.q1) <= 1e-10
+        assert abs(infos[b].H - ref.H) <= 1e-9 * abs(ref.H)
+        assert abs(infos[b].H - oracle.hamiltonian(X[:, s], ref.p0, lm.CONON, 0.1)) <= 1e-9 * abs(ref.H)
+
+
 def test_batched_feedback_single_precision_shoots():
     sizes, offs, X, Y = curve_batch(5, 300)
     prm = lm.make_params(2, lm.CONON, 0.1, dtype=lm.F32)

@@ -101,6 +101,29 @@ def test_coincident_particles_exert_no_force(orc):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("tau", [0.0, 0.3])
+@pytest.mark.parametrize("nidx", [5, 300])
+def test_rhs_rows_equals_rows_of_the_full_rhs_bitwise(orc, kernel, dim, tau, nidx):
+    """The sampled-rows form of the right-hand side (which every full-size comparison uses)
+    returns exactly the selected rows of the full evaluation, for unsorted and repeated
+    indices, the first and last rows, and coincident particles; both sides of its threaded
+    branch (few rows and many)."""
+    n = 150
+    q, p = _rand(n, dim, seed=[31, dim, nidx])
+    q[:, 7] = q[:, 99]                        # a coincident pair
+    rng = np.random.default_rng([32, nidx])
+    idx = np.concatenate([[n - 1, 0, 7, 99, 7], rng.integers(0, n, size=nidx - 5)])[:nidx]
+    assert len(set(idx.tolist())) < nidx      # repeats, and not sorted
+    assert not np.all(np.diff(idx) >= 0)
+    dq, dp = orc.rhs(q, p, kernel, 0.4, tau)
+    rq, rp = orc.rhs_rows(q, p, idx, kernel, 0.4, tau)
+    assert rq.shape == (dim, nidx) and rp.shape == (dim, nidx)
+    assert np.array_equal(rq, dq[:, idx])
+    assert np.array_equal(rp, dp[:, idx])
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("n,dim", [(1, 2), (2, 2), (3, 3), (7, 2), (20, 3)])
 def test_c_oracle_matches_numpy_mini(orc, kernel, n, dim):
     q, p = _rand(n, dim, seed=[13, n, dim])
