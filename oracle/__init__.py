@@ -75,6 +75,8 @@ def lib():
         L.orc_shoot_adjoint.argtypes = [i, l, i, d, d, d, i, P, P, P, P, P, P]
         L.orc_velocity.restype = None
         L.orc_velocity.argtypes = [i, l, l, i, d, P, P, P, P]
+        L.orc_flow_points.restype = None
+        L.orc_flow_points.argtypes = [i, l, l, i, d, d, d, i, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -199,6 +201,18 @@ def velocity(q, p, x, kernel: int, sigma: float) -> np.ndarray:
     u = np.empty_like(x)
     lib().orc_velocity(dim, n, m, kernel, sigma, _ptr(q), _ptr(p), _ptr(x), _ptr(u))
     return u
+
+
+def flow_points(q0, p0, x0, kernel: int, sigma: float, steps: int, T: float = 1.0, tau: float = 0.0):
+    """RK4 over [0, T] of the particles (q, p) together with passive points x carried by the
+    velocity field u of equation "u"; returns (q(T), p(T), x(T)), x given as (dim, m)."""
+    q0, p0, x0 = _c(q0), _c(p0), _c(x0)
+    dim, n = q0.shape
+    m = x0.shape[1]
+    q1, p1, x1 = np.empty_like(q0), np.empty_like(p0), np.empty_like(x0)
+    lib().orc_flow_points(dim, n, m, kernel, sigma, tau, T, steps, _ptr(q0), _ptr(p0), _ptr(x0),
+                          _ptr(q1), _ptr(p1), _ptr(x1))
+    return q1, p1, x1
 
 
 def rhs_vjp(q, p, a, b, kernel: int, sigma: float, tau: float = 0.0):

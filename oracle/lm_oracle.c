@@ -443,3 +443,60 @@ void orc_velocity(int dim, long n, long m, int kernel, double sigma,
         for (int c = 0; c < dim; ++c) u[c * m + a] = v[c];
     }
 }
+
+/* ---- Flow of arbitrary points along the geodesic: m passive points x carried by the
+ * velocity field of equation "u" while the particles evolve by the N-particle system,
+ *   dx_a/dt = sum_j G(|x_a - q_j|) p_j,
+ * the whole state (q, p, x) advanced by the same classical RK4 steps as orc_shoot.  The
+ * points do not act on the particles.  (The tau term of the inexact system moves only the
+ * particles: the field of equation "u" has none.) --------------------------------------- */
+void orc_flow_points(int dim, long n, long m, int kernel, double sigma, double tau, double T, int steps,
+                     const double *q0, const double *p0, const double *x0,
+                     double *q1, double *p1, double *x1)
+{
+    size_t mn = (size_t)dim * (size_t)n, mm = (size_t)dim * (size_t)m;
+    double *q = (double *)malloc(sizeof(double) * mn), *p = (double *)malloc(sizeof(double) * mn);
+    double *x = (double *)malloc(sizeof(double) * mm);
+    double *qs = (double *)malloc(sizeof(double) * mn), *ps = (double *)malloc(sizeof(double) * mn);
+    double *xs = (double *)malloc(sizeof(double) * mm);
+    double *kq[4], *kp[4], *kx[4];
+    for (int s = 0; s < 4; ++s) {
+        kq[s] = (double *)malloc(sizeof(double) * mn);
+        kp[s] = (double *)malloc(sizeof(double) * mn);
+        kx[s] = (double *)malloc(sizeof(double) * mm);
+    }
+    memcpy(q, q0, sizeof(double) * mn);
+    memcpy(p, p0, sizeof(double) * mn);
+    memcpy(x, x0, sizeof(double) * mm);
+    double dt = T / steps;
+    const double cstage[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int step = 0; step < steps; ++step) {
+        for (int s = 0; s < 4; ++s) {
+            /* stage s: its input state (q, p, x) + c_s dt k_{s-1}; then k_s at that state */
+            const double *qin = q, *pin = p, *xin = x;
+            if (s > 0) {
+                for (size_t k = 0; k < mn; ++k) {
+                    qs[k] = q[k] + cstage[s] * dt * kq[s - 1][k];
+                    ps[k] = p[k] + cstage[s] * dt * kp[s - 1][k];
+                }
+                for (size_t k = 0; k < mm; ++k) xs[k] = x[k] + cstage[s] * dt * kx[s - 1][k];
+                qin = qs;
+                pin = ps;
+                xin = xs;
+            }
+            orc_rhs(dim, n, kernel, sigma, tau, qin, pin, kq[s], kp[s]);
+            orc_velocity(dim, n, m, kernel, sigma, qin, pin, xin, kx[s]);
+        }
+        for (size_t k = 0; k < mn; ++k) {
+            q[k] = q[k] + dt / 6.0 * (kq[0][k] + 2.0 * kq[1][k] + 2.0 * kq[2][k] + kq[3][k]);
+            p[k] = p[k] + dt / 6.0 * (kp[0][k] + 2.0 * kp[1][k] + 2.0 * kp[2][k] + kp[3][k]);
+        }
+        for (size_t k = 0; k < mm; ++k)
+            x[k] = x[k] + dt / 6.0 * (kx[0][k] + 2.0 * kx[1][k] + 2.0 * kx[2][k] + kx[3][k]);
+    }
+    memcpy(q1, q, sizeof(double) * mn);
+    memcpy(p1, p, sizeof(double) * mn);
+    memcpy(x1, x, sizeof(double) * mm);
+    free(q); free(p); free(x); free(qs); free(ps); free(xs);
+    for (int s = 0; s < 4; ++s) { free(kq[s]); free(kp[s]); free(kx[s]); }
+}

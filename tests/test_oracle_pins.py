@@ -360,3 +360,91 @@ def test_velocity_field_at_particles_is_particle_velocity(orc):
         assert np.allclose(u, dq, rtol=1e-14, atol=1e-15)
         far = np.full((3, 2), 50.0)
         assert np.max(np.abs(orc.velocity(q, p, far, kernel, 0.4))) < 1e-40
+
+
+# ---------------------------------------------------------------- flow of arbitrary points (equation "u")
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_points_at_the_particles_follow_them_bitwise(orc, kernel, dim):
+    """Points placed on the particles have the particles' velocity at every stage (the
+    velocity sum of a particle is the field at its position), so they follow q(t) exactly;
+    the particles themselves evolve as in the plain shoot."""
+    q, p = _rand(23, dim, seed=40)
+    x = np.concatenate([q, q[:, :5]], axis=1)           # also repeated points
+    q1, p1, x1 = orc.flow_points(q, p, x, kernel, 0.4, 17, T=0.9)
+    qs, ps = orc.shoot(q, p, kernel, 0.4, 17, T=0.9)
+    assert np.array_equal(q1, qs) and np.array_equal(p1, ps)
+    assert np.array_equal(x1[:, :23], qs) and np.array_equal(x1[:, 23:], qs[:, :5])
+
+
+def _lone_particle_conon_ahead(z0, P, sigma, t):
+    """A point on the line of a lone particle (conon), z = signed distance ahead of it along
+    p: dz/dt = (exp(-|z|/sigma) - 1) P.  For z > 0, sigma ln(exp(z/sigma) - 1) decreases at
+    rate P; for z < 0 the distance behind grows by the mirror image."""
+    if z0 > 0:
+        return sigma * math.log1p(math.expm1(z0 / sigma) * math.exp(-P * t / sigma))
+    return -sigma * math.log1p(math.expm1(-z0 / sigma) * math.exp(P * t / sigma))
+
+
+def test_lone_particle_carries_points_on_straight_lines(orc):
+    """One particle moves at constant momentum; the field it carries is parallel to p
+    everywhere, so every point moves on a straight line parallel to p, and a point on the
+    particle's line of motion follows the closed form of its 1-D equation."""
+    sigma = 0.3
+    q0 = np.array([[0.2], [-0.1], [0.4]])
+    p0 = np.array([[0.6], [0.3], [-0.2]])
+    P = float(np.linalg.norm(p0))
+    e = p0[:, 0] / P
+    zs = [0.05, 0.2, 0.7, -0.1, -0.5]
+    line = np.stack([q0[:, 0] + z * e for z in zs], axis=1)
+    off = q0 + np.array([[0.3, -0.2], [0.1, 0.4], [0.45, 0.25]])         # off the line
+    x0 = np.concatenate([line, off], axis=1)
+    for n, tol in [(20, 1e-6), (200, 1e-10)]:
+        q1, p1, x1 = orc.flow_points(q0, p0, x0, 0, sigma, n, T=1.0)
+        assert np.allclose(q1, q0 + p0, rtol=0, atol=1e-14) and np.array_equal(p1, p0)
+        for a, z0 in enumerate(zs):
+            want = q1[:, 0] + _lone_particle_conon_ahead(z0, P, sigma, 1.0) * e
+            assert np.max(np.abs(x1[:, a] - want)) < tol
+    # displacements parallel to p: no component across it
+    d = x1 - x0
+    across = d - np.outer(e, e @ d)
+    assert np.max(np.abs(across)) < 1e-14
+
+
+def test_lone_particle_gaussian_point_by_quadrature(orc):
+    """Gaussian kernel, a point ahead on the line: dz/dt = -(1 - exp(-z^2/sigma^2)) P, so
+    t = int_{z(t)}^{z0} dz / ((1 - exp(-z^2/sigma^2)) P)."""
+    sigma, z0 = 0.4, 0.3
+    q0 = np.array([[0.0], [0.0]])
+    p0 = np.array([[0.5], [0.0]])
+    x0 = np.array([[z0], [0.0]])
+    _, _, x1 = orc.flow_points(q0, p0, x0, 1, sigma, 400, T=1.0)
+    z1 = x1[0, 0] - 0.5
+    t, _ = scipy.integrate.quad(lambda z: 1.0 / (-math.expm1(-(z / sigma) ** 2) * 0.5), z1, z0,
+                                epsabs=1e-14, epsrel=1e-13)
+    assert t == pytest.approx(1.0, rel=1e-10)
+    assert x1[1, 0] == 0.0
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_flow_of_points_time_rescaling(orc, kernel):
+    """The points carried by c*p0 to t = 1 are those carried by p0 to t = c."""
+    q, p = _rand(12, 2, seed=41, pscale=0.4)
+    x = np.random.default_rng(42).uniform(-1, 1, (2, 30))
+    c = 1.0 / 0.6
+    _, _, xa = orc.flow_points(q, c * p, x, kernel, 0.5, 25, T=1.0)
+    _, _, xb = orc.flow_points(q, p, x, kernel, 0.5, 25, T=c)
+    assert np.allclose(xa, xb, rtol=0, atol=1e-14)
+
+
+def test_far_points_do_not_move_and_flow_is_fourth_order(orc):
+    """Points far outside the particles' reach stay put; the point flow converges at fourth
+    order in the step (errors fall about 16x per halving)."""
+    q, p = _rand(8, 2, seed=43, pscale=0.5)
+    x = np.concatenate([np.random.default_rng(44).uniform(-1, 1, (2, 6)), np.full((2, 1), 80.0)], axis=1)
+    ref = orc.flow_points(q, p, x, 0, 0.4, 640)[2]
+    assert np.array_equal(ref[:, -1], x[:, -1])
+    errs = [np.max(np.abs(orc.flow_points(q, p, x, 0, 0.4, n)[2] - ref)) for n in (10, 20, 40)]
+    assert 12.0 < errs[0] / errs[1] < 20.0 and 12.0 < errs[1] / errs[2] < 20.0
