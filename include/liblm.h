@@ -282,6 +282,22 @@ lm_status lm_lbfgs_match(const lm_params *params, const lm_lbfgs_opts *opts, int
 lm_status lm_velocity(const lm_params *params, int64_t n, const void *q, const void *p,
                       int64_t m, const void *x, void *u, void *stream);
 
+/* Flow of arbitrary points along the geodesic (equation "u"; section "The prediction ability
+ * of Algorithm 1"): shoots the particles (q0, p0) over [0, t1] with `steps` classical RK4 steps,
+ * exactly as lm_shoot, and carries m passive points x along the velocity field of the moving
+ * particles, dx_a/dt = u(x_a) = sum_j G(|x_a - q_j|) p_j, advanced by the same RK4 stages
+ * (every stage evaluates u at the stage's points from the stage's particles).  The points do
+ * not act on the particles; the tau term of the inexact system moves only the particles.
+ * Warps grids or contours by the diffeomorphism the momenta generate, and continues a match
+ * beyond its target (t1 > 1).  cutoff > 0 skips tiles of points farther than the radius from
+ * a tile of particles (the bound of lm_params.cutoff applies to the velocity sums).
+ * q0, p0: (dim, n); x0, x1: (dim, m), element type by params->dtype.  x1 receives x(t1) and may
+ * be x0 itself; q1/p1 (nullable) receive q(t1), p(t1) and may be q0/p0 themselves.  x0/x1 must
+ * not overlap the particle buffers.  Asynchronous. */
+lm_status lm_flow_points(const lm_params *params, int64_t n, const void *q0, const void *p0, int64_t m,
+                         const void *x0, double t1, int32_t steps, void *q1, void *p1, void *x1,
+                         void *stream);
+
 /* ---------------------------------------------------------------------------------------
  * Batches of independent problems.  B problems of uneven size are concatenated in one
  * component-major array (dim, ntot), ntot = sum of the sizes: problem b owns columns

@@ -23,7 +23,7 @@ SOLVE_AUTO, SOLVE_CG, SOLVE_DENSE = 0, 1, 2
 
 # every symbol include/liblm.h declares
 EXPORTS = ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
-           "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
+           "lm_feedback_step", "lm_velocity", "lm_flow_points", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
            "lm_lbfgs_match", "lm_batch_default_tuning", "lm_batch_autotune", "lm_rhs_batched",
            "lm_shoot_batched", "lm_feedback_match_batched", "lm_pair_plan", "lm_last_error", "lm_version"]
 BATCH_BUCKETS = 4
@@ -118,6 +118,7 @@ def load():
         L.lm_feedback_step.argtypes = [PP, ctypes.POINTER(lm_match_opts), i64, P, P, P, P,
                                        ctypes.POINTER(lm_step_info), P]
         L.lm_velocity.argtypes = [PP, i64, P, P, i64, P, P, P]
+        L.lm_flow_points.argtypes = [PP, i64, P, P, i64, P, d, i32, P, P, P, P]
         L.lm_rhs_vjp.argtypes = [PP, i64, P, P, P, P, P, P, P]
         L.lm_shoot_adjoint.argtypes = [PP, i64, P, P, d, i32, i32, P, P, P, P, P, P, P]
         L.lm_energy_grad.argtypes = [PP, i64, P, P, P, d, d, i32, i32, ctypes.POINTER(d), P, P, P]
@@ -131,7 +132,7 @@ def load():
                                                 ctypes.POINTER(lm_match_info), P, PT, P]
         L.lm_pair_plan.argtypes = [PP, i64, ctypes.POINTER(lm_plan_info)]
         for name in ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
-                     "lm_feedback_step", "lm_velocity", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
+                     "lm_feedback_step", "lm_velocity", "lm_flow_points", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
                      "lm_lbfgs_match", "lm_batch_default_tuning", "lm_batch_autotune", "lm_rhs_batched",
                      "lm_shoot_batched", "lm_feedback_match_batched", "lm_pair_plan"]:
             getattr(L, name).restype = ctypes.c_int
@@ -288,6 +289,20 @@ def lm_velocity(params: lm_params, q, p, x, u, stream=None):
         _check_tensor(t, params.dim, m, params.dtype, nm)
     return _check(load().lm_velocity(ctypes.byref(params), n, _ptr(q), _ptr(p), m, _ptr(x), _ptr(u),
                                      _stream(stream)))
+
+
+def lm_flow_points(params: lm_params, q0, p0, x0, t1: float, steps: int, x1, q1=None, p1=None, stream=None):
+    """Shoots (q0, p0) over [0, t1] and carries the points x0 (dim, m) along the velocity
+    field; x(t1) to x1, and q(t1), p(t1) to q1, p1 when given."""
+    dim, n = q0.shape
+    m = x0.shape[1]
+    for t, nm in [(q0, "q0"), (p0, "p0"), (q1, "q1"), (p1, "p1")]:
+        if t is not None:
+            _check_tensor(t, params.dim, n, params.dtype, nm)
+    for t, nm in [(x0, "x0"), (x1, "x1")]:
+        _check_tensor(t, params.dim, m, params.dtype, nm)
+    return _check(load().lm_flow_points(ctypes.byref(params), n, _ptr(q0), _ptr(p0), m, _ptr(x0), float(t1),
+                                        int(steps), _ptr(q1), _ptr(p1), _ptr(x1), _stream(stream)))
 
 
 def lm_rhs_vjp(params: lm_params, q, p, a, b, aq, ap, stream=None):

@@ -143,15 +143,30 @@ int64_t vjp_part_elems(const lm_params* prm, int64_t n)
     return 4 * (int64_t)prm->dim * n + m;
 }
 
+// Passive points carried along by a shoot (equation "u"): positions x (dim, m), advanced in
+// place, with stage buffers ax, bx and the RK4 running sum cx (dim*m T each).  box (cutoff
+// mode, tiles_of(m)*8 doubles) receives the tile boxes of every stage's points.
+template <class T>
+struct Points {
+    int64_t m = 0;
+    T* x = nullptr;
+    T *ax = nullptr, *bx = nullptr, *cx = nullptr;
+    double* box = nullptr;
+};
+
 // RK4 shoot of (q, p) in place over [0, t1] with `steps` steps.  a*, b*: stage buffers, c*:
 // the RK4 running sum (dim*n T each); part: the split workspace.  box (non-null in cutoff
-// mode, tiles_of(n)*8 doubles) receives the tile boxes of every stage input.
+// mode, tiles_of(n)*8 doubles) receives the tile boxes of every stage input.  pts
+// (nullable): points advected by the velocity field of every stage's particles; each stage
+// evaluates their velocities before the particles' own launch overwrites that stage's
+// inputs' successor.
 template <class T>
 lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, int32_t steps, T* aq, T* ap,
-                        T* bq, T* bp, T* cq, T* cp, double* part, hipStream_t st, double* box = nullptr)
+                        T* bq, T* bp, T* cq, T* cp, double* part, hipStream_t st, double* box = nullptr,
+                        const Points<T>* pts = nullptr)
 {
     const double dt = t1 / steps;
-    if (!box && n <= lm::kSmallMax) {
+    if (!box && !pts && n <= lm::kSmallMax) {
         // the whole shoot in one launch (one workgroup holds the problem)
         lm::SmallShootArgs<T> a{};
         a.q = q;
@@ -177,6 +192,19 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
         cut.box_s = cut.box_t = box;
         cut.rc2 = prm->cutoff * prm->cutoff;
     }
+    lm::EpiArgs<T> ex{};
+    Cut xcut;
+    if (pts) {
+        ex.dt = dt;
+        ex.tau = 0.0;
+        ex.base_q = pts->x;
+        ex.acc_q = pts->cx;
+        if (box) {
+            xcut.box_s = box;
+            xcut.box_t = pts->box;
+            xcut.rc2 = cut.rc2;
+        }
+    }
     for (int32_t s = 0; s < steps; ++s) {
         // stage 1: input y, output A ; stage 2: A -> B ; stage 3: B -> A ; stage 4: A -> y
         const T* in_q[4] = {q, aq, bq, aq};
@@ -189,6 +217,16 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
             e.out_q = out_q[k];
             e.out_p = out_p[k];
             if (box) LM_HIP(lm::launch_tile_boxes<T>(prm->dim, in_q[k], n, box, st));
+            if (pts) {
+                // the points' stage on the same buffer rotation: x -> A -> B -> A -> x
+                const T* in_x[4] = {pts->x, pts->ax, pts->bx, pts->ax};
+                T* out_x[4] = {pts->ax, pts->bx, pts->ax, pts->x};
+                ex.kind = lm::EPI_RK1 + k;
+                ex.out_q = out_x[k];
+                if (box) LM_HIP(lm::launch_tile_boxes<T>(prm->dim, in_x[k], pts->m, pts->box, st));
+                LM_TRY(pair_eval<T>(prm, false, in_q[k], in_p[k], n, in_x[k], (const T*)nullptr, pts->m, ex, part, st,
+                                    xcut));
+            }
             LM_TRY(pair_eval<T>(prm, true, in_q[k], in_p[k], n, in_q[k], in_p[k], n, e, part, st, cut));
         }
     }
@@ -256,6 +294,59 @@ lm_status shoot_t(const lm_params* prm, int64_t n, const T* q0, const T* p0, dou
     if (q1 != q0) LM_HIP(hipMemcpyAsync(q1, q0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
     if (p1 != p0) LM_HIP(hipMemcpyAsync(p1, p0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
     return shoot_inplace<T>(prm, n, q1, p1, t1, steps, aq, ap, bq, bp, cq, cp, part, st);
+}
+
+// Shoot of (q0, p0) over [0, t1] carrying the points x0 (dim, m) along: results to q1, p1 (each
+// nullable: then kept in workspace) and x1 (may alias x0).
+template <class T>
+lm_status flow_t(const lm_params* prm, int64_t n, const T* q0, const T* p0, int64_t m, const T* x0, double t1,
+                 int32_t steps, T* q1, T* p1, T* x1, hipStream_t st)
+{
+    const int64_t mq = (int64_t)prm->dim * n, mx = (int64_t)prm->dim * m;
+    Workspace ws(st);
+    T *aq, *ap, *bq, *bp, *cq, *cp, *sq, *sp;
+    double* part;
+    Points<T> pts;
+    pts.m = m;
+    pts.x = x1;
+    LM_TRY(ws.get(&aq, mq));
+    LM_TRY(ws.get(&ap, mq));
+    LM_TRY(ws.get(&bq, mq));
+    LM_TRY(ws.get(&bp, mq));
+    LM_TRY(ws.get(&cq, mq));
+    LM_TRY(ws.get(&cp, mq));
+    LM_TRY(ws.get(&pts.ax, mx));
+    LM_TRY(ws.get(&pts.bx, mx));
+    LM_TRY(ws.get(&pts.cx, mx));
+    const int64_t pe = std::max(part_elems(prm, n, n), part_elems(prm, m, n));
+    LM_TRY(ws.get(&part, pe));
+    const bool order = prm->cutoff > 0.0;
+    Ordering ord;
+    if (order) {
+        if (n > kMaxCutN || m > kMaxCutN) return fail(LM_EINVAL, "cutoff mode needs n, m < 2^31");
+        LM_TRY(ord.alloc(ws, n));
+        LM_TRY(ws.get(&pts.box, lm::tiles_of(m) * 8));
+    }
+    // the particles evolve in sq, sp: q1/p1 themselves unless they are absent or the cutoff
+    // mode keeps the particles in Morton order
+    if (order || !q1) LM_TRY(ws.get(&sq, mq)); else sq = q1;
+    if (order || !p1) LM_TRY(ws.get(&sp, mq)); else sp = p1;
+    if (x1 != x0) LM_HIP(hipMemcpyAsync(x1, x0, mx * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (order) {
+        LM_TRY(ord.compute<T>(prm->dim, q0, n, ws, st));
+        LM_HIP((lm::launch_permute<T, T>(sq, q0, ord.perm, n, prm->dim, false, st)));
+        LM_HIP((lm::launch_permute<T, T>(sp, p0, ord.perm, n, prm->dim, false, st)));
+    } else {
+        if (sq != q0) LM_HIP(hipMemcpyAsync(sq, q0, mq * sizeof(T), hipMemcpyDeviceToDevice, st));
+        if (sp != p0) LM_HIP(hipMemcpyAsync(sp, p0, mq * sizeof(T), hipMemcpyDeviceToDevice, st));
+    }
+    LM_TRY(shoot_inplace<T>(prm, n, sq, sp, t1, steps, aq, ap, bq, bp, cq, cp, part, st, order ? ord.box : nullptr,
+                            &pts));
+    if (order) {
+        if (q1) LM_HIP((lm::launch_permute<T, T>(q1, sq, ord.perm, n, prm->dim, true, st)));
+        if (p1) LM_HIP((lm::launch_permute<T, T>(p1, sp, ord.perm, n, prm->dim, true, st)));
+    }
+    return LM_OK;
 }
 
 // Hamiltonian in double: H = 1/2 sum_c p_c . (K p)_c.  q, p double.
@@ -1237,6 +1328,37 @@ lm_status lm_velocity(const lm_params* prm, int64_t n, const void* q, const void
     return velocity_t<float>(prm, n, (const float*)q, (const float*)p, m, (const float*)x, (float*)u, st);
 }
 
+
+lm_status lm_flow_points(const lm_params* prm, int64_t n, const void* q0, const void* p0, int64_t m, const void* x0,
+                         double t1, int32_t steps, void* q1, void* p1, void* x1, void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    LM_TRY(check_n(m, "m"));
+    if (!q0 || !p0 || !x0 || !x1) return fail(LM_EINVAL, "NULL buffer");
+    if (steps < 1) return fail(LM_EINVAL, "steps must be >= 1 (got %d)", steps);
+    if (!is_finite(t1)) return fail(LM_EINVAL, "t1 must be finite");
+    const size_t es = prm->dtype == LM_F64 ? sizeof(double) : sizeof(float);
+    const size_t bq = (size_t)prm->dim * (size_t)n * es, bx = (size_t)prm->dim * (size_t)m * es;
+    // the points must not share memory with the particles' buffers
+    auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
+        const char *x = (const char*)a, *y = (const char*)b;
+        return a && b && x < y + nb && y < x + na;
+    };
+    const void* parts[4] = {q0, p0, q1, p1};
+    for (const void* b : parts)
+        if (overlap(x1, bx, b, bq) || overlap(x0, bx, b, bq))
+            return fail(LM_EINVAL, "x0/x1 must not overlap the particle buffers");
+    if ((q1 && q1 != q0 && overlap(q1, bq, q0, bq)) || (p1 && p1 != p0 && overlap(p1, bq, p0, bq)) ||
+        (q1 && p1 && overlap(q1, bq, p1, bq)))
+        return fail(LM_EINVAL, "q1/p1 must be q0/p0 themselves or disjoint buffers");
+    hipStream_t st = (hipStream_t)stream;
+    if (prm->dtype == LM_F64)
+        return flow_t<double>(prm, n, (const double*)q0, (const double*)p0, m, (const double*)x0, t1, steps,
+                              (double*)q1, (double*)p1, (double*)x1, st);
+    return flow_t<float>(prm, n, (const float*)q0, (const float*)p0, m, (const float*)x0, t1, steps, (float*)q1,
+                         (float*)p1, (float*)x1, st);
+}
 
 lm_status lm_rhs_vjp(const lm_params* prm, int64_t n, const double* q, const double* p, const double* a,
                      const double* b, double* aq, double* ap, void* stream)

@@ -147,15 +147,17 @@ __device__ __forceinline__ void epilogue(const EpiArgs<T>& e, int64_t n, int64_t
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const int64_t k = c * n + i;
-            double aq = wgt * kq[c], ap = wgt * kp[c];
-            if (e.kind != EPI_RK1) {
-                aq += (double)e.acc_q[k];
-                ap += (double)e.acc_p[k];
-            }
+            double aq = wgt * kq[c];
+            if (e.kind != EPI_RK1) aq += (double)e.acc_q[k];
             e.acc_q[k] = (T)aq;
-            e.acc_p[k] = (T)ap;
             e.out_q[k] = (T)((double)e.base_q[k] + a * kq[c]);
-            e.out_p[k] = (T)((double)e.base_p[k] + a * kp[c]);
+            if constexpr (FORCE) {
+                // (without forces the targets are passive points: positions only)
+                double ap = wgt * kp[c];
+                if (e.kind != EPI_RK1) ap += (double)e.acc_p[k];
+                e.acc_p[k] = (T)ap;
+                e.out_p[k] = (T)((double)e.base_p[k] + a * kp[c]);
+            }
         }
         break;
     }
@@ -166,9 +168,11 @@ __device__ __forceinline__ void epilogue(const EpiArgs<T>& e, int64_t n, int64_t
         for (int c = 0; c < DIM; ++c) {
             const int64_t k = c * n + i;
             const double sq = (double)e.acc_q[k] + kq[c];
-            const double sp = (double)e.acc_p[k] + kp[c];
             e.out_q[k] = (T)((double)e.base_q[k] + h6 * sq);
-            e.out_p[k] = (T)((double)e.base_p[k] + h6 * sp);
+            if constexpr (FORCE) {
+                const double sp = (double)e.acc_p[k] + kp[c];
+                e.out_p[k] = (T)((double)e.base_p[k] + h6 * sp);
+            }
         }
         break;
     }

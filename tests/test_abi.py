@@ -50,6 +50,14 @@ def test_binding_lists_every_declared_symbol():
     assert sorted(_lib.EXPORTS) == header_functions()
 
 
+def test_package_exposes_every_binding():
+    import paper_1510_03816_amd as pkg
+    from paper_1510_03816_amd import _lib
+    for name in _lib.EXPORTS:
+        if name != "lm_last_error":            # exposed as last_error()
+            assert callable(getattr(pkg, name)), name
+
+
 def test_struct_layouts_match_header(tmp_path):
     """Compile a C probe against the header and compare every field offset with ctypes."""
     from paper_1510_03816_amd import _lib
@@ -105,6 +113,25 @@ def test_invalid_sizes_and_pointers_rejected(lib):
                              ctypes.c_double, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.lm_shoot(ctypes.byref(p), 5, a, b, 1.0, 0, a, b, None) == -1          # steps < 1
     assert lib.lm_shoot(ctypes.byref(p), 5, a, b, float("inf"), 10, a, b, None) == -1
+
+
+def test_flow_points_arguments_rejected(lib):
+    """Points overlapping the particle buffers, bad sizes and step counts are refused before
+    anything is enqueued (fake device addresses: nothing is dereferenced)."""
+    P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.lm_flow_points.argtypes = [P, i64, P, P, i64, P, d, i32, P, P, P, P]
+    p = _params(dim=2)
+    q0, p0, x0 = 0x10000, 0x20000, 0x30000
+    call = lambda n, m, x0_, steps, q1, p1, x1, t1=1.0: lib.lm_flow_points(
+        ctypes.byref(p), n, q0, p0, m, x0_, t1, steps, q1, p1, x1, None)
+    assert call(10, 5, x0, 0, None, None, x0) == -1                  # steps < 1
+    assert call(10, 0, x0, 5, None, None, x0) == -1                  # m < 1
+    assert call(0, 5, x0, 5, None, None, x0) == -1                   # n < 1
+    assert call(10, 5, x0, 5, None, None, None) == -1                # x1 missing
+    assert call(10, 5, x0, 5, None, None, q0 + 8) == -1              # x1 inside q0
+    assert call(10, 5, p0 + 80, 5, None, None, x0) == -1             # x0 inside p0
+    assert call(10, 5, x0, 5, q0 + 8, None, x0) == -1                # q1 overlapping q0, not equal
+    assert call(10, 5, x0, 5, None, None, x0, t1=float("nan")) == -1
 
 
 def test_package_import_fails_loudly_without_library(tmp_path, monkeypatch):
