@@ -298,6 +298,22 @@ lm_status lm_flow_points(const lm_params *params, int64_t n, const void *q0, con
                          const void *x0, double t1, int32_t steps, void *q1, void *p1, void *x1,
                          void *stream);
 
+/* lm_shoot for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same shoot, with the same
+ * kernels and results as lm_shoot, but its scratch memory (stage buffers, RK4 running sums,
+ * the pair kernels' partial sums) comes from one fixed array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends; the call allocates and frees
+ * nothing.  Every call on one GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (other threads, other streams) race and corrupt each other's results, so the caller
+ * must order them.  cutoff must be 0 (LM_EUNSUPPORTED otherwise).  A size whose scratch
+ * exceeds the array -- 6 dim n element-size bytes plus the partial sums of the pair plan
+ * (FP64 3-D: n = 16384 fits, n = 24576 does not) -- returns LM_ENOMEM with the bytes it
+ * would need.
+ * The stream must belong to the current device (LM_EINVAL otherwise).  Arguments and
+ * aliasing as lm_shoot.  Asynchronous. */
+lm_status lm_shoot_noalloc(const lm_params *params, int64_t n, const void *q0, const void *p0,
+                           double t1, int32_t steps, void *q1, void *p1, void *stream);
+
 /* ---------------------------------------------------------------------------------------
  * Batches of independent problems.  B problems of uneven size are concatenated in one
  * component-major array (dim, ntot), ntot = sum of the sizes: problem b owns columns

@@ -22,7 +22,7 @@ F64, F32 = 0, 1
 SOLVE_AUTO, SOLVE_CG, SOLVE_DENSE = 0, 1, 2
 
 # every symbol include/liblm.h declares
-EXPORTS = ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
+EXPORTS = ["lm_rhs", "lm_shoot", "lm_shoot_noalloc", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
            "lm_feedback_step", "lm_velocity", "lm_flow_points", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
            "lm_lbfgs_match", "lm_batch_default_tuning", "lm_batch_autotune", "lm_rhs_batched",
            "lm_shoot_batched", "lm_feedback_match_batched", "lm_pair_plan", "lm_last_error", "lm_version"]
@@ -111,6 +111,7 @@ def load():
         PP = ctypes.POINTER(lm_params)
         L.lm_rhs.argtypes = [PP, i64, P, P, P, P, P]
         L.lm_shoot.argtypes = [PP, i64, P, P, d, i32, P, P, P]
+        L.lm_shoot_noalloc.argtypes = [PP, i64, P, P, d, i32, P, P, P]
         L.lm_hamiltonian.argtypes = [PP, i64, P, P, ctypes.POINTER(d), P]
         L.lm_ksolve.argtypes = [PP, i64, P, P, P, d, i32, i32, ctypes.POINTER(i32), P]
         L.lm_feedback_match.argtypes = [PP, ctypes.POINTER(lm_match_opts), i64, P, P, P, P,
@@ -131,7 +132,7 @@ def load():
         L.lm_feedback_match_batched.argtypes = [PP, ctypes.POINTER(lm_match_opts), i32, P, P, P, P, P,
                                                 ctypes.POINTER(lm_match_info), P, PT, P]
         L.lm_pair_plan.argtypes = [PP, i64, ctypes.POINTER(lm_plan_info)]
-        for name in ["lm_rhs", "lm_shoot", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
+        for name in ["lm_rhs", "lm_shoot", "lm_shoot_noalloc", "lm_hamiltonian", "lm_ksolve", "lm_feedback_match",
                      "lm_feedback_step", "lm_velocity", "lm_flow_points", "lm_rhs_vjp", "lm_shoot_adjoint", "lm_energy_grad",
                      "lm_lbfgs_match", "lm_batch_default_tuning", "lm_batch_autotune", "lm_rhs_batched",
                      "lm_shoot_batched", "lm_feedback_match_batched", "lm_pair_plan"]:
@@ -206,6 +207,15 @@ def lm_shoot(params: lm_params, q0, p0, t1: float, steps: int, q1, p1, stream=No
         _check_tensor(t, params.dim, n, params.dtype, nm)
     return _check(load().lm_shoot(ctypes.byref(params), n, _ptr(q0), _ptr(p0), float(t1), int(steps),
                                   _ptr(q1), _ptr(p1), _stream(stream)))
+
+
+def lm_shoot_noalloc(params: lm_params, q0, p0, t1: float, steps: int, q1, p1, stream=None):
+    """lm_shoot with the library's fixed scratch array instead of allocated workspace."""
+    dim, n = q0.shape
+    for t, nm in [(q0, "q0"), (p0, "p0"), (q1, "q1"), (p1, "p1")]:
+        _check_tensor(t, params.dim, n, params.dtype, nm)
+    return _check(load().lm_shoot_noalloc(ctypes.byref(params), n, _ptr(q0), _ptr(p0), float(t1), int(steps),
+                                          _ptr(q1), _ptr(p1), _stream(stream)))
 
 
 def lm_hamiltonian(params: lm_params, q, p, stream=None) -> float:

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1099,6 +1100,62 @@ lm_status lbfgs_impl(const lm_params* prm, const lm_lbfgs_opts* o, int64_t n, co
     return result;
 }
 
+// ---------------------------------------------------------------------------------------
+// lm_shoot_noalloc: lm_shoot with its scratch memory (stage buffers, RK4 running sums and
+// the pair kernels' partial sums) carved out of one fixed device array instead of the
+// stream-ordered allocator, for callers that cannot allocate.
+// ---------------------------------------------------------------------------------------
+
+// The fixed scratch array: one copy per GPU, resident from the library's first use on that
+// GPU until the process ends.  Host code never uses this name as an address (on the host it
+// is a stand-in, not device memory); scratch_base() gives each device's own copy's address.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_base[kMaxDevices] = {};
+
+// Device address of device `dev`'s copy of the scratch array; `dev` must be the current
+// device.  Looked up once per device (hipGetSymbolAddress) and kept.
+lm_status scratch_base(int dev, unsigned char** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(LM_EINVAL, "device %d is beyond the %d tracked", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_base[dev]) {
+        void* ptr = nullptr;
+        LM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(LM_EHIP, "hipGetSymbolAddress gave no address for the scratch array");
+        g_scratch_base[dev] = (unsigned char*)ptr;
+    }
+    *out = g_scratch_base[dev];
+    return LM_OK;
+}
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Scratch bytes of a shoot of n points: six state arrays (two stage buffers and the RK4
+// running sum, for q and p) and the partial sums of any pair kernel the plan may pick.
+size_t noalloc_bytes(const lm_params* prm, int64_t n)
+{
+    const size_t es = prm->dtype == LM_F64 ? sizeof(double) : sizeof(float);
+    return 6 * align256((size_t)prm->dim * (size_t)n * es) + align256((size_t)part_elems(prm, n, n) * sizeof(double));
+}
+
+template <class T>
+lm_status shoot_noalloc_t(const lm_params* prm, int64_t n, const T* q0, const T* p0, double t1, int32_t steps,
+                          T* q1, T* p1, unsigned char* base, hipStream_t st)
+{
+    const size_t sb = align256((size_t)prm->dim * (size_t)n * sizeof(T));
+    T* buf[6];
+    for (int k = 0; k < 6; ++k) buf[k] = (T*)(base + k * sb);
+    double* part = (double*)(base + 6 * sb);
+    const int64_t m = (int64_t)prm->dim * n;
+    if (q1 != q0) LM_HIP(hipMemcpyAsync(q1, q0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (p1 != p0) LM_HIP(hipMemcpyAsync(p1, p0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return shoot_inplace<T>(prm, n, q1, p1, t1, steps, buf[0], buf[1], buf[2], buf[3], buf[4], buf[5], part, st);
+}
+
 }  // namespace
 
 // =========================================================================================
@@ -1446,6 +1503,37 @@ lm_status lm_lbfgs_match(const lm_params* prm, const lm_lbfgs_opts* o, int64_t n
     EnergyWork EW;
     LM_TRY(EW.alloc(ws, prm, n, o->steps, o->ckpt_every));
     return lbfgs_impl(prm, o, n, X, Y, p0, info, EW, ws, st);
+}
+
+lm_status lm_shoot_noalloc(const lm_params* prm, int64_t n, const void* q0, const void* p0, double t1,
+                           int32_t steps, void* q1, void* p1, void* stream)
+{
+    LM_TRY(check_params(prm));
+    LM_TRY(check_n(n));
+    if (!q0 || !p0 || !q1 || !p1) return fail(LM_EINVAL, "NULL buffer");
+    if (steps < 1) return fail(LM_EINVAL, "steps must be >= 1 (got %d)", steps);
+    if (!is_finite(t1)) return fail(LM_EINVAL, "t1 must be finite");
+    if (q1 == p1) return fail(LM_EINVAL, "q1 and p1 must be distinct buffers");
+    if (prm->cutoff > 0.0) return fail(LM_EUNSUPPORTED, "lm_shoot_noalloc sums every pair: cutoff must be 0");
+    const size_t need = noalloc_bytes(prm, n);
+    if (need > kScratchBytes)
+        return fail(LM_ENOMEM, "lm_shoot_noalloc: n = %lld needs %zu bytes of scratch, beyond its fixed %zu bytes",
+                    (long long)n, need, kScratchBytes);
+    hipStream_t st = (hipStream_t)stream;
+    int cur = -1;
+    LM_HIP(hipGetDevice(&cur));
+    if (st) {
+        int sdev = -1;
+        LM_HIP(hipStreamGetDevice(st, &sdev));
+        if (sdev != cur) return fail(LM_EINVAL, "the stream belongs to device %d, the current device is %d", sdev, cur);
+    }
+    unsigned char* base = nullptr;
+    LM_TRY(scratch_base(cur, &base));
+    if (prm->dtype == LM_F64)
+        return shoot_noalloc_t<double>(prm, n, (const double*)q0, (const double*)p0, t1, steps, (double*)q1,
+                                       (double*)p1, base, st);
+    return shoot_noalloc_t<float>(prm, n, (const float*)q0, (const float*)p0, t1, steps, (float*)q1, (float*)p1,
+                                  base, st);
 }
 
 }  // extern "C"
