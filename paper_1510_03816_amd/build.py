@@ -29,20 +29,41 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into liblm.so (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + sources()
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     # the host pass does not know the packed-fp32 feature and says so; drop that noise
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
-        sys.stderr.write(out + "\n")
+        sys.stderr.write(" ".join(cmd) + "\n" + out + "\n")
         raise RuntimeError("hipcc failed (exit %d)" % res.returncode)
-    if out.strip() and verbose:
-        print(out)
+    return out
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every HIP source into liblm.so (always recompiles): one object per source,
+    compiled in parallel, then one link."""
+    import concurrent.futures
+    import tempfile
+    tmp = LIB + ".tmp%d" % os.getpid()
+    inc = ["-I", os.path.join(ROOT, "include")]
+    jobs = jobs or min(8, os.cpu_count() or 1)
+    with tempfile.TemporaryDirectory(prefix="liblm_build_") as td:
+        objs = [os.path.join(td, os.path.basename(s)[:-4] + ".o") for s in sources()]
+        cmds = [[HIPCC] + [f for f in FLAGS if f != "-shared"] + inc + ["-c", "-o", o, s]
+                for s, o in zip(sources(), objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+            outs = list(ex.map(_run, cmds))
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        outs.append(_run(link))
+    if verbose:
+        for out in outs:
+            if out.strip():
+                print(out)
     os.replace(tmp, LIB)
     return LIB
 

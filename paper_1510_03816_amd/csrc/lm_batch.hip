@@ -274,8 +274,10 @@ lm_status batch_steps(const lm_params* prm, const BatchPlan& pl, T* q, T* p, dou
 }
 
 // Side streams that start after the work already on a stream and that the stream then waits
-// for (join).  Destroyed after st has drained.
-constexpr int kFactorStreams = 8;
+// for (join).  Destroyed after st has drained.  Four: HIP maps a process's streams onto four
+// hardware queues by default, and streams beyond those share queues instead of adding
+// concurrency.
+constexpr int kFactorStreams = 4;
 
 struct SideStreams {
     std::vector<hipStream_t> s;
