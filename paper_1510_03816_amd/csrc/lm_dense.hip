@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void lm_kbuild_kernel(const double* __restrict
             s = __builtin_fma(d, d, s);
         }
         const double a = (KER == LM_KERNEL_CONON) ? __builtin_sqrt(s) * kq : s * kq;
-        row[j] = exp2_nonpos(a) + (j == i ? tau : 0.0);
+        row[j] = exp2_nonpos_fine(a) + (j == i ? tau : 0.0);
     }
 }
 

@@ -102,3 +102,33 @@ def test_environment_overrides(monkeypatch):
 def test_invalid_arguments():
     with pytest.raises(lm.LmError):
         plan(0)
+
+
+def test_device_exponential_constants_are_the_generators():
+    """The hex constants of the device exponentials in lm_math.h (degree 9 for the pair sums,
+    degree 10 for the dense kernel matrix) are exactly what gen_exp_coeffs.py derives, and the
+    polynomials they form stay within 4e-14 and 6e-16 of 2^f on the reduced interval
+    (evaluated in high precision from the rounded coefficients)."""
+    import re
+    import subprocess
+    import sys
+    import mpmath as mp
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1510_03816_amd", "csrc")
+    src = open(os.path.join(csrc, "lm_math.h")).read()
+    mp.mp.dps = 40
+    for fn, deg, bound in [("exp2_nonpos(", 9, 4e-14), ("exp2_nonpos_fine(", 10, 6e-16)]:
+        out = subprocess.run([sys.executable, os.path.join(csrc, "gen_exp_coeffs.py"), str(deg)],
+                             stdout=subprocess.PIPE, text=True, check=True).stdout
+        want = [float.fromhex(v) for v in re.findall(r"^C\d+\s*=\s*(\S+)$", out, flags=re.M)]
+        start = src.index("double " + fn)
+        body = src[src.index("double p = ", start):src.index("return __builtin_ldexp", start)]
+        got = [float.fromhex(v) if v.startswith("0x") else float(v)
+               for v in re.findall(r"(0x1\.[0-9a-f]+p-?\d+|1\.0)\)?;", body)]
+        assert got == want and len(got) == deg + 1, fn
+        worst = 0
+        for t in mp.linspace(-0.5, 0.5, 801):
+            pv = mp.mpf(0)
+            for c in got:
+                pv = pv * t + mp.mpf(c)
+            worst = max(worst, abs(pv / mp.power(2, t) - 1))
+        assert worst < bound, fn
