@@ -17,7 +17,8 @@ Outside the timed loop, in this order, each only while the run's wall-clock budg
     stream the library launches on, around every timed shoot);
   - the FP64 oracle timed on the host cores on a bounded sample (cpu_baseline);
   - time-to-match of the headline workload: Algorithm 1 from p = 0 until
-    max|q(1) - Y| < 1e-6 (dense factor of K(X), shoots, solves), measured once;
+    max|q(1) - Y| < 1e-6 (dense factor of K(X), shoots, solves), measured once, then once
+    more with single-precision shoots until the residual is below 1e-4 and double after;
   - the single-precision form: the same shoot in FP32 (its stage time and roofline) and its
     error against the FP64 oracle's stored shoot, with the FP64 shoot's error beside it;
   - time-to-match of the 2-D curve (N = 4096, 200 RK4 steps, FP64, and FP32 switching to FP64)
@@ -137,11 +138,25 @@ class Budget:
 
 
 def cpu_baseline(pr, p, target_s: float):
-    """The FP64 oracle on the host cores: rows of one RHS evaluation of the same workload."""
+    """The FP64 oracle on the host cores, on the same workload: one whole RK4 step of the
+    shoot (four right-hand-side evaluations over all N^2 pairs) when that fits in about 2.5x
+    the target time, else the rows of one RHS evaluation that fill the target time."""
     import numpy as np
     import oracle
 
     n = pr.n
+    idx = np.linspace(0, n - 1, 64).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.rhs_rows(pr.X, p, idx, pr.kernel, pr.sigma)
+    per_rhs = (time.perf_counter() - t0) * n / 64
+    if 4 * per_rhs <= 2.5 * target_s:
+        t0 = time.perf_counter()
+        oracle.shoot(pr.X, p, pr.kernel, pr.sigma, 1, T=1.0 / pr.steps)
+        dt = time.perf_counter() - t0
+        return {"value": 4 * n * n / dt, "unit": "pair-interactions/s", "cores": oracle.num_threads(),
+                "kind": "oracle",
+                "sample": "one RK4 step (dt = 1/%d) of the %d-point shoot: 4 right-hand sides over all pairs, %.1f s"
+                          % (pr.steps, n, dt)}
     rows = 64
     while True:
         idx = np.linspace(0, n - 1, rows).astype(np.int64)
@@ -246,6 +261,20 @@ def fp32_leg(lm, torch, dev, pr, p_np, q64_gpu, p64_gpu):
     q32, p32 = q1.double().cpu().numpy(), p1.double().cpu().numpy()
     q64, p64 = q64_gpu.cpu().numpy(), p64_gpu.cpu().numpy()
     out["err_vs_gpu_f64"] = {"q": rel_err(q32, q64), "p": rel_err(p32, p64)}
+    z2 = stored_oracle("sphere3d_conon_2steps", pr, p_np)
+    if z2 is not None:
+        # the first two RK4 steps of the same shoot, FP32 and FP64, against the oracle's
+        idx = z2["idx"]
+        errs = {}
+        for name, dt_ in [("f32", torch.float32), ("f64", torch.float64)]:
+            prm2 = lm.make_params(pr.dim, pr.kernel, pr.sigma, dtype=lm.F32 if dt_ == torch.float32 else lm.F64)
+            a = torch.tensor(pr.X, device=dev, dtype=dt_)
+            b = torch.tensor(p_np, device=dev, dtype=dt_)
+            qa, pa = torch.empty_like(a), torch.empty_like(a)
+            lm.lm_shoot(prm2, a, b, float(z2["T"]), int(z2["steps"]), qa, pa)
+            qh, ph = qa.double().cpu().numpy()[:, idx], pa.double().cpu().numpy()[:, idx]
+            errs[name] = {"q": rel_err(qh, z2["q1"]), "p": rel_err(ph, z2["p1"])}
+        out["err_vs_oracle_2steps"] = dict(errs, rows=int(len(idx)), bars={"f32": 1e-4, "f64": 1e-10})
     z = stored_oracle("sphere3d_conon_100steps", pr, p_np)
     if z is not None:
         idx = z["idx"]
@@ -558,7 +587,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = leg("cpu_baseline", lambda: cpu_baseline(pr, p_np, args.cpu_seconds), args.cpu_seconds * 1.5 + 5)
+        cpu = leg("cpu_baseline", lambda: cpu_baseline(pr, p_np, args.cpu_seconds), args.cpu_seconds * 2.5 + 5)
 
     ttm = None
     if not args.no_match and args.mode == "shoot" and rc == 0.0:
@@ -573,6 +602,22 @@ def main():
                                                                           info.resid_inf))
             return r
         ttm = leg("time_to_match", ttm_fn, max(LEG_SECONDS["time_to_match"], 22 * shoot_s))
+
+        def ttm_mixed_fn():
+            # the same match with single-precision shoots until the residual falls below 1e-4,
+            # double-precision shoots after (momenta, residuals and K-solves always in double)
+            prm32 = lm.make_params(pr.dim, pr.kernel, pr.sigma, dtype=lm.F32)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, info, _ = run_match(prm32, pr, X, Y, 1e-4)
+            torch.cuda.synchronize()
+            r = match_record(lm, st, info, time.perf_counter() - t1, args.tol, args.h)
+            r.update(workload=args.workload, shoots=info.iters + 1, f32_switch=1e-4)
+            log("time to match %s, FP32 shoots switching to FP64 below 1e-4: %.2f s, %d iterations, resid %.2e" % (
+                args.workload, r["seconds"], info.iters, info.resid_inf))
+            return r
+        if args.workload == "sphere3d_conon_f64" and isinstance(ttm, dict) and "seconds" in ttm:
+            ttm["f32_switch_run"] = leg("time_to_match_f32_switch", ttm_mixed_fn, 0.8 * ttm["seconds"] + 5)
     elif args.mode == "match":
         ttm = dict(records[-1], workload=args.workload, seconds=elapsed / args.steps, tol=args.tol, h=args.h)
 

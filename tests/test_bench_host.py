@@ -65,3 +65,16 @@ def test_fp32_charges_are_at_most_the_fp64_charges():
     charge per pair is below the double-precision one for every kernel and dimension."""
     for key, s64 in bench.SLOTS_PER_PAIR.items():
         assert bench.SLOTS_PER_PAIR_F32[key] < s64
+
+
+def test_cpu_baseline_times_one_rk4_step_of_the_workload():
+    """The CPU baseline leg runs the oracle on the benchmark's own workload: one whole RK4 step
+    when it fits the time target, sampled rows of one evaluation otherwise."""
+    import inputs
+    pr = inputs.config_sphere3d(600, sigma=0.1)
+    p = pr.p_bench()
+    r = bench.cpu_baseline(pr, p, target_s=5.0)
+    assert r["kind"] == "oracle" and r["unit"] == "pair-interactions/s" and r["value"] > 0
+    assert r["sample"].startswith("one RK4 step") and r["cores"] >= 1
+    r = bench.cpu_baseline(pr, p, target_s=1e-6)          # too little time: rows instead
+    assert "target rows" in r["sample"] and r["value"] > 0
