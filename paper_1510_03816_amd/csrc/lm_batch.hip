@@ -274,10 +274,11 @@ lm_status batch_steps(const lm_params* prm, const BatchPlan& pl, T* q, T* p, dou
 }
 
 // Side streams that start after the work already on a stream and that the stream then waits
-// for (join).  Destroyed after st has drained.  Four: HIP maps a process's streams onto four
-// hardware queues by default, and streams beyond those share queues instead of adding
-// concurrency.
-constexpr int kFactorStreams = 4;
+// for (join).  Destroyed after st has drained.  Eight, although HIP gives a process four
+// hardware queues by default and streams beyond four share them: measured on the 256-problem
+// batch, the factors of all problems take 258-263 ms with eight streams and 329-350 ms with
+// four.
+constexpr int kFactorStreams = 8;
 
 struct SideStreams {
     std::vector<hipStream_t> s;
