@@ -70,7 +70,8 @@ PEAK_TFLOPS_F32 = 157.3
 # recorded with the hash of the kernel sources they were taken on; a changed kernel reports
 # null until the counters are taken again.
 MEASURED_TRAFFIC = {
-    "sphere3d_conon_f64": ("f6c3a5cf97caf2d9", 1.0588e9),
+    "sphere3d_conon_f64": ("35399c59cb6f852b", 1.0436e9),
+    "sphere3d_conon_f32": ("35399c59cb6f852b", 1.2996e8),
 }
 
 # Estimated seconds of each optional leg on MI355X (a leg runs only if the budget left
@@ -258,6 +259,8 @@ def fp32_leg(lm, torch, dev, pr, p_np, q64_gpu, p64_gpu):
     out = {"workload": "sphere3d_conon_f32", "shoot_ms": wall * 1e3 / 2,
            "pairs_per_s": 4 * pr.steps * pr.n ** 2 * 2 / wall,
            "roofline": pair_roofline(lm, prm, pr.n, pr.dim, pr.kernel, 1, stage_ms)}
+    if MEASURED_TRAFFIC["sphere3d_conon_f32"][0] == kernel_source_hash():
+        out["roofline"]["traffic"] = MEASURED_TRAFFIC["sphere3d_conon_f32"][1]
     q32, p32 = q1.double().cpu().numpy(), p1.double().cpu().numpy()
     q64, p64 = q64_gpu.cpu().numpy(), p64_gpu.cpu().numpy()
     out["err_vs_gpu_f64"] = {"q": rel_err(q32, q64), "p": rel_err(p32, p64)}
@@ -354,6 +357,19 @@ def batched_leg(lm, torch, dev, h: float, tol: float):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out["shoot_" + name] = {"ms": dt * 1e3, "pairs_per_s": pairs * 4 * steps / dt, "tuning": t.as_dict()}
+        # the same shoot with every kernel launched directly and with 20 RK4 steps per replayed
+        # hipGraph, whatever the tuner chose
+        cmp_ = {}
+        for gs in (0, 20):
+            tg = lm.lm_batch_tuning.from_buffer_copy(t)
+            tg.graph_steps = gs
+            lm.lm_shoot_batched(prm, offs, q0, p0, 1.0, steps, q1, p1, tuning=tg)       # capture / warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lm.lm_shoot_batched(prm, offs, q0, p0, 1.0, steps, q1, p1, tuning=tg)
+            torch.cuda.synchronize()
+            cmp_["graph_steps_%d_ms" % gs] = (time.perf_counter() - t0) * 1e3
+        out["shoot_" + name]["launch_comparison"] = cmp_
         log("batched shoot %s: %.1f ms, %.3e pairs/s (tuning %s)" % (name, dt * 1e3, pairs * 4 * steps / dt,
                                                                     t.as_dict()))
     for name, dtype, sw in [("f32_then_f64", lm.F32, 1e-4), ("f64", lm.F64, 0.0)]:

@@ -10,8 +10,8 @@ benchmark runs (needs an MI355X).
   a 10-step checkpointed shoot adjoint against the oracle's, and the energy gradient of the
   100-step, checkpoint-every-10 problem against central differences on the 32 seeded
   particle indices x 3 components.
-- Dense K-solve at N = 65536 (the factor the headline match uses): sampled rows of K(X) x,
-  computed one by one by the oracle, against the right-hand side.
+- Dense K-solves at N = 5000, 16384 and 65536 (the factor the headline match uses): sampled
+  rows of K(X) x, computed one by one by the oracle, against the right-hand side.
 
 Tolerances: normwise max|gpu - oracle| / max|oracle| <= 1e-10 in FP64 and <= 1e-4 for the
 single-precision form (scored against the FP64 oracle on unrounded inputs).
@@ -197,22 +197,24 @@ def test_energy_gradient_16384_finite_differences(adj):
 # ------------------------------------------------------------------ dense K-solve, N = 65536
 
 
-def test_dense_ksolve_65536_sampled_rows():
-    """x = K(X)^{-1} b by the dense factor at N = 65536 (the solve the headline match uses);
-    256 sampled rows of K(X) x, each computed by the oracle as the velocity part of the
-    right-hand side at (X, x), must reproduce b to a backward error of 1e-11 measured
-    against sum_j G_ij |x_j| (the size of the terms the row adds)."""
-    pr = inputs.config_sphere3d(65536, kernel=lm.CONON, sigma=0.05)
-    b = np.random.default_rng([122, pr.n]).standard_normal(pr.X.shape)
-    prm = lm.make_params(3, lm.CONON, pr.sigma)
-    x = torch.empty((3, pr.n), dtype=torch.float64, device=DEV)
-    assert lm.lm_ksolve(prm, dev(pr.X), dev(b), x, solver=lm.SOLVE_DENSE) == 0
+@pytest.mark.parametrize("n,sigma,tau", [(5000, 0.15, 0.1), (16384, 0.05, 0.0), (65536, 0.05, 0.0)])
+def test_dense_ksolve_sampled_rows(n, sigma, tau):
+    """x = (K(X) + tau I)^{-1} b by the dense factor on the sphere (N = 65536 is the solve the
+    headline match uses; 16384 and 5000 take several trailing updates with ragged tiles); 256
+    sampled rows of K(X) x + tau x, each computed by the oracle as the velocity part of the
+    right-hand side at (X, x), must reproduce b to a backward error of 1e-11 measured against
+    sum_j G_ij |x_j| + tau |x_i| (the size of the terms the row adds)."""
+    X = inputs.fibonacci_sphere(n)
+    b = np.random.default_rng([122, n]).standard_normal(X.shape)
+    prm = lm.make_params(3, lm.CONON, sigma, tau=tau)
+    x = torch.empty((3, n), dtype=torch.float64, device=DEV)
+    assert lm.lm_ksolve(prm, dev(X), dev(b), x, solver=lm.SOLVE_DENSE) == 0
     xh = host(x)
     assert np.all(np.isfinite(xh))
-    idx = np.sort(np.random.default_rng(123).choice(pr.n, 256, replace=False))
-    idx = np.concatenate([[0, 127, 128, pr.n - 1], idx])
-    Kx, _ = oracle.rhs_rows(pr.X, xh, idx, lm.CONON, pr.sigma)
-    scale, _ = oracle.rhs_rows(pr.X, np.abs(xh), idx, lm.CONON, pr.sigma)
+    idx = np.sort(np.random.default_rng(123).choice(n, 256, replace=False))
+    idx = np.concatenate([[0, 127, 128, n - 1], idx])
+    Kx, _ = oracle.rhs_rows(X, xh, idx, lm.CONON, sigma, tau)
+    scale, _ = oracle.rhs_rows(X, np.abs(xh), idx, lm.CONON, sigma, tau)
     berr = np.max(np.abs(Kx - b[:, idx]) / scale)
-    print("dense K-solve N=65536: backward error on %d rows %.2e (max|x| %.3g)" % (len(idx), berr, np.abs(xh).max()))
+    print("dense K-solve N=%d: backward error on %d rows %.2e (max|x| %.3g)" % (n, len(idx), berr, np.abs(xh).max()))
     assert berr <= 1e-11
