@@ -2,8 +2,9 @@
 benchmark runs (needs an MI355X).
 
 - 3-D sphere, N = 65536: the first two RK4 steps (dt = 1/100) of the 100-step shoot from the
-  throughput momenta, FP64 with both kernels and FP32 with the conical one, against the
-  oracle's stored shoots (tests/golden/make_oracle_shoots.py, sampled rows).
+  throughput momenta, FP64 with both kernels and FP32 with the conical one, and the whole
+  100-step conical shoot in FP64 and FP32, against the oracle's stored shoots
+  (tests/golden/make_oracle_shoots.py, sampled rows).
 - 2-D curve, N = 4096: the whole 200-step shoot, FP64 and FP32, against the oracle's stored
   shoot (every row).
 - Differentiation workload, N = 16384 (Gaussian sigma = 0.1): the right-hand side's VJP and
@@ -95,6 +96,23 @@ def test_sphere_65536_two_steps_match_stored_oracle(name, kernel, dtype):
     if dtype == lm.F64:
         # total momentum is a linear invariant, kept by RK4 to rounding
         assert np.max(np.abs(p1.sum(axis=1) - p0.sum(axis=1))) <= 1e-9 * np.abs(p0).sum(axis=1).max()
+
+
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+def test_sphere_65536_whole_shoot_matches_stored_oracle(dtype):
+    """The benchmark's step itself: the whole 100-step shoot of the N = 65536 sphere (conon
+    sigma = 0.05, throughput momenta) in the launch shape bench.py times, against the oracle's
+    stored shoot (1.5 h of host time) on 4096 sampled rows; the single-precision form is scored
+    against the same FP64 oracle."""
+    pr = inputs.config_sphere3d(65536, kernel=lm.CONON, sigma=0.05, steps=100)
+    p0 = pr.p_bench()
+    z = stored("sphere3d_conon_100steps", pr, p0)
+    assert int(z["steps"]) == 100 and float(z["T"]) == 1.0
+    q1, p1, plan = gpu_shoot(pr, p0, dtype, 1.0, 100)
+    idx = z["idx"]
+    eq, ep = rel_err(q1[:, idx], z["q1"]), rel_err(p1[:, idx], z["p1"])
+    print("N=65536 100-step shoot dtype=%d plan %s: rel err q %.2e p %.2e" % (dtype, plan, eq, ep))
+    assert eq <= TOL[dtype] and ep <= TOL[dtype]
 
 
 # ------------------------------------------------------------------ 2-D curve, N = 4096, 200 steps
