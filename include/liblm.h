@@ -139,8 +139,10 @@ lm_status lm_rhs(const lm_params *params, int64_t n, const void *q, const void *
  * precision, every pair, from 128 tiles of 64 points on); 0: the one-sided kernel, one
  * target per lane.  The environment variable LM_SYM = 0 or 1 overrides that size rule and
  * LM_SYM_WAVES = 1, 2, 4 or 8 fixes the symmetric kernel's workgroup width (for tuning and
- * tests; both are read at every launch).  small = 1: shoots of this size (at most 256 points,
- * no cutoff) run whole inside one workgroup instead.  LM_EINVAL on bad arguments. */
+ * tests; both are read at every launch).  small = 1: shoots of this size (at most 128 points,
+ * no cutoff) run whole inside one workgroup instead, of 4 or 8 waves by size (LM_SMALL = 0 or
+ * 1 overrides the size rule, 1 allowing up to 256 points, and LM_SMALL_WAVES = 4, 8 or 16 fixes
+ * the width, for tuning and tests).  LM_EINVAL on bad arguments. */
 typedef struct lm_plan_info {
     int32_t symmetric;
     int32_t waves;           /* wavefronts per workgroup of the pair-sum launch */

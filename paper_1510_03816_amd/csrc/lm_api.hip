@@ -167,7 +167,7 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
                         const Points<T>* pts = nullptr)
 {
     const double dt = t1 / steps;
-    if (!box && !pts && n <= lm::kSmallMax) {
+    if (!box && !pts && lm::small_path(n, prm->dim, sizeof(T) == 4)) {
         // the whole shoot in one launch (one workgroup holds the problem)
         lm::SmallShootArgs<T> a{};
         a.q = q;
@@ -1191,7 +1191,7 @@ lm_status lm_pair_plan(const lm_params* prm, int64_t n, lm_plan_info* info)
     info->waves = pl.sym_waves > 0 ? pl.sym_waves : lm::kWaves;
     info->workgroups = pl.sym_waves > 0 ? pl.sym_nsb * (pl.sym_nsb + 1) / 2 : pl.itiles * pl.nsplit;
     info->partial_slots = pl.nsplit;
-    info->small = !cut && n <= lm::kSmallMax;
+    info->small = !cut && lm::small_path(n, prm->dim, prm->dtype == LM_F32);
     info->rows = pl.sym_waves > 0 ? pl.sym_rows : 1;
     return LM_OK;
 }

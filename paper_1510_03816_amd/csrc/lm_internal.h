@@ -142,6 +142,10 @@ hipError_t launch_batch_copy_f32_to_f64(double* dst, const float* src, int dim, 
 // Whole shoots of problems of at most kSmallMax points, one workgroup each (see
 // lm_small_shoot_kernel): (q, p) advanced in place by `steps` RK4 steps of size dt.
 constexpr int kSmallMax = 256;
+// Whether a shoot of n points takes that one-workgroup path (without tile skipping): up to 128
+// points.  The environment variable LM_SMALL = 0 or 1 overrides the size rule (1: every size up
+// to kSmallMax), for tuning and tests.  Defined in lm_kernels.hip.
+bool small_path(int64_t n, int dim, bool fp32);
 
 template <class T>
 struct SmallShootArgs {

@@ -1274,11 +1274,15 @@ hipError_t launch_batch_copy_f32_to_f64(double* dst, const float* src, int dim, 
 // one workgroup: its stage input lives in LDS, each owner thread keeps its particle's RK4
 // state (step input and running sum, in double precision) in registers, and all
 // 4 x steps stages run inside the kernel with two barriers each.  This removes the one
-// launch per stage that bounds small problems by launch latency.  The four waves split
-// the work as (target tile, source chunk): one tile and four chunks up to 64 points, two
-// and two up to 128, four tiles of all sources up to 256; chunk partials are added in chunk
-// order.  One workgroup per problem: grid = problems (offs non-null) or one problem of
-// ntot points.
+// launch per stage that bounds small problems by launch latency.  The W waves split the work
+// as (target tile, source chunk): one tile and W chunks up to 64 points, two tiles and W/2
+// chunks up to 128, four tiles and W/4 chunks beyond; chunk partials are added in chunk
+// order.  W = 4 up to 64 points (32 in single precision), 8 beyond: more waves hide the
+// dependency latency that one wave per SIMD leaves exposed, once each wave has enough pairs to
+// pay for the longer barriers and sums (100 RK4 steps, ms, W = 4 / 8 / 16: FP64 2-D 64 points
+// 1.06 / 1.07 / 1.13, 96 points 2.55 / 2.16 / 2.18; FP32 2-D 64 points 0.75 / 0.69 / 0.90).
+// Shoots take this path up to 128 points (small_path).  One workgroup per problem: grid =
+// problems (offs non-null) or one problem of ntot points.
 // ---------------------------------------------------------------------------------------
 
 template <int DIM, int KER>
@@ -1320,18 +1324,18 @@ __device__ __forceinline__ void sum_lds(const float* __restrict__ sq, const floa
     for (int c = 0; c < DIM; ++c) { v[c] += (double)vs[c]; f[c] += (double)fs[c]; }
 }
 
-template <class T, int DIM, int KER>
-__global__ __launch_bounds__(256) void lm_small_shoot_kernel(SmallShootArgs<T> a)
+template <class T, int DIM, int KER, int W>
+__global__ __launch_bounds__(64 * W) void lm_small_shoot_kernel(SmallShootArgs<T> a)
 {
     __shared__ T sq[DIM * kSmallMax];
     __shared__ T sp[DIM * kSmallMax];
-    __shared__ double red[4][2 * DIM][kSmallMax];
+    __shared__ double red[W][2 * DIM][64];    // each wave's partials, by lane
     const int64_t off = a.offs ? a.offs[blockIdx.x] : 0;
     const int n = a.offs ? (int)(a.offs[blockIdx.x + 1] - off) : (int)a.ntot;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tiles = (n + 63) / 64;
     const int tp = tiles <= 1 ? 1 : (tiles <= 2 ? 2 : 4);
-    const int nchunk = 4 / tp;
+    const int nchunk = W / tp;
     const int tile = wave % tp, chunk = wave / tp;
     const int i = tile * 64 + lane;
     const int ic = i < n ? i : n - 1;
@@ -1370,17 +1374,18 @@ __global__ __launch_bounds__(256) void lm_small_shoot_kernel(SmallShootArgs<T> a
             sum_lds<DIM, KER>(sq, sp, j0, j1, qi, psi, a.kq, v, f);
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                red[chunk][c][i] = v[c];
-                red[chunk][DIM + c][i] = f[c];
+                red[wave][c][lane] = v[c];
+                red[wave][DIM + c][lane] = f[c];
             }
             __syncthreads();
             if (owner) {
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) {
-                    double sv = red[0][c][i], sf = red[0][DIM + c][i];
+                    // chunk ch of this tile is wave ch * tp + tile (the owner's wave is chunk 0)
+                    double sv = red[tile][c][lane], sf = red[tile][DIM + c][lane];
                     for (int ch = 1; ch < nchunk; ++ch) {
-                        sv += red[ch][c][i];
-                        sf += red[ch][DIM + c][i];
+                        sv += red[ch * tp + tile][c][lane];
+                        sf += red[ch * tp + tile][DIM + c][lane];
                     }
                     const double kqc = sv + a.tau * (double)sp[c * kSmallMax + i];
                     const double kpc = sf;
@@ -1418,21 +1423,52 @@ __global__ __launch_bounds__(256) void lm_small_shoot_kernel(SmallShootArgs<T> a
         }
 }
 
+template <class T, int DIM, int KER>
+hipError_t launch_small_shoot_w(const SmallShootArgs<T>& a, int problems, int waves, hipStream_t st)
+{
+    if (waves == 4)
+        hipLaunchKernelGGL((lm_small_shoot_kernel<T, DIM, KER, 4>), dim3(problems), dim3(256), 0, st, a);
+    else if (waves == 8)
+        hipLaunchKernelGGL((lm_small_shoot_kernel<T, DIM, KER, 8>), dim3(problems), dim3(512), 0, st, a);
+    else
+        hipLaunchKernelGGL((lm_small_shoot_kernel<T, DIM, KER, 16>), dim3(problems), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
+static int small_shoot_waves(int64_t n, bool fp32)
+{
+    // LM_SMALL_WAVES = 4, 8 or 16 fixes the width (tuning and tests; read at every launch)
+    const char* e = getenv("LM_SMALL_WAVES");
+    const int fixed = e ? atoi(e) : 0;
+    if (fixed == 4 || fixed == 8 || fixed == 16) return fixed;
+    return n <= (fp32 ? 32 : 64) ? 4 : (n <= 128 ? 8 : 16);   // 16: only under LM_SMALL = 1
+}
+
+// Measured (100 RK4 steps, ms; one workgroup of 4 / 8 / 16 waves against one launch per stage):
+// FP64 2-D 96 points 2.55 / 2.16 / 2.18 against 2.46, 128 points 3.33 / 2.77 / 2.74 against 2.96,
+// 160 points 7.99 / 6.40 / 5.99 against 3.37, 256 points 12.67 / 10.10 / 9.40 against 4.64; FP64
+// 3-D 128 points 3.96 / 3.20 / 3.25 against 3.55; FP32 2-D 128 points 2.03 / 1.23 / 1.25 against
+// 2.16, FP32 3-D 192 points 7.03 / 3.51 / 3.41 against 3.28.  Past two tiles the one-workgroup
+// path loses: its work grows as n^2 on one CU while a stage of the other path stays near its
+// launch cost.
+bool small_path(int64_t n, int dim, bool fp32)
+{
+    (void)dim;
+    (void)fp32;
+    const char* e = getenv("LM_SMALL");
+    if (e && (e[0] == '0' || e[0] == '1') && e[1] == 0) return e[0] == '1' && n <= kSmallMax;
+    return n <= 128;
+}
+
 template <class T>
 hipError_t launch_small_shoot(int dim, int kernel, const SmallShootArgs<T>& a, int problems, hipStream_t st)
 {
-    if (dim == 2) {
-        if (kernel == LM_KERNEL_CONON)
-            hipLaunchKernelGGL((lm_small_shoot_kernel<T, 2, LM_KERNEL_CONON>), dim3(problems), dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL((lm_small_shoot_kernel<T, 2, LM_KERNEL_GAUSS>), dim3(problems), dim3(256), 0, st, a);
-    } else {
-        if (kernel == LM_KERNEL_CONON)
-            hipLaunchKernelGGL((lm_small_shoot_kernel<T, 3, LM_KERNEL_CONON>), dim3(problems), dim3(256), 0, st, a);
-        else
-            hipLaunchKernelGGL((lm_small_shoot_kernel<T, 3, LM_KERNEL_GAUSS>), dim3(problems), dim3(256), 0, st, a);
-    }
-    return hipGetLastError();
+    const int w = small_shoot_waves(a.offs ? kSmallMax : a.ntot, sizeof(T) == 4);
+    if (dim == 2)
+        return kernel == LM_KERNEL_CONON ? launch_small_shoot_w<T, 2, LM_KERNEL_CONON>(a, problems, w, st)
+                                         : launch_small_shoot_w<T, 2, LM_KERNEL_GAUSS>(a, problems, w, st);
+    return kernel == LM_KERNEL_CONON ? launch_small_shoot_w<T, 3, LM_KERNEL_CONON>(a, problems, w, st)
+                                     : launch_small_shoot_w<T, 3, LM_KERNEL_GAUSS>(a, problems, w, st);
 }
 template hipError_t launch_small_shoot<double>(int, int, const SmallShootArgs<double>&, int, hipStream_t);
 template hipError_t launch_small_shoot<float>(int, int, const SmallShootArgs<float>&, int, hipStream_t);

@@ -135,7 +135,7 @@ def test_shoot_matches_oracle(name, make, steps, dtype):
 @pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
 @pytest.mark.parametrize("n", [2, 63, 64, 65, 127, 128, 129, 200, 255, 256, 257])
 def test_small_problem_shoot_matches_oracle(n, dtype):
-    """Problems of at most 256 points are shot in one launch (one workgroup, every stage in
+    """Small problems (up to 128 points) are shot in one launch (one workgroup, every stage in
     the kernel); sizes across its tile/chunk splits and the boundary to the stage-per-launch
     path, with the inexact term, against the oracle."""
     dim, kernel = (3, lm.GAUSS) if n % 2 else (2, lm.CONON)
@@ -148,6 +148,28 @@ def test_small_problem_shoot_matches_oracle(n, dtype):
     torch.cuda.synchronize()
     eq, ep = rel_err(host(q1), oq), rel_err(host(p1), op)
     print("n=%d dtype=%d: %.2e %.2e" % (n, dtype, eq, ep))
+    assert eq <= TOL[dtype] and ep <= TOL[dtype]
+
+
+@pytest.mark.parametrize("waves", [4, 8, 16])
+@pytest.mark.parametrize("n,dim,dtype", [(3, 2, lm.F64), (64, 3, lm.F64), (100, 2, lm.F64), (192, 2, lm.F64),
+                                         (224, 3, lm.F64), (33, 2, lm.F32), (256, 3, lm.F32)])
+def test_small_problem_shoot_every_width(n, dim, dtype, waves, monkeypatch):
+    """The one-workgroup shoot at each of its widths (4, 8, 16 waves: one to four target tiles,
+    1 to 16 source chunks; LM_SMALL = 1 takes it up to 256 points) against the oracle, on the
+    structured workloads."""
+    monkeypatch.setenv("LM_SMALL", "1")
+    monkeypatch.setenv("LM_SMALL_WAVES", str(waves))
+    pr = inputs.config_curve2d(n, sigma=0.3) if dim == 2 else inputs.config_sphere3d(n, kernel=lm.GAUSS, sigma=0.3)
+    q0, p0 = rounded(pr.X, dtype), rounded(pr.p_bench(), dtype)
+    oq, op = oracle.shoot(q0, p0, pr.kernel, pr.sigma, 40, tau=0.05)
+    prm = lm.make_params(dim, pr.kernel, pr.sigma, dtype=dtype, tau=0.05)
+    assert lm.lm_pair_plan(prm, n)["small"] == 1
+    q1, p1 = torch.empty_like(dev(q0, dtype)), torch.empty_like(dev(q0, dtype))
+    lm.lm_shoot(prm, dev(q0, dtype), dev(p0, dtype), 1.0, 40, q1, p1)
+    torch.cuda.synchronize()
+    eq, ep = rel_err(host(q1), oq), rel_err(host(p1), op)
+    print("n=%d dim=%d dtype=%d waves=%d: %.2e %.2e" % (n, dim, dtype, waves, eq, ep))
     assert eq <= TOL[dtype] and ep <= TOL[dtype]
 
 

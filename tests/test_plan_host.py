@@ -13,6 +13,8 @@ def _clean_env(monkeypatch):
     monkeypatch.delenv("LM_SYM", raising=False)
     monkeypatch.delenv("LM_SYM_WAVES", raising=False)
     monkeypatch.delenv("LM_SYM_ROWS", raising=False)
+    monkeypatch.delenv("LM_SMALL", raising=False)
+    monkeypatch.delenv("LM_SMALL_WAVES", raising=False)
 
 
 def plan(n, dtype=lm.F64, cutoff=0.0, dim=3):
@@ -47,7 +49,22 @@ def test_size_rule(n, waves, rows):
 def test_small_sizes_keep_one_sided_kernel(n):
     p = plan(n)
     assert p["symmetric"] == 0 and p["waves"] == 4 and p["rows"] == 1
-    assert p["small"] == (1 if n <= 256 else 0)
+    assert p["small"] == (1 if n <= 128 else 0)
+
+
+@pytest.mark.parametrize("n,dim,dtype,small", [
+    (1, 2, lm.F64, 1), (128, 2, lm.F64, 1), (129, 2, lm.F64, 0), (128, 3, lm.F32, 1), (129, 3, lm.F32, 0),
+    (256, 2, lm.F32, 0),
+])
+def test_one_workgroup_shoot_sizes(n, dim, dtype, small, monkeypatch):
+    """Shoots run whole inside one workgroup up to 128 points, where that beats one launch per
+    stage; never with tile skipping.  LM_SMALL forces either path (1: up to 256 points)."""
+    assert lm.lm_pair_plan(lm.make_params(dim, lm.CONON, 0.3, dtype=dtype), n)["small"] == small
+    assert lm.lm_pair_plan(lm.make_params(dim, lm.CONON, 0.3, dtype=dtype, cutoff=0.5), n)["small"] == 0
+    monkeypatch.setenv("LM_SMALL", "1")
+    assert lm.lm_pair_plan(lm.make_params(dim, lm.CONON, 0.3, dtype=dtype), n)["small"] == (1 if n <= 256 else 0)
+    monkeypatch.setenv("LM_SMALL", "0")
+    assert lm.lm_pair_plan(lm.make_params(dim, lm.CONON, 0.3, dtype=dtype), n)["small"] == 0
 
 
 def test_one_sided_split_rule(monkeypatch):
