@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -80,6 +81,31 @@ void default_tuning(lm_batch_tuning* t, int64_t nmax)
     t->stage_us = 0.0;
 }
 
+// Compute units of the current device (256 on MI355X when the query fails).
+int device_cus()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        return prop.multiProcessorCount;
+    return 256;
+}
+
+// Fewest waves per launch of a batched match's shoots: kFillWavesPerSimd per SIMD (four SIMDs
+// per CU); LM_BATCH_FILL overrides the per-SIMD figure (0 keeps the tuning's shape).  On the
+// tail of the 256-curve match (the 1 to 16 largest curves, 3229 to 4065 points), per 100-step
+// shoot: in single precision 10.5-48.3 ms against 53-59 ms with the whole batch's splits, within
+// 12% of the best split a sweep found; in double precision, one-wave superblocks for the 1, 2
+// and 4 largest took 19.4, 21.1 and 30.1 ms against 28.2, 40.4 and 42.5 ms with two waves.
+constexpr int kFillWavesPerSimd = 2;
+
+int64_t match_min_waves()
+{
+    int64_t per_simd = kFillWavesPerSimd;
+    if (const char* e = std::getenv("LM_BATCH_FILL")) per_simd = std::max(0L, std::strtol(e, nullptr, 10));
+    return per_simd * 4 * device_cus();
+}
+
 int bucket_of(const lm_batch_tuning& t, int64_t nb)
 {
     for (int k = 0; k < LM_BATCH_BUCKETS; ++k)
@@ -107,8 +133,16 @@ struct BatchPlan {
 
 // Builds the work list on the host and uploads it (the host vectors are copied before this
 // returns: the copies are synchronous with respect to the host).
+// include (nullable) selects the problems to plan.  min_waves > 0 asks for at least that many
+// waves per launch: while the plan has fewer, the symmetric problems' workgroups are narrowed
+// (half the waves, half the superblock side, down to one wave), then the one-sided problems'
+// source splits are doubled together (each up to 64 chunks and at most one chunk per source
+// point).  A tuning made for a whole batch can leave a few of its problems, the tail of a
+// batched match, on a small part of the chip: one 4065-point problem split in two is 128 waves
+// on 1024 SIMDs, and in double precision with two-wave superblocks 72.
 lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs_d, const lm_batch_tuning& t,
-                    Workspace& ws, BatchPlan* pl, hipStream_t st, bool f64, const std::vector<int>* include = nullptr)
+                    Workspace& ws, BatchPlan* pl, hipStream_t st, bool f64, const std::vector<int>* include = nullptr,
+                    int64_t min_waves = 0)
 {
     struct Item {
         int4 w;
@@ -118,11 +152,51 @@ lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs
     std::vector<int4> fin;
     std::vector<int64_t> part_off((size_t)B, -1);
     int64_t part_elems = 0;
-    const int64_t side = (int64_t)lm::kSymRows * t.sym_waves;   // tiles per superblock
+    auto planned = [&](int32_t b) { return !include || (*include)[b]; };
+    auto symmetric = [&](int64_t nb) { return f64 && t.sym_min > 0 && nb >= t.sym_min; };
+
+    // waves of the symmetric problems with sw waves per workgroup (superblocks of kSymRows * sw
+    // tiles, one workgroup per superblock pair)
+    auto sym_waves_at = [&](int sw) {
+        const int64_t sd = (int64_t)lm::kSymRows * sw;
+        int64_t w = 0;
+        for (int32_t b = 0; b < B; ++b) {
+            const int64_t nb = offs[b + 1] - offs[b];
+            if (!planned(b) || !symmetric(nb)) continue;
+            const int64_t S = ((nb + 63) / 64 + sd - 1) / sd;
+            w += S * (S + 1) / 2 * sw;
+        }
+        return w;
+    };
+    // source splits of the one-sided problems: the tuning's, times mult
+    std::vector<int32_t> split((size_t)B, 0);
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t nb = offs[b + 1] - offs[b];
+        if (planned(b) && !symmetric(nb)) split[b] = (int32_t)std::min<int64_t>(t.split[bucket_of(t, nb)], nb);
+    }
+    auto split_times = [&](int32_t b, int64_t mult) {
+        return (int32_t)std::min<int64_t>({(int64_t)split[b] * mult, 64, offs[b + 1] - offs[b]});
+    };
+    auto one_sided_waves_at = [&](int64_t mult) {
+        int64_t w = 0;
+        for (int32_t b = 0; b < B; ++b)
+            if (split[b] > 0) w += (offs[b + 1] - offs[b] + 63) / 64 * split_times(b, mult);
+        return w;
+    };
+    int sw = t.sym_waves;
+    int64_t mult = 1;
+    if (min_waves > 0) {
+        while (sw > 1 && sym_waves_at(sw) + one_sided_waves_at(1) < min_waves) sw /= 2;
+        const int64_t symw = sym_waves_at(sw);
+        while (symw + one_sided_waves_at(mult) < min_waves && one_sided_waves_at(2 * mult) > one_sided_waves_at(mult))
+            mult *= 2;
+    }
+    const int64_t side = (int64_t)lm::kSymRows * sw;   // tiles per superblock
+
     for (int32_t b = 0; b < B; ++b) {
         if (include && !(*include)[b]) continue;
         const int64_t nb = offs[b + 1] - offs[b];
-        if (f64 && t.sym_min > 0 && nb >= t.sym_min) {
+        if (symmetric(nb)) {
             // symmetric: one item per superblock pair (X <= Y), S + 1 partial-sum slots
             const int64_t nt = (nb + 63) / 64;
             const int64_t S = (nt + side - 1) / side;
@@ -136,7 +210,7 @@ lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs
             for (int64_t t0 = 0; t0 < nb; t0 += 64) fin.push_back(make_int4(b, (int)t0, (int)(S + 1), 0));
             continue;
         }
-        const int32_t S = (int32_t)std::min<int64_t>(t.split[bucket_of(t, nb)], nb);
+        const int32_t S = split_times(b, mult);
         const int64_t chunk = (nb + S - 1) / S;
         if (S > 1) {
             part_off[b] = part_elems;
@@ -158,7 +232,7 @@ lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs
     for (size_t k = 0; k < items.size(); ++k) w[k] = items[k].w;
     for (size_t k = 0; k < sym.size(); ++k) ws_sym[k] = sym[k].w;
     pl->nsym = (int32_t)ws_sym.size();
-    pl->sym_waves = t.sym_waves;
+    pl->sym_waves = sw;
     LM_TRY(ws.get(&pl->sym_items_d, std::max<int32_t>(pl->nsym, 1)));
     if (pl->nsym > 0)
         LM_HIP(hipMemcpyAsync(pl->sym_items_d, ws_sym.data(), ws_sym.size() * sizeof(int4), hipMemcpyHostToDevice, st));
@@ -476,13 +550,7 @@ lm_status autotune_t(const lm_params* prm, int32_t B, const int64_t* offs, const
     LM_TRY(stage_time(*best, &cur));
 
     // grid size: one wave per item, or a persistent grid of 1, 2, 4, 8 workgroups per CU
-    int cus = 256;
-    {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cus = prop.multiProcessorCount;
-    }
+    const int cus = device_cus();
     for (int g : {1, 2, 4, 8}) {
         lm_batch_tuning t = *best;
         t.groups = g * cus;
@@ -669,6 +737,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
 
     // work lists of the problems shot in each precision, rebuilt when those sets change
     std::vector<int> in64((size_t)B, -1), in32((size_t)B, -1);
+    const int64_t fill = match_min_waves();
     std::unique_ptr<Workspace> pws64, pws32;
     BatchPlan pl64, pl32;
     StepGraph g64, g32;
@@ -686,13 +755,13 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         if (any64 && want64 != in64) {
             g64.reset();
             pws64.reset(new Workspace(st));
-            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws64, &pl64, st, true, &want64));
+            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws64, &pl64, st, true, &want64, fill));
             in64 = want64;
         }
         if (any32 && want32 != in32) {
             g32.reset();
             pws32.reset(new Workspace(st));
-            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws32, &pl32, st, false, &want32));
+            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws32, &pl32, st, false, &want32, fill));
             in32 = want32;
         }
 

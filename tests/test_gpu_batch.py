@@ -171,7 +171,22 @@ def test_autotune_picks_a_valid_shape(dtype):
     assert rel_err(host(a[1]), host(a[3])) <= TOL[dtype] * 0.1
 
 
-def test_batched_feedback_matches_oracle_per_problem():
+# LM_BATCH_FILL: waves per SIMD below which a match's shoots split their one-sided problems'
+# sources further (unset: the library's default; "0": the tuning's splits only; "8": splits up to
+# one chunk per source point on these small problems)
+FILLS = [None, "0", "8"]
+
+
+def set_fill(monkeypatch, fill):
+    if fill is None:
+        monkeypatch.delenv("LM_BATCH_FILL", raising=False)
+    else:
+        monkeypatch.setenv("LM_BATCH_FILL", fill)
+
+
+@pytest.mark.parametrize("fill", FILLS)
+def test_batched_feedback_matches_oracle_per_problem(fill, monkeypatch):
+    set_fill(monkeypatch, fill)
     sizes, offs, X, Y = curve_batch(5, 300)
     prm = lm.make_params(2, lm.CONON, 0.1)
     p0 = torch.zeros((2, int(offs[-1])), dtype=torch.float64, device=DEV)
@@ -215,7 +230,9 @@ def test_batched_inexact_feedback_matches_oracle_per_problem():
         assert abs(infos[b].H - oracle.hamiltonian(X[:, s], ref.p0, lm.CONON, 0.1)) <= 1e-9 * abs(ref.H)
 
 
-def test_batched_feedback_single_precision_shoots():
+@pytest.mark.parametrize("fill", FILLS)
+def test_batched_feedback_single_precision_shoots(fill, monkeypatch):
+    set_fill(monkeypatch, fill)
     sizes, offs, X, Y = curve_batch(5, 300)
     prm = lm.make_params(2, lm.CONON, 0.1, dtype=lm.F32)
     p0 = torch.zeros((2, int(offs[-1])), dtype=torch.float64, device=DEV)
