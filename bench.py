@@ -70,8 +70,8 @@ PEAK_TFLOPS_F32 = 157.3
 # recorded with the hash of the kernel sources they were taken on; a changed kernel reports
 # null until the counters are taken again.
 MEASURED_TRAFFIC = {
-    "sphere3d_conon_f64": ("35399c59cb6f852b", 1.0436e9),
-    "sphere3d_conon_f32": ("35399c59cb6f852b", 1.2996e8),
+    "sphere3d_conon_f64": ("246f6dbde3421f44", 1.0436e9),
+    "sphere3d_conon_f32": ("246f6dbde3421f44", 1.2993e8),
 }
 
 # Estimated seconds of each optional leg on MI355X (a leg runs only if the budget left
