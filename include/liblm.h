@@ -173,7 +173,11 @@ lm_status lm_hamiltonian(const lm_params *params, int64_t n, const void *q, cons
  * conversion of a velocity field u at the landmarks into momenta p (Algorithm 1, step 4,
  * read as p = K(X)^{-1} u).  solver: LM_SOLVE_CG (matrix-free conjugate gradients, stops when
  * ||b_c - K x_c||_2 <= rtol ||b_c||_2 for every c or after max_iter iterations), LM_SOLVE_DENSE
- * (Cholesky factor, rtol and max_iter unused) or LM_SOLVE_AUTO.  X, b, x: double (dim, n);
+ * (Cholesky factor, rtol and max_iter unused; its triangular sweeps take one launch per
+ * 128-row block, or, once the factor spans more than 8 blocks, three launches per 8 blocks
+ * through stored inverses of the diagonal 1024 x 1024 parts, 7 x 128^2 more doubles per
+ * block (1.4% of the factor at n = 65536); the
+ * environment variable LM_DENSE_SUPER = 0/1 forces either form) or LM_SOLVE_AUTO.  X, b, x: double (dim, n);
  * x may alias b.  *iters_out (HOST, nullable) receives the CG iteration count (0 for dense).
  * cutoff is ignored: every pair enters K.  Synchronous.  LM_ESINGULAR if K is not
  * numerically positive definite (a CG curvature p.Kp <= 0 or a non-positive Cholesky

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -455,13 +456,24 @@ lm_status ksolve_impl(const lm_params* prm, int64_t n, const double* X, const do
     return LM_OK;
 }
 
-// Dense Cholesky factor of K(X) + tau I (see lm_dense.hip).
+// Dense Cholesky factor of K(X) + tau I (see lm_dense.hip).  With W set, the solves run the
+// superblock sweeps (W: the diagonal superblocks' inverses; scratch: their work vectors).
 struct DenseFactor {
     double* L = nullptr;
     double* Linv = nullptr;
+    double* W = nullptr;
+    double* scratch = nullptr;
     int* info = nullptr;
     int64_t n = 0;
 };
+
+// Superblock sweeps for an n-point factor: LM_DENSE_SUPER (0/1) overrides the default (on
+// when n spans more than one superblock of 8 x 128 rows).
+bool use_super(int64_t n)
+{
+    if (const char* e = std::getenv("LM_DENSE_SUPER")) return e[0] == '1';
+    return lm::dense_super_default(n);
+}
 
 // Whether the dense factor of an n-point problem fits in half the free device memory.
 bool dense_fits(int64_t n)
@@ -469,7 +481,9 @@ bool dense_fits(int64_t n)
     if (n >= lm::kDenseMaxN) return false;
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return false;
-    const double need = 8.0 * (double)n * (double)n + 8.0 * (double)lm::dense_linv_elems(n);
+    double need = 8.0 * (double)n * (double)n + 8.0 * (double)lm::dense_linv_elems(n);
+    if (use_super(n))
+        need += 8.0 * (double)(lm::dense_super_elems(n) + lm::dense_solve_scratch_elems(n));
     return need <= 0.5 * (double)freeb;
 }
 
@@ -480,9 +494,14 @@ lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspa
     LM_TRY(ws.get(&f->L, n * n));
     LM_TRY(ws.get(&f->Linv, lm::dense_linv_elems(n)));
     LM_TRY(ws.get(&f->info, 1));
+    if (use_super(n)) {
+        LM_TRY(ws.get(&f->W, lm::dense_super_elems(n)));
+        LM_TRY(ws.get(&f->scratch, lm::dense_solve_scratch_elems(n)));
+    }
     double kq, wscale;
     kernel_scales(prm, &kq, &wscale);
     LM_HIP(lm::launch_dense_factor(prm->dim, prm->kernel, kq, prm->tau, X, n, f->L, f->Linv, f->info, st));
+    if (f->W) LM_HIP(lm::launch_dense_super(f->L, f->Linv, n, f->W, st));
     int info = 0;
     LM_HIP(hipMemcpyAsync(&info, f->info, sizeof(int), hipMemcpyDeviceToHost, st));
     LM_HIP(hipStreamSynchronize(st));
@@ -495,7 +514,10 @@ lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspa
 lm_status dense_solve(const DenseFactor& f, int dim, const double* b, double* x, hipStream_t st)
 {
     if (x != b) LM_HIP(hipMemcpyAsync(x, b, (size_t)dim * f.n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    LM_HIP(lm::launch_dense_solve(f.L, f.Linv, f.n, dim, x, f.n, st));
+    if (f.W)
+        LM_HIP(lm::launch_dense_solve_super(f.L, f.Linv, f.W, f.n, dim, x, f.n, f.scratch, st));
+    else
+        LM_HIP(lm::launch_dense_solve(f.L, f.Linv, f.n, dim, x, f.n, st));
     return LM_OK;
 }
 

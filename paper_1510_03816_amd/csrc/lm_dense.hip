@@ -21,7 +21,9 @@
 // in launch k every workgroup subtracts panel k's contribution from its rows, and the
 // workgroup that owns block k+1 (k-1 backward) then finishes that block with the stored
 // inverse of its diagonal block.  The panel kernel also writes each panel transposed into
-// the unused upper triangle, where the forward sweep reads it as contiguous rows.
+// the unused upper triangle, where the forward sweep reads it as contiguous rows.  Large
+// factors use the superblock form instead (three launches per 8 blocks, through the stored
+// inverses of the diagonal superblocks; below the batched solves).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -815,6 +817,291 @@ hipError_t launch_batch_dense_solve(const double* L, const int64_t* loff, const 
 }
 
 // ---------------------------------------------------------------------------------------
+// Superblock sweeps.  The per-block sweeps above take one launch per 128-row block, and
+// each launch ends with one workgroup finishing the next block: at N = 65536 that is 1024
+// dependent launches per solve.  Here kSuper consecutive blocks form a superblock s whose
+// diagonal part L_ss is inverted once, after the factor: W_s = L_ss^{-1} is block lower
+// triangular with W_ii = Linv_i and, for i > m,
+//   W_im = -Linv_i sum_{j=m}^{i-1} L_ij W_jm
+// (from L_ss W_s = I).  A forward sweep is then, per superblock, three launches:
+//   prod: every block product W_im t_m (m <= i) by its own workgroup into a partial buffer;
+//   sum:  x_i = sum_m of those partials in increasing m (one workgroup per block) into z;
+//   rows: every row past the superblock subtracts L[r, s] x_s, the panel of kSuper * 128
+//         columns read from its transposed copy in the upper triangle (contiguous rows).
+// The backward sweep mirrors it with W_s^T (blocks (W_mi)^T, m >= i), reading L's rows
+// below the diagonal.  The forward sweep writes its result into the scratch z and uses y
+// as the accumulator; the backward sweep uses z as the accumulator and writes x into y.
+// W_im and W_im^T are stored for every superblock (the products read rows: W^T rows for
+// W t, W rows for W^T t), 2 * kSuper(kSuper-1)/2 blocks of 128 x 128 per superblock.
+// ---------------------------------------------------------------------------------------
+constexpr int kSuper = 8;
+constexpr int kSuperPairs = kSuper * (kSuper - 1) / 2;   // off-diagonal blocks of W_s
+constexpr int kSuperProds = kSuper * (kSuper + 1) / 2;   // block products of one sweep step
+
+int super_count(int64_t n) { return (dense_panels(n) + kSuper - 1) / kSuper; }
+int64_t dense_super_elems(int64_t n) { return 2 * (int64_t)super_count(n) * kSuperPairs * kPanel * kPanel; }
+int64_t dense_solve_scratch_elems(int64_t n) { return 3 * n + (int64_t)kSuperProds * 3 * kPanel; }
+
+// Block (i, m), m < i, of W_s, and its transpose.
+__host__ __device__ __forceinline__ int64_t super_blk(int64_t s, int i, int m)
+{
+    return (s * kSuperPairs + i * (i - 1) / 2 + m) * kPanel * kPanel;
+}
+__host__ __device__ __forceinline__ int64_t super_blk_t(int ns, int64_t s, int i, int m)
+{
+    return ((int64_t)ns * kSuperPairs) * kPanel * kPanel + super_blk(s, i, m);
+}
+__device__ __forceinline__ int block_rows(int64_t n, int64_t blk)
+{
+    const int64_t r = n - blk * kPanel;
+    return r < kPanel ? (int)r : kPanel;
+}
+
+// acc[u][v] += sum_k A[tr + 16u][k] B[k][tc + 16v] over the 128 x 128 x 128 product of the
+// row-major blocks A (leading dimension lda; entries with row >= arows or k >= kdim read as
+// zero) and B (ldb; k >= kdim or column >= bcols read as zero), thread (tr, tc) = (tid / 16,
+// tid % 16).  k runs in chunks of 16 staged in LDS (A transposed), each added in increasing k.
+__device__ void gemm128_acc(const double* __restrict__ A, int64_t lda, int arows, int kdim,
+                            const double* __restrict__ B, int64_t ldb, int bcols, double (&acc)[8][8],
+                            double (*As)[kPanel + 1], double (*Bs)[kPanel + 1])
+{
+    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+    for (int k0 = 0; k0 < kPanel; k0 += 16) {
+        double av[8], bv[8];
+        {
+            const int r = tid >> 1, kk = (tid & 1) * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                av[u] = (r < arows && k0 + kk + u < kdim) ? A[(int64_t)r * lda + k0 + kk + u] : 0.0;
+            const int kb = tid >> 4, c = (tid & 15) * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                bv[u] = (k0 + kb < kdim && c + u < bcols) ? B[(int64_t)(k0 + kb) * ldb + c + u] : 0.0;
+        }
+        __syncthreads();   // the previous chunk's reads are done
+        {
+            const int r = tid >> 1, kk = (tid & 1) * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) As[kk + u][r] = av[u];
+            const int kb = tid >> 4, c = (tid & 15) * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) Bs[kb][c + u] = bv[u];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < 16; ++k) {
+            double a[8], b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                a[u] = As[k][tr + 16 * u];
+                b[u] = Bs[k][tc + 16 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int v = 0; v < 8; ++v) acc[u][v] = __builtin_fma(a[u], b[v], acc[u][v]);
+        }
+    }
+    __syncthreads();
+}
+
+// Step d of building the W_s (all superblocks, blocks i = m + d): S = sum_{j=m}^{i-1} L_ij W_jm
+// (W_mm = Linv_m), stored in the slot of W_im^T for the next kernel.
+__global__ __launch_bounds__(256) void lm_super_s_kernel(const double* __restrict__ L, const double* __restrict__ Linv,
+                                                         double* __restrict__ W, int64_t n, int nb, int ns, int d)
+{
+    __shared__ double As[16][kPanel + 1];
+    __shared__ double Bs[16][kPanel + 1];
+    const int64_t s = blockIdx.x / (kSuper - d);
+    const int m = (int)(blockIdx.x % (kSuper - d)), i = m + d;
+    const int64_t b0 = s * kSuper;
+    if (b0 + i >= nb) return;
+    const int bi = block_rows(n, b0 + i), bm = block_rows(n, b0 + m);
+    double acc[8][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+    for (int j = m; j < i; ++j) {
+        const double* Aij = L + ((b0 + i) * kPanel) * n + (b0 + j) * kPanel;
+        const double* Bjm = (j == m) ? Linv + (b0 + m) * kPanel * kPanel : W + super_blk(s, j, m);
+        gemm128_acc(Aij, n, bi, block_rows(n, b0 + j), Bjm, kPanel, bm, acc, As, Bs);
+    }
+    double* S = W + super_blk_t(ns, s, i, m);
+    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) S[(tr + 16 * u) * kPanel + tc + 16 * v] = acc[u][v];
+}
+
+// Step d, second half: W_im = -Linv_i S (S read from the W_im^T slot), stored with its
+// transpose.  Every read of S is done (gemm128_acc ends with a barrier) before the slot is
+// overwritten.
+__global__ __launch_bounds__(256) void lm_super_w_kernel(const double* __restrict__ Linv, double* __restrict__ W,
+                                                         int64_t n, int nb, int ns, int d)
+{
+    __shared__ double As[16][kPanel + 1];
+    __shared__ double Bs[16][kPanel + 1];
+    const int64_t s = blockIdx.x / (kSuper - d);
+    const int m = (int)(blockIdx.x % (kSuper - d)), i = m + d;
+    const int64_t b0 = s * kSuper;
+    if (b0 + i >= nb) return;
+    const int bi = block_rows(n, b0 + i), bm = block_rows(n, b0 + m);
+    double acc[8][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+    double* Wt = W + super_blk_t(ns, s, i, m);
+    gemm128_acc(Linv + (b0 + i) * kPanel * kPanel, kPanel, bi, bi, Wt, kPanel, bm, acc, As, Bs);
+    double* Wim = W + super_blk(s, i, m);
+    const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int r = tr + 16 * u, c = tc + 16 * v;
+            Wim[r * kPanel + c] = -acc[u][v];
+            Wt[c * kPanel + r] = -acc[u][v];
+        }
+}
+
+// One superblock step's block products: workgroup p takes pair (a, b), a >= b, with
+// p = a(a+1)/2 + b.  Forward: (i, m) = (a, b), out = W_im t_m, reading rows of W_im^T (LinvT
+// for i = m).  Backward: (i, m) = (b, a), out = W_mi^T t_m, reading rows of W_mi (Linv for
+// i = m).  t_m: block b0 + m of t (zero past n); out: DIM x kPanel doubles at part + p.
+// Thread (h, r) sums its half of the rows for output r, 16 loads in flight; halves added in
+// order.
+template <int DIM, bool BWD>
+__global__ __launch_bounds__(256) void lm_super_prod_kernel(const double* __restrict__ Linv, const double* __restrict__ W,
+                                                            int64_t n, int nb, int ns, int64_t s,
+                                                            const double* __restrict__ t, int64_t ldt,
+                                                            double* __restrict__ part)
+{
+    __shared__ double tv[DIM][kPanel];
+    __shared__ double half[DIM][kPanel];
+    const int p = blockIdx.x;
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= p) ++a;
+    const int b = p - a * (a + 1) / 2;
+    const int i = BWD ? b : a, m = BWD ? a : b;
+    const int64_t b0 = s * kSuper;
+    const double* Mrows;
+    if (i == m)
+        Mrows = Linv + ((BWD ? 0 : (int64_t)nb) + b0 + i) * kPanel * kPanel;
+    else
+        Mrows = BWD ? W + super_blk(s, m, i) : W + super_blk_t(ns, s, i, m);
+    const int64_t t0 = (b0 + m) * kPanel;
+    const int bm = block_rows(n, b0 + m);
+    for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
+        const int c = e / kPanel, r = e % kPanel;
+        tv[c][r] = r < bm ? t[c * ldt + t0 + r] : 0.0;
+    }
+    __syncthreads();
+    const int r = threadIdx.x & (kPanel - 1), h = threadIdx.x >> 7;
+    double acc[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) acc[c] = 0.0;
+    const double* col = Mrows + (int64_t)(h * 64) * kPanel + r;
+    for (int j0 = 0; j0 < 64; j0 += 16) {
+        double lv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) lv[u] = col[(j0 + u) * kPanel];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc[c] = __builtin_fma(lv[u], tv[c][h * 64 + j0 + u], acc[c]);
+    }
+    if (h == 1)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) half[c][r] = acc[c];
+    __syncthreads();
+    if (h == 0)
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) part[((int64_t)p * DIM + c) * kPanel + r] = acc[c] + half[c][r];
+}
+
+// x_i = sum of the step's partials for block i in increasing m (forward: m = 0 .. i, pairs
+// (i, m); backward: m = i .. q-1, pairs (m, i)), written to rows b0 + i of x (ldx).
+template <int DIM, bool BWD>
+__global__ __launch_bounds__(kPanel) void lm_super_sum_kernel(int64_t n, int64_t s, int q,
+                                                              const double* __restrict__ part,
+                                                              double* __restrict__ x, int64_t ldx)
+{
+    const int i = blockIdx.x, r = threadIdx.x;
+    const int64_t row = (s * kSuper + i) * kPanel + r;
+    if (row >= n) return;
+    double v[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) v[c] = 0.0;
+    const int mb = BWD ? i : 0, me = BWD ? q : i + 1;
+    for (int m = mb; m < me; ++m) {
+        const int p = BWD ? m * (m + 1) / 2 + i : i * (i + 1) / 2 + m;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) v[c] += part[((int64_t)p * DIM + c) * kPanel + r];
+    }
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) x[c * ldx + row] = v[c];
+}
+
+// acc[c][col] -= sum_{m < w} L[m0 + m][col] x[c][m] for col in [c0, c1): rows m0 .. m0 + w - 1
+// of L, contiguous in col (forward: columns past the superblock, the panel's transposed copy
+// in the upper triangle; backward: columns before it, L below the diagonal).  x: rows m0 ..
+// m0 + w - 1 of xs (ldx), staged in LDS.  A workgroup takes 64 columns at a time, one per
+// lane; wave wv sums m over its quarter of [0, kSuper * kPanel) in batches of 32 loads, and
+// the four wave sums are added in wave order.
+template <int DIM>
+__global__ __launch_bounds__(256) void lm_super_rows_kernel(const double* __restrict__ L, int64_t n, int64_t m0, int w,
+                                                            const double* __restrict__ xs, int64_t ldx,
+                                                            double* __restrict__ acc, int64_t lda, int64_t c0,
+                                                            int64_t c1)
+{
+    constexpr int kW = kSuper * kPanel;
+    __shared__ double xv[DIM][kW];
+    __shared__ double red[4][DIM][64];
+    for (int e = threadIdx.x; e < DIM * kW; e += blockDim.x) {
+        const int c = e / kW, m = e % kW;
+        xv[c][m] = m < w ? xs[c * ldx + m0 + m] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q4 = (w + 3) / 4;
+    const int mb = wave * q4, me = (mb + q4 < w) ? mb + q4 : w;
+    for (int64_t cb = c0 + (int64_t)blockIdx.x * 64; cb < c1; cb += (int64_t)gridDim.x * 64) {
+        const int64_t col = cb + lane;
+        const bool ok = col < c1;
+        const double* lp = L + (m0 + mb) * n + (ok ? col : cb);
+        double sacc[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) sacc[c] = 0.0;
+        int m = mb;
+        for (; m + 32 <= me; m += 32, lp += 32 * n) {
+            double lv[32];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) lv[u] = lp[(int64_t)u * n];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                for (int u = 0; u < 32; ++u) sacc[c] = __builtin_fma(lv[u], xv[c][m + u], sacc[c]);
+        }
+        for (; m < me; ++m, lp += n) {
+            const double lv = *lp;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) sacc[c] = __builtin_fma(lv, xv[c][m], sacc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) red[wave][c][lane] = sacc[c];
+        __syncthreads();
+        if (wave == 0 && ok)
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+                acc[c * lda + col] -= ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Host launchers.
 // ---------------------------------------------------------------------------------------
 
@@ -907,6 +1194,71 @@ hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, in
         else
             hipLaunchKernelGGL(lm_trsv_bwd_kernel<3>, g, dim3(256), 0, st, L, Linv, n, nb, k, y, ldy);
     }
+    return hipGetLastError();
+}
+
+bool dense_super_default(int64_t n) { return dense_panels(n) > kSuper; }
+
+hipError_t launch_dense_super(const double* L, const double* Linv, int64_t n, double* W, hipStream_t st)
+{
+    const int nb = dense_panels(n), ns = super_count(n);
+    for (int d = 1; d < kSuper && d < nb; ++d) {
+        const dim3 g((unsigned)(ns * (kSuper - d)));
+        hipLaunchKernelGGL(lm_super_s_kernel, g, dim3(256), 0, st, L, Linv, W, n, nb, ns, d);
+        hipLaunchKernelGGL(lm_super_w_kernel, g, dim3(256), 0, st, Linv, W, n, nb, ns, d);
+    }
+    return hipGetLastError();
+}
+
+template <int DIM>
+static void super_sweeps(const double* L, const double* Linv, const double* W, int64_t n, double* y, int64_t ldy,
+                         double* scratch, hipStream_t st)
+{
+    const int nb = dense_panels(n), ns = super_count(n);
+    double* z = scratch;                 // DIM x n, leading dimension n
+    double* part = scratch + 3 * n;      // kSuperProds x DIM x kPanel
+    auto groups = [](int64_t cols) -> unsigned {
+        const int64_t g = (cols + 63) / 64;
+        return (unsigned)(g < 2048 ? g : 2048);
+    };
+    // forward: L z = y (y is the accumulator)
+    for (int s = 0; s < ns; ++s) {
+        const int64_t b0 = (int64_t)s * kSuper;
+        const int q = (int)((nb - b0) < kSuper ? (nb - b0) : kSuper);
+        const int64_t m0 = b0 * kPanel;
+        const int w = (int)((n - m0) < (int64_t)q * kPanel ? (n - m0) : (int64_t)q * kPanel);
+        hipLaunchKernelGGL((lm_super_prod_kernel<DIM, false>), dim3(q * (q + 1) / 2), dim3(256), 0, st, Linv, W, n,
+                           nb, ns, (int64_t)s, (const double*)y, ldy, part);
+        hipLaunchKernelGGL((lm_super_sum_kernel<DIM, false>), dim3(q), dim3(kPanel), 0, st, n, (int64_t)s, q,
+                           (const double*)part, z, n);
+        const int64_t c0 = m0 + w;
+        if (c0 < n)
+            hipLaunchKernelGGL(lm_super_rows_kernel<DIM>, dim3(groups(n - c0)), dim3(256), 0, st, L, n, m0, w,
+                               (const double*)z, n, y, ldy, c0, n);
+    }
+    // backward: L^T x = z (z is the accumulator, x goes to y)
+    for (int s = ns - 1; s >= 0; --s) {
+        const int64_t b0 = (int64_t)s * kSuper;
+        const int q = (int)((nb - b0) < kSuper ? (nb - b0) : kSuper);
+        const int64_t m0 = b0 * kPanel;
+        const int w = (int)((n - m0) < (int64_t)q * kPanel ? (n - m0) : (int64_t)q * kPanel);
+        hipLaunchKernelGGL((lm_super_prod_kernel<DIM, true>), dim3(q * (q + 1) / 2), dim3(256), 0, st, Linv, W, n,
+                           nb, ns, (int64_t)s, (const double*)z, n, part);
+        hipLaunchKernelGGL((lm_super_sum_kernel<DIM, true>), dim3(q), dim3(kPanel), 0, st, n, (int64_t)s, q,
+                           (const double*)part, y, ldy);
+        if (m0 > 0)
+            hipLaunchKernelGGL(lm_super_rows_kernel<DIM>, dim3(groups(m0)), dim3(256), 0, st, L, n, m0, w,
+                               (const double*)y, ldy, z, n, (int64_t)0, m0);
+    }
+}
+
+hipError_t launch_dense_solve_super(const double* L, const double* Linv, const double* W, int64_t n, int dim,
+                                    double* y, int64_t ldy, double* scratch, hipStream_t st)
+{
+    if (dim == 2)
+        super_sweeps<2>(L, Linv, W, n, y, ldy, scratch, st);
+    else
+        super_sweeps<3>(L, Linv, W, n, y, ldy, scratch, st);
     return hipGetLastError();
 }
 

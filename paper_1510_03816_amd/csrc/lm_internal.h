@@ -295,6 +295,17 @@ hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const
 // y <- (L L^T)^{-1} y for dim component vectors (component c at y + c * ldy), in place.
 hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, int dim, double* y, int64_t ldy,
                               hipStream_t st);
+// Superblock sweeps (three launches per 8 diagonal blocks instead of one per block): the
+// inverses of the factor's diagonal superblocks (dense_super_elems doubles, built by
+// launch_dense_super once the factor is done), then y <- (L L^T)^{-1} y as above with
+// dense_solve_scratch_elems doubles of scratch.  dense_super_default: whether n has more
+// than one superblock.
+int64_t dense_super_elems(int64_t n);
+int64_t dense_solve_scratch_elems(int64_t n);
+bool dense_super_default(int64_t n);
+hipError_t launch_dense_super(const double* L, const double* Linv, int64_t n, double* W, hipStream_t st);
+hipError_t launch_dense_solve_super(const double* L, const double* Linv, const double* W, int64_t n, int dim,
+                                    double* y, int64_t ldy, double* scratch, hipStream_t st);
 
 // Batched solves, one workgroup per flagged problem (every flagged problem must have at most
 // batch_solve_max() points): y_b <- (L_b L_b^T)^{-1} y_b in the batch's (dim, ntot) layout.

@@ -515,13 +515,18 @@ def test_feedback_cutoff_matches_exact_iteration():
     assert rel_err(host(p0), ref.p0) <= 1e-8
 
 
+@pytest.mark.parametrize("sweeps", ["block", "super"])
 @pytest.mark.parametrize("n,dim,kernel,sigma,tau", [
     (1, 2, 0, 0.5, 0.0), (127, 2, 0, 0.5, 0.0), (128, 3, 1, 0.4, 0.0), (129, 2, 0, 0.2, 0.3),
-    (333, 3, 0, 0.3, 0.0), (1000, 2, 0, 0.1, 0.0), (2500, 3, 0, 0.15, 0.1),
+    (333, 3, 0, 0.3, 0.0), (1000, 2, 0, 0.1, 0.0), (1024, 3, 0, 0.15, 0.0), (1100, 3, 1, 0.1, 0.05),
+    (2500, 3, 0, 0.15, 0.1), (3072, 2, 0, 0.1, 0.0),
 ])
-def test_dense_ksolve_matches_cholesky(n, dim, kernel, sigma, tau):
+def test_dense_ksolve_matches_cholesky(n, dim, kernel, sigma, tau, sweeps, monkeypatch):
     """Blocked GPU Cholesky (MFMA trailing updates) against the oracle's textbook Cholesky,
-    across panel boundaries and ragged tails."""
+    across panel boundaries and ragged tails, with both solve forms: one launch per 128-row
+    block, and superblocks of 8 blocks through their stored inverses (forced on at every size
+    here: one superblock up to 1024 points, a ragged second from 1025)."""
+    monkeypatch.setenv("LM_DENSE_SUPER", "1" if sweeps == "super" else "0")
     X = inputs.fibonacci_sphere(n) if dim == 3 else inputs.config_curve2d(n).X
     b = np.random.default_rng([109, n]).standard_normal(X.shape)
     K = oracle.kmatrix(X, kernel, sigma) + tau * np.eye(n)
@@ -531,15 +536,19 @@ def test_dense_ksolve_matches_cholesky(n, dim, kernel, sigma, tau):
     prm = lm.make_params(dim, kernel, sigma, tau=tau)
     x = dev(b)
     lm.lm_ksolve(prm, dev(X), x, x, solver=lm.SOLVE_DENSE)       # in place
-    cond = np.linalg.cond(K) if n <= 1000 else 1e4
+    ev = np.linalg.eigvalsh(K)          # K is symmetric positive definite
+    cond = ev[-1] / ev[0]
     err = rel_err(host(x), want)
     print("n=%d cond %.1e dense rel err %.2e" % (n, cond, err))
     assert err <= max(1e-12, 1e-15 * cond)
 
 
-def test_dense_ksolve_several_trailing_updates_matches_cg():
+@pytest.mark.parametrize("sweeps", ["block", "super"])
+def test_dense_ksolve_several_trailing_updates_matches_cg(sweeps, monkeypatch):
     """N = 5000: three trailing updates on 128 x 128 tiles (the last tile row ragged), checked
-    against conjugate gradients on the same system (matrix-free, through the pair kernel)."""
+    against conjugate gradients on the same system (matrix-free, through the pair kernel);
+    both solve forms (superblocks: five, the last ragged)."""
+    monkeypatch.setenv("LM_DENSE_SUPER", "1" if sweeps == "super" else "0")
     n = 5000
     X = inputs.fibonacci_sphere(n)
     b = np.random.default_rng([113, n]).standard_normal(X.shape)
