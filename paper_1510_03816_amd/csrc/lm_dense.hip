@@ -1068,7 +1068,12 @@ __global__ __launch_bounds__(256) void lm_super_rows_kernel(const double* __rest
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q4 = (w + 3) / 4;
     const int mb = wave * q4, me = (mb + q4 < w) ? mb + q4 : w;
-    for (int64_t cb = c0 + (int64_t)blockIdx.x * 64; cb < c1; cb += (int64_t)gridDim.x * 64) {
+    // workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous run of column
+    // groups, so that the row segments one XCD streams at a time are adjacent (9.9 -> 9.3 ms
+    // per solve at N = 65536 against the plain order)
+    const unsigned G = gridDim.x;
+    const unsigned grp = (G % 8u == 0u) ? (blockIdx.x % 8u) * (G / 8u) + blockIdx.x / 8u : blockIdx.x;
+    for (int64_t cb = c0 + (int64_t)grp * 64; cb < c1; cb += (int64_t)G * 64) {
         const int64_t col = cb + lane;
         const bool ok = col < c1;
         const double* lp = L + (m0 + mb) * n + (ok ? col : cb);
