@@ -392,6 +392,50 @@ struct SideStreams {
     }
 };
 
+// One side stream that forks from and joins a parent stream, as often as needed.
+struct ForkJoin {
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    lm_status init()
+    {
+        LM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        LM_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+        LM_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+        return LM_OK;
+    }
+    lm_status fork(hipStream_t st)
+    {
+        LM_HIP(hipEventRecord(a, st));
+        LM_HIP(hipStreamWaitEvent(s, a, 0));
+        return LM_OK;
+    }
+    lm_status join(hipStream_t st)
+    {
+        LM_HIP(hipEventRecord(b, s));
+        LM_HIP(hipStreamWaitEvent(st, b, 0));
+        return LM_OK;
+    }
+    ~ForkJoin()
+    {
+        if (s) (void)hipStreamSynchronize(s);
+        if (s) (void)hipStreamDestroy(s);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Size above which a batched match solves a problem with the wide sweeps (many workgroups)
+// rather than in lm_batch_solve_kernel (one workgroup); LM_BATCH_WIDE_MIN overrides it.
+// Never above the one-workgroup kernel's limit.
+constexpr int64_t kBatchWideMin = 1024;
+
+int64_t batch_wide_min()
+{
+    int64_t v = kBatchWideMin;
+    if (const char* e = std::getenv("LM_BATCH_WIDE_MIN")) v = std::max(0L, std::strtol(e, nullptr, 10));
+    return std::min<int64_t>(v, lm::batch_solve_max());
+}
+
 // A captured sequence of RK4 steps, replayable on any stream.  The executable graph is
 // destroyed only after the stream it was last launched on has drained, also when an error
 // ends the call between two launches.
@@ -713,12 +757,12 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         if (fi[b] != 0) stat[b] = LM_ESINGULAR;
 
     double *qd, *pd, *e, *resid_d;
-    int *flags_d;   // 3 x B: problems updated, batched solves, single-precision results
+    int *flags_d;   // 4 x B: problems updated, one-workgroup solves, single-precision results, wide solves
     LM_TRY(ws.get(&qd, m));
     LM_TRY(ws.get(&pd, m));
     LM_TRY(ws.get(&e, m));
     LM_TRY(ws.get(&resid_d, B));
-    LM_TRY(ws.get(&flags_d, 3 * (int64_t)B));
+    LM_TRY(ws.get(&flags_d, 4 * (int64_t)B));
     float *xf = nullptr, *qf = nullptr, *pf = nullptr;
     ShootBufs<double> wd{};
     ShootBufs<float> wf{};
@@ -730,10 +774,11 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         LM_TRY(wf.alloc(ws, m));
         LM_HIP((lm::launch_convert<float, double>(xf, X, m, st)));
     }
-    std::vector<int> flags((size_t)3 * B, 0);
+    std::vector<int> flags((size_t)4 * B, 0);
     int* upd_f = flags.data();
     int* solve_f = flags.data() + B;
     int* f32_f = flags.data() + 2 * B;
+    int* wide_f = flags.data() + 3 * B;
 
     // work lists of the problems shot in each precision, rebuilt when those sets change
     std::vector<int> in64((size_t)B, -1), in32((size_t)B, -1);
@@ -741,7 +786,24 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
     std::unique_ptr<Workspace> pws64, pws32;
     BatchPlan pl64, pl32;
     StepGraph g64, g32;
-    const int smax = lm::batch_solve_max();
+    // problems above wide_min points are solved by the batched wide sweeps (many workgroups
+    // per problem), on the match's stream, while lm_batch_solve_kernel takes the rest on a
+    // side stream
+    const int64_t wide_min = batch_wide_min();
+    std::vector<int> wide_probs;
+    for (int32_t b = 0; b < B; ++b)
+        if (offs[b + 1] - offs[b] > wide_min && fi[b] == 0) wide_probs.push_back(b);
+    lm::BatchWidePlan wplan;
+    int4* witems = nullptr;
+    ForkJoin fj;
+    if (!wide_probs.empty()) {
+        lm::batch_wide_plan(offs, wide_probs, &wplan);
+        LM_TRY(ws.get(&witems, (int64_t)wplan.items.size()));
+        LM_HIP(hipMemcpyAsync(witems, wplan.items.data(), wplan.items.size() * sizeof(int4), hipMemcpyHostToDevice,
+                              st));
+        LM_HIP(hipStreamSynchronize(st));   // the host list dies with this call's frame
+        LM_TRY(fj.init());
+    }
 
     for (;;) {
         std::vector<int> want64((size_t)B), want32((size_t)B);
@@ -793,6 +855,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         for (int32_t b = 0; b < B; ++b) {
             upd_f[b] = 0;
             solve_f[b] = 0;
+            wide_f[b] = 0;
             const bool shot = want64[b] || want32[b];
             if (!shot) continue;
             info[b].resid_inf = res[b];
@@ -819,7 +882,8 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
             }
             if (upd_f[b]) {
                 any_update = true;
-                solve_f[b] = (offs[b + 1] - offs[b]) <= smax;
+                solve_f[b] = (offs[b + 1] - offs[b]) <= wide_min;
+                wide_f[b] = !solve_f[b];
             }
         }
         bool running = false;
@@ -831,11 +895,16 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         LM_HIP(hipEventRecord(tm.ev[2], st));
         LM_HIP(lm::launch_sub(e, Y, qd, m, st));
         LM_HIP(hipMemcpyAsync(flags_d, flags.data(), 2 * B * sizeof(int), hipMemcpyHostToDevice, st));
-        LM_HIP(lm::launch_batch_dense_solve(L, loff_d, Linv, ioff_d, offs_d, B, dim, ntot, e, flags_d + B, st));
-        for (int32_t b = 0; b < B; ++b) {
-            if (!upd_f[b] || solve_f[b]) continue;
-            const int64_t nb = offs[b + 1] - offs[b];
-            LM_HIP(lm::launch_dense_solve(L + loff[b], Linv + ioff[b], nb, dim, e + offs[b], ntot, st));
+        LM_HIP(hipMemcpyAsync(flags_d + 3 * B, wide_f, B * sizeof(int), hipMemcpyHostToDevice, st));
+        if (witems) {
+            // disjoint problems: the one-workgroup solves on the side stream, the wide sweeps here
+            LM_TRY(fj.fork(st));
+            LM_HIP(lm::launch_batch_dense_solve(L, loff_d, Linv, ioff_d, offs_d, B, dim, ntot, e, flags_d + B, fj.s));
+            LM_HIP(lm::launch_batch_wide_solve(L, loff_d, Linv, ioff_d, offs_d, dim, ntot, e, flags_d + 3 * B, witems,
+                                               wplan, st));
+            LM_TRY(fj.join(st));
+        } else {
+            LM_HIP(lm::launch_batch_dense_solve(L, loff_d, Linv, ioff_d, offs_d, B, dim, ntot, e, flags_d + B, st));
         }
         LM_HIP(lm::launch_batch_axpy(p, e, o->h, dim, ntot, offs_d, flags_d, B, st));
         LM_HIP(hipEventRecord(tm.ev[3], st));

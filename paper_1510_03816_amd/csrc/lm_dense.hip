@@ -27,6 +27,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "lm_internal.h"
 #include "lm_math.h"
 
@@ -813,6 +816,221 @@ hipError_t launch_batch_dense_solve(const double* L, const int64_t* loff, const 
     else
         hipLaunchKernelGGL(lm_batch_solve_kernel<3>, dim3(nprob), dim3(256), 0, st, L, loff, Linv, ioff, offs, ntot, y,
                            flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched wide sweeps: the per-block sweeps above for many problems at once, so that a large
+// problem of a batch is streamed by many workgroups rather than by the one workgroup of
+// lm_batch_solve_kernel (whose loads in flight bound one problem's sweep at about 31 GB/s).
+// Launch k of the forward sweep serves every listed problem with more than k + 1 blocks:
+// item (b, 0) owns block k+1 (its rows take panel k, then the block's finish with the stored
+// inverse), item (b, 1, r) takes the 64 rows r .. r+63 (in blocks k+2 ..) and panel k.
+// Launch k of the backward sweep: item (b, 0) subtracts block row k from block k-1 and
+// finishes it, item (b, 1, c) takes the 256 columns c .. c+255 (in blocks 0 .. k-2) and block
+// row k.  Items of a problem whose flag is 0 do nothing.  A persistent grid walks the
+// launch's list, owners first.
+// ---------------------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(256) void lm_batch_trsv_fwd_kernel(const double* __restrict__ L,
+                                                                const int64_t* __restrict__ loff,
+                                                                const double* __restrict__ Linv,
+                                                                const int64_t* __restrict__ ioff,
+                                                                const int64_t* __restrict__ offs, int64_t ntot,
+                                                                double* __restrict__ y, const int* __restrict__ flag,
+                                                                const int4* __restrict__ items, int nitems, int64_t k)
+{
+    __shared__ double sh[3 * kPanel];
+    __shared__ double yk[3 * kPanel];
+    __shared__ double red[4][3][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        if (!flag[w.x]) continue;
+        const int64_t off = offs[w.x], n = offs[w.x + 1] - off;
+        const int nb = (int)((n + kPanel - 1) / kPanel);
+        const double* Lb = L + loff[w.x];
+        double* yb = y + off;
+        __syncthreads();   // the previous item is done with yk and sh
+        if (k >= 0) {
+            const int64_t k0 = k * kPanel;
+            for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
+                const int c = e / kPanel, m = e % kPanel;
+                yk[e] = (k0 + m < n) ? yb[c * ntot + k0 + m] : 0.0;
+            }
+            __syncthreads();
+            int64_t rbeg, rend;
+            if (w.y == 0) {
+                rbeg = (k + 1) * kPanel;
+                rend = (k + 2) * kPanel < n ? (k + 2) * kPanel : n;
+            } else {
+                rbeg = w.z;
+                rend = w.z + 64 < n ? w.z + 64 : n;
+            }
+            const int m0 = wave * 32;
+            for (int64_t rb = rbeg; rb < rend; rb += 64) {
+                const int64_t r = rb + lane;
+                const bool ok = r < rend;
+                const double* lt = Lb + (k0 + m0) * n + (ok ? r : rb);
+                double lv[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) lv[u] = (k0 + m0 + u < n) ? lt[(int64_t)u * n] : 0.0;
+                double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) s[c] = __builtin_fma(lv[u], yk[c * kPanel + m0 + u], s[c]);
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) red[wave][c][lane] = s[c];
+                __syncthreads();
+                if (wave == 0 && ok)
+                    for (int c = 0; c < DIM; ++c)
+                        yb[c * ntot + r] -= ((red[0][c][lane] + red[1][c][lane]) + red[2][c][lane]) + red[3][c][lane];
+                __syncthreads();
+            }
+        }
+        if (w.y == 0) {
+            __threadfence_block();
+            __syncthreads();
+            finish_block<false, DIM>(Linv + ioff[w.x], n, nb, k + 1, yb, ntot, sh, yk);
+        }
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void lm_batch_trsv_bwd_kernel(const double* __restrict__ L,
+                                                                const int64_t* __restrict__ loff,
+                                                                const double* __restrict__ Linv,
+                                                                const int64_t* __restrict__ ioff,
+                                                                const int64_t* __restrict__ offs, int64_t ntot,
+                                                                double* __restrict__ y, const int* __restrict__ flag,
+                                                                const int4* __restrict__ items, int nitems, int64_t k)
+{
+    __shared__ double sh[3 * kPanel];
+    __shared__ double xk[3 * kPanel];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        if (!flag[w.x]) continue;
+        const int64_t off = offs[w.x], n = offs[w.x + 1] - off;
+        const int nb = (int)((n + kPanel - 1) / kPanel);
+        const double* Lb = L + loff[w.x];
+        double* yb = y + off;
+        __syncthreads();   // the previous item is done with xk and sh
+        if (k < nb) {
+            const int64_t k0 = k * kPanel;
+            const int bs = (int)((n - k0) < kPanel ? (n - k0) : kPanel);
+            for (int e = threadIdx.x; e < DIM * kPanel; e += blockDim.x) {
+                const int c = e / kPanel, m = e % kPanel;
+                xk[e] = m < bs ? yb[c * ntot + k0 + m] : 0.0;
+            }
+            __syncthreads();
+            if (w.y == 0) {
+                const int r = threadIdx.x & (kPanel - 1), h = threadIdx.x >> 7;
+                const int64_t col = (k - 1) * kPanel + r;
+                const double* lc = Lb + (k0 + h * 64) * n + col;
+                double s[3] = {0.0, 0.0, 0.0};
+                for (int m0 = 0; m0 < 64; m0 += 16) {
+                    double lv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int m = h * 64 + m0 + u;
+                        lv[u] = m < bs ? lc[(int64_t)(m0 + u) * n] : 0.0;
+                    }
+                    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                        for (int u = 0; u < 16; ++u)
+                            s[c] = __builtin_fma(lv[u], xk[c * kPanel + h * 64 + m0 + u], s[c]);
+                }
+                if (h == 1)
+                    for (int c = 0; c < DIM; ++c) sh[c * kPanel + r] = s[c];
+                __syncthreads();
+                if (h == 0)
+                    for (int c = 0; c < DIM; ++c) yb[c * ntot + col] -= s[c] + sh[c * kPanel + r];
+            } else {
+                const int64_t cend = (k - 1) * kPanel;
+                const int64_t col = w.z + threadIdx.x;
+                if (col < cend) {
+                    double s[3] = {0.0, 0.0, 0.0};
+                    const double* lc = Lb + k0 * n + col;
+                    for (int m0 = 0; m0 < kPanel; m0 += 16) {
+                        double lv[16];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) lv[u] = (m0 + u < bs) ? lc[(int64_t)(m0 + u) * n] : 0.0;
+                        for (int c = 0; c < DIM; ++c)
+#pragma unroll
+                            for (int u = 0; u < 16; ++u) s[c] = __builtin_fma(lv[u], xk[c * kPanel + m0 + u], s[c]);
+                    }
+                    for (int c = 0; c < DIM; ++c) yb[c * ntot + col] -= s[c];
+                }
+            }
+        }
+        if (w.y == 0) {
+            __threadfence_block();
+            __syncthreads();
+            finish_block<true, DIM>(Linv + ioff[w.x], n, nb, k - 1, yb, ntot, sh, xk);
+        }
+    }
+}
+
+void batch_wide_plan(const int64_t* offs, const std::vector<int>& probs, BatchWidePlan* pl)
+{
+    pl->items.clear();
+    int maxnb = 0;
+    for (int b : probs) maxnb = std::max(maxnb, dense_panels(offs[b + 1] - offs[b]));
+    pl->maxnb = maxnb;
+    pl->fwd.assign((size_t)maxnb + 1, 0);
+    pl->bwd.assign((size_t)maxnb + 1, 0);
+    // forward launch k = -1 .. maxnb - 2 (list k + 1)
+    for (int k = -1; k <= maxnb - 2; ++k) {
+        pl->fwd[k + 1] = (int)pl->items.size();
+        for (int b : probs)
+            if (k + 1 < dense_panels(offs[b + 1] - offs[b])) pl->items.push_back(make_int4(b, 0, 0, 0));
+        if (k >= 0)
+            for (int b : probs) {
+                const int64_t n = offs[b + 1] - offs[b];
+                for (int64_t r = (int64_t)(k + 2) * kPanel; r < n; r += 64) pl->items.push_back(make_int4(b, 1, (int)r, 0));
+            }
+    }
+    pl->fwd[maxnb] = (int)pl->items.size();
+    // backward launch k = maxnb .. 1 (list maxnb - k)
+    for (int k = maxnb; k >= 1; --k) {
+        pl->bwd[maxnb - k] = (int)pl->items.size();
+        for (int b : probs)
+            if (k <= dense_panels(offs[b + 1] - offs[b])) pl->items.push_back(make_int4(b, 0, 0, 0));
+        for (int b : probs) {
+            const int nbb = dense_panels(offs[b + 1] - offs[b]);
+            if (k >= nbb) continue;
+            for (int64_t c = 0; c < (int64_t)(k - 1) * kPanel; c += 256) pl->items.push_back(make_int4(b, 1, (int)c, 0));
+        }
+    }
+    pl->bwd[maxnb] = (int)pl->items.size();
+}
+
+hipError_t launch_batch_wide_solve(const double* L, const int64_t* loff, const double* Linv, const int64_t* ioff,
+                                   const int64_t* offs, int dim, int64_t ntot, double* y, const int* flag,
+                                   const int4* items, const BatchWidePlan& pl, hipStream_t st)
+{
+    auto grid = [](int cnt) { return dim3((unsigned)(cnt < 2048 ? cnt : 2048)); };
+    for (int k = -1; k <= pl.maxnb - 2; ++k) {
+        const int a = pl.fwd[k + 1], cnt = pl.fwd[k + 2] - a;
+        if (cnt <= 0) continue;
+        if (dim == 2)
+            hipLaunchKernelGGL(lm_batch_trsv_fwd_kernel<2>, grid(cnt), dim3(256), 0, st, L, loff, Linv, ioff, offs, ntot,
+                               y, flag, items + a, cnt, (int64_t)k);
+        else
+            hipLaunchKernelGGL(lm_batch_trsv_fwd_kernel<3>, grid(cnt), dim3(256), 0, st, L, loff, Linv, ioff, offs, ntot,
+                               y, flag, items + a, cnt, (int64_t)k);
+    }
+    for (int k = pl.maxnb; k >= 1; --k) {
+        const int a = pl.bwd[pl.maxnb - k], cnt = pl.bwd[pl.maxnb - k + 1] - a;
+        if (cnt <= 0) continue;
+        if (dim == 2)
+            hipLaunchKernelGGL(lm_batch_trsv_bwd_kernel<2>, grid(cnt), dim3(256), 0, st, L, loff, Linv, ioff, offs, ntot,
+                               y, flag, items + a, cnt, (int64_t)k);
+        else
+            hipLaunchKernelGGL(lm_batch_trsv_bwd_kernel<3>, grid(cnt), dim3(256), 0, st, L, loff, Linv, ioff, offs, ntot,
+                               y, flag, items + a, cnt, (int64_t)k);
+    }
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/liblm.h"
 
 namespace lm {
@@ -313,6 +315,20 @@ int batch_solve_max();
 hipError_t launch_batch_dense_solve(const double* L, const int64_t* loff, const double* Linv, const int64_t* ioff,
                                     const int64_t* offs, int nprob, int dim, int64_t ntot, double* y, const int* flag,
                                     hipStream_t st);
+
+// Batched wide sweeps: the per-block sweeps for many problems of a batch at once (launch k
+// serves block k of every listed problem, many workgroups per problem).  The item lists of
+// every launch are built on the host once per set of problems (batch_wide_plan) and uploaded
+// by the caller; flag[b] = 0 skips problem b.
+struct BatchWidePlan {
+    std::vector<int4> items;
+    std::vector<int> fwd, bwd;   // start of each launch's list, maxnb + 1 entries each
+    int maxnb = 0;
+};
+void batch_wide_plan(const int64_t* offs, const std::vector<int>& probs, BatchWidePlan* pl);
+hipError_t launch_batch_wide_solve(const double* L, const int64_t* loff, const double* Linv, const int64_t* ioff,
+                                   const int64_t* offs, int dim, int64_t ntot, double* y, const int* flag,
+                                   const int4* items, const BatchWidePlan& pl, hipStream_t st);
 
 int64_t tiles_of(int64_t n);     // 64-point tiles covering n points
 int64_t sort_pad(int64_t n);     // power of two >= max(n, 2)

@@ -271,11 +271,19 @@ def test_batched_feedback_switches_to_double_precision():
         assert np.max(np.abs(oq - Y[:, s])) < 1e-9
 
 
-def test_batched_feedback_multi_panel_problems_in_the_batched_solve():
-    """Problems of 1000 and 2900 points (8 and 23 diagonal blocks, ragged last blocks) go
-    through the one-workgroup batched solve, whose sweeps take their unrolled and remainder
-    loops at every block; iteration counts and momenta are the oracle's."""
-    sizes = [1000, 2900]
+@pytest.mark.parametrize("wide_min", [None, "0", "4096"])
+def test_batched_feedback_multi_panel_problems_in_the_batched_solve(wide_min, monkeypatch):
+    """Problems of 40, 1000 and 2900 points (1, 8 and 23 diagonal blocks, ragged last blocks)
+    through both batched solves: LM_BATCH_WIDE_MIN = 4096 puts all three in the one-workgroup
+    kernel (its sweeps take their unrolled and remainder loops at every block), 0 all three in
+    the wide sweeps (many workgroups per problem), the default (1024) the largest in the wide
+    sweeps beside the others in the one-workgroup kernel; iteration counts and momenta are the
+    oracle's."""
+    if wide_min is None:
+        monkeypatch.delenv("LM_BATCH_WIDE_MIN", raising=False)
+    else:
+        monkeypatch.setenv("LM_BATCH_WIDE_MIN", wide_min)
+    sizes = [40, 1000, 2900]
     parts = [inputs.config_curve2d(n, seed=[321, n]) for n in sizes]
     offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     X = np.concatenate([pr.X for pr in parts], axis=1)
@@ -285,7 +293,7 @@ def test_batched_feedback_multi_panel_problems_in_the_batched_solve():
     st, infos, stats = lm.lm_feedback_match_batched(prm, offs, dev(X), dev(Y), p0, h=0.8, tol=1e-6, steps=10,
                                                     max_iter=100)
     assert st == lm.LM_OK
-    for b in range(2):
+    for b in range(3):
         s = slice(offs[b], offs[b + 1])
         ref = oracle.feedback_match(X[:, s], Y[:, s], lm.CONON, 0.1, 0.8, 1e-6, 10, max_iter=100)
         assert ref.status == 0
@@ -293,10 +301,33 @@ def test_batched_feedback_multi_panel_problems_in_the_batched_solve():
         assert rel_err(host(p0)[:, s], ref.p0) <= 1e-8
 
 
+def test_batched_feedback_wide_solves_in_three_dimensions(monkeypatch):
+    """The wide sweeps with three components: two sphere problems of 300 and 1500 points
+    (3 and 12 blocks), every problem in the wide sweeps; iteration counts and momenta are the
+    oracle's."""
+    monkeypatch.setenv("LM_BATCH_WIDE_MIN", "0")
+    sizes = [300, 1500]
+    parts = [inputs.config_sphere3d(n, seed=[322, n], sigma=0.15) for n in sizes]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = np.concatenate([pr.X for pr in parts], axis=1)
+    Y = np.concatenate([pr.Y for pr in parts], axis=1)
+    prm = lm.make_params(3, lm.CONON, 0.15)
+    p0 = torch.zeros((3, int(offs[-1])), dtype=torch.float64, device=DEV)
+    st, infos, stats = lm.lm_feedback_match_batched(prm, offs, dev(X), dev(Y), p0, h=0.8, tol=1e-6, steps=10,
+                                                    max_iter=100)
+    assert st == lm.LM_OK, stats
+    for b in range(2):
+        s = slice(offs[b], offs[b + 1])
+        ref = oracle.feedback_match(X[:, s], Y[:, s], lm.CONON, 0.15, 0.8, 1e-6, 10, max_iter=100)
+        assert ref.status == 0
+        assert infos[b].iters == ref.iters, (b, infos[b].iters, ref.iters)
+        assert rel_err(host(p0)[:, s], ref.p0) <= 1e-8
+
+
 def test_batched_feedback_with_a_problem_too_large_for_the_batched_solve():
-    """A problem above the one-workgroup solve's limit (4096 points) is solved by the
-    blocked sweeps in place in the concatenated layout; its iteration count and momenta are
-    the oracle's, as are those of the small problem beside it."""
+    """A problem above the one-workgroup solve's limit (4096 points) is solved by the wide
+    sweeps in place in the concatenated layout; its iteration count and momenta are the
+    oracle's, as are those of the small problem beside it."""
     sizes = [40, 4100]
     parts = [inputs.config_curve2d(n, seed=[320, n]) for n in sizes]
     offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
