@@ -388,8 +388,9 @@ lm_status lm_shoot_batched(const lm_params *params, int32_t B, const int64_t *of
  * LM_EDIVERGED, LM_ESINGULAR, LM_ENOTCONV that some problem ended with.  tuning: nullable
  * (NULL = the default shape); when the problems still running would launch fewer than two
  * waves per SIMD, a shoot narrows the symmetric superblocks and splits the one-sided sources
- * further (environment LM_BATCH_FILL: waves per SIMD, 0 = keep the tuning's shape).
- * Synchronous. */
+ * further (environment LM_BATCH_FILL: waves per SIMD, 0 = keep the tuning's shape).  The
+ * solves of problems above 1024 points run across many workgroups per problem, the rest with
+ * one workgroup each (environment LM_BATCH_WIDE_MIN: the size threshold).  Synchronous. */
 lm_status lm_feedback_match_batched(const lm_params *params, const lm_match_opts *opts, int32_t B,
                                     const int64_t *offs, const double *X, const double *Y,
                                     double *p0, double *q1, lm_match_info *info, int32_t *status,
