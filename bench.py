@@ -243,7 +243,7 @@ def pair_roofline(lm, prm, n, dim, kernel, dtype, stage_ms, cutoff=0.0):
 def match_record(lm, st, info, seconds, tol, h):
     return {"seconds": seconds, "status": lm.STATUS_NAMES[st], "iters": info.iters, "resid_inf": info.resid_inf,
             "factor_ms": info.factor_ms, "shoot_ms": info.shoot_ms, "solve_ms": info.solve_ms,
-            "cg_iters": info.cg_iters, "tol": tol, "h": h, "paper_H_2H": 2 * info.H}
+            "cg_iters": info.cg_iters, "shoots": info.shoots, "tol": tol, "h": h, "paper_H_2H": 2 * info.H}
 
 
 def fp32_leg(lm, torch, dev, pr, p_np, q64_gpu, p64_gpu):
@@ -387,6 +387,7 @@ def batched_leg(lm, torch, dev, h: float, tol: float):
         out["time_to_match_" + name] = {
             "seconds": dt, "status": lm.STATUS_NAMES[st], "converged": sum(1 for s in stats if s == 0),
             "iters_max": max(its), "iters_mean": sum(its) / len(its),
+            "shoots_max": max(i.shoots for i in infos),
             "resid_max": max(i.resid_inf for i in infos), "shoot_ms": infos[0].shoot_ms,
             "solve_ms": infos[0].solve_ms, "factor_ms": infos[0].factor_ms, "tol": tol, "h": h,
             "f32_switch": sw}
@@ -552,7 +553,7 @@ def main():
                 st, info, _ = run_match(prm, pr, X, Y)
                 rec = {"status": lm.STATUS_NAMES[st], "iters": info.iters, "resid_inf": info.resid_inf,
                        "factor_ms": info.factor_ms, "shoot_ms": info.shoot_ms, "solve_ms": info.solve_ms}
-                return info.iters + 1, info.shoot_ms, info.solve_ms, info.factor_ms, rec
+                return info.shoots, info.shoot_ms, info.solve_ms, info.factor_ms, rec
             st, info = lm.lm_feedback_step(prm, X, Y, p_iter, h=args.h, tol=args.tol, steps=pr.steps,
                                            cg_max_iter=args.cg_max_iter, solver=lm.SOLVE_CG)
             rec = {"status": lm.STATUS_NAMES[st], "resid_inf": info.resid_inf, "cg_iters": info.cg_iters,
@@ -613,7 +614,7 @@ def main():
             st, info, _ = run_match(prm, pr, X, Y)
             torch.cuda.synchronize()
             r = match_record(lm, st, info, time.perf_counter() - t1, args.tol, args.h)
-            r.update(workload=args.workload, shoots=info.iters + 1)
+            r.update(workload=args.workload)
             log("time to match %s: %.2f s, %d iterations, resid %.2e" % (args.workload, r["seconds"], info.iters,
                                                                           info.resid_inf))
             return r
@@ -628,7 +629,7 @@ def main():
             st, info, _ = run_match(prm32, pr, X, Y, 1e-4)
             torch.cuda.synchronize()
             r = match_record(lm, st, info, time.perf_counter() - t1, args.tol, args.h)
-            r.update(workload=args.workload, shoots=info.iters + 1, f32_switch=1e-4)
+            r.update(workload=args.workload, f32_switch=1e-4)
             log("time to match %s, FP32 shoots switching to FP64 below 1e-4: %.2f s, %d iterations, resid %.2e" % (
                 args.workload, r["seconds"], info.iters, info.resid_inf))
             return r

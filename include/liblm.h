@@ -118,9 +118,11 @@ typedef struct lm_match_info {
     double resid_inf;     /* max_{c,i} |Y - q(1)| of the final shoot */
     double H;             /* Hamiltonian 1/2 sum_ij (p_i.p_j) G(|X_i-X_j|) at (X, p0);
                              the values the paper prints are 2H */
-    double shoot_ms;      /* GPU time of all shoots (iters + 1 of them) */
+    double shoot_ms;      /* GPU time of all shoots */
     double solve_ms;      /* GPU time of all K-solves and momentum updates */
     double factor_ms;     /* GPU time of the dense factorisation (0 with CG) */
+    int32_t shoots;       /* shoots integrated: iters + 1, less one when p0 is zero (no landmark
+                             then moves: the first shoot is the identity map, q(1) = X) */
 } lm_match_info;
 
 /* Right-hand side of the N-particle system (equation "N-particle"; with tau > 0 the inexact

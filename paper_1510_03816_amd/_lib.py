@@ -51,7 +51,7 @@ class lm_match_opts(ctypes.Structure):
 class lm_match_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32), ("resid_inf", ctypes.c_double),
                 ("H", ctypes.c_double), ("shoot_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
-                ("factor_ms", ctypes.c_double)]
+                ("factor_ms", ctypes.c_double), ("shoots", ctypes.c_int32)]
 
 
 class lm_plan_info(ctypes.Structure):

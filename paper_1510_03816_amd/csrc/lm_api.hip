@@ -667,15 +667,20 @@ struct FeedbackWork {
 
 // Algorithm 1, steps 1-2: q(1) of the shoot from (X, p) into w.q1, and r = max |Y - q(1)|
 // (read back to the host: it decides the next launch).
+// still: p is zero, so no landmark moves and q(1) = X (the double-precision RK4 steps give
+// exactly that: every increment is a sum of products with a zero momentum); the shoot is then
+// not integrated.
 lm_status feedback_shoot_residual(const lm_params* prm, const lm_match_opts* o, int64_t n, const double* X,
                                   const double* Y, const double* p, FeedbackWork& w, double* r, hipStream_t st,
-                                  hipEvent_t after_shoot = nullptr)
+                                  hipEvent_t after_shoot = nullptr, bool still = false)
 {
     const int dim = prm->dim;
     const int64_t m = (int64_t)dim * n;
     const int64_t* perm = w.ord.perm;
     double* box = w.ordered ? w.ord.box : nullptr;
-    if (prm->dtype == LM_F32) {
+    if (still) {
+        LM_HIP(hipMemcpyAsync(w.q1, X, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else if (prm->dtype == LM_F32) {
         // single-precision shoot; the momenta, the residual and the solve stay in double
         if (w.ordered) {
             LM_HIP((lm::launch_permute<float, double>(w.qf, X, perm, n, dim, false, st)));
@@ -1307,11 +1312,25 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
     p64.dtype = LM_F64;
     const bool may_switch = prm->dtype == LM_F32 && o->f32_switch > 0.0;
     bool fp64 = prm->dtype == LM_F64;
+    // zero initial momenta (the paper's starting guess): the first shoot is the identity map
+    bool still = false;
+    {
+        const int64_t m = (int64_t)prm->dim * n;
+        double pmax = 1.0;
+        LM_HIP(lm::launch_zero(w.delta, m, st));
+        LM_HIP((lm::launch_maxabsdiff<double, double>(p0, w.delta, m, w.red, w.rdev, st)));
+        LM_HIP(hipMemcpyAsync(&pmax, w.rdev, sizeof(double), hipMemcpyDeviceToHost, st));
+        LM_HIP(hipStreamSynchronize(st));
+        still = pmax == 0.0;
+
+    }
     for (int32_t shot = 0;; ++shot) {
         // Algorithm 1, steps 1-2: shoot (X, p) to t = 1, residual r = max |Y - q(1)|
         LM_HIP(hipEventRecord(timer.ev[0], st));
-        LM_TRY(feedback_shoot_residual(fp64 ? &p64 : prm, o, n, X, Y, p0, w, &r, st, timer.ev[1]));
+        LM_TRY(feedback_shoot_residual(fp64 ? &p64 : prm, o, n, X, Y, p0, w, &r, st, timer.ev[1],
+                                       shot == 0 && still));
         info->shoot_ms += timer.ms(0, 1);
+        if (!(shot == 0 && still)) ++info->shoots;
         if (shot < o->hist_len) o->resid_hist[shot] = r;
         if (!is_finite(r)) {
             result = fail(LM_EDIVERGED, "feedback iteration %d: non-finite residual", k);

@@ -805,12 +805,27 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         LM_TRY(fj.init());
     }
 
+    // problems starting from zero momenta (the paper's starting guess) do not move: their
+    // first shoot is the identity map, q(1) = X, and is not integrated
+    std::vector<int> still((size_t)B, 0), nshoot((size_t)B, 0);
+    {
+        std::vector<double> pm((size_t)B, 1.0);
+        LM_HIP(lm::launch_zero(e, m, st));
+        LM_HIP(lm::launch_batch_maxabsdiff<double>(p, e, dim, ntot, offs_d, B, resid_d, st));
+        LM_HIP(hipMemcpyAsync(pm.data(), resid_d, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        LM_HIP(hipStreamSynchronize(st));
+        for (int32_t b = 0; b < B; ++b) still[b] = pm[b] == 0.0;
+    }
+    bool first = true;
+
     for (;;) {
         std::vector<int> want64((size_t)B), want32((size_t)B);
         bool any64 = false, any32 = false;
         for (int32_t b = 0; b < B; ++b) {
-            want64[b] = stat[b] == -1 && prec[b] == 1;
-            want32[b] = stat[b] == -1 && prec[b] == 0;
+            const bool moving = !(first && still[b]);
+            want64[b] = stat[b] == -1 && prec[b] == 1 && moving;
+            want32[b] = stat[b] == -1 && prec[b] == 0 && moving;
+            nshoot[b] += want64[b] || want32[b];
             any64 = any64 || want64[b];
             any32 = any32 || want32[b];
         }
@@ -830,8 +845,8 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         // shoot every running problem from (X, p): double-precision ones in place on qd,
         // single-precision ones on qf, copied into qd afterwards
         LM_HIP(hipEventRecord(tm.ev[0], st));
+        if (any64 || first) LM_HIP(hipMemcpyAsync(qd, X, m * sizeof(double), hipMemcpyDeviceToDevice, st));
         if (any64) {
-            LM_HIP(hipMemcpyAsync(qd, X, m * sizeof(double), hipMemcpyDeviceToDevice, st));
             LM_HIP(hipMemcpyAsync(pd, p, m * sizeof(double), hipMemcpyDeviceToDevice, st));
             LM_TRY(batch_shoot_inplace<double>(&p64, pl64, qd, pd, 1.0, o->steps, tun.graph_steps, wd, st, &g64));
         }
@@ -856,7 +871,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
             upd_f[b] = 0;
             solve_f[b] = 0;
             wide_f[b] = 0;
-            const bool shot = want64[b] || want32[b];
+            const bool shot = want64[b] || want32[b] || (first && still[b] && stat[b] == -1);
             if (!shot) continue;
             info[b].resid_inf = res[b];
             bool hold = false;
@@ -886,6 +901,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
                 wide_f[b] = !solve_f[b];
             }
         }
+        first = false;
         bool running = false;
         for (int32_t b = 0; b < B; ++b) running = running || stat[b] == -1;
         if (!running) break;
@@ -956,6 +972,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         info[b].shoot_ms = shoot_ms;
         info[b].solve_ms = solve_ms;
         info[b].factor_ms = factor_ms;
+        info[b].shoots = nshoot[b];
         if (stat[b] == LM_ESINGULAR) info[b].resid_inf = NAN;
         if (status) status[b] = stat[b];
     }

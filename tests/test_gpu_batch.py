@@ -200,6 +200,7 @@ def test_batched_feedback_matches_oracle_per_problem(fill, monkeypatch):
         ref = oracle.feedback_match(X[:, s], Y[:, s], lm.CONON, 0.1, 0.8, 1e-6, 20, max_iter=200)
         assert ref.status == 0
         assert infos[b].iters == ref.iters, (b, infos[b].iters, ref.iters)
+        assert infos[b].shoots == infos[b].iters     # from rest: the first shoot is the identity map
         assert abs(infos[b].resid_inf - ref.resid) <= 1e-9
         assert rel_err(gp[:, s], ref.p0) <= 1e-8
         assert rel_err(gq[:, s], ref.q1) <= 1e-10

@@ -338,6 +338,41 @@ def test_feedback_single_precision_shoot():
     assert rel_err(p0, ref.p0) <= 1e-4
 
 
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+def test_match_from_rest_does_not_integrate_the_first_shoot(dtype):
+    """Zero initial momenta (Algorithm 1's start) leave every landmark at rest, every term of
+    the right-hand side having a momentum factor, so the first shoot is the identity map: the
+    match integrates one shoot fewer than its updates + 1, its first residual is max|Y - X|
+    exactly, and its iteration count and momenta are the oracle's, which integrates that
+    shoot (FP32, on the well-conditioned circle -> ellipse as the single-precision test above:
+    the oracle's count or one more, momenta to 1e-4).  From non-zero momenta every shoot is
+    integrated."""
+    if dtype == lm.F64:
+        pr, tol, steps = inputs.config_curve2d(700), 1e-6, 40
+    else:
+        pr, tol = inputs.config_circle_ellipse(64), 1e-5
+        steps = pr.steps
+    prm = lm.make_params(2, lm.CONON, pr.sigma, dtype=dtype)
+    p0 = torch.zeros((2, pr.n), dtype=torch.float64, device=DEV)
+    st, info, hist = lm.lm_feedback_match(prm, dev(pr.X), dev(pr.Y), p0, h=0.8, tol=tol, steps=steps,
+                                          max_iter=200)
+    ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, tol, steps, max_iter=200)
+    assert st == 0 and ref.status == 0
+    assert info.shoots == info.iters
+    assert hist[0] == np.max(np.abs(pr.Y - pr.X))
+    if dtype == lm.F64:
+        assert info.iters == ref.iters
+        assert rel_err(host(p0), ref.p0) <= 1e-8
+    else:
+        assert 0 <= info.iters - ref.iters <= 1
+        assert rel_err(host(p0), ref.p0) <= 1e-4
+    p_start = dev(0.5 * ref.p0)
+    st2, info2, hist2 = lm.lm_feedback_match(prm, dev(pr.X), dev(pr.Y), p_start, h=0.8, tol=tol, steps=steps,
+                                             max_iter=200)
+    assert st2 == 0
+    assert info2.shoots == info2.iters + 1 == len(hist2)
+
+
 def test_feedback_single_precision_switches_to_double():
     """With f32_switch the match shoots in single precision until the residual is below the
     switch, then in double: it reaches a tolerance single precision cannot, in the oracle's
