@@ -18,7 +18,7 @@ Outside the timed loop, in this order, each only while the run's wall-clock budg
   - the FP64 oracle timed on the host cores on a bounded sample (cpu_baseline);
   - time-to-match of the headline workload: Algorithm 1 from p = 0 until
     max|q(1) - Y| < 1e-6 (dense factor of K(X), shoots, solves), measured once, then once
-    more with single-precision shoots until the residual is below 1e-4 and double after;
+    more with single-precision shoots until the residual is below 1e-5 and double after;
   - the single-precision form: the same shoot in FP32 (its stage time and roofline) and its
     error against the FP64 oracle's stored shoot, with the FP64 shoot's error beside it;
   - time-to-match of the 2-D curve (N = 4096, 200 RK4 steps, FP64, and FP32 switching to FP64)
@@ -73,6 +73,9 @@ MEASURED_TRAFFIC = {
     "sphere3d_conon_f64": ("246f6dbde3421f44", 1.0436e9),
     "sphere3d_conon_f32": ("246f6dbde3421f44", 1.2993e8),
 }
+
+# Residual below which the headline's mixed-precision match moves from FP32 to FP64 shoots
+F32_SWITCH = 1e-5
 
 # Estimated seconds of each optional leg on MI355X (a leg runs only if the budget left
 # covers it), refined in the run by what the headline shoot measured.
@@ -621,17 +624,20 @@ def main():
         ttm = leg("time_to_match", ttm_fn, max(LEG_SECONDS["time_to_match"], 22 * shoot_s))
 
         def ttm_mixed_fn():
-            # the same match with single-precision shoots until the residual falls below 1e-4,
-            # double-precision shoots after (momenta, residuals and K-solves always in double)
+            # the same match with single-precision shoots until the residual falls below 1e-5,
+            # double-precision shoots after (momenta, residuals and K-solves always in double).
+            # The FP32 shoot's endpoint error on this workload is about 1e-6 against the oracle,
+            # so residuals down to 1e-5 are resolved: the residual history is the FP64 one to two
+            # digits at every switch from 1e-4 to 1e-5, and single precision's floor is 3e-6.
             prm32 = lm.make_params(pr.dim, pr.kernel, pr.sigma, dtype=lm.F32)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            st, info, _ = run_match(prm32, pr, X, Y, 1e-4)
+            st, info, _ = run_match(prm32, pr, X, Y, F32_SWITCH)
             torch.cuda.synchronize()
             r = match_record(lm, st, info, time.perf_counter() - t1, args.tol, args.h)
-            r.update(workload=args.workload, f32_switch=1e-4)
-            log("time to match %s, FP32 shoots switching to FP64 below 1e-4: %.2f s, %d iterations, resid %.2e" % (
-                args.workload, r["seconds"], info.iters, info.resid_inf))
+            r.update(workload=args.workload, f32_switch=F32_SWITCH)
+            log("time to match %s, FP32 shoots switching to FP64 below %g: %.2f s, %d iterations, resid %.2e" % (
+                args.workload, F32_SWITCH, r["seconds"], info.iters, info.resid_inf))
             return r
         if args.workload == "sphere3d_conon_f64" and isinstance(ttm, dict) and "seconds" in ttm:
             ttm["f32_switch_run"] = leg("time_to_match_f32_switch", ttm_mixed_fn, 0.8 * ttm["seconds"] + 5)

@@ -107,7 +107,10 @@ typedef struct lm_match_opts {
                              > 0: single-precision shoots until a residual below f32_switch,
                              double-precision shoots after; the stopping test then accepts only
                              a double-precision residual (a single-precision one below tol is
-                             re-shot in double precision before any further update) */
+                             re-shot in double precision before any further update).  A
+                             single-precision residual not below 0.9 times the previous one
+                             (the floor of single-precision shoots) also switches, re-shooting
+                             those momenta in double precision */
 } lm_match_opts;
 
 /* What a feedback match reports (HOST struct).  GPU times come from HIP events on the

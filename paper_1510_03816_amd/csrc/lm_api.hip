@@ -1305,7 +1305,7 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
     if (w.dense) info->factor_ms = timer.ms(0, 1);
 
     lm_status result = LM_OK;
-    double r = 0.0, prev_step = INFINITY;
+    double r = 0.0, prev_step = INFINITY, prev_r = INFINITY;
     int32_t k = 0;   // momentum updates made
     // single-precision shoots until the residual drops below f32_switch (if set), then double
     lm_params p64 = *prm;
@@ -1339,11 +1339,13 @@ lm_status lm_feedback_match(const lm_params* prm, const lm_match_opts* o, int64_
         bool hold = false;   // re-shoot the same momenta in double precision
         if (may_switch && !fp64) {
             if (r < o->f32_switch) fp64 = true;
-            if (r < o->tol) {
+            if (r < o->tol || r >= lm::kF32Stall * prev_r) {
+                // below tol, or at the single-precision floor (the residual stopped falling)
                 hold = true;
                 fp64 = true;
             }
         }
+        prev_r = r;
         if (!hold && (o->stop_rule == 0 ? (r < o->tol) : (k >= 1 && prev_step < o->tol))) break;
         if (k >= o->max_iter) {
             result = fail(LM_ENOTCONV, "feedback: %d updates without reaching tol %.3g (residual %.3g)", k, o->tol, r);

@@ -752,7 +752,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
     // per-problem state: stat -1 while running; upd = momentum updates made; prec = 1 once
     // the problem's shoots are double precision
     std::vector<int32_t> stat((size_t)B, -1), upd((size_t)B, 0), prec((size_t)B, f32 ? 0 : 1);
-    std::vector<double> res((size_t)B, 0.0);
+    std::vector<double> res((size_t)B, 0.0), prevr((size_t)B, INFINITY);
     for (int32_t b = 0; b < B; ++b)
         if (fi[b] != 0) stat[b] = LM_ESINGULAR;
 
@@ -880,11 +880,14 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
             } else {
                 if (may_switch && prec[b] == 0) {
                     if (res[b] < o->f32_switch) prec[b] = 1;
-                    if (res[b] < o->tol) {
-                        hold = true;   // re-shoot the same momenta in double precision
+                    if (res[b] < o->tol || res[b] >= lm::kF32Stall * prevr[b]) {
+                        // below tol, or at the single-precision floor: re-shoot the same
+                        // momenta in double precision
+                        hold = true;
                         prec[b] = 1;
                     }
                 }
+                prevr[b] = res[b];
                 if (!hold && res[b] < o->tol) stat[b] = LM_OK;
                 else if (upd[b] >= o->max_iter) stat[b] = LM_ENOTCONV;
                 else if (!hold) upd_f[b] = 1;

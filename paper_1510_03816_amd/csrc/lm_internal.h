@@ -330,6 +330,13 @@ hipError_t launch_batch_wide_solve(const double* L, const int64_t* loff, const d
                                    const int64_t* offs, int dim, int64_t ntot, double* y, const int* flag,
                                    const int4* items, const BatchWidePlan& pl, hipStream_t st);
 
+// Matches with single-precision shoots: a shoot whose residual is not below kF32Stall times
+// the previous one has reached the floor of single-precision shoots (the feedback iteration
+// otherwise shrinks the residual by a factor of about 2 to 4 per update), so the same momenta
+// are re-shot in double precision and the match stays there.  On the 65536-point sphere the
+// floor is about 3e-6 and the residual ratios before it 0.24 to 0.61.
+constexpr double kF32Stall = 0.9;
+
 int64_t tiles_of(int64_t n);     // 64-point tiles covering n points
 int64_t sort_pad(int64_t n);     // power of two >= max(n, 2)
 

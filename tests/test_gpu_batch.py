@@ -272,6 +272,25 @@ def test_batched_feedback_switches_to_double_precision():
         assert np.max(np.abs(oq - Y[:, s])) < 1e-9
 
 
+def test_batched_feedback_single_precision_floor_switches_to_double():
+    """f32_switch below the single-precision floor (1e-12): each problem's residual stops
+    falling at its floor, where the problem switches to double precision; every problem
+    reaches tol = 1e-9 within two updates of the oracle's count (either way: the single-precision
+    updates before the switch move its residuals slightly)."""
+    sizes, offs, X, Y = curve_batch(5, 300)
+    prm = lm.make_params(2, lm.CONON, 0.1, dtype=lm.F32)
+    p0 = torch.zeros((2, int(offs[-1])), dtype=torch.float64, device=DEV)
+    st, infos, stats = lm.lm_feedback_match_batched(prm, offs, dev(X), dev(Y), p0, h=0.8, tol=1e-9, steps=20,
+                                                    max_iter=200, f32_switch=1e-12)
+    assert st == lm.LM_OK, stats
+    for b in range(len(sizes)):
+        s = slice(offs[b], offs[b + 1])
+        ref = oracle.feedback_match(X[:, s], Y[:, s], lm.CONON, 0.1, 0.8, 1e-9, 20, max_iter=200)
+        assert ref.status == 0
+        assert infos[b].resid_inf < 1e-9
+        assert abs(infos[b].iters - ref.iters) <= 2, (b, infos[b].iters, ref.iters)
+
+
 @pytest.mark.parametrize("wide_min", [None, "0", "4096"])
 def test_batched_feedback_multi_panel_problems_in_the_batched_solve(wide_min, monkeypatch):
     """Problems of 40, 1000 and 2900 points (1, 8 and 23 diagonal blocks, ragged last blocks)

@@ -394,6 +394,24 @@ def test_feedback_single_precision_switches_to_double():
     assert rel_err(host(q1), oq) <= 1e-10
 
 
+def test_feedback_single_precision_floor_switches_to_double():
+    """A switch threshold below what single-precision shoots resolve (1e-12, against a floor of
+    about 1e-5 on this curve): the residual stops falling at the floor, the match re-shoots in
+    double precision there and reaches tol = 1e-9 within two updates of the oracle's count
+    (either way: the single-precision updates before the switch move its residuals slightly)."""
+    pr = inputs.config_curve2d(700)
+    prm = lm.make_params(2, lm.CONON, pr.sigma, dtype=lm.F32)
+    p0 = torch.zeros((2, pr.n), dtype=torch.float64, device=DEV)
+    st, info, hist = lm.lm_feedback_match(prm, dev(pr.X), dev(pr.Y), p0, h=0.8, tol=1e-9, steps=40, max_iter=200,
+                                          f32_switch=1e-12)
+    ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-9, 40, max_iter=200)
+    print("floor switch: gpu %d updates, %d shoots | oracle %d; residuals %s" % (
+        info.iters, info.shoots, ref.iters, " ".join("%.1e" % h for h in hist)))
+    assert st == 0 and ref.status == 0
+    assert info.resid_inf < 1e-9
+    assert abs(info.iters - ref.iters) <= 2
+
+
 @pytest.mark.parametrize("tau,solver", [(0.05, lm.SOLVE_DENSE), (0.3, lm.SOLVE_DENSE), (0.3, lm.SOLVE_CG)])
 def test_feedback_inexact_matches_oracle(tau, solver):
     """Inexact matching (eq. N-particle-inexact, Table 5's stopping rule on successive
