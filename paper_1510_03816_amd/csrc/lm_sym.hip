@@ -54,7 +54,7 @@ __host__ __device__ constexpr int sym_stride(int dim) { return 2 * dim + 1; }
 __device__ __forceinline__ int64_t tiles_of_dev(int64_t n) { return (n + kSymSteps - 1) / kSymSteps; }
 
 // Per-precision pieces: FMA, the conon's squared-distance floor (see pair_f64), 1/sqrt and the
-// exponential 2^x (kq carries log2 e; in single precision the hardware 2^x).
+// exponential 2^x (in single precision the hardware 2^x).
 template <class T>
 struct SymMath;
 template <>
@@ -73,9 +73,10 @@ struct SymMath<float> {
 };
 
 // The symmetric part of a pair: d = q_i - q_j, kernel value g and force weight w (without
-// the constant, which is applied to the sums).
+// the constant, which is applied to the sums).  Positions are in the exponent's units (see
+// sym_superblock_pair): the kernel value is 2^-r for the conon, 2^-(r^2) for the Gaussian.
 template <class T, int DIM, int KER>
-__device__ __forceinline__ void sym_pair(const T (&qi)[DIM], const T (&qj)[DIM], T kq, T (&d)[DIM], T& g, T& w)
+__device__ __forceinline__ void sym_pair(const T (&qi)[DIM], const T (&qj)[DIM], T (&d)[DIM], T& g, T& w)
 {
     using M = SymMath<T>;
     // conon: the squared distance starts at a tiny floor so the self pair and padding points
@@ -88,10 +89,10 @@ __device__ __forceinline__ void sym_pair(const T (&qi)[DIM], const T (&qj)[DIM],
     }
     if constexpr (KER == LM_KERNEL_CONON) {
         const T rho = M::rsq(s);
-        g = M::ex(s * rho * kq);
+        g = M::ex(-(s * rho));
         w = g * rho;
     } else {
-        g = M::ex(s * kq);
+        g = M::ex(-s);
         w = g;
     }
 }
@@ -102,7 +103,7 @@ __device__ __forceinline__ void sym_pair(const T (&qi)[DIM], const T (&qj)[DIM],
 // full rate, while single-precision LDS atomic adds measured 16 times slower for the kernel.
 template <class T, int DIM, int KER, bool FORCE, int ROWS, bool JSIDE>
 __device__ __forceinline__ void sym_step(const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM], const T* __restrict__ src,
-                                         T kq, T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc)
+                                         T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc)
 {
     using M = SymMath<T>;
     T qj[DIM], pj[DIM];
@@ -115,7 +116,7 @@ __device__ __forceinline__ void sym_step(const T (&qi)[ROWS][DIM], const T (&pi)
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         T d[DIM], g, w;
-        sym_pair<T, DIM, KER>(qi[r], qj, kq, d, g, w);
+        sym_pair<T, DIM, KER>(qi[r], qj, d, g, w);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             v[r][c] = M::fma(g, pj[c], v[r][c]);
@@ -148,29 +149,29 @@ __device__ __forceinline__ void sym_step(const T (&qi)[ROWS][DIM], const T (&pi)
 // (jbuf + lane * sym_stride(DIM)), acc = this lane's first word of the wave's column array.
 template <class T, int DIM, int KER, bool FORCE, int ROWS, bool JSIDE>
 __device__ __forceinline__ void sym_block(const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM], const T* __restrict__ jb,
-                                          T kq, T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc)
+                                          T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc)
 {
     constexpr int E = sym_stride(DIM);
     for (int k0 = 0; k0 < kSymSteps; k0 += kSymUnroll) {
 #pragma unroll
         for (int u = 0; u < kSymUnroll; ++u)
-            sym_step<T, DIM, KER, FORCE, ROWS, JSIDE>(qi, pi, jb + (k0 + u) * E, kq, v, f, acc + k0 + u);
+            sym_step<T, DIM, KER, FORCE, ROWS, JSIDE>(qi, pi, jb + (k0 + u) * E, v, f, acc + k0 + u);
     }
 }
 
-// Loads column tile J into jbuf: entry e (0..127) holds point J*64 + (e mod 64), its q then
-// its p (the pad word is never read); points past n are zero (zero momentum: they add
-// exactly nothing to real points).
+// Loads column tile J into jbuf: entry e (0..127) holds point J*64 + (e mod 64), its q (times
+// ks) then its p (the pad word is never read); points past n are zero (zero momentum: they
+// add exactly nothing to real points).
 template <class T, int DIM>
 __device__ __forceinline__ void sym_stage(T* __restrict__ jbuf, const T* __restrict__ q, const T* __restrict__ p,
-                                          int64_t ld, int64_t n, int64_t J)
+                                          int64_t ld, int64_t n, int64_t J, T ks)
 {
     constexpr int E = sym_stride(DIM);
     for (int t = threadIdx.x; t < kSymSteps * 2 * DIM; t += blockDim.x) {
         const int c = t >> 6, l = t & 63;
         const int64_t j = J * kSymSteps + l;
         T x = (T)0;
-        if (j < n) x = (c < DIM) ? q[c * ld + j] : p[(c - DIM) * ld + j];
+        if (j < n) x = (c < DIM) ? ks * q[c * ld + j] : p[(c - DIM) * ld + j];
         jbuf[l * E + c] = x;
         jbuf[(l + 64) * E + c] = x;
     }
@@ -197,7 +198,7 @@ __device__ __forceinline__ bool sym_tiles_far(const double* __restrict__ a, cons
 template <class T, int DIM, int KER, bool FORCE, bool CUT, int ROWS, class A>
 __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[ROWS], int64_t J, int64_t NT,
                                          const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM],
-                                         const T* __restrict__ jb, T kq, A (&v)[ROWS][DIM], A (&f)[ROWS][DIM],
+                                         const T* __restrict__ jb, A (&v)[ROWS][DIM], A (&f)[ROWS][DIM],
                                          double* __restrict__ acc, const double* __restrict__ box, double rc2)
 {
     bool far[ROWS];
@@ -210,7 +211,7 @@ __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[ROWS], in
     // every row tile meets J from both sides, except near the diagonal (and skipped tiles)
     const bool all = (diag ? J > I[ROWS - 1] : I[ROWS - 1] < NT) && !any_far;
     if (all) {
-        sym_block<T, DIM, KER, FORCE, ROWS, true>(qi, pi, jb, kq, v, f, acc);
+        sym_block<T, DIM, KER, FORCE, ROWS, true>(qi, pi, jb, v, f, acc);
         return;
     }
 #pragma unroll
@@ -226,9 +227,9 @@ __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[ROWS], in
             f1[0][c] = f[r][c];
         }
         if (m == SYM_BOTH)
-            sym_block<T, DIM, KER, FORCE, 1, true>(q1, p1, jb, kq, v1, f1, acc);
+            sym_block<T, DIM, KER, FORCE, 1, true>(q1, p1, jb, v1, f1, acc);
         else
-            sym_block<T, DIM, KER, FORCE, 1, false>(q1, p1, jb, kq, v1, f1, acc);
+            sym_block<T, DIM, KER, FORCE, 1, false>(q1, p1, jb, v1, f1, acc);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             v[r][c] = v1[0][c];
@@ -261,7 +262,14 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
 
     const bool diag = X == Y;
     const int64_t NT = tiles_of_dev(n);
-    const T kq = (T)kqd;
+    // Positions in the exponent's units, q' = ks q: ks = -kq for the conon (the kernel value
+    // is then 2^-|q'_i - q'_j|) and sqrt(-kq) for the Gaussian (2^-|q'_i - q'_j|^2), which
+    // takes the multiply by kq out of every pair.  The conon's force weight g/r' times d'
+    // equals g d / r; the Gaussian's g d' carries one factor ks, divided out of the force
+    // constant.  (Tile boxes and the cutoff stay in the original units.)
+    const double ksd = (KER == LM_KERNEL_CONON) ? -kqd : __builtin_sqrt(-kqd);
+    const T ks = (T)ksd;
+    const double fscale = (KER == LM_KERNEL_CONON) ? wscale : wscale / ksd;
 
     // CUT: bit k of `need` says whether column tile Y * side + k lies within the cutoff of some
     // row tile of the superblock; the others are neither staged nor evaluated (their column
@@ -298,7 +306,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
         const bool live = i < n;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            qi[r][c] = live ? q[c * ld + i] : (T)0;
+            qi[r][c] = live ? ks * q[c * ld + i] : (T)0;
             pi[r][c] = live ? p[c * ld + i] : (T)0;
             vs[r][c] = 0.0;
             fs[r][c] = 0.0;
@@ -308,7 +316,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     for (int t = threadIdx.x; t < nw * EC * 128; t += blockDim.x) region[t] = 0.0;
     const int64_t J0 = Y * side;
     const int64_t J1 = (J0 + side < NT) ? (J0 + side) : NT;
-    if (need & 1u) sym_stage<T, DIM>(jbuf, q, p, ld, n, J0);
+    if (need & 1u) sym_stage<T, DIM>(jbuf, q, p, ld, n, J0, ks);
     __syncthreads();
 
     const T* jb = jbuf + lane * E;
@@ -317,7 +325,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     double* pc = part + slot_col * (2 * DIM) * n;
     for (int64_t J = J0; J < J1; ++J) {
         if constexpr (sizeof(T) == sizeof(double)) {
-            sym_tile<T, DIM, KER, FORCE, CUT, ROWS>(diag, I, J, NT, qi, pi, jb, kq, vs, fs, acc, box, rc2);
+            sym_tile<T, DIM, KER, FORCE, CUT, ROWS>(diag, I, J, NT, qi, pi, jb, vs, fs, acc, box, rc2);
         } else {
             T v[ROWS][DIM], f[ROWS][DIM];
 #pragma unroll
@@ -327,7 +335,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
                     v[r][c] = (T)0;
                     f[r][c] = (T)0;
                 }
-            sym_tile<T, DIM, KER, FORCE, CUT, ROWS>(diag, I, J, NT, qi, pi, jb, kq, v, f, acc, box, rc2);
+            sym_tile<T, DIM, KER, FORCE, CUT, ROWS>(diag, I, J, NT, qi, pi, jb, v, f, acc, box, rc2);
 #pragma unroll
             for (int r = 0; r < ROWS; ++r)
 #pragma unroll
@@ -349,9 +357,9 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
                 rg[l + 64] = 0.0;
             }
             const int64_t j = J * kSymSteps + l;
-            if (j < n) pc[c * n + j] = (c < DIM) ? s : s * wscale;
+            if (j < n) pc[c * n + j] = (c < DIM) ? s : s * fscale;
         }
-        if (J + 1 < J1 && ((need >> (J + 1 - J0)) & 1u)) sym_stage<T, DIM>(jbuf, q, p, ld, n, J + 1);
+        if (J + 1 < J1 && ((need >> (J + 1 - J0)) & 1u)) sym_stage<T, DIM>(jbuf, q, p, ld, n, J + 1, ks);
         __syncthreads();
     }
 
@@ -363,7 +371,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             pr[c * n + i] = vs[r][c];
-            if (FORCE) pr[(DIM + c) * n + i] = fs[r][c] * wscale;
+            if (FORCE) pr[(DIM + c) * n + i] = fs[r][c] * fscale;
         }
     }
 }
