@@ -91,10 +91,12 @@ struct Cut {
 };
 
 // One evaluation of the pair sums with targets (qt, pt) [nt] and sources (qs, ps) [ns].
+// tscale > 0: the sources are in the exponent's units and the targets are multiplied by
+// tscale (see PairArgs).
 template <class T>
 lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, int64_t ns, const T* qt,
                     const T* pt, int64_t nt, const lm::EpiArgs<T>& epi, double* part, hipStream_t st,
-                    const Cut& cut = Cut())
+                    const Cut& cut = Cut(), double tscale = 0.0)
 {
     const bool sym_ok = qs == qt && ps == pt && ns == nt;
     lm::PairPlan pl = lm::plan_pair(nt, ns, cut.box_s != nullptr, sym_ok, sizeof(T) == 4 ? lm::SYM_F32 : lm::SYM_F64);
@@ -107,6 +109,8 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
     a.ns = ns;
     a.jchunk = pl.jchunk;
     kernel_scales(prm, &a.kq, &a.wscale);
+    a.tscale = tscale;
+    if (tscale > 0.0 && prm->kernel != LM_KERNEL_CONON) a.wscale /= std::sqrt(-a.kq);
     a.part = part;
     a.box_s = cut.box_s;
     a.box_t = cut.box_t;
@@ -189,6 +193,19 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
     e.base_p = p;
     e.acc_q = cq;
     e.acc_p = cp;
+    // With one-sided pair sums and no tile skipping the stages run on positions in the
+    // exponent's units (ks q), which takes a multiply out of every pair: the first stage
+    // reads ks y from B (written here, then by each step's last stage, when B is free), and
+    // the other stages' position outputs are written scaled.  The state y stays unscaled.
+    double kq0, ws0;
+    kernel_scales(prm, &kq0, &ws0);
+    const double ks = prm->kernel == LM_KERNEL_CONON ? -kq0 : std::sqrt(-kq0);
+    const bool pre = !box && lm::plan_pair(n, n, false, true, sizeof(T) == 4 ? lm::SYM_F32 : lm::SYM_F64).sym_waves == 0;
+    if (pre) {
+        e.qscale = ks;
+        e.out_qs = bq;
+        LM_HIP(lm::launch_scaled_copy<T>(bq, q, ks, (int64_t)prm->dim * n, st));
+    }
     Cut cut;
     if (box) {
         cut.box_s = cut.box_t = box;
@@ -209,7 +226,7 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
     }
     for (int32_t s = 0; s < steps; ++s) {
         // stage 1: input y, output A ; stage 2: A -> B ; stage 3: B -> A ; stage 4: A -> y
-        const T* in_q[4] = {q, aq, bq, aq};
+        const T* in_q[4] = {pre ? bq : q, aq, bq, aq};
         const T* in_p[4] = {p, ap, bp, ap};
         T* out_q[4] = {aq, bq, aq, q};
         T* out_p[4] = {ap, bp, ap, p};
@@ -227,9 +244,10 @@ lm_status shoot_inplace(const lm_params* prm, int64_t n, T* q, T* p, double t1, 
                 ex.out_q = out_x[k];
                 if (box) LM_HIP(lm::launch_tile_boxes<T>(prm->dim, in_x[k], pts->m, pts->box, st));
                 LM_TRY(pair_eval<T>(prm, false, in_q[k], in_p[k], n, in_x[k], (const T*)nullptr, pts->m, ex, part, st,
-                                    xcut));
+                                    xcut, pre ? ks : 0.0));
             }
-            LM_TRY(pair_eval<T>(prm, true, in_q[k], in_p[k], n, in_q[k], in_p[k], n, e, part, st, cut));
+            LM_TRY(pair_eval<T>(prm, true, in_q[k], in_p[k], n, in_q[k], in_p[k], n, e, part, st, cut,
+                                pre ? 1.0 : 0.0));
         }
     }
     return LM_OK;

@@ -50,6 +50,11 @@ struct EpiArgs {
     T* acc_p;
     T* out_q;          // stage output
     T* out_p;
+    // qscale > 0 (a shoot on positions in the exponent's units): RK1-RK3 write their stage
+    // output positions times qscale (the next stage's pair-sum input), and RK4, which writes
+    // the state itself, also writes it times qscale to out_qs (the next step's first input)
+    double qscale;
+    T* out_qs;
 };
 
 template <class T>
@@ -62,6 +67,11 @@ struct PairArgs {
     int64_t jchunk;    // sources per wave chunk
     double kq;         // base-2 exponent scale: conon -log2(e)/sigma, Gaussian -log2(e)/sigma^2
     double wscale;     // force-weight constant: conon 1/sigma, Gaussian 2/sigma^2
+    // tscale > 0: the sources are in the exponent's units (q' = k q, k = -kq for the conon,
+    // sqrt(-kq) for the Gaussian) and the targets are multiplied by tscale as they are loaded
+    // (1 when they are in those units already); wscale then carries the Gaussian's 1/k.  Only
+    // the one-sided kernel without tile skipping takes this form.
+    double tscale;
     double* part;      // split partial sums (nsplit, 2 dim, nt), used when nsplit > 1
     const double* box_s;   // cutoff mode: source tile boxes (8 doubles per 64-point tile), else null
     const double* box_t;   // cutoff mode: target tile boxes
@@ -268,6 +278,9 @@ hipError_t launch_vjp(int dim, int kernel, const VjpArgs& a, const PairPlan& pl,
 // epilogue (launch_vjp adds them).
 hipError_t launch_sym_vjp(int dim, int kernel, const VjpArgs& a, int waves, int64_t nsb, hipStream_t st);
 hipError_t launch_scale(double* y, double alpha, const double* x, int64_t m, hipStream_t st);
+// y = (T)(alpha * x), m elements
+template <class T>
+hipError_t launch_scaled_copy(T* y, const T* x, double alpha, int64_t m, hipStream_t st);
 
 template <class TA, class TB>
 hipError_t launch_maxabsdiff(const TA* x, const TB* y, int64_t m, double* partial, double* out, hipStream_t st);

@@ -40,10 +40,13 @@ namespace lm {
 // -log2(e)/sigma, for the Gaussian -log2(e)/sigma^2, so the kernel value is 2^(kq r) or
 // 2^(kq r^2) (exp2_nonpos in double, the hardware 2^x in single precision).  The force
 // weight's constant (1/sigma for the conon, 2/sigma^2 for the Gaussian) is folded into the
-// target momentum `psi` by the caller.
+// target momentum `psi` by the caller.  PRE: the positions are in the exponent's units
+// (q' = k q with k = -kq for the conon, sqrt(-kq) for the Gaussian), so the kernel value is
+// 2^-r' (2^-r'^2) and kq is not used; the conon's weight g/r' times d' is then g d / r, the
+// Gaussian's g d' carries a factor k that the caller takes out of psi.
 // ---------------------------------------------------------------------------------------
 
-template <int DIM, int KER, bool FORCE>
+template <int DIM, int KER, bool FORCE, bool PRE = false>
 __device__ __forceinline__ void pair_f64(const double (&qi)[DIM], const double (&psi)[DIM],
                                          const double (&qj)[DIM], const double (&pj)[DIM],
                                          double kq, double (&v)[DIM], double (&f)[DIM])
@@ -63,10 +66,10 @@ __device__ __forceinline__ void pair_f64(const double (&qi)[DIM], const double (
     if constexpr (KER == LM_KERNEL_CONON) {
         const double rho = rsqrt_pos(s);
         const double r = s * rho;
-        g = exp2_nonpos(r * kq);
+        g = PRE ? exp2_nonpos(-r) : exp2_nonpos(r * kq);
         w = g * rho;
     } else {
-        g = exp2_nonpos(s * kq);
+        g = PRE ? exp2_nonpos(-s) : exp2_nonpos(s * kq);
         w = g;
     }
 #pragma unroll
@@ -81,7 +84,7 @@ __device__ __forceinline__ void pair_f64(const double (&qi)[DIM], const double (
     }
 }
 
-template <int DIM, int KER, bool FORCE>
+template <int DIM, int KER, bool FORCE, bool PRE = false>
 __device__ __forceinline__ void pair_f32(const float (&qi)[DIM], const float (&psi)[DIM],
                                          const float (&qj)[DIM], const float (&pj)[DIM],
                                          float kq, float (&v)[DIM], float (&f)[DIM])
@@ -96,10 +99,10 @@ __device__ __forceinline__ void pair_f32(const float (&qi)[DIM], const float (&p
     float g, w;
     if constexpr (KER == LM_KERNEL_CONON) {
         const float rho = rsqrt_f32(s);
-        g = exp2_f32(s * rho * kq);
+        g = PRE ? exp2_f32(-(s * rho)) : exp2_f32(s * rho * kq);
         w = g * rho;
     } else {
-        g = exp2_f32(s * kq);
+        g = PRE ? exp2_f32(-s) : exp2_f32(s * kq);
         w = g;
     }
 #pragma unroll
@@ -150,7 +153,8 @@ __device__ __forceinline__ void epilogue(const EpiArgs<T>& e, int64_t n, int64_t
             double aq = wgt * kq[c];
             if (e.kind != EPI_RK1) aq += (double)e.acc_q[k];
             e.acc_q[k] = (T)aq;
-            e.out_q[k] = (T)((double)e.base_q[k] + a * kq[c]);
+            const double nq = (double)e.base_q[k] + a * kq[c];
+            e.out_q[k] = (T)(e.qscale > 0.0 ? e.qscale * nq : nq);
             if constexpr (FORCE) {
                 // (without forces the targets are passive points: positions only)
                 double ap = wgt * kp[c];
@@ -168,7 +172,9 @@ __device__ __forceinline__ void epilogue(const EpiArgs<T>& e, int64_t n, int64_t
         for (int c = 0; c < DIM; ++c) {
             const int64_t k = c * n + i;
             const double sq = (double)e.acc_q[k] + kq[c];
-            e.out_q[k] = (T)((double)e.base_q[k] + h6 * sq);
+            const double nq = (double)e.base_q[k] + h6 * sq;
+            e.out_q[k] = (T)nq;
+            if (e.qscale > 0.0) e.out_qs[k] = (T)(e.qscale * nq);
             if constexpr (FORCE) {
                 const double sp = (double)e.acc_p[k] + kp[c];
                 e.out_p[k] = (T)((double)e.base_p[k] + h6 * sp);
@@ -192,7 +198,7 @@ __device__ __forceinline__ void epilogue(const EpiArgs<T>& e, int64_t n, int64_t
 
 // Sums sources [j0, j1) into (v, f) for one target per lane.  Sources are wave-uniform:
 // the loads become scalar loads and the values SGPR operands.
-template <int DIM, int KER, bool FORCE>
+template <int DIM, int KER, bool FORCE, bool PRE = false>
 __device__ __forceinline__ void sum_sources(const double* __restrict__ qs, const double* __restrict__ ps,
                                             int64_t ns, int64_t j0, int64_t j1, const double (&qi)[DIM],
                                             const double (&psi)[DIM], double kq, double (&v)[DIM],
@@ -208,7 +214,7 @@ __device__ __forceinline__ void sum_sources(const double* __restrict__ qs, const
                 qj[c] = qs[c * ns + j + u];
                 pj[c] = ps[c * ns + j + u];
             }
-            pair_f64<DIM, KER, FORCE>(qi, psi, qj, pj, kq, v, f);
+            pair_f64<DIM, KER, FORCE, PRE>(qi, psi, qj, pj, kq, v, f);
         }
     }
     for (; j < j1; ++j) {
@@ -218,13 +224,13 @@ __device__ __forceinline__ void sum_sources(const double* __restrict__ qs, const
             qj[c] = qs[c * ns + j];
             pj[c] = ps[c * ns + j];
         }
-        pair_f64<DIM, KER, FORCE>(qi, psi, qj, pj, kq, v, f);
+        pair_f64<DIM, KER, FORCE, PRE>(qi, psi, qj, pj, kq, v, f);
     }
 }
 
 // Single precision: pairs summed in float over runs of 64 sources, the runs added in double,
 // which keeps the rounding error of long sums at the level of one run.
-template <int DIM, int KER, bool FORCE>
+template <int DIM, int KER, bool FORCE, bool PRE = false>
 __device__ __forceinline__ void sum_sources(const float* __restrict__ qs, const float* __restrict__ ps,
                                             int64_t ns, int64_t j0, int64_t j1, const float (&qi)[DIM],
                                             const float (&psi)[DIM], double kqd, double (&v)[DIM],
@@ -246,7 +252,7 @@ __device__ __forceinline__ void sum_sources(const float* __restrict__ qs, const 
                     qj[c] = qs[c * ns + j + u];
                     pj[c] = ps[c * ns + j + u];
                 }
-                pair_f32<DIM, KER, FORCE>(qi, psi, qj, pj, kq, vs, fs);
+                pair_f32<DIM, KER, FORCE, PRE>(qi, psi, qj, pj, kq, vs, fs);
             }
         }
         for (; j < je; ++j) {
@@ -256,7 +262,7 @@ __device__ __forceinline__ void sum_sources(const float* __restrict__ qs, const 
                 qj[c] = qs[c * ns + j];
                 pj[c] = ps[c * ns + j];
             }
-            pair_f32<DIM, KER, FORCE>(qi, psi, qj, pj, kq, vs, fs);
+            pair_f32<DIM, KER, FORCE, PRE>(qi, psi, qj, pj, kq, vs, fs);
         }
 #pragma unroll
         for (int c = 0; c < DIM; ++c) { v[c] += (double)vs[c]; f[c] += (double)fs[c]; }
@@ -276,7 +282,7 @@ __device__ __forceinline__ void sum_sources(const float* __restrict__ qs, const 
 // so skipping is a scalar branch.
 // ---------------------------------------------------------------------------------------
 
-template <class T, int DIM, int KER, bool FORCE, bool CUT>
+template <class T, int DIM, int KER, bool FORCE, bool CUT, bool PRE = false>
 __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
 {
     const int lane = threadIdx.x & (kTile - 1);
@@ -289,7 +295,7 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
     T qi[DIM], psi[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        qi[c] = a.qt[c * a.nt + ic];
+        qi[c] = PRE ? (T)(a.tscale * (double)a.qt[c * a.nt + ic]) : a.qt[c * a.nt + ic];
         psi[c] = FORCE ? (T)(a.wscale * (double)a.pt[c * a.nt + ic]) : (T)0;
     }
 
@@ -302,7 +308,7 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
     for (int c = 0; c < DIM; ++c) { v[c] = 0.0; f[c] = 0.0; }
 
     if constexpr (!CUT) {
-        sum_sources<DIM, KER, FORCE>(a.qs, a.ps, a.ns, j0, j1, qi, psi, a.kq, v, f);
+        sum_sources<DIM, KER, FORCE, PRE>(a.qs, a.ps, a.ns, j0, j1, qi, psi, a.kq, v, f);
     } else {
         const double* __restrict__ tb = a.box_t + (int64_t)blockIdx.x * 8;
         double tlo[DIM], thi[DIM];
@@ -843,6 +849,7 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
     uint8_t* flags = nullptr;   // symmetric with tile skipping: which superblock pairs wrote
     int64_t sbp = kTile;
     if (pl.sym_waves > 0) {
+        if (a.tscale > 0.0) return hipErrorInvalidValue;   // the symmetric kernels scale positions themselves
         {
             SymArgs<T> s{};
             s.q = a.qs;
@@ -865,7 +872,12 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
         }
     } else {
         dim3 grid((unsigned)pl.itiles, (unsigned)pl.nsplit);
-        hipLaunchKernelGGL((lm_pair_kernel<T, DIM, KER, FORCE, CUT>), grid, dim3(kTile * kWaves), 0, st, a);
+        if (a.tscale > 0.0) {
+            if constexpr (CUT) return hipErrorInvalidValue;   // boxes and cutoff are in the original units
+            else hipLaunchKernelGGL((lm_pair_kernel<T, DIM, KER, FORCE, false, true>), grid, dim3(kTile * kWaves), 0, st, a);
+        } else {
+            hipLaunchKernelGGL((lm_pair_kernel<T, DIM, KER, FORCE, CUT>), grid, dim3(kTile * kWaves), 0, st, a);
+        }
         err = hipGetLastError();
     }
     if (err != hipSuccess || pl.nsplit == 1) return err;
@@ -963,6 +975,23 @@ hipError_t launch_convert(TO* y, const TI* x, int64_t m, hipStream_t st)
 }
 
 template hipError_t launch_convert<float, double>(float*, const double*, int64_t, hipStream_t);
+
+template <class T>
+__global__ __launch_bounds__(256) void lm_scaled_copy_kernel(T* __restrict__ y, const T* __restrict__ x, double alpha,
+                                                             int64_t m)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+        y[k] = (T)(alpha * (double)x[k]);
+}
+
+template <class T>
+hipError_t launch_scaled_copy(T* y, const T* x, double alpha, int64_t m, hipStream_t st)
+{
+    hipLaunchKernelGGL(lm_scaled_copy_kernel<T>, dim3(blocks_for(m, 256)), dim3(256), 0, st, y, x, alpha, m);
+    return hipGetLastError();
+}
+template hipError_t launch_scaled_copy<float>(float*, const float*, double, int64_t, hipStream_t);
+template hipError_t launch_scaled_copy<double>(double*, const double*, double, int64_t, hipStream_t);
 
 int64_t tiles_of(int64_t n) { return (n + kTile - 1) / kTile; }
 
