@@ -482,8 +482,9 @@ def main():
     args = parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; the pair sums would shard by target rows with one "
-              "all-gather of (q, p) per RK stage, which is not built here. Use --gpus 1.", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; the pair sums would shard by target rows with one "
+              "all-gather of (q, p) per RK stage, which the library does not implement. Use --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
