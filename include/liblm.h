@@ -198,7 +198,9 @@ lm_status lm_ksolve(const lm_params *params, int64_t n, const double *X, const d
  * X, Y: double (dim, n).  p0: double (dim, n), in: initial momenta (zeros in the paper),
  * out: the final momenta.  q1 (nullable): double (dim, n), receives q(1) of the last
  * shoot.  info: HOST.  params->dtype = LM_F32 shoots in single precision while the
- * momenta, the residual and the K-solves stay in double.  opts->solver picks the K-solve;
+ * momenta, the residual and the K-solves stay in double; the dense factor's trailing updates
+ * then multiply in single precision (the solves only steer the iteration; environment
+ * LM_FACTOR_F32 = 0/1 overrides).  opts->solver picks the K-solve;
  * a dense factor is built once per call (K(X) is fixed during a match).  Synchronous.
  * Returns LM_OK, LM_ENOTCONV, LM_EDIVERGED (non-finite residual, as the paper's NaN for
  * h > 1) or LM_ESINGULAR; in every case p0 and info describe the last iterate. */

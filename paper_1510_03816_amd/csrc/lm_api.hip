@@ -505,9 +505,12 @@ bool dense_fits(int64_t n)
     return need <= 0.5 * (double)freeb;
 }
 
+// f32_update: the trailing updates multiply in single precision (for solves that only steer a
+// match with single-precision shoots); LM_FACTOR_F32 (0/1) overrides the choice.
 lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspace& ws, DenseFactor* f,
-                       hipStream_t st)
+                       hipStream_t st, bool f32_update = false)
 {
+    if (const char* e = std::getenv("LM_FACTOR_F32")) f32_update = e[0] == '1';
     f->n = n;
     LM_TRY(ws.get(&f->L, n * n));
     LM_TRY(ws.get(&f->Linv, lm::dense_linv_elems(n)));
@@ -518,7 +521,8 @@ lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspa
     }
     double kq, wscale;
     kernel_scales(prm, &kq, &wscale);
-    LM_HIP(lm::launch_dense_factor(prm->dim, prm->kernel, kq, prm->tau, X, n, f->L, f->Linv, f->info, st));
+    LM_HIP(lm::launch_dense_factor(prm->dim, prm->kernel, kq, prm->tau, X, n, f->L, f->Linv, f->info, st,
+                                   f32_update));
     if (f->W) LM_HIP(lm::launch_dense_super(f->L, f->Linv, n, f->W, st));
     int info = 0;
     LM_HIP(hipMemcpyAsync(&info, f->info, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -678,7 +682,9 @@ struct FeedbackWork {
                              const double* X, hipStream_t st)
     {
         LM_TRY(pick_solver(o->solver, n, &dense));
-        if (dense) LM_TRY(dense_factor(prm, n, X, ws, &fac, st));
+        // a match with single-precision shoots steers by solves that need not be exact: its
+        // factor's trailing updates multiply in single precision
+        if (dense) LM_TRY(dense_factor(prm, n, X, ws, &fac, st, prm->dtype == LM_F32));
         return LM_OK;
     }
 };

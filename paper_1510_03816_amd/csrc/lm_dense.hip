@@ -449,6 +449,122 @@ __global__ __launch_bounds__(256, 2) void lm_syrk128_kernel(double* __restrict__
     }
 }
 
+
+// The same 128 x 128 trailing update with the products in single precision, for factors whose
+// solves only steer an iteration (matches with single-precision shoots): the staged operands
+// are rounded to float, multiplied on v_mfma_f32_16x16x4f32 (twice the FP64 matrix rate) with
+// float accumulation over the block's columns, and the result is subtracted from the FP64
+// matrix.  The factor is then accurate to about the single-precision rounding of each update
+// (a solve to roughly cond(K) times 1e-6).  Operand layout (measured): lane l supplies A[l%16]
+// [l/16] and B[l/16][l%16] and holds D[4 (l/16) + r][l%16], r < 4, of the 16 x 16 block.  Wave
+// w computes the 64 x 64 quarter (w/2, w%2) as 4 x 4 blocks, 16 instructions per k-step of 4;
+// the staged rows have a pitch of 34 floats, so that the 32 lanes of a half-wave read 16 rows
+// at two columns from distinct banks.
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256, 2) void lm_syrk128_f32_kernel(double* __restrict__ K, int64_t n, int64_t k0,
+                                                                int bs, int64_t t0)
+{
+    constexpr int KC = 32;
+    constexpr int LD = KC + 2;
+    __shared__ float Ai[128 * LD];
+    __shared__ float Aj[128 * LD];
+    const int64_t id = blockIdx.x;
+    int64_t ti = (int64_t)((__builtin_sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= id) ++ti;
+    while (ti * (ti + 1) / 2 > id) --ti;
+    const int64_t tj = id - ti * (ti + 1) / 2;
+    const int64_t ri = t0 + ti * 128, rj = t0 + tj * 128;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const bool diag = (ti == tj);
+    const bool active = !(diag && wc > wr);
+
+    // staging as in lm_syrk128_kernel (FP64 loads), rounded to float as it is stored
+    constexpr int RS = 256 / KC, NU = 128 / RS;
+    const int sc = tid % KC, sr = tid / KC;
+    const int64_t rows_i = (n - ri) < 128 ? (n - ri) : 128;
+    const int64_t rows_j = (n - rj) < 128 ? (n - rj) : 128;
+    const __amdgpu_buffer_rsrc_t bi =
+        __builtin_amdgcn_make_buffer_rsrc(K + ri * n + k0, (short)0, (int)(rows_i * n * 8), kSyrkRsrcWord3);
+    const __amdgpu_buffer_rsrc_t bj =
+        __builtin_amdgcn_make_buffer_rsrc(K + rj * n + k0, (short)0, (int)(rows_j * n * 8), kSyrkRsrcWord3);
+    const unsigned rowstep = (unsigned)(RS * n * 8);
+    const unsigned lane_off = (unsigned)((sr * n + sc) * 8);
+    double pa[NU], pb[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const unsigned off = syrk_col_off(lane_off, sc < bs);
+        pa[u] = syrk_load(bi, off + u * rowstep);
+        pb[u] = syrk_load(bj, off + u * rowstep);
+    }
+
+    v4f32 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = v4f32{0.f, 0.f, 0.f, 0.f};
+
+    // this lane's operand rows: row 16 a + l%16 of the wave's 64, column k4 + l/16
+    const float* ai = Ai + (wr * 64 + (lane & 15)) * LD + (lane >> 4);
+    const float* aj = Aj + (wc * 64 + (lane & 15)) * LD + (lane >> 4);
+    for (int kc = 0; kc < bs; kc += KC) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            Ai[(sr + RS * u) * LD + sc] = (float)pa[u];
+            Aj[(sr + RS * u) * LD + sc] = (float)pb[u];
+        }
+        __syncthreads();
+        const int kn = kc + KC;
+        if (kn < bs) {
+            const unsigned off = syrk_col_off(lane_off + (unsigned)kn * 8, kn + sc < bs);
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                pa[u] = syrk_load(bi, off + u * rowstep);
+                pb[u] = syrk_load(bj, off + u * rowstep);
+            }
+        }
+        if (active) {
+#pragma unroll 2
+            for (int k4 = 0; k4 < KC; k4 += 4) {
+                float fa[4], fb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) fa[a] = ai[a * 16 * LD + k4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) fb[c] = aj[c * 16 * LD + k4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[c], acc[a][c], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    // read-modify-write by row block: all 16 loads of a block issued before its first store
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        double old[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = ri + wr * 64 + a * 16 + 4 * (lane >> 4) + r;
+                const int64_t gj = rj + wc * 64 + c * 16 + (lane & 15);
+                old[c][r] = (gi < n && gj <= gi) ? K[gi * n + gj] : 0.0;
+            }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = ri + wr * 64 + a * 16 + 4 * (lane >> 4) + r;
+                const int64_t gj = rj + wc * 64 + c * 16 + (lane & 15);
+                if (gi < n && gj <= gi) K[gi * n + gj] = old[c][r] - (double)acc[a][c][r];
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // Triangular sweeps for `dim` right-hand sides (component-major vectors of length n).
 // ---------------------------------------------------------------------------------------
@@ -1335,7 +1451,7 @@ int dense_panels(int64_t n) { return (int)((n + kPanel - 1) / kPanel); }
 int64_t dense_linv_elems(int64_t n) { return 2 * (int64_t)dense_panels(n) * kPanel * kPanel; }
 
 hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,
-                               double* Linv, int* info, hipStream_t st)
+                               double* Linv, int* info, hipStream_t st, bool f32_update)
 {
     if (n <= 0 || n >= kDenseMaxN) return hipErrorInvalidValue;
     hipLaunchKernelGGL(lm_int_zero_kernel, dim3(1), dim3(64), 0, st, info);
@@ -1381,8 +1497,12 @@ hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const
         const int width = (int)(kend - kb);
         if (rest >= 1024) {
             const int64_t nt = (rest + 127) / 128;
-            hipLaunchKernelGGL(lm_syrk128_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n, kb,
-                               width, kend);
+            if (f32_update)
+                hipLaunchKernelGGL(lm_syrk128_f32_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n,
+                                   kb, width, kend);
+            else
+                hipLaunchKernelGGL(lm_syrk128_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n, kb,
+                                   width, kend);
         } else {
             const int64_t nt = (rest + 63) / 64;
             hipLaunchKernelGGL(lm_syrk_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n, kb,

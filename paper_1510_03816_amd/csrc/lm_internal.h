@@ -305,8 +305,10 @@ hipError_t launch_convert(TO* y, const TI* x, int64_t m, hipStream_t st);
 constexpr int64_t kDenseMaxN = (int64_t)1 << 21;
 int dense_panels(int64_t n);
 int64_t dense_linv_elems(int64_t n);
+// f32_update: the trailing updates of 1024 rows or more multiply in single precision (a factor
+// for solves that only steer an iteration; about cond(K) times 1e-6 relative).
 hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,
-                               double* Linv, int* info, hipStream_t st);
+                               double* Linv, int* info, hipStream_t st, bool f32_update = false);
 // y <- (L L^T)^{-1} y for dim component vectors (component c at y + c * ldy), in place.
 hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, int dim, double* y, int64_t ldy,
                               hipStream_t st);

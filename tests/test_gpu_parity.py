@@ -614,6 +614,54 @@ def test_dense_ksolve_several_trailing_updates_matches_cg(sweeps, monkeypatch):
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("n,dim,sigma,tau", [(2500, 3, 0.15, 0.1), (5000, 3, 0.15, 0.1), (3000, 2, 0.1, 0.0)])
+def test_dense_ksolve_with_single_precision_updates(n, dim, sigma, tau, monkeypatch):
+    """The factor whose trailing updates multiply in single precision (matches with FP32 shoots
+    use it; LM_FACTOR_F32 = 1 forces it here): one (n = 2500) to three (n = 5000) updates take
+    that path, the rest and the diagonal blocks stay in double.  Against the oracle's Cholesky
+    solve the relative error stays within cond(K) times 1e-6, the single-precision rounding of
+    the updates carried through the solve."""
+    monkeypatch.setenv("LM_FACTOR_F32", "1")
+    X = inputs.fibonacci_sphere(n) if dim == 3 else inputs.config_curve2d(n).X
+    b = np.random.default_rng([131, n]).standard_normal(X.shape)
+    K = oracle.kmatrix(X, lm.CONON, sigma) + tau * np.eye(n)
+    st, L = oracle.cholesky(K)
+    assert st == 0
+    want = np.stack([oracle.cholesky_solve(L, b[c]) for c in range(dim)])
+    ev = np.linalg.eigvalsh(K)
+    cond = ev[-1] / ev[0]
+    prm = lm.make_params(dim, lm.CONON, sigma, tau=tau)
+    x = dev(b)
+    lm.lm_ksolve(prm, dev(X), x, x, solver=lm.SOLVE_DENSE)
+    err = rel_err(host(x), want)
+    print("n=%d cond %.1e single-precision updates: rel err %.2e" % (n, cond, err))
+    assert err <= 1e-6 * cond
+    monkeypatch.setenv("LM_FACTOR_F32", "0")
+    x64 = dev(b)
+    lm.lm_ksolve(prm, dev(X), x64, x64, solver=lm.SOLVE_DENSE)
+    assert rel_err(host(x64), want) <= max(1e-12, 1e-15 * cond)
+
+
+def test_mixed_precision_match_with_single_precision_factor_updates():
+    """A match with FP32 shoots switching to FP64 on a 2600-point curve, whose dense factor
+    takes a single-precision trailing update: it reaches tol = 1e-8 with an FP64 residual in
+    the oracle's iteration count or one more, and its q(1) is the oracle's shoot of the
+    momenta it returns."""
+    pr = inputs.config_curve2d(2600)
+    prm = lm.make_params(2, lm.CONON, pr.sigma, dtype=lm.F32)
+    p0 = torch.zeros((2, pr.n), dtype=torch.float64, device=DEV)
+    q1 = torch.empty_like(p0)
+    st, info, hist = lm.lm_feedback_match(prm, dev(pr.X), dev(pr.Y), p0, h=0.8, tol=1e-8, steps=20, max_iter=200,
+                                          q1=q1, f32_switch=1e-4)
+    ref = oracle.feedback_match(pr.X, pr.Y, 0, pr.sigma, 0.8, 1e-8, 20, max_iter=200)
+    print("mixed 2600: gpu %d updates | oracle %d" % (info.iters, ref.iters))
+    assert st == 0 and ref.status == 0
+    assert abs(info.iters - ref.iters) <= 1
+    assert info.resid_inf < 1e-8
+    oq, _ = oracle.shoot(pr.X, host(p0), 0, pr.sigma, 20)
+    assert rel_err(host(q1), oq) <= 1e-10
+
+
 def test_dense_ksolve_reports_singular_kernel_matrix():
     X = np.zeros((2, 300))          # every point at the origin: K is the all-ones matrix
     X[0, :] = np.linspace(0, 1e-9, 300)
