@@ -247,14 +247,16 @@ constexpr int64_t kSymOneWaveTiles = 128;
 // symmetric kernel takes 502 us per stage against 574 one-sided (conon: 3784 against 5542),
 // at N = 16384 149 against 120.
 constexpr int64_t kSymCutTiles = 768;
-// Single precision: the size rule never picks the symmetric kernel.  Its shared part (the
-// hardware 2^x and 1/sqrt) is too small a share of a pair for symmetry to pay for the column
-// traffic: 1973 us per stage at N = 65536 against 1996 for the one-sided kernel, slower at
-// every smaller size measured (557 against 519 at 32768, 176 against 144 at 16384).
+// Single precision (column sums in registers, two row tiles per wave), 3-D conon sphere
+// shoots, us per stage, one-sided against symmetric with two | four waves: N = 16384 138 against
+// 142 | 169, 24576 282 against 267 | 265, 32768 500-504 against 436-439 | 449-456, 49152 1073
+// against 956 | 911-914, 65536 1945 against 1708 | 1603, 98304 4215-4220 against 3769-3779 |
+// 3516.  Four rows per wave: 1686-1695 at 65536 (two waves).
 #ifndef LM_SYM_MIN_TILES_F32
-#define LM_SYM_MIN_TILES_F32 (int64_t(1) << 40)
+#define LM_SYM_MIN_TILES_F32 384
 #endif
 constexpr int64_t kSymMinTilesF32 = LM_SYM_MIN_TILES_F32;
+constexpr int64_t kSymF32FourWaveTiles = 768;
 // The VJP (heavier pairs, 154-162 VGPRs) gains from 128 tiles on: at N = 8192 one wave per
 // workgroup 136 us against 158 one-sided, at 16384 two waves 415 against 545, at 65536 two
 // waves 6436 against 9632 (four: 6594).

@@ -55,12 +55,12 @@ SymPlan plan_sym(int64_t n, bool force, int kind, bool cut)
     SymPlan sp{};
     const int64_t T = tiles_of(n);
     // LM_SYM_WAVES fixes the workgroup width and LM_SYM_ROWS the row tiles per wave (tuning
-    // runs, tests of every shape); four rows exist for double-precision sums without cutoff
+    // runs, tests of every shape); four rows exist for sums with forces and without cutoff
     const char* env = getenv("LM_SYM_WAVES");
     const int fixed = env ? atoi(env) : 0;
     const char* env_rows = getenv("LM_SYM_ROWS");
     const int fixed_rows = env_rows ? atoi(env_rows) : 0;
-    const bool wide_ok = kind == SYM_F64 && !cut;
+    const bool wide_ok = (kind == SYM_F64 || kind == SYM_F32) && !cut;
     int rows = kSymRows;
     int w = 0;
     if (fixed == 1 || fixed == 2 || fixed == 4 || fixed == 8) {
@@ -76,7 +76,9 @@ SymPlan plan_sym(int64_t n, bool force, int kind, bool cut)
         // (3-D Gaussian N = 65536 shoot 158 ms against 190 ms with 8-tile superblocks)
         rows = (wide_ok && fixed_rows != kSymRows) ? kSymRowsWide : kSymRows;
         w = cut ? 2 : 8 / rows;
-    } else if (T >= (kind == SYM_F32 ? kSymMinTilesF32 : kSymMinTiles)) {
+    } else if (kind == SYM_F32 && T >= kSymMinTilesF32) {
+        w = T >= kSymF32FourWaveTiles ? 4 : 2;
+    } else if (kind == SYM_F64 && T >= kSymMinTiles) {
         w = 2;
     } else if (kind == SYM_F64 && T >= kSymOneWaveTiles) {
         w = 1;

@@ -11,7 +11,8 @@
 // stages, K x, with or without tile skipping, and a batch's larger problems); targets distinct
 // from the sources keep the one-sided kernel in lm_kernels.hip.  In single precision a row
 // point's pairs with one column tile (64 steps) are summed in float and those sums in double,
-// as the one-sided kernel sums runs of 64 sources; column-side terms are added in double.
+// as the one-sided kernel sums runs of 64 sources, and a column point's terms from one wave's
+// rows likewise: in float over the tile, in double from there on.
 //
 // Decomposition.  The 64-point tiles are grouped into superblocks of B = R W tiles; a
 // workgroup of W wavefronts takes one pair (X, Y), X <= Y, of superblocks.  Wave w owns the
@@ -23,7 +24,9 @@
 //     steps every lane meets every point of the tile once;
 //   - the column-side terms go to the wave's own LDS array with ds_add_f64 at the same entry
 //     l + k (128 entries, the two halves added at the end), so no two lanes of an instruction
-//     touch the same word and each wave's sums have a fixed order;
+//     touch the same word and each wave's sums have a fixed order (single precision: in
+//     registers that rotate across the wavefront with the entries, added to the array once
+//     per tile);
 //   - after the tile, the W waves' arrays are added in wave order and written out.
 // In a diagonal superblock (X = Y) a row tile meets the column tiles after it symmetrically,
 // itself one-sidedly (all 64 x 64 ordered pairs, the self pair included), and skips the ones
@@ -50,6 +53,19 @@ namespace {
 // Values per staged column point: q and p, padded by one so that the 64 lanes' reads of
 // consecutive entries (an odd stride) fall in distinct LDS banks.
 __host__ __device__ constexpr int sym_stride(int dim) { return 2 * dim + 1; }
+
+// Words per component of a wave's column array: 128 in double precision (entry l + k at step
+// k, the two halves added at the end), 64 in single precision (entry l, written once per tile).
+template <class T>
+__host__ __device__ constexpr int sym_col_words() { return sizeof(T) == sizeof(double) ? 128 : 64; }
+
+// Dynamic LDS of a workgroup of `waves` wavefronts: their column arrays (EC components) and
+// the staged column tile.
+template <class T, int DIM>
+size_t sym_lds_bytes(int waves, int ec)
+{
+    return (size_t)waves * ec * sym_col_words<T>() * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
+}
 
 __device__ __forceinline__ int64_t tiles_of_dev(int64_t n) { return (n + kSymSteps - 1) / kSymSteps; }
 
@@ -97,20 +113,33 @@ __device__ __forceinline__ void sym_pair(const T (&qi)[DIM], const T (&qj)[DIM],
     }
 }
 
-// One step: the ROWS row points of this lane against column entry `src` (q then p).  With
-// JSIDE the column-side terms are added into the wave's column array at `acc` (component c
-// at acc[c * 128]).  The column arrays are double in both precisions: ds_add_f64 runs at
-// full rate, while single-precision LDS atomic adds measured 16 times slower for the kernel.
+// Lane l receives x of lane (l + 1) mod 64: a rotation of the whole wavefront by one lane
+// (DPP wave_rol; every source lane is in range, so bound_ctrl changes nothing and lets the
+// compiler fold the move into the add that consumes it).
+__device__ __forceinline__ float wave_rotate_down(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x134, 0xF, 0xF, true));
+}
+
+// One step: the ROWS row points of this lane against column entry cj (q then p).  With
+// JSIDE the column-side terms go to the column sums of that entry.  Double precision adds
+// them into the wave's column array at `acc` (component c at acc[c * 128]) with ds_add_f64.
+// Single precision keeps them in registers, ca[c]: lane l's value is the running sum of the
+// entry it meets at this step, and adding the step's terms to the neighbour's value (one
+// wavefront rotation, folded into the add) moves every sum along with its entry, since at
+// the next step lane l meets the entry lane l + 1 met at this one (the force sums hold +cw d).
 template <class T, int DIM, int KER, bool FORCE, int ROWS, bool JSIDE>
-__device__ __forceinline__ void sym_step(const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM], const T* __restrict__ src,
-                                         T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc)
+__device__ __forceinline__ void sym_step(const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM], const T (&cj)[2 * DIM],
+                                         T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc,
+                                         T (&ca)[2 * DIM])
 {
     using M = SymMath<T>;
+    constexpr bool REG = sizeof(T) == sizeof(float);   // column sums in registers
     T qj[DIM], pj[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        qj[c] = src[c];
-        pj[c] = src[DIM + c];
+        qj[c] = cj[c];
+        pj[c] = cj[DIM + c];
     }
     T tv[DIM], tf[DIM];
 #pragma unroll
@@ -130,16 +159,26 @@ __device__ __forceinline__ void sym_step(const T (&qi)[ROWS][DIM], const T (&pi)
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
                 f[r][c] = M::fma(cw, d[c], f[r][c]);
-                if (JSIDE) tf[c] = (r == 0) ? -cw * d[c] : M::fma(-cw, d[c], tf[c]);
+                // the column point's force is -cw d; single precision sums +cw d (FMAs without
+                // a negated operand) and subtracts the tile's sum once
+                if (JSIDE && REG) tf[c] = (r == 0) ? cw * d[c] : M::fma(cw, d[c], tf[c]);
+                if (JSIDE && !REG) tf[c] = (r == 0) ? -cw * d[c] : M::fma(-cw, d[c], tf[c]);
             }
         }
     }
-    if constexpr (JSIDE) {
+    if constexpr (JSIDE && REG) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            __hip_atomic_fetch_add(acc + c * 128, (double)tv[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            ca[c] = wave_rotate_down(ca[c]) + tv[c];
+            if (FORCE) ca[DIM + c] = wave_rotate_down(ca[DIM + c]) + tf[c];
+        }
+    } else if constexpr (JSIDE) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            __hip_atomic_fetch_add(acc + c * sym_col_words<T>(), (double)tv[c], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
             if (FORCE)
-                __hip_atomic_fetch_add(acc + (DIM + c) * 128, (double)tf[c], __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(acc + (DIM + c) * sym_col_words<T>(), (double)tf[c], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
@@ -147,15 +186,52 @@ __device__ __forceinline__ void sym_step(const T (&qi)[ROWS][DIM], const T (&pi)
 
 // All 64 steps of one (row tile(s), column tile) block.  jb = this lane's first column entry
 // (jbuf + lane * sym_stride(DIM)), acc = this lane's first word of the wave's column array.
+// In single precision the register column sums start at zero; after the 64th step lane l
+// holds those of entry l + 63, and one more rotation brings entry l to lane l, which adds
+// them (in double) to word l of the column array: each lane owns its word, so no atomics.
 template <class T, int DIM, int KER, bool FORCE, int ROWS, bool JSIDE>
 __device__ __forceinline__ void sym_block(const T (&qi)[ROWS][DIM], const T (&pi)[ROWS][DIM], const T* __restrict__ jb,
                                           T (&v)[ROWS][DIM], T (&f)[ROWS][DIM], double* __restrict__ acc)
 {
     constexpr int E = sym_stride(DIM);
-    for (int k0 = 0; k0 < kSymSteps; k0 += kSymUnroll) {
+    constexpr bool REG = JSIDE && sizeof(T) == sizeof(float);
+    T ca[2 * DIM];
 #pragma unroll
-        for (int u = 0; u < kSymUnroll; ++u)
-            sym_step<T, DIM, KER, FORCE, ROWS, JSIDE>(qi, pi, jb + (k0 + u) * E, v, f, acc + k0 + u);
+    for (int c = 0; c < 2 * DIM; ++c) ca[c] = (T)0;
+    if constexpr (sizeof(T) == sizeof(float)) {
+        // single precision: the next step's column entry is read while this one is evaluated
+        // (after the 64th step that is entry l + 64, the copy of entry l, never used)
+        T cj[2 * DIM];
+#pragma unroll
+        for (int c = 0; c < 2 * DIM; ++c) cj[c] = jb[c];
+        for (int k0 = 0; k0 < kSymSteps; k0 += kSymUnroll) {
+#pragma unroll
+            for (int u = 0; u < kSymUnroll; ++u) {
+                T nx[2 * DIM];
+#pragma unroll
+                for (int c = 0; c < 2 * DIM; ++c) nx[c] = jb[(k0 + u + 1) * E + c];
+                sym_step<T, DIM, KER, FORCE, ROWS, JSIDE>(qi, pi, cj, v, f, acc + k0 + u, ca);
+#pragma unroll
+                for (int c = 0; c < 2 * DIM; ++c) cj[c] = nx[c];
+            }
+        }
+    } else {
+        for (int k0 = 0; k0 < kSymSteps; k0 += kSymUnroll) {
+#pragma unroll
+            for (int u = 0; u < kSymUnroll; ++u) {
+                T cj[2 * DIM];
+#pragma unroll
+                for (int c = 0; c < 2 * DIM; ++c) cj[c] = jb[(k0 + u) * E + c];
+                sym_step<T, DIM, KER, FORCE, ROWS, JSIDE>(qi, pi, cj, v, f, acc + k0 + u, ca);
+            }
+        }
+    }
+    if constexpr (REG) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            acc[c * sym_col_words<T>()] += (double)wave_rotate_down(ca[c]);
+            if (FORCE) acc[(DIM + c) * sym_col_words<T>()] -= (double)wave_rotate_down(ca[DIM + c]);
+        }
     }
 }
 
@@ -174,6 +250,44 @@ __device__ __forceinline__ void sym_stage(T* __restrict__ jbuf, const T* __restr
         if (j < n) x = (c < DIM) ? ks * q[c * ld + j] : p[(c - DIM) * ld + j];
         jbuf[l * E + c] = x;
         jbuf[(l + 64) * E + c] = x;
+    }
+}
+
+// The same in two halves, so that the global reads of the next tile can be issued before the
+// current one is evaluated: sym_fetch reads this thread's values into registers, sym_put
+// stores them.  For workgroups where kSymFetch values per thread cover the tile
+// (sym_fetch_fits); narrower ones stage with sym_stage.
+constexpr int kSymFetch = 2;
+template <int DIM>
+__device__ __forceinline__ bool sym_fetch_fits()
+{
+    return (int)blockDim.x * kSymFetch >= kSymSteps * 2 * DIM;
+}
+template <class T, int DIM>
+__device__ __forceinline__ void sym_fetch(T (&x)[kSymFetch], const T* __restrict__ q, const T* __restrict__ p,
+                                          int64_t ld, int64_t n, int64_t J, T ks)
+{
+#pragma unroll
+    for (int u = 0; u < kSymFetch; ++u) {
+        const int t = threadIdx.x + u * blockDim.x;
+        const int c = t >> 6, l = t & 63;
+        const int64_t j = J * kSymSteps + l;
+        x[u] = (T)0;
+        if (t < kSymSteps * 2 * DIM && j < n) x[u] = (c < DIM) ? ks * q[c * ld + j] : p[(c - DIM) * ld + j];
+    }
+}
+template <class T, int DIM>
+__device__ __forceinline__ void sym_put(T* __restrict__ jbuf, const T (&x)[kSymFetch])
+{
+    constexpr int E = sym_stride(DIM);
+#pragma unroll
+    for (int u = 0; u < kSymFetch; ++u) {
+        const int t = threadIdx.x + u * blockDim.x;
+        const int c = t >> 6, l = t & 63;
+        if (t < kSymSteps * 2 * DIM) {
+            jbuf[l * E + c] = x[u];
+            jbuf[(l + 64) * E + c] = x[u];
+        }
     }
 }
 
@@ -257,8 +371,9 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const int64_t side = ROWS * (int64_t)nw;
-    double* region = lds_words;                                // [nw][EC][128]
-    T* jbuf = reinterpret_cast<T*>(region + nw * EC * 128);    // [128][E]
+    constexpr int CW = sym_col_words<T>();
+    double* region = lds_words;                               // [nw][EC][CW]
+    T* jbuf = reinterpret_cast<T*>(region + nw * EC * CW);    // [128][E]
 
     const bool diag = X == Y;
     const int64_t NT = tiles_of_dev(n);
@@ -313,17 +428,22 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
         }
     }
 
-    for (int t = threadIdx.x; t < nw * EC * 128; t += blockDim.x) region[t] = 0.0;
+    for (int t = threadIdx.x; t < nw * EC * CW; t += blockDim.x) region[t] = 0.0;
     const int64_t J0 = Y * side;
     const int64_t J1 = (J0 + side < NT) ? (J0 + side) : NT;
     if (need & 1u) sym_stage<T, DIM>(jbuf, q, p, ld, n, J0, ks);
     __syncthreads();
 
     const T* jb = jbuf + lane * E;
-    double* acc = region + wave * EC * 128 + lane;
+    double* acc = region + wave * EC * CW + lane;
     const int64_t slot_col = diag ? S : X;
     double* pc = part + slot_col * (2 * DIM) * n;
     for (int64_t J = J0; J < J1; ++J) {
+        // single precision: the next tile's reads are in flight while this one is evaluated
+        const bool fetch = sizeof(T) == sizeof(float) && sym_fetch_fits<DIM>();
+        const bool next = J + 1 < J1 && ((need >> (J + 1 - J0)) & 1u);
+        T nx[kSymFetch];
+        if (fetch && next) sym_fetch<T, DIM>(nx, q, p, ld, n, J + 1, ks);
         if constexpr (sizeof(T) == sizeof(double)) {
             sym_tile<T, DIM, KER, FORCE, CUT, ROWS>(diag, I, J, NT, qi, pi, jb, vs, fs, acc, box, rc2);
         } else {
@@ -345,21 +465,29 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
                 }
         }
         __syncthreads();
-        // column sums of tile J, in double: the waves in order, each wave's two halves in order
+        // column sums of tile J, in double: the waves in order (in double precision each wave's
+        // two halves in order)
         for (int t = threadIdx.x; t < EC * 64; t += blockDim.x) {
             const int c = t >> 6, l = t & 63;
             double s = 0.0;
             for (int w = 0; w < nw; ++w) {
-                double* rg = region + (w * EC + c) * 128;
+                double* rg = region + (w * EC + c) * CW;
                 s += rg[l];
-                s += rg[l + 64];
                 rg[l] = 0.0;
-                rg[l + 64] = 0.0;
+                if (CW == 128) {
+                    s += rg[l + 64];
+                    rg[l + 64] = 0.0;
+                }
             }
             const int64_t j = J * kSymSteps + l;
             if (j < n) pc[c * n + j] = (c < DIM) ? s : s * fscale;
         }
-        if (J + 1 < J1 && ((need >> (J + 1 - J0)) & 1u)) sym_stage<T, DIM>(jbuf, q, p, ld, n, J + 1, ks);
+        if (next) {
+            if (fetch)
+                sym_put<T, DIM>(jbuf, nx);
+            else
+                sym_stage<T, DIM>(jbuf, q, p, ld, n, J + 1, ks);
+        }
         __syncthreads();
     }
 
@@ -419,9 +547,9 @@ hipError_t launch_sym_t(const SymArgs<T>& a, int waves, hipStream_t st)
     const int64_t S = a.nsb;
     const dim3 grid((unsigned)(S * (S + 1) / 2));
     if (a.rows == kSymRowsWide) {
-        if constexpr (sizeof(T) == sizeof(double) && FORCE) {
+        if constexpr (FORCE) {
             if (a.box == nullptr) {
-                const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
+                const size_t lds = sym_lds_bytes<T, DIM>(waves, EC);
                 hipLaunchKernelGGL((lm_sym_pair_wide_kernel<T, DIM, KER>), grid, dim3(64 * waves), lds, st, a);
                 return hipGetLastError();
             }
@@ -432,7 +560,7 @@ hipError_t launch_sym_t(const SymArgs<T>& a, int waves, hipStream_t st)
     } else if (a.rows != kSymRows) {
         return hipErrorInvalidValue;
     }
-    const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
+    const size_t lds = sym_lds_bytes<T, DIM>(waves, EC);
     const dim3 block(64 * waves);
     if (a.box == nullptr) {
         hipLaunchKernelGGL((lm_sym_pair_kernel<T, DIM, KER, FORCE, false>), grid, block, lds, st, a);
@@ -471,7 +599,7 @@ static hipError_t launch_batch_sym_t(const BatchArgs<T>& a, hipStream_t st)
 {
     constexpr int EC = FORCE ? 2 * DIM : DIM;
     const int waves = a.sym_waves;
-    const size_t lds = (size_t)waves * EC * 128 * sizeof(double) + (size_t)128 * sym_stride(DIM) * sizeof(T);
+    const size_t lds = sym_lds_bytes<T, DIM>(waves, EC);
     hipLaunchKernelGGL((lm_batch_sym_kernel<T, DIM, KER, FORCE>), dim3((unsigned)a.nsym), dim3(64 * waves), lds, st, a);
     return hipGetLastError();
 }

@@ -96,19 +96,22 @@ def test_sym_rhs_matches_oracle(n, dim, kernel, waves, dtype):
         assert np.all(dp == 0.0)
 
 
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
 @pytest.mark.parametrize("waves", [1, 2, 4])
 @pytest.mark.parametrize("kernel", [lm.CONON, lm.GAUSS])
 @pytest.mark.parametrize("dim", [2, 3])
 @pytest.mark.parametrize("n", [1, 65, 700, 3007])
-def test_sym_wide_rows_match_oracle(n, dim, kernel, waves):
+def test_sym_wide_rows_match_oracle(n, dim, kernel, waves, dtype):
     """Four row tiles per wave (the widest tier's kernel), forced at small sizes: the sums
     with forces run it, the velocity-only K x of a CG solve falls back to two rows."""
     q, p = inputs.random_state(n, dim, seed=[120, n, dim], box=1.0, pscale=0.3)
+    q, p = rounded(q, dtype), rounded(p, dtype)
     sigma, tau = (0.3 if dim == 3 else 0.25), 0.1
     dq_o, dp_o = oracle.rhs(q, p, kernel, sigma, tau)
+    print("sym wide rhs n=%d dim=%d kernel=%d waves=%d dtype=%d" % (n, dim, kernel, waves, dtype), flush=True)
     with _env(LM_SYM=1, LM_SYM_WAVES=waves, LM_SYM_ROWS=4):
-        dq, dp = gpu_rhs(q, p, kernel, sigma, tau)
-    assert rel_err(dq, dq_o) <= 1e-10 and rel_err(dp, dp_o) <= 1e-10
+        dq, dp = gpu_rhs(q, p, kernel, sigma, tau, dtype)
+    assert rel_err(dq, dq_o) <= TOL[dtype] and rel_err(dp, dp_o) <= TOL[dtype]
 
 
 def test_sym_wide_rows_shoot_and_velocity_only_products():

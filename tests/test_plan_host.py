@@ -83,8 +83,21 @@ def test_one_sided_split_rule(monkeypatch):
     assert p["workgroups"] == 79 * 39 and p["partial_slots"] == 39
 
 
-def test_single_precision_keeps_one_sided_kernel_and_cutoff_runs_symmetric_in_double():
-    assert plan(65536, dtype=lm.F32)["symmetric"] == 0
+@pytest.mark.parametrize("n,waves", [(24512, 0), (24513, 2), (32768, 2), (49088, 2), (49089, 4), (65536, 4),
+                                     (131072, 4)])
+def test_single_precision_size_rule(n, waves):
+    """Single precision: the one-sided kernel below 384 tiles, then the symmetric kernel with
+    two row tiles per wave, two waves and four from 768 tiles."""
+    p = plan(n, dtype=lm.F32)
+    T = -(-n // 64)
+    if waves == 0:
+        assert p["symmetric"] == 0
+    else:
+        assert p["symmetric"] == 1 and p["waves"] == waves and p["rows"] == 2
+        assert (p["workgroups"], p["partial_slots"]) == sym(T, waves)[1:]
+
+
+def test_cutoff_runs_symmetric_in_double_only():
     p = plan(65536, cutoff=0.3)                 # tile skipping: two rows, two waves, 4-tile superblocks
     assert p["symmetric"] == 1 and p["rows"] == 2 and p["waves"] == 2 and p["partial_slots"] == 257
     assert plan(49088, cutoff=0.3)["symmetric"] == 0        # 768 tiles needed with tile skipping
@@ -107,7 +120,7 @@ def test_environment_overrides(monkeypatch):
     monkeypatch.setenv("LM_SYM_WAVES", "4")
     p = plan(65536)
     assert p["waves"] == 4 and p["rows"] == 4 and (p["workgroups"], p["partial_slots"]) == sym(1024, 4, 4)[1:]
-    assert plan(65536, dtype=lm.F32)["rows"] == 2     # four rows: double precision only
+    assert plan(65536, dtype=lm.F32)["rows"] == 4     # forced: four rows in single precision too
     monkeypatch.delenv("LM_SYM_ROWS")
     monkeypatch.setenv("LM_SYM_WAVES", "3")   # not a width: the size rule applies
     assert plan(65536)["waves"] == 2 and plan(65536)["rows"] == 4
