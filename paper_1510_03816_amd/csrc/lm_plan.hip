@@ -11,10 +11,10 @@ PairPlan plan_pair(int64_t nt, int64_t ns, bool cut, bool sym_ok, int kind)
 {
     PairPlan pl{};
     pl.itiles = (nt + kTile - 1) / kTile;
-    // tile skipping runs symmetric in double precision only, and by the size rule only from
-    // kSymCutTiles tiles: with much skipped, the symmetric kernel's fixed costs (superblock
-    // tests, the flags, the finish) need a large N to pay off
-    if (sym_ok && nt == ns && (!cut || kind == SYM_F64)) {
+    // tile skipping runs symmetric (sums with forces) by the size rule only from kSymCutTiles
+    // tiles: with much skipped, the symmetric kernel's fixed costs (superblock tests, the
+    // flags, the finish) need a large N to pay off
+    if (sym_ok && nt == ns && (!cut || kind == SYM_F64 || kind == SYM_F32)) {
         const char* e = getenv("LM_SYM");
         const int mode = e ? atoi(e) : -1;
         const bool small_cut = cut && mode != 1 && pl.itiles < kSymCutTiles;
@@ -77,7 +77,8 @@ SymPlan plan_sym(int64_t n, bool force, int kind, bool cut)
         rows = (wide_ok && fixed_rows != kSymRows) ? kSymRowsWide : kSymRows;
         w = cut ? 2 : 8 / rows;
     } else if (kind == SYM_F32 && T >= kSymMinTilesF32) {
-        w = T >= kSymF32FourWaveTiles ? 4 : 2;
+        // with tile skipping superblocks of 4 tiles, as in double precision
+        w = (T >= kSymF32FourWaveTiles && !cut) ? 4 : 2;
     } else if (kind == SYM_F64 && T >= kSymMinTiles) {
         w = 2;
     } else if (kind == SYM_F64 && T >= kSymOneWaveTiles) {

@@ -564,8 +564,8 @@ hipError_t launch_sym_t(const SymArgs<T>& a, int waves, hipStream_t st)
     const dim3 block(64 * waves);
     if (a.box == nullptr) {
         hipLaunchKernelGGL((lm_sym_pair_kernel<T, DIM, KER, FORCE, false>), grid, block, lds, st, a);
-    } else if constexpr (sizeof(T) == sizeof(double) && FORCE) {
-        // tile skipping: double-precision sums with forces (the shoot's stages)
+    } else if constexpr (FORCE) {
+        // tile skipping: sums with forces (the shoot's stages)
         hipLaunchKernelGGL((lm_sym_pair_kernel<T, DIM, KER, FORCE, true>), grid, block, lds, st, a);
     } else {
         return hipErrorInvalidValue;

@@ -97,12 +97,14 @@ def test_single_precision_size_rule(n, waves):
         assert (p["workgroups"], p["partial_slots"]) == sym(T, waves)[1:]
 
 
-def test_cutoff_runs_symmetric_in_double_only():
+def test_cutoff_size_rule():
     p = plan(65536, cutoff=0.3)                 # tile skipping: two rows, two waves, 4-tile superblocks
     assert p["symmetric"] == 1 and p["rows"] == 2 and p["waves"] == 2 and p["partial_slots"] == 257
     assert plan(49088, cutoff=0.3)["symmetric"] == 0        # 768 tiles needed with tile skipping
     assert plan(49152, cutoff=0.3)["symmetric"] == 1
-    assert plan(65536, dtype=lm.F32, cutoff=0.3)["symmetric"] == 0
+    p = plan(65536, dtype=lm.F32, cutoff=0.3)   # single precision: the same shape
+    assert p["symmetric"] == 1 and p["rows"] == 2 and p["waves"] == 2 and p["partial_slots"] == 257
+    assert plan(49088, dtype=lm.F32, cutoff=0.3)["symmetric"] == 0
     assert plan(100, cutoff=0.3)["small"] == 0
 
 
