@@ -141,8 +141,8 @@ lm_status lm_rhs(const lm_params *params, int64_t n, const void *q, const void *
 /* Launch plan of the pair sums of n points under `params` (host only: no GPU work, no
  * allocation): the kernel that lm_rhs and every RK4 stage of lm_shoot use, and its shape.
  * symmetric = 1: each unordered pair is evaluated once and serves both particles (double
- * precision, every pair, from 128 tiles of 64 points on); 0: the one-sided kernel, one
- * target per lane.  The environment variable LM_SYM = 0 or 1 overrides that size rule and
+ * precision from 128 tiles of 64 points on, single precision from 384; with tile skipping
+ * from 768 in both); 0: the one-sided kernel, one target per lane.  The environment variable LM_SYM = 0 or 1 overrides that size rule and
  * LM_SYM_WAVES = 1, 2, 4 or 8 fixes the symmetric kernel's workgroup width (for tuning and
  * tests; both are read at every launch).  small = 1: shoots of this size (at most 128 points,
  * no cutoff) run whole inside one workgroup instead, of 4 or 8 waves by size (LM_SMALL = 0 or
@@ -348,10 +348,10 @@ typedef struct lm_batch_tuning {
                                              0 = one wave per work item */
     int32_t graph_steps;                  /* RK4 steps per captured hipGraph in a shoot;
                                              0 = every kernel launched directly */
-    int32_t sym_min;                      /* double precision: problems of at least sym_min
-                                             points evaluate each unordered pair once (the
-                                             symmetric kernel, one superblock pair per
-                                             workgroup); 0 = never */
+    int32_t sym_min;                      /* problems of at least sym_min points evaluate
+                                             each unordered pair once (the symmetric
+                                             kernel, one superblock pair per workgroup);
+                                             0 = never */
     int32_t sym_waves;                    /* its wavefronts per workgroup: 1, 2, 4 or 8 */
     double stage_us;                      /* written by lm_batch_autotune: measured time of
                                              one stage with this shape (microseconds) */
@@ -363,7 +363,7 @@ lm_status lm_batch_default_tuning(int32_t B, const int64_t *offs, lm_batch_tunin
 /* Autotuner: times candidate launch shapes on this batch (right-hand-side evaluations at
  * (q, p), dim x ntot device arrays of params->dtype, and short graph-replayed shoots) with
  * HIP events, one parameter at a time from the default (grid size, then each occupied
- * bucket's source split, then in double precision the symmetric threshold and width, then the
+ * bucket's source split, then the symmetric threshold and width, then the
  * steps per graph), and writes the fastest to *out.
  * Synchronous; q and p are not modified. */
 lm_status lm_batch_autotune(const lm_params *params, int32_t B, const int64_t *offs,

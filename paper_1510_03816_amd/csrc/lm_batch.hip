@@ -23,8 +23,9 @@
 
 namespace {
 
-// Default size from which a batch's double-precision problems use the symmetric kernel (the
-// autotuner's choice on the 256-curve workload: 256, two waves per workgroup).
+// Default size from which a batch's problems use the symmetric kernel (the autotuner's choice
+// on the 256-curve workload in both precisions: 256; FP64 with two waves per workgroup, FP32
+// with one or two).
 constexpr int32_t kDefaultSymMin = 256;
 
 using namespace lmh;
@@ -141,7 +142,7 @@ struct BatchPlan {
 // batched match, on a small part of the chip: one 4065-point problem split in two is 128 waves
 // on 1024 SIMDs, and in double precision with two-wave superblocks 72.
 lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs_d, const lm_batch_tuning& t,
-                    Workspace& ws, BatchPlan* pl, hipStream_t st, bool f64, const std::vector<int>* include = nullptr,
+                    Workspace& ws, BatchPlan* pl, hipStream_t st, const std::vector<int>* include = nullptr,
                     int64_t min_waves = 0)
 {
     struct Item {
@@ -153,7 +154,7 @@ lm_status make_plan(int dim, int32_t B, const int64_t* offs, const int64_t* offs
     std::vector<int64_t> part_off((size_t)B, -1);
     int64_t part_elems = 0;
     auto planned = [&](int32_t b) { return !include || (*include)[b]; };
-    auto symmetric = [&](int64_t nb) { return f64 && t.sym_min > 0 && nb >= t.sym_min; };
+    auto symmetric = [&](int64_t nb) { return t.sym_min > 0 && nb >= t.sym_min; };
 
     // waves of the symmetric problems with sw waves per workgroup (superblocks of kSymRows * sw
     // tiles, one workgroup per superblock pair)
@@ -510,7 +511,7 @@ lm_status shoot_batched_t(const lm_params* prm, int32_t B, const int64_t* offs, 
     int64_t* offs_d;
     LM_TRY(upload_offs(B, offs, ws, &offs_d, st));
     BatchPlan pl;
-    LM_TRY(make_plan(prm->dim, B, offs, offs_d, tun, ws, &pl, st, sizeof(T) == 8));
+    LM_TRY(make_plan(prm->dim, B, offs, offs_d, tun, ws, &pl, st));
     const int64_t m = (int64_t)prm->dim * pl.ntot;
     if (q1 != q0) LM_HIP(hipMemcpyAsync(q1, q0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
     if (p1 != p0) LM_HIP(hipMemcpyAsync(p1, p0, m * sizeof(T), hipMemcpyDeviceToDevice, st));
@@ -587,7 +588,7 @@ lm_status autotune_t(const lm_params* prm, int32_t B, const int64_t* offs, const
     auto stage_time = [&](const lm_batch_tuning& t, double* ms) -> lm_status {
         Workspace pws(st);
         BatchPlan pl;
-        LM_TRY(make_plan(prm->dim, B, offs, offs_d, t, pws, &pl, st, sizeof(T) == 8));
+        LM_TRY(make_plan(prm->dim, B, offs, offs_d, t, pws, &pl, st));
         return time_ms([&]() { return batch_rhs<T>(prm, pl, q, p, dq, dp, st); }, 5, st, ms);
     };
     double cur;
@@ -605,8 +606,8 @@ lm_status autotune_t(const lm_params* prm, int32_t B, const int64_t* offs, const
             *best = t;
         }
     }
-    // double precision: the size from which problems go symmetric (0 = none), then its width
-    if (sizeof(T) == 8) {
+    // the size from which problems go symmetric (0 = none), then its width
+    {
         for (int sm : {0, 512, 1024, 2048, 4096}) {   // the default, 256, is the starting point
             lm_batch_tuning t = *best;
             t.sym_min = sm;
@@ -652,7 +653,7 @@ lm_status autotune_t(const lm_params* prm, int32_t B, const int64_t* offs, const
     {
         Workspace pws(st);
         BatchPlan pl;
-        LM_TRY(make_plan(prm->dim, B, offs, offs_d, *best, pws, &pl, st, sizeof(T) == 8));
+        LM_TRY(make_plan(prm->dim, B, offs, offs_d, *best, pws, &pl, st));
         double bt = 0.0;
         int bg = 0;
         for (int gs : {0, 1, 5, 20}) {
@@ -832,13 +833,13 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
         if (any64 && want64 != in64) {
             g64.reset();
             pws64.reset(new Workspace(st));
-            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws64, &pl64, st, true, &want64, fill));
+            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws64, &pl64, st, &want64, fill));
             in64 = want64;
         }
         if (any32 && want32 != in32) {
             g32.reset();
             pws32.reset(new Workspace(st));
-            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws32, &pl32, st, false, &want32, fill));
+            LM_TRY(make_plan(dim, B, offs, offs_d, tun, *pws32, &pl32, st, &want32, fill));
             in32 = want32;
         }
 
@@ -947,7 +948,7 @@ lm_status match_batched(const lm_params* prm, const lm_match_opts* o, int32_t B,
     {
         Workspace hws(st);
         BatchPlan pl;
-        LM_TRY(make_plan(dim, B, offs, offs_d, tun, hws, &pl, st, true));
+        LM_TRY(make_plan(dim, B, offs, offs_d, tun, hws, &pl, st));
         // H is the kernel form alone (equation "H"): the inexact advection weight tau is not
         // part of it, so the velocities are summed with tau = 0
         lm::EpiArgs<double> ev{};
@@ -1027,7 +1028,7 @@ lm_status lm_rhs_batched(const lm_params* prm, int32_t B, const int64_t* offs, c
     int64_t* offs_d;
     LM_TRY(upload_offs(B, offs, ws, &offs_d, st));
     BatchPlan pl;
-    LM_TRY(make_plan(prm->dim, B, offs, offs_d, t, ws, &pl, st, prm->dtype == LM_F64));
+    LM_TRY(make_plan(prm->dim, B, offs, offs_d, t, ws, &pl, st));
     if (prm->dtype == LM_F32)
         return batch_rhs<float>(prm, pl, (const float*)q, (const float*)p, (float*)dq, (float*)dp, st);
     return batch_rhs<double>(prm, pl, (const double*)q, (const double*)p, (double*)dq, (double*)dp, st);

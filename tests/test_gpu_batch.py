@@ -425,31 +425,33 @@ def _sym_tuning(offs, sym_min, waves, split=1):
     return t
 
 
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
 @pytest.mark.parametrize("waves", [1, 2, 4, 8])
 @pytest.mark.parametrize("dim,kernel,tau", [(2, lm.CONON, 0.0), (3, lm.CONON, 0.1), (2, lm.GAUSS, 0.2),
                                             (3, lm.GAUSS, 0.0)])
-def test_batched_symmetric_rhs_matches_oracle(dim, kernel, tau, waves):
+def test_batched_symmetric_rhs_matches_oracle(dim, kernel, tau, waves, dtype):
     """Every problem symmetric (sym_min = 1), at every width: ragged tiles and superblocks,
     one-point and one-tile problems."""
     offs, q, p = ragged_batch(SIZES + [1100], dim, seed=304)
-    prm = lm.make_params(dim, kernel, 0.3, tau=tau)
-    dq, dp = torch.empty_like(dev(q)), torch.empty_like(dev(q))
-    lm.lm_rhs_batched(prm, offs, dev(q), dev(p), dq, dp, tuning=_sym_tuning(offs, 1, waves))
+    q, p = rounded(q, dtype), rounded(p, dtype)
+    prm = lm.make_params(dim, kernel, 0.3, tau=tau, dtype=dtype)
+    dq, dp = torch.empty_like(dev(q, dtype)), torch.empty_like(dev(q, dtype))
+    lm.lm_rhs_batched(prm, offs, dev(q, dtype), dev(p, dtype), dq, dp, tuning=_sym_tuning(offs, 1, waves))
     torch.cuda.synchronize()
     gq, gp = host(dq), host(dp)
     for b in range(len(offs) - 1):
         s = slice(offs[b], offs[b + 1])
         oq, op = oracle.rhs(q[:, s], p[:, s], kernel, 0.3, tau)
-        assert rel_err(gq[:, s], oq) <= 1e-10, (b, rel_err(gq[:, s], oq))
+        assert rel_err(gq[:, s], oq) <= TOL[dtype], (b, rel_err(gq[:, s], oq))
         if offs[b + 1] - offs[b] > 1:
-            assert rel_err(gp[:, s], op) <= 1e-10, (b, rel_err(gp[:, s], op))
+            assert rel_err(gp[:, s], op) <= TOL[dtype], (b, rel_err(gp[:, s], op))
         else:
             assert np.all(gp[:, s] == 0.0)
 
 
 def test_batched_mixed_symmetric_and_split_problems():
     """Problems from 200 points symmetric, the smaller ones one-sided with split sums, in the
-    same stage; single precision ignores the threshold."""
+    same stage, in both precisions."""
     offs, q, p = ragged_batch(SIZES + [1100], 2, seed=305)
     for dtype in (lm.F64, lm.F32):
         qq, pp = rounded(q, dtype), rounded(p, dtype)
@@ -465,23 +467,37 @@ def test_batched_mixed_symmetric_and_split_problems():
                 assert rel_err(host(dp)[:, s], op) <= TOL[dtype], (dtype, b)
 
 
-def test_batched_symmetric_shoot_graph_replays_and_oracle():
-    offs, q, p = ragged_batch([40, 300, 1029, 7, 513], 2, seed=306, pscale=0.3)
-    prm = lm.make_params(2, lm.CONON, 0.2)
+@pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
+def test_batched_symmetric_shoot_graph_replays_and_oracle(dtype):
+    """Problems from 100 points symmetric, graph-replayed and direct.  Single precision runs
+    curves like the matching workloads: on the random states the shoot amplifies rounding so
+    much that the FP32 one-sided kernel itself lands 5e-4 from the oracle in p (FP64 8e-12)."""
+    if dtype == lm.F64:
+        offs, q, p = ragged_batch([40, 300, 1029, 7, 513], 2, seed=306, pscale=0.3)
+        sigma, T, steps = 0.2, 0.9, 7
+    else:
+        sizes, offs, q, Y = curve_batch(6, 1100)
+        p = np.concatenate([inputs.bench_momentum(q[:, offs[b]:offs[b + 1]], Y[:, offs[b]:offs[b + 1]],
+                                                  inputs.curve_kernel_mass(int(sizes[b]), 2 * np.pi, 0.1, 0))
+                            for b in range(len(sizes))], axis=1)
+        sigma, T, steps = 0.1, 1.0, 20
+        assert max(sizes) >= 100
+    q, p = rounded(q, dtype), rounded(p, dtype)
+    prm = lm.make_params(2, lm.CONON, sigma, dtype=dtype)
     t = _sym_tuning(offs, 100, 2)
     out = []
     for gs in [0, 3, 0]:
         t.graph_steps = gs
-        q1, p1 = torch.empty_like(dev(q)), torch.empty_like(dev(q))
-        lm.lm_shoot_batched(prm, offs, dev(q), dev(p), 0.9, 7, q1, p1, tuning=t)
+        q1, p1 = torch.empty_like(dev(q, dtype)), torch.empty_like(dev(q, dtype))
+        lm.lm_shoot_batched(prm, offs, dev(q, dtype), dev(p, dtype), T, steps, q1, p1, tuning=t)
         torch.cuda.synchronize()
         out.append((host(q1), host(p1)))
     for gq, gp in out[1:]:
         assert np.array_equal(gq, out[0][0]) and np.array_equal(gp, out[0][1])
     for b in range(len(offs) - 1):
         s = slice(offs[b], offs[b + 1])
-        oq, op = oracle.shoot(q[:, s], p[:, s], lm.CONON, 0.2, 7, T=0.9)
-        assert rel_err(out[0][0][:, s], oq) <= 1e-10 and rel_err(out[0][1][:, s], op) <= 1e-10
+        oq, op = oracle.shoot(q[:, s], p[:, s], lm.CONON, sigma, steps, T=T)
+        assert rel_err(out[0][0][:, s], oq) <= TOL[dtype] and rel_err(out[0][1][:, s], op) <= TOL[dtype], b
 
 
 def test_batched_symmetric_feedback_matches_oracle_per_problem():
