@@ -111,7 +111,7 @@ lm_status pair_eval(const lm_params* prm, bool force, const T* qs, const T* ps, 
     kernel_scales(prm, &a.kq, &a.wscale);
     a.tscale = tscale;
     if (tscale > 0.0 && prm->kernel != LM_KERNEL_CONON) a.wscale /= std::sqrt(-a.kq);
-    a.part = part;
+    a.part = reinterpret_cast<T*>(part);   // the workspace is sized in doubles; slots are T
     a.box_s = cut.box_s;
     a.box_t = cut.box_t;
     a.rc2 = cut.rc2;

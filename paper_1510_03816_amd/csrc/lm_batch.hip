@@ -281,7 +281,7 @@ lm_status batch_eval(const lm_params* prm, const BatchPlan& pl, const T* q, cons
     a.items = pl.items_d;
     a.nitems = pl.nitems;
     a.part_off = pl.part_off_d;
-    a.part = pl.part;
+    a.part = reinterpret_cast<T*>(pl.part);   // sized in doubles; the partial sums are T
     a.sym_items = pl.sym_items_d;
     a.nsym = pl.nsym;
     a.sym_waves = pl.sym_waves;

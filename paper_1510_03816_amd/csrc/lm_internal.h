@@ -72,7 +72,8 @@ struct PairArgs {
     // (1 when they are in those units already); wscale then carries the Gaussian's 1/k.  Only
     // the one-sided kernel without tile skipping takes this form.
     double tscale;
-    double* part;      // split partial sums (nsplit, 2 dim, nt), used when nsplit > 1
+    T* part;           // split partial sums (nsplit, 2 dim, nt), used when nsplit > 1, in T (each
+                       // partial is a double sum rounded once; they are added in double)
     const double* box_s;   // cutoff mode: source tile boxes (8 doubles per 64-point tile), else null
     const double* box_t;   // cutoff mode: target tile boxes
     double rc2;            // cutoff radius squared
@@ -124,8 +125,8 @@ struct BatchArgs {
     const int64_t* offs;     // problem b owns [offs[b], offs[b+1])
     const int4* items;       // (problem, first target, chunk, chunks), sorted by cost
     int32_t nitems;
-    const int64_t* part_off; // split problems: offset of their partials in part (doubles)
-    double* part;
+    const int64_t* part_off; // split problems: offset of their partials in part (elements)
+    T* part;                 // partial sums in T, added in double
     double kq;
     double wscale;
     EpiArgs<T> epi;          // over the concatenated arrays (n = ntot)
@@ -203,7 +204,7 @@ struct SymArgs {
     int rows;            // row tiles per wave: kSymRows, or kSymRowsWide (double, forces, no cutoff)
     double kq;
     double wscale;
-    double* part;        // (nsb + 1, 2 dim, n) partial sums
+    T* part;             // (nsb + 1, 2 dim, n) partial sums in T, added in double
     const double* box;   // tile skipping: tile boxes (8 doubles per 64-point tile), else null
     double rc2;          // cutoff radius squared
     uint8_t* flags;      // tile skipping: one byte per superblock pair, 0 = nothing written

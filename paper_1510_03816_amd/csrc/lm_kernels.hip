@@ -356,11 +356,11 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_pair_kernel(PairArgs<T> a)
     }
     if (!live) return;
     if (gridDim.y > 1) {
-        double* part = a.part + (int64_t)blockIdx.y * (2 * DIM) * a.nt;
+        T* part = a.part + (int64_t)blockIdx.y * (2 * DIM) * a.nt;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            part[c * a.nt + i] = v[c];
-            part[(DIM + c) * a.nt + i] = f[c];
+            part[c * a.nt + i] = (T)v[c];
+            part[(DIM + c) * a.nt + i] = (T)f[c];
         }
         return;
     }
@@ -381,7 +381,7 @@ constexpr int kFinishListSlots = 2048;
 // (At most 128 VGPRs: four workgroups per CU, so the 1024 workgroups of an N = 65536 stage
 // run in one round.)
 template <class T, int DIM, bool FORCE>
-__global__ __launch_bounds__(256, 4) void lm_finish_kernel(const double* __restrict__ part, int nsplit,
+__global__ __launch_bounds__(256, 4) void lm_finish_kernel(const T* __restrict__ part, int nsplit,
                                                         int64_t nt, EpiArgs<T> e, const uint8_t* __restrict__ flags,
                                                         int64_t sbp)
 {
@@ -405,10 +405,10 @@ __global__ __launch_bounds__(256, 4) void lm_finish_kernel(const double* __restr
         // every slot written: a plain strided loop (the compiler keeps the loads in flight;
         // 89 against 94 us per stage at N = 65536 for the explicit four-slot batches below)
         if (live) {
-            const double* ps = part + i;
+            const T* ps = part + i;
             for (int s = wave; s < nsplit; s += 4)
 #pragma unroll
-                for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
+                for (int c = 0; c < NV; ++c) acc[c] += (double)ps[s * slot + c * nt];
         }
     } else if (nsplit <= kFinishListSlots) {
         // with tile skipping most slots hold nothing: the workgroup marks the written slots
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256, 4) void lm_finish_kernel(const double* __restr
         }
         __syncthreads();
         if (live) {
-            const double* ps = part + i;
+            const T* ps = part + i;
             const int* ls = list[wave];
             int j = 0;
             for (; j + 3 < cnt; j += 4) {
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(256, 4) void lm_finish_kernel(const double* __restr
                 for (int u = 0; u < 4; ++u) {
                     const int64_t s = ls[j + u];
 #pragma unroll
-                    for (int c = 0; c < NV; ++c) x[u][c] = ps[s * slot + c * nt];
+                    for (int c = 0; c < NV; ++c) x[u][c] = (double)ps[s * slot + c * nt];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
@@ -450,17 +450,17 @@ __global__ __launch_bounds__(256, 4) void lm_finish_kernel(const double* __restr
             for (; j < cnt; ++j) {
                 const int64_t s = ls[j];
 #pragma unroll
-                for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
+                for (int c = 0; c < NV; ++c) acc[c] += (double)ps[s * slot + c * nt];
             }
         }
     } else if (live) {
         // (more slots than the list holds: the partial-sum cap keeps the symmetric plans
         // below it, so this plain loop is a fallback)
-        const double* ps = part + i;
+        const T* ps = part + i;
         for (int s = wave; s < nsplit; s += 4)
             if (written(s))
 #pragma unroll
-                for (int c = 0; c < NV; ++c) acc[c] += ps[s * slot + c * nt];
+                for (int c = 0; c < NV; ++c) acc[c] += (double)ps[s * slot + c * nt];
     }
     if (wave > 0)
 #pragma unroll
@@ -882,7 +882,7 @@ static hipError_t launch_pair_t(const PairArgs<T>& a, const PairPlan& pl, hipStr
     }
     if (err != hipSuccess || pl.nsplit == 1) return err;
     hipLaunchKernelGGL((lm_finish_kernel<T, DIM, FORCE>), dim3(blocks_for(a.nt, 64, 1u << 30)), dim3(256), 0, st,
-                       (const double*)a.part, pl.nsplit, a.nt, a.epi, (const uint8_t*)flags, sbp);
+                       (const T*)a.part, pl.nsplit, a.nt, a.epi, (const uint8_t*)flags, sbp);
     return hipGetLastError();
 }
 
@@ -1113,11 +1113,11 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_batch_pair_kernel(BatchArgs
         if (w.w == 1) {
             epilogue<T, DIM, FORCE>(a.epi, a.ntot, off + il, v, f);
         } else {
-            double* pp = a.part + a.part_off[w.x] + (int64_t)w.z * (2 * DIM) * nb;
+            T* pp = a.part + a.part_off[w.x] + (int64_t)w.z * (2 * DIM) * nb;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                pp[c * nb + il] = v[c];
-                pp[(DIM + c) * nb + il] = f[c];
+                pp[c * nb + il] = (T)v[c];
+                pp[(DIM + c) * nb + il] = (T)f[c];
             }
         }
     }
@@ -1138,19 +1138,19 @@ __global__ __launch_bounds__(kTile * kWaves) void lm_batch_finish_kernel(BatchAr
         const int64_t nb = a.offs[w.x + 1] - off;
         const int64_t il = w.y + lane;
         if (il >= nb) continue;
-        const double* pp = a.part + a.part_off[w.x];
+        const T* pp = a.part + a.part_off[w.x];
         double v[DIM], f[DIM];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            v[c] = pp[c * nb + il];
-            f[c] = pp[(DIM + c) * nb + il];
+            v[c] = (double)pp[c * nb + il];
+            f[c] = (double)pp[(DIM + c) * nb + il];
         }
         for (int s = 1; s < w.z; ++s) {
-            const double* ps = pp + (int64_t)s * (2 * DIM) * nb;
+            const T* ps = pp + (int64_t)s * (2 * DIM) * nb;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) {
-                v[c] += ps[c * nb + il];
-                f[c] += ps[(DIM + c) * nb + il];
+                v[c] += (double)ps[c * nb + il];
+                f[c] += (double)ps[(DIM + c) * nb + il];
             }
         }
         epilogue<T, DIM, FORCE>(a.epi, a.ntot, off + il, v, f);

@@ -354,13 +354,13 @@ __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[ROWS], in
 
 // One workgroup's superblock pair (X, Y) of a point set of n points: component c of point i at
 // q[c * ld + i] (ld = n for one problem, the batch's total for a batched one); partial sums in
-// part, (S + 1) slots of 2 dim x n doubles.  CUT: flags[b] (b = the pair's number) says
+// part, (S + 1) slots of 2 dim x n values of T (each a double sum, rounded once).  CUT: flags[b] (b = the pair's number) says
 // whether the pair wrote its slots; a pair whose tiles are all farther apart than the cutoff
 // writes nothing else (lm_finish_kernel skips its slots).
 template <class T, int DIM, int KER, bool FORCE, bool CUT, int ROWS>
 __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, const T* __restrict__ p, int64_t ld,
                                                     int64_t n, int64_t S, int64_t X, int64_t Y, double kqd,
-                                                    double wscale, double* __restrict__ part,
+                                                    double wscale, T* __restrict__ part,
                                                     const double* __restrict__ box, double rc2,
                                                     uint8_t* __restrict__ flags, int64_t b)
 {
@@ -437,7 +437,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
     const T* jb = jbuf + lane * E;
     double* acc = region + wave * EC * CW + lane;
     const int64_t slot_col = diag ? S : X;
-    double* pc = part + slot_col * (2 * DIM) * n;
+    T* pc = part + slot_col * (2 * DIM) * n;
     for (int64_t J = J0; J < J1; ++J) {
         // single precision: the next tile's reads are in flight while this one is evaluated
         const bool fetch = sizeof(T) == sizeof(float) && sym_fetch_fits<DIM>();
@@ -480,7 +480,7 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
                 }
             }
             const int64_t j = J * kSymSteps + l;
-            if (j < n) pc[c * n + j] = (c < DIM) ? s : s * fscale;
+            if (j < n) pc[c * n + j] = (T)((c < DIM) ? s : s * fscale);
         }
         if (next) {
             if (fetch)
@@ -491,15 +491,15 @@ __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, con
         __syncthreads();
     }
 
-    double* pr = part + Y * (2 * DIM) * n;
+    T* pr = part + Y * (2 * DIM) * n;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
         const int64_t i = I[r] * kSymSteps + lane;
         if (I[r] >= NT || i >= n) continue;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            pr[c * n + i] = vs[r][c];
-            if (FORCE) pr[(DIM + c) * n + i] = fs[r][c] * fscale;
+            pr[c * n + i] = (T)vs[r][c];
+            if (FORCE) pr[(DIM + c) * n + i] = (T)(fs[r][c] * fscale);
         }
     }
 }
