@@ -502,15 +502,23 @@ bool dense_fits(int64_t n)
     double need = 8.0 * (double)n * (double)n + 8.0 * (double)lm::dense_linv_elems(n);
     if (use_super(n))
         need += 8.0 * (double)(lm::dense_super_elems(n) + lm::dense_solve_scratch_elems(n));
+    need += 4.0 * (double)lm::dense_panel_f32_elems(n);   // a single-precision factor's panel copy
     return need <= 0.5 * (double)freeb;
 }
 
 // f32_update: the trailing updates multiply in single precision (for solves that only steer a
-// match with single-precision shoots); LM_FACTOR_F32 (0/1) overrides the choice.
+// match with single-precision shoots), staging a float copy of each update's operand columns;
+// LM_FACTOR_F32 (0/1) overrides the choice and LM_FACTOR_F32_PANEL=0 stages from the FP64
+// matrix instead (the same result; for comparison).
 lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspace& ws, DenseFactor* f,
                        hipStream_t st, bool f32_update = false)
 {
     if (const char* e = std::getenv("LM_FACTOR_F32")) f32_update = e[0] == '1';
+    float* panel = nullptr;
+    if (f32_update) {
+        const char* e = std::getenv("LM_FACTOR_F32_PANEL");
+        if (!(e && e[0] == '0')) LM_TRY(ws.get(&panel, lm::dense_panel_f32_elems(n)));
+    }
     f->n = n;
     LM_TRY(ws.get(&f->L, n * n));
     LM_TRY(ws.get(&f->Linv, lm::dense_linv_elems(n)));
@@ -522,7 +530,7 @@ lm_status dense_factor(const lm_params* prm, int64_t n, const double* X, Workspa
     double kq, wscale;
     kernel_scales(prm, &kq, &wscale);
     LM_HIP(lm::launch_dense_factor(prm->dim, prm->kernel, kq, prm->tau, X, n, f->L, f->Linv, f->info, st,
-                                   f32_update));
+                                   f32_update, panel));
     if (f->W) LM_HIP(lm::launch_dense_super(f->L, f->Linv, n, f->W, st));
     int info = 0;
     LM_HIP(hipMemcpyAsync(&info, f->info, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -28,6 +28,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "lm_internal.h"
@@ -450,11 +451,28 @@ __global__ __launch_bounds__(256, 2) void lm_syrk128_kernel(double* __restrict__
 }
 
 
+// The block's columns of the trailing rows rounded to float once, for the single-precision
+// update below: P[(r - t0) w + c] = K[r][k0 + c], t0 <= r < n, c < w (one workgroup per row).
+// Every tile pair then stages four bytes per operand instead of eight, from a compact copy.
+__global__ __launch_bounds__(256) void lm_panel_f32_kernel(const double* __restrict__ K, int64_t n, int64_t k0, int w,
+                                                           int64_t t0, float* __restrict__ P)
+{
+    const int64_t r = t0 + blockIdx.x;
+    for (int c = threadIdx.x; c < w; c += blockDim.x) P[(r - t0) * w + c] = (float)K[r * n + k0 + c];
+}
+
+__device__ __forceinline__ float syrk_load_f32(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
 // The same 128 x 128 trailing update with the products in single precision, for factors whose
 // solves only steer an iteration (matches with single-precision shoots): the staged operands
 // are rounded to float, multiplied on v_mfma_f32_16x16x4f32 (twice the FP64 matrix rate) with
 // float accumulation over the block's columns, and the result is subtracted from the FP64
-// matrix.  The factor is then accurate to about the single-precision rounding of each update
+// matrix.  PANEL: the operands come from the float copy lm_panel_f32_kernel made (P, pitch bs,
+// row t0 first); else they are read from K as FP64 and rounded as they are staged (the same
+// floats either way).  The factor is then accurate to about the single-precision rounding of each update
 // (a solve to roughly cond(K) times 1e-6).  Operand layout (measured): lane l supplies A[l%16]
 // [l/16] and B[l/16][l%16] and holds D[4 (l/16) + r][l%16], r < 4, of the 16 x 16 block.  Wave
 // w computes the 64 x 64 quarter (w/2, w%2) as 4 x 4 blocks, 16 instructions per k-step of 4;
@@ -462,9 +480,12 @@ __global__ __launch_bounds__(256, 2) void lm_syrk128_kernel(double* __restrict__
 // at two columns from distinct banks.
 typedef float v4f32 __attribute__((ext_vector_type(4)));
 
+template <bool PANEL>
 __global__ __launch_bounds__(256, 2) void lm_syrk128_f32_kernel(double* __restrict__ K, int64_t n, int64_t k0,
-                                                                int bs, int64_t t0)
+                                                                int bs, int64_t t0, const float* __restrict__ P)
 {
+    using S = typename std::conditional<PANEL, float, double>::type;   // a staged value
+    constexpr unsigned ES = sizeof(S);
     constexpr int KC = 32;
     constexpr int LD = KC + 2;
     __shared__ float Ai[128 * LD];
@@ -480,23 +501,33 @@ __global__ __launch_bounds__(256, 2) void lm_syrk128_f32_kernel(double* __restri
     const bool diag = (ti == tj);
     const bool active = !(diag && wc > wr);
 
-    // staging as in lm_syrk128_kernel (FP64 loads), rounded to float as it is stored
+    // staging as in lm_syrk128_kernel (buffer loads from the tile's first row), rounded to
+    // float as it is stored unless it comes from the float copy
     constexpr int RS = 256 / KC, NU = 128 / RS;
     const int sc = tid % KC, sr = tid / KC;
     const int64_t rows_i = (n - ri) < 128 ? (n - ri) : 128;
     const int64_t rows_j = (n - rj) < 128 ? (n - rj) : 128;
-    const __amdgpu_buffer_rsrc_t bi =
-        __builtin_amdgcn_make_buffer_rsrc(K + ri * n + k0, (short)0, (int)(rows_i * n * 8), kSyrkRsrcWord3);
-    const __amdgpu_buffer_rsrc_t bj =
-        __builtin_amdgcn_make_buffer_rsrc(K + rj * n + k0, (short)0, (int)(rows_j * n * 8), kSyrkRsrcWord3);
-    const unsigned rowstep = (unsigned)(RS * n * 8);
-    const unsigned lane_off = (unsigned)((sr * n + sc) * 8);
-    double pa[NU], pb[NU];
+    const int64_t pitch = PANEL ? bs : n;   // elements between rows of the operand buffer
+    const void* base_i = PANEL ? (const void*)(P + (ri - t0) * bs) : (const void*)(K + ri * n + k0);
+    const void* base_j = PANEL ? (const void*)(P + (rj - t0) * bs) : (const void*)(K + rj * n + k0);
+    const __amdgpu_buffer_rsrc_t bi = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base_i), (short)0,
+                                                                        (int)(rows_i * pitch * ES), kSyrkRsrcWord3);
+    const __amdgpu_buffer_rsrc_t bj = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base_j), (short)0,
+                                                                        (int)(rows_j * pitch * ES), kSyrkRsrcWord3);
+    const unsigned rowstep = (unsigned)(RS * pitch * ES);
+    const unsigned lane_off = (unsigned)((sr * pitch + sc) * ES);
+    auto load = [&](__amdgpu_buffer_rsrc_t r, unsigned off) -> S {
+        if constexpr (PANEL)
+            return syrk_load_f32(r, off);
+        else
+            return syrk_load(r, off);
+    };
+    S pa[NU], pb[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
         const unsigned off = syrk_col_off(lane_off, sc < bs);
-        pa[u] = syrk_load(bi, off + u * rowstep);
-        pb[u] = syrk_load(bj, off + u * rowstep);
+        pa[u] = load(bi, off + u * rowstep);
+        pb[u] = load(bj, off + u * rowstep);
     }
 
     v4f32 acc[4][4];
@@ -517,11 +548,11 @@ __global__ __launch_bounds__(256, 2) void lm_syrk128_f32_kernel(double* __restri
         __syncthreads();
         const int kn = kc + KC;
         if (kn < bs) {
-            const unsigned off = syrk_col_off(lane_off + (unsigned)kn * 8, kn + sc < bs);
+            const unsigned off = syrk_col_off(lane_off + (unsigned)kn * ES, kn + sc < bs);
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                pa[u] = syrk_load(bi, off + u * rowstep);
-                pb[u] = syrk_load(bj, off + u * rowstep);
+                pa[u] = load(bi, off + u * rowstep);
+                pb[u] = load(bj, off + u * rowstep);
             }
         }
         if (active) {
@@ -1450,8 +1481,10 @@ int dense_panels(int64_t n) { return (int)((n + kPanel - 1) / kPanel); }
 // the inverses of the diagonal blocks, then their transposes
 int64_t dense_linv_elems(int64_t n) { return 2 * (int64_t)dense_panels(n) * kPanel * kPanel; }
 
+int64_t dense_panel_f32_elems(int64_t n) { return n * kOuter * kPanel; }
+
 hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,
-                               double* Linv, int* info, hipStream_t st, bool f32_update)
+                               double* Linv, int* info, hipStream_t st, bool f32_update, float* panel)
 {
     if (n <= 0 || n >= kDenseMaxN) return hipErrorInvalidValue;
     hipLaunchKernelGGL(lm_int_zero_kernel, dim3(1), dim3(64), 0, st, info);
@@ -1497,10 +1530,15 @@ hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const
         const int width = (int)(kend - kb);
         if (rest >= 1024) {
             const int64_t nt = (rest + 127) / 128;
-            if (f32_update)
-                hipLaunchKernelGGL(lm_syrk128_f32_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n,
-                                   kb, width, kend);
-            else
+            if (f32_update && panel) {
+                hipLaunchKernelGGL(lm_panel_f32_kernel, dim3((unsigned)rest), dim3(256), 0, st, (const double*)K, n, kb,
+                                   width, kend, panel);
+                hipLaunchKernelGGL(lm_syrk128_f32_kernel<true>, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K,
+                                   n, kb, width, kend, (const float*)panel);
+            } else if (f32_update) {
+                hipLaunchKernelGGL(lm_syrk128_f32_kernel<false>, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st,
+                                   K, n, kb, width, kend, (const float*)nullptr);
+            } else
                 hipLaunchKernelGGL(lm_syrk128_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, K, n, kb,
                                    width, kend);
         } else {

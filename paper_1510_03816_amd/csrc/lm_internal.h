@@ -309,9 +309,13 @@ constexpr int64_t kDenseMaxN = (int64_t)1 << 21;
 int dense_panels(int64_t n);
 int64_t dense_linv_elems(int64_t n);
 // f32_update: the trailing updates of 1024 rows or more multiply in single precision (a factor
-// for solves that only steer an iteration; about cond(K) times 1e-6 relative).
+// for solves that only steer an iteration; about cond(K) times 1e-6 relative).  panel
+// (nullable, dense_panel_f32_elems(n) floats): a buffer for the float copy of each update's
+// operand columns, which the update then stages at half the bytes (the same result).
+int64_t dense_panel_f32_elems(int64_t n);
 hipError_t launch_dense_factor(int dim, int kernel, double kq, double tau, const double* X, int64_t n, double* K,
-                               double* Linv, int* info, hipStream_t st, bool f32_update = false);
+                               double* Linv, int* info, hipStream_t st, bool f32_update = false,
+                               float* panel = nullptr);
 // y <- (L L^T)^{-1} y for dim component vectors (component c at y + c * ldy), in place.
 hipError_t launch_dense_solve(const double* L, const double* Linv, int64_t n, int dim, double* y, int64_t ldy,
                               hipStream_t st);

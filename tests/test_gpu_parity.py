@@ -642,6 +642,25 @@ def test_dense_ksolve_with_single_precision_updates(n, dim, sigma, tau, monkeypa
     assert rel_err(host(x64), want) <= max(1e-12, 1e-15 * cond)
 
 
+@pytest.mark.parametrize("n,dim", [(2500, 3), (5000, 3), (3001, 2)])
+def test_single_precision_updates_from_the_float_panel_copy_are_bitwise_the_same(n, dim, monkeypatch):
+    """The single-precision trailing updates stage a float copy of each update's operand
+    columns (ragged tiles at the end, rows past n read as zero); staged from the FP64 matrix
+    and rounded on the way into LDS (LM_FACTOR_F32_PANEL = 0) they multiply the same floats in
+    the same order, so the solves agree bit for bit."""
+    monkeypatch.setenv("LM_FACTOR_F32", "1")
+    X = inputs.fibonacci_sphere(n) if dim == 3 else inputs.config_curve2d(n).X
+    b = np.random.default_rng([132, n]).standard_normal(X.shape)
+    prm = lm.make_params(dim, lm.CONON, 0.15, tau=0.1)
+    out = []
+    for panel in ("1", "0"):
+        monkeypatch.setenv("LM_FACTOR_F32_PANEL", panel)
+        x = dev(b)
+        lm.lm_ksolve(prm, dev(X), x, x, solver=lm.SOLVE_DENSE)
+        out.append(host(x))
+    assert np.all(np.isfinite(out[0])) and np.array_equal(out[0], out[1])
+
+
 def test_mixed_precision_match_with_single_precision_factor_updates():
     """A match with FP32 shoots switching to FP64 on a 2600-point curve, whose dense factor
     takes a single-precision trailing update: it reaches tol = 1e-8 with an FP64 residual in
