@@ -115,7 +115,9 @@ __device__ __forceinline__ void sym_pair(const T (&qi)[DIM], const T (&qj)[DIM],
 
 // Lane l receives x of lane (l + 1) mod 64: a rotation of the whole wavefront by one lane
 // (DPP wave_rol; every source lane is in range, so bound_ctrl changes nothing and lets the
-// compiler fold the move into the add that consumes it).
+// compiler fold the move into the add that consumes it).  All 64 lanes must be active: the
+// symmetric kernels call it only in code every lane of the wave runs (lanes past n hold zero
+// momenta, and every branch around it depends on the wave's tiles alone).
 __device__ __forceinline__ float wave_rotate_down(float x)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x134, 0xF, 0xF, true));
@@ -354,9 +356,9 @@ __device__ __forceinline__ void sym_tile(bool diag, const int64_t (&I)[ROWS], in
 
 // One workgroup's superblock pair (X, Y) of a point set of n points: component c of point i at
 // q[c * ld + i] (ld = n for one problem, the batch's total for a batched one); partial sums in
-// part, (S + 1) slots of 2 dim x n values of T (each a double sum, rounded once).  CUT: flags[b] (b = the pair's number) says
-// whether the pair wrote its slots; a pair whose tiles are all farther apart than the cutoff
-// writes nothing else (lm_finish_kernel skips its slots).
+// part, (S + 1) slots of 2 dim x n values of T (each a double sum, rounded once).  CUT:
+// flags[b] (b = the pair's number) says whether the pair wrote its slots; a pair whose tiles
+// are all farther apart than the cutoff writes nothing else (lm_finish_kernel skips its slots).
 template <class T, int DIM, int KER, bool FORCE, bool CUT, int ROWS>
 __device__ __forceinline__ void sym_superblock_pair(const T* __restrict__ q, const T* __restrict__ p, int64_t ld,
                                                     int64_t n, int64_t S, int64_t X, int64_t Y, double kqd,
