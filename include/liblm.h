@@ -201,8 +201,9 @@ lm_status lm_ksolve(const lm_params *params, int64_t n, const double *X, const d
  * momenta, the residual and the K-solves stay in double; the dense factor's trailing updates
  * then multiply in single precision (the solves only steer the iteration; environment
  * LM_FACTOR_F32 = 0/1 overrides), staged from a float copy of each update's columns
- * (dense_fits counts its n x 1024 floats; LM_FACTOR_F32_PANEL = 0 stages from the double
- * matrix instead, with the same result).  opts->solver picks the K-solve;
+ * (n x 1024 floats, counted in the dense solver's memory check; LM_FACTOR_F32_PANEL = 0
+ * stages from the double matrix instead, with the same result).  opts->solver picks the
+ * K-solve;
  * a dense factor is built once per call (K(X) is fixed during a match).  Synchronous.
  * Returns LM_OK, LM_ENOTCONV, LM_EDIVERGED (non-finite residual, as the paper's NaN for
  * h > 1) or LM_ESINGULAR; in every case p0 and info describe the last iterate. */
