@@ -141,7 +141,7 @@ lm_status lm_rhs(const lm_params *params, int64_t n, const void *q, const void *
 /* Launch plan of the pair sums of n points under `params` (host only: no GPU work, no
  * allocation): the kernel that lm_rhs and every RK4 stage of lm_shoot use, and its shape.
  * symmetric = 1: each unordered pair is evaluated once and serves both particles (double
- * precision from 128 tiles of 64 points on, single precision from 384; with tile skipping
+ * precision from 128 tiles of 64 points on, single precision from 256; with tile skipping
  * from 768 in both); 0: the one-sided kernel, one target per lane.  The environment variable LM_SYM = 0 or 1 overrides that size rule and
  * LM_SYM_WAVES = 1, 2, 4 or 8 fixes the symmetric kernel's workgroup width (for tuning and
  * tests; both are read at every launch).  small = 1: shoots of this size (at most 128 points,

@@ -248,15 +248,18 @@ constexpr int64_t kSymOneWaveTiles = 128;
 // symmetric kernel takes 502 us per stage against 574 one-sided (conon: 3784 against 5542),
 // at N = 16384 149 against 120.
 constexpr int64_t kSymCutTiles = 768;
-// Single precision (column sums in registers, two row tiles per wave), 3-D conon sphere
-// shoots, us per stage, one-sided against symmetric with two | four waves: N = 16384 138 against
-// 142 | 169, 24576 282 against 267 | 265, 32768 500-504 against 436-439 | 449-456, 49152 1073
-// against 956 | 911-914, 65536 1945 against 1708 | 1603, 98304 4215-4220 against 3769-3779 |
-// 3516.  Four rows per wave: 1686-1695 at 65536 (two waves).
+// Single precision (column sums in registers, two row tiles per wave, float partial sums),
+// 3-D conon sphere shoots, us per stage, one-sided against symmetric with one | two | four
+// waves: N = 12288 81.6 against 89.9 | 97.2 | 121.1, 16384 137.6 against 133.0 | 139.2 |
+// 164.4, 20480 199.8 against 189.2 | 192.3 | 213.4, 24576 280.8 against 258.2 | 261.2 | 261.9,
+// 32768 501.7 against 435.6 | 421.7 | 439.4; with double partial sums 49152 1073 against
+// 956 (two) | 911-914 (four), 65536 1945 against 1708 | 1603, 98304 4215-4220 against
+// 3769-3779 | 3516.  Four rows per wave: 1686-1695 at 65536 (two waves).
 #ifndef LM_SYM_MIN_TILES_F32
-#define LM_SYM_MIN_TILES_F32 384
+#define LM_SYM_MIN_TILES_F32 256
 #endif
 constexpr int64_t kSymMinTilesF32 = LM_SYM_MIN_TILES_F32;
+constexpr int64_t kSymF32TwoWaveTiles = 512;
 constexpr int64_t kSymF32FourWaveTiles = 768;
 // The VJP (heavier pairs, 154-162 VGPRs) gains from 128 tiles on: at N = 8192 one wave per
 // workgroup 136 us against 158 one-sided, at 16384 two waves 415 against 545, at 65536 two

@@ -78,7 +78,10 @@ SymPlan plan_sym(int64_t n, bool force, int kind, bool cut)
         w = cut ? 2 : 8 / rows;
     } else if (kind == SYM_F32 && T >= kSymMinTilesF32) {
         // with tile skipping superblocks of 4 tiles, as in double precision
-        w = (T >= kSymF32FourWaveTiles && !cut) ? 4 : 2;
+        if (cut)
+            w = 2;
+        else
+            w = T >= kSymF32FourWaveTiles ? 4 : T >= kSymF32TwoWaveTiles ? 2 : 1;
     } else if (kind == SYM_F64 && T >= kSymMinTiles) {
         w = 2;
     } else if (kind == SYM_F64 && T >= kSymOneWaveTiles) {

@@ -83,11 +83,11 @@ def test_one_sided_split_rule(monkeypatch):
     assert p["workgroups"] == 79 * 39 and p["partial_slots"] == 39
 
 
-@pytest.mark.parametrize("n,waves", [(24512, 0), (24513, 2), (32768, 2), (49088, 2), (49089, 4), (65536, 4),
-                                     (131072, 4)])
+@pytest.mark.parametrize("n,waves", [(16320, 0), (16321, 1), (24576, 1), (32704, 1), (32705, 2), (49088, 2),
+                                     (49089, 4), (65536, 4), (131072, 4)])
 def test_single_precision_size_rule(n, waves):
-    """Single precision: the one-sided kernel below 384 tiles, then the symmetric kernel with
-    two row tiles per wave, two waves and four from 768 tiles."""
+    """Single precision: the one-sided kernel below 256 tiles, then the symmetric kernel with
+    two row tiles per wave: one wave, two from 512 tiles, four from 768."""
     p = plan(n, dtype=lm.F32)
     T = -(-n // 64)
     if waves == 0:
