@@ -156,19 +156,27 @@ def test_sym_agrees_with_one_sided_kernel(kernel):
     assert rel_err(b[0], a[0]) <= 1e-13 and rel_err(b[1], a[1]) <= 1e-13
 
 
-@pytest.mark.parametrize("n", [12289, 30000])
-def test_sym_by_size_rule_sampled(n):
-    """Sizes where the size rule itself picks the symmetric kernel (two waves per workgroup;
-    four are covered at N = 65536 by the full-size tests); sampled rows against the oracle,
-    and the forces sum to zero."""
+@pytest.mark.parametrize("n,dtype,waves", [(12289, lm.F64, 2), (30000, lm.F64, 2), (17000, lm.F32, 1),
+                                           (33000, lm.F32, 2)])
+def test_sym_by_size_rule_sampled(n, dtype, waves):
+    """Sizes where the size rule itself picks the symmetric kernel (one or two waves per
+    workgroup; four are covered at N = 65536 by the full-size tests); sampled rows against the
+    oracle, and the forces sum to zero: in FP64 within 1e-9 of the largest force, in FP32 within
+    1e-6 of the sum of the forces' magnitudes (the rows' and the columns' float sums round the
+    same pair terms in different orders; measured 4.6e-8 at N = 17000)."""
     pr = inputs.config_sphere3d(n)
-    q, p = pr.X, pr.p_bench()
-    dq, dp = gpu_rhs(q, p, pr.kernel, pr.sigma)
+    q, p = rounded(pr.X, dtype), rounded(pr.p_bench(), dtype)
+    plan = lm.lm_pair_plan(lm.make_params(3, pr.kernel, pr.sigma, dtype=dtype), n)
+    assert plan["symmetric"] == 1 and plan["waves"] == waves
+    dq, dp = gpu_rhs(q, p, pr.kernel, pr.sigma, dtype=dtype)
     idx = np.sort(np.random.default_rng(113).choice(n, 128, replace=False))
     idx = np.concatenate([[0, 63, 64, 127, 128, n - 1], idx])
     rq, rp = oracle.rhs_rows(q, p, idx, pr.kernel, pr.sigma)
-    assert rel_err(dq[:, idx], rq) <= 1e-10 and rel_err(dp[:, idx], rp) <= 1e-10
-    assert np.max(np.abs(dp.sum(axis=1))) <= 1e-9 * np.max(np.abs(dp))
+    assert rel_err(dq[:, idx], rq) <= TOL[dtype] and rel_err(dp[:, idx], rp) <= TOL[dtype]
+    if dtype == lm.F64:
+        assert np.max(np.abs(dp.sum(axis=1))) <= 1e-9 * np.max(np.abs(dp))
+    else:
+        assert np.all(np.abs(dp.sum(axis=1)) <= 1e-6 * np.abs(dp).sum(axis=1))
 
 
 @pytest.mark.parametrize("dtype", [lm.F64, lm.F32])
